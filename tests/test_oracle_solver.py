@@ -1,0 +1,216 @@
+"""Pins of the oracle's Jacobi PCG and of the discrete problem it solves.
+
+* Constant coefficient: fast diagonalisation (1D generalised eigenproblems,
+  Kronecker structure) is an independent exact solver.
+* Variable coefficient: SuperLU.
+* Stopping rule of Table tab:solver_settings, failure codes.
+* O(h^{k+1}) L2 convergence (Eq. L2norm) on a manufactured solution with the
+  reciprocal-density coefficient of a droplet.
+* App. D: the diffuse 1D phase-change pressure (Eq. stefan_diffuse_pressure) solves the
+  pressure Poisson problem whose right-hand side comes from the diffuse velocity
+  (Eq. stefan_diffuse_velocity); the discrete solution converges to it and is
+  invariant across the flat interface (Sec. "One-dimensional phase change").
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import oracle
+import workloads as W
+from indep import global_1d
+
+
+def test_pcg_matches_fast_diagonalisation():
+    k, n = 2, (5, 4, 3)
+    rho = 3.0
+    m = W.Mesh(ncells=n, degree=k, rho_l=rho, rho_g=rho, extent=(1.0, 0.8, 0.6))
+    c = 1.0 / rho
+    op = oracle.Operator(m, phi=np.zeros(m.ndofs))
+    rng = np.random.default_rng(5)
+    b = rng.uniform(-1, 1, m.ndofs)
+    b[m.boundary_mask()] = 0.0
+    x, info = op.pcg(b, rtol=1e-14)
+    assert info["status"] == 0
+    # fast diagonalisation on the interior nodes
+    mats = []
+    for d in range(3):
+        M, K = global_1d(k, n[d], m.h[d])
+        M, K = M[1:-1, 1:-1], K[1:-1, 1:-1]
+        lam, V = sla.eigh(K, M)            # K V = M V diag(lam), V^T M V = I
+        mats.append((lam, V))
+    Nx, Ny, Nz = m.nnodes
+    B = b.reshape(Nz, Ny, Nx)[1:-1, 1:-1, 1:-1]
+    (lx, Vx), (ly, Vy), (lz, Vz) = mats
+    T = np.einsum("ia,jb,kc,kji->cba", Vx, Vy, Vz, B)       # apply V^T in each direction
+    T = T / (c * (lx[None, None, :] + ly[None, :, None] + lz[:, None, None]))
+    U = np.einsum("ia,jb,kc,cba->kji", Vx, Vy, Vz, T)
+    ref = np.zeros((Nz, Ny, Nx))
+    ref[1:-1, 1:-1, 1:-1] = U
+    ref = ref.ravel()
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-12
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_pcg_matches_direct_variable_coefficient(k):
+    m = W.unit_cube(4 if k == 2 else 3, k, 1000.0, 1.0)
+    m.eps = 2.0 / 4
+    phi = W.droplet_phi(m, 0.25, m.eps)
+    op = oracle.Operator(m, phi=phi)
+    b = oracle.manufactured_sine_rhs(m, 0.25, m.eps)
+    x, info = op.pcg(b, rtol=1e-13)
+    ref = spla.spsolve(op.to_scipy().tocsc(), b)
+    assert info["status"] == 0
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-9
+    r = b - op.matvec(x)
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(b) * 1.0001
+
+
+def test_pcg_stopping_rule_and_failures():
+    m = W.unit_cube(3, 2, 10.0, 1.0)
+    m.eps = 0.2
+    phi = W.droplet_phi(m, 0.3, m.eps)
+    op = oracle.Operator(m, phi=phi)
+    b = oracle.sine_load(m)
+    x, info = op.pcg(b, rtol=1e-6)
+    assert info["status"] == 0 and info["rel_residual"] < 1e-6
+    # the rule is relative to the initial residual: a warm start keeps iterating
+    x2, info2 = op.pcg(b, x0=x, rtol=1e-6)
+    assert info2["iterations"] >= 1
+    assert np.linalg.norm(b - op.matvec(x2)) < np.linalg.norm(b - op.matvec(x))
+    # absolute tolerance alone
+    _, info3 = op.pcg(b, rtol=0.0, atol=1e300)
+    assert info3["status"] == 0 and info3["iterations"] == 0
+    # max_iter reached
+    _, info4 = op.pcg(b, rtol=1e-14, max_iter=1)
+    assert info4["status"] == 1
+    # breakdown: negative density makes the operator indefinite
+    mneg = W.unit_cube(3, 2, -10.0, -1.0)
+    opn = oracle.Operator(mneg, phi=phi)
+    _, info5 = opn.pcg(b, rtol=1e-10)
+    assert info5["status"] == 2
+    # NaN in the right-hand side
+    bn = b.copy()
+    bn[20] = np.nan
+    _, info6 = op.pcg(bn, rtol=1e-10)
+    assert info6["status"] == 2
+
+
+def _l2_error_sine(m, p):
+    nq = m.degree + 3
+    x, y, z, w = oracle.qp_coords(m, nq)
+    ph = oracle.eval_qp(m, p, nq)
+    ex = np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+    return math.sqrt(np.sum(w * (ph - ex) ** 2))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k,levels", [(2, (8, 16, 32)), (3, (6, 12)), (4, (4, 8))])
+def test_convergence_order(k, levels):
+    """Fixed eps = 0.05 and density ratio 10, so that the coefficient is resolved."""
+    errs = []
+    for n in levels:
+        m = W.unit_cube(n, k, 10.0, 1.0)
+        m.eps = 0.05
+        phi = W.droplet_phi(m, 0.25, m.eps)
+        op = oracle.Operator(m, phi=phi)
+        b = oracle.manufactured_sine_rhs(m, 0.25, m.eps)
+        p, info = op.pcg(b, rtol=1e-12)
+        assert info["status"] == 0
+        errs.append(_l2_error_sine(m, p))
+    rates = [math.log(errs[i] / errs[i + 1], levels[i + 1] / levels[i]) for i in range(len(errs) - 1)]
+    assert rates[-1] > k + 1 - 0.35, (errs, rates)
+
+
+def _slab_case(n, k, heaviside, ratio=1000.0, mdot=2.0, eps=0.04):
+    m = W.Mesh(ncells=(n, 2, 1), degree=k, bc=(0, 0, 1, 1, 1, 1),
+               rho_l=ratio, rho_g=1.0, heaviside=heaviside, extent=(1.0, 2.0 / n, 1.0 / n))
+    m.eps = eps
+    phi = W.slab_phi(m, 0.5, eps)
+    return m, phi, mdot
+
+
+def _slab_solution(m, phi, mdot):
+    """Solve with the right-hand side of the diffuse 1D phase-change flow and compare with
+    the diffuse pressure of App. D."""
+    from indep import heaviside_closed
+    lin = m.heaviside == W.H_LINEAR
+    rl, rg = m.rho_l, m.rho_g
+    x, _, _, _ = oracle.qp_coords(m)
+    eps = m.eps
+    ph = np.tanh((0.5 - x) / (2 * eps))
+    H = heaviside_closed(ph, linear=lin)
+    if lin:
+        dHdphi = 0.5
+    else:
+        a = np.arctanh(np.clip(ph, -0.999999999999, 0.999999999999))
+        dHdphi = np.where(np.abs(a) < 1.5, (1 + np.cos(2 * np.pi * a / 3)) / (3 * (1 - ph ** 2)), 0.0)
+    dphidx = -(1 - ph ** 2) / (2 * eps)
+    dHdx = dHdphi * dphidx
+    # Eq. stefan_diffuse_velocity with a static interface (u_bar = mdot / rho_l)
+    u = mdot / rl + mdot * (1 - H) * (1 / rg - 1 / rl)
+    du = -mdot * dHdx * (1 / rg - 1 / rl)
+    # pressure Poisson from the momentum balance: (1/rho) p' = -u u'  ->  a(p,q) = (-u u', q')
+    ell = oracle.rhs_flux(m, -u * du, np.zeros_like(u), np.zeros_like(u))
+    X, _, _ = m.node_grid()
+    phin = np.tanh((0.5 - X.ravel()) / (2 * eps))
+    p_exact_nodes = mdot ** 2 * heaviside_closed(phin, linear=lin) * (1 / rg - 1 / rl)
+    op_full = oracle.Operator(m, phi=phi, constrained=False)
+    op = oracle.Operator(m, phi=phi, constrained=True)
+    b = oracle.constrain_rhs(op_full, m, ell, g_bnd=p_exact_nodes)
+    p = spla.spsolve(op.to_scipy().tocsc(), b)
+    # L2 error against Eq. stefan_diffuse_pressure
+    nq = m.degree + 3
+    xq, _, _, w = oracle.qp_coords(m, nq)
+    phq = np.tanh((0.5 - xq) / (2 * eps))
+    pex = mdot ** 2 * heaviside_closed(phq, linear=lin) * (1 / rg - 1 / rl)
+    err = math.sqrt(np.sum(w * (oracle.eval_qp(m, p, nq) - pex) ** 2)) / math.sqrt(np.sum(w * pex ** 2))
+    return p, err
+
+
+@pytest.mark.parametrize("heaviside", [W.H_LINEAR, W.H_PAPER])
+def test_app_d_diffuse_pressure(heaviside):
+    k = 2
+    errs = []
+    levels = (32, 64, 128)
+    for n in levels:
+        m, phi, mdot = _slab_case(n, k, heaviside)
+        p, err = _slab_solution(m, phi, mdot)
+        errs.append(err)
+        # invariance across the flat interface (y, z directions)
+        Nx, Ny, Nz = m.nnodes
+        P = p.reshape(Nz, Ny, Nx)
+        assert np.abs(P - P[0:1, 0:1, :]).max() < 1e-9 * np.abs(P).max()
+    rate = math.log(errs[-2] / errs[-1], 2)
+    # the sine ramp is only C^1 at |d| = 3 eps, which limits the rate below k+1
+    assert errs[-1] < 1e-4 and rate > (2.7 if heaviside == W.H_LINEAR else 2.5), (errs, rate)
+
+
+def test_app_d_rejects_arithmetic_density():
+    """The same right-hand side with an arithmetic density mean gives a different pressure:
+    only the reciprocal interpolation of Eq. rhoEff is consistent with App. D."""
+    m, phi, mdot = _slab_case(64, 2, W.H_LINEAR)
+    p, err = _slab_solution(m, phi, mdot)
+    assert err < 1e-4
+    # build the arithmetic-mean operator through explicit Gauss-point coefficients
+    from indep import heaviside_closed
+    ph = oracle.eval_qp(m, phi)
+    H = heaviside_closed(ph, linear=True)
+    c_arith = 1.0 / (H * m.rho_l + (1 - H) * m.rho_g)
+    op_a = oracle.Operator(m, cq=c_arith, constrained=True)
+    op_full = oracle.Operator(m, cq=c_arith, constrained=False)
+    X, _, _ = m.node_grid()
+    phin = np.tanh((0.5 - X.ravel()) / (2 * m.eps))
+    pex = mdot ** 2 * heaviside_closed(phin, linear=True) * (1 / m.rho_g - 1 / m.rho_l)
+    x, _, _, _ = oracle.qp_coords(m)
+    eps = m.eps
+    phq = np.tanh((0.5 - x) / (2 * eps))
+    Hq = heaviside_closed(phq, linear=True)
+    u = mdot / m.rho_l + mdot * (1 - Hq) * (1 / m.rho_g - 1 / m.rho_l)
+    du = -mdot * 0.5 * (-(1 - phq ** 2) / (2 * eps)) * (1 / m.rho_g - 1 / m.rho_l)
+    ell = oracle.rhs_flux(m, -u * du, 0 * u, 0 * u)
+    b = oracle.constrain_rhs(op_full, m, ell, g_bnd=pex)
+    pa = spla.spsolve(op_a.to_scipy().tocsc(), b)
+    assert np.linalg.norm(pa - pex) / np.linalg.norm(pex) > 0.05
