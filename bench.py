@@ -1,0 +1,178 @@
+"""Benchmark: matrix-free variable-coefficient pressure-Poisson operator on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): unit cube,
+64^3 cells, Q2 (129^3 = 2,146,689 DoFs), droplet phi = tanh((0.25-|x-c|)/(2 eps)),
+eps = 2h, rho_l/rho_g = 1000/1, Dirichlet faces.
+
+One step = 100 FP64 operator applies on seed-1 uniform[-1,1] vectors (every
+apply reads its own x and phi copy and writes its own y, so the 1.7 GB working
+set streams from HBM instead of the 256 MB Infinity Cache), then one FP64
+Jacobi-PCG solve and one FP64/FP32 defect-correction solve to rtol 1e-8 with
+the manufactured right-hand side b = A_D p*, p* = sin(pi x) sin(pi y) sin(pi z).
+
+value = operator MDoF/s of the applies (N * applies / apply time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_DOF_F64 = 24.0      # x read, phi read, y written once per DoF
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--applies", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", action="store_true", help="also time Q3/Q4 and FP32 applies")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline():
+    """The FP64 oracle (CSR assembled by full quadrature, CSR SpMV) on the host
+    cores, on a bounded sample: 32^3 cells Q2 of the same droplet workload."""
+    import oracle
+    import workloads as W
+    wl = W.droplet_at_scale(k=2, n=32, nvec=1, seed=1)
+    m = wl.mesh
+    t0 = time.perf_counter()
+    op = oracle.Operator(m, phi=wl.phi)
+    t_asm = time.perf_counter() - t0
+    x = wl.vectors[0]
+    op.matvec(x)
+    op.matvec(x)
+    ts = []
+    for _ in range(10):
+        t0 = time.perf_counter()
+        op.matvec(x)
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    return {"value": m.ndofs / t / 1e6, "unit": "MDoF/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 CSR SpMV, median of 10 after 2 warm-ups, droplet 32^3 cells Q2 "
+                      f"({m.ndofs} DoFs, nnz {op.nnz}); assembly {t_asm:.2f} s not included"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the operator's multi-GPU sharding is a design "
+              "note); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2401_07805_amd as vpp
+
+    dev = torch.device("cuda", 0)
+    wl = W.droplet_at_scale(k=2, nvec=0)
+    m = wl.mesh
+    N = m.ndofs
+    napp = args.applies
+    log(f"workload {wl.name} N={N}")
+    # one phi copy per problem handle; applies rotate over them
+    npool = max(1, min(napp, math.ceil(600e6 / (BYTES_PER_DOF_F64 * N))))
+    phi_t = torch.from_numpy(wl.phi).to(dev)
+    probs = []
+    for i in range(npool):
+        p = vpp.Problem.from_mesh(m)
+        p.set_phi(phi_t)
+        probs.append(p)
+    cache = os.path.join(ROOT, "paper_2401_07805_amd", "tune_cache.json")
+    cfg = probs[0].tune(cache)
+    for p in probs[1:]:
+        p.set_config(cfg["variant"], cfg["tile"])
+    log(f"kernel config {cfg}")
+    xs_host = W.uniform_vectors(1, napp, N)
+    xs = torch.from_numpy(xs_host).to(dev)
+    del xs_host
+    ys = torch.empty_like(xs)
+    pstar = torch.from_numpy(W.sine_field(m)).to(dev)
+    pstar[torch.from_numpy(m.boundary_mask()).to(dev)] = 0.0
+    b = probs[0].apply(pstar)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(napp):
+            probs[i % npool].apply(xs[i], out=ys[i])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_apply = e0.elapsed_time(e1) / 1e3
+        t0 = time.perf_counter()
+        p64, i64 = probs[0].cg_solve(b, rtol=1e-8)
+        t_cg64 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pmx, imx = probs[0].cg_solve(b, rtol=1e-8, precision="mixed", inner_rtol=1e-3)
+        t_cgmx = time.perf_counter() - t0
+        return t_apply, t_cg64, i64, p64, t_cgmx, imx, pmx
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    res = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    t_apply = sum(r[0] for r in res)
+    value = N * napp * args.steps / t_apply / 1e6
+    per_apply = t_apply / (napp * args.steps)
+    achieved = BYTES_PER_DOF_F64 * N / per_apply / 1e9
+    last = res[-1]
+    err64 = float(torch.linalg.norm(last[3] - pstar) / torch.linalg.norm(pstar))
+    errmx = float(torch.linalg.norm(last[6] - pstar) / torch.linalg.norm(pstar))
+    out = {
+        "metric": "operator MDoF/s + CG time to rtol 1e-8, FP64 vs FP32-mixed, Q2/Q3 hex",
+        "value": value,
+        "unit": "MDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "droplet 64^3 cells Q2, rho 1000/1, eps=2h, 100 applies + FP64 and mixed PCG to 1e-8",
+                   "ndofs": N, "applies_per_step": napp, "kernel": cfg},
+        "apply_us": per_apply * 1e6,
+        "cg_fp64_s": float(np.median([r[1] for r in res])),
+        "cg_fp64_iters": last[2]["iterations"],
+        "cg_fp64_true_rel_res": last[2]["true_rel_residual"],
+        "cg_fp64_err_vs_exact": err64,
+        "cg_mixed_s": float(np.median([r[4] for r in res])),
+        "cg_mixed_inner_iters": last[5]["iterations"],
+        "cg_mixed_outer": last[5]["outer_iterations"],
+        "cg_mixed_true_rel_res": last[5]["true_rel_residual"],
+        "cg_mixed_err_vs_exact": errmx,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * vpp -- matrix-free variable-coefficient pressure-Poisson operator on MI355X.
+ *
+ * Problem (App. F, pressure terms of Eq. weakNavierStokes; Sec. "Numerical
+ * framework"): find p in Q_k (Dirichlet-constrained) with
+ *     a(p,q) = sum_cells sum_{Gauss x_q} W_q c(x_q) grad p . grad q = l(q)
+ * on a uniform box of hexahedra, with (k+1)^3 Gauss points per cell and the
+ * reciprocal density of Eq. rhoEff as coefficient,
+ *     c = 1/rho(phi) = H(phi)/rho_l + (1 - H(phi))/rho_g,
+ * where phi is the nodal conservative level set (Eq. initial_phi), interpolated
+ * to the Gauss points with the Q_k basis and clamped to [-1,1].  H is either
+ * the linear indicator (phi+1)/2 or the sine ramp of Eq. heaviside, which in
+ * terms of phi does not depend on eps (via Eq. distance).
+ * The operator is applied matrix-free, y = sum_i R_i^T A_i R_i x
+ * (Sec. "Numerical framework"), and solved by Jacobi-preconditioned CG with
+ * the stopping rule of Table tab:solver_settings.
+ *
+ * Conventions for every entry point:
+ *  - Vectors are device pointers on the problem's device, length N =
+ *    prod_d (k n_d + 1), lexicographic node order with x fastest,
+ *    g = i + Nx (j + Ny l).  The caller owns them.
+ *  - Dirichlet rows/columns: the operator is A_D = [A_II 0; 0 I] (identity on
+ *    nodes of Dirichlet faces; their entries of x never reach free rows).
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *    are stream-ordered and asynchronous unless stated otherwise.
+ *  - Calls on one problem (or one batch) must not overlap in time: they share
+ *    the library's workspace.
+ *  - Errors are return codes; argument checks run before any launch.  The
+ *    message of the last error on the calling thread is in vpp_last_error().
+ */
+#ifndef VPP_H
+#define VPP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VPP_ABI_VERSION 1
+
+typedef struct vpp_problem_s* vpp_problem;
+typedef struct vpp_batch_s* vpp_batch;
+
+typedef enum {
+    VPP_OK = 0,
+    VPP_ERR_INVALID_ARG = 1,
+    VPP_ERR_UNSUPPORTED = 2,
+    VPP_ERR_OUT_OF_MEMORY = 3,
+    VPP_ERR_HIP = 4,
+    VPP_ERR_NOT_CONVERGED = 5,
+    VPP_ERR_BREAKDOWN = 6,
+    VPP_ERR_STATE = 7
+} vpp_status;
+
+enum { VPP_BC_DIRICHLET = 0, VPP_BC_NEUMANN = 1 };       /* faces x-,x+,y-,y+,z-,z+ */
+enum { VPP_H_LINEAR = 0, VPP_H_PAPER = 1 };              /* (phi+1)/2 | Eq. heaviside */
+enum { VPP_FP64 = 0, VPP_FP32 = 1, VPP_MIXED = 2 };
+
+/* Mesh, element degree and material law of one problem. */
+typedef struct {
+    int32_t ncells[3];      /* cells per direction, >= 1 */
+    double origin[3];
+    double extent[3];       /* box lengths, > 0 */
+    int32_t degree;         /* k in {2,3,4} */
+    int32_t bc[6];          /* VPP_BC_* per face */
+    double rho_l, rho_g;    /* liquid (phi>0) and gas densities, > 0 */
+    int32_t heaviside;      /* VPP_H_* */
+    int32_t device;         /* HIP device ordinal */
+} vpp_desc;
+
+/* CG controls.  Convergence (Table tab:solver_settings): ||r||_2 < atol or
+ * ||r||_2 / ||r0||_2 < rtol, r0 the initial residual.  precision VPP_MIXED runs
+ * FP64 defect correction around an FP32 inner PCG solved to inner_rtol;
+ * check_every = number of iterations between host-side convergence checks
+ * (0 = library default).  Scalars of every CG are FP64. */
+typedef struct {
+    double rtol, atol;
+    int32_t max_iter, precision;
+    double inner_rtol;
+    int32_t inner_max_iter, check_every;
+} vpp_cg_opts;
+
+typedef struct {
+    int32_t iterations;        /* CG iterations (inner iterations summed for VPP_MIXED) */
+    int32_t outer_iterations;  /* defect-correction steps (0 unless VPP_MIXED) */
+    int32_t status;            /* vpp_status of the solve */
+    double rel_residual;       /* ||r|| / ||r0|| as tracked by the (outer) iteration */
+    double true_rel_residual;  /* ||b - A x|| / ||b - A x0|| recomputed in FP64 at the end */
+} vpp_cg_info;
+
+/* Kernel configuration: cells of one workgroup tile (tx, ty, tz). */
+typedef struct {
+    int32_t tile[3];
+    int32_t variant;           /* 0 = cell-per-thread, 1 = plane-per-thread */
+} vpp_kernel_config;
+
+/* Create a problem on desc->device (host call, allocates device workspace and
+ * the per-degree tables).  VPP_ERR_INVALID_ARG for null pointers, degree not in
+ * {2,3,4}, ncells < 1, extent <= 0, rho <= 0 or unknown enum values. */
+vpp_status vpp_create(const vpp_desc* desc, vpp_problem* out);
+vpp_status vpp_destroy(vpp_problem p);
+
+int64_t vpp_num_dofs(vpp_problem p);        /* prod_d (k n_d + 1), -1 on null */
+int64_t vpp_num_qpoints(vpp_problem p);     /* prod_d n_d * (k+1)^3, -1 on null */
+
+/* Copy nodal phi (FP64 device pointer, N entries) into the problem and build the
+ * Jacobi diagonal for it (Table tab:solver_settings, "diagonal" preconditioner).
+ * Must precede apply / solve / gradient calls. */
+vpp_status vpp_set_phi(vpp_problem p, const double* phi, void* stream);
+
+/* y = A_D x.  prec VPP_FP64: x, y are double*; VPP_FP32: float* (the
+ * coefficient and tables are then FP32 too).  x and y must not alias. */
+vpp_status vpp_apply(vpp_problem p, int32_t prec, const void* x, void* y, void* stream);
+
+/* diag(A_D) in FP64 (1 on Dirichlet rows). */
+vpp_status vpp_diagonal(vpp_problem p, double* diag, void* stream);
+
+/* Jacobi PCG (FP64 or mixed) for A_D x = b.  x holds the initial guess on entry
+ * and the last iterate on exit (also when not converged).  Synchronises the
+ * stream; returns VPP_ERR_NOT_CONVERGED / VPP_ERR_BREAKDOWN with info filled. */
+vpp_status vpp_cg_solve(vpp_problem p, const double* b, double* x, const vpp_cg_opts* opts,
+                        vpp_cg_info* info, void* stream);
+
+/* Adjoint pieces for J(p(phi)) with A_D p = b, b independent of phi.
+ * grad_coef: g_q = dJ/dc_q = -W_q grad(lam_h) . grad(p_h) at every Gauss point
+ *   (Dirichlet entries of p and lam count as zero), where lam solves
+ *   A_D lam = dJ/dp.  Output layout: cell-major, cell = cx + nx (cy + ny cz),
+ *   Gauss index q0 + (k+1)(q1 + (k+1) q2) within a cell; vpp_num_qpoints entries.
+ * grad_phi: dJ/dphi_j = sum_q g_q (1/rho_l - 1/rho_g) H'(phi_h(x_q))
+ *   [|phi_h(x_q)| < 1] N_j(x_q)  (chain rule through the clamp, H and Eq. rhoEff). */
+vpp_status vpp_grad_coef(vpp_problem p, const double* pv, const double* lam, double* g_q,
+                         void* stream);
+vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* stream);
+
+/* Kernel configuration of a problem (what the autotuner chooses).  Setting an
+ * unsupported one returns VPP_ERR_UNSUPPORTED.  vpp_tune times the candidates on
+ * this problem (synchronises) and keeps the fastest; with a non-NULL cache path
+ * the choice is read from / added to that JSON file. */
+vpp_status vpp_get_config(vpp_problem p, vpp_kernel_config* cfg);
+vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg);
+vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream);
+/* Candidate list for a degree: writes up to `cap` configs, returns the count. */
+int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap);
+
+/* Batch of independent problems (same degree, FP64) with nrhs[i] right-hand sides
+ * each, applied by ONE persistent kernel that pulls (problem, tile) work items
+ * from a device queue; the coefficient of a tile is computed once and reused for
+ * all right-hand sides of its problem.  The launch is recorded in a hipGraph.
+ * tune_cache: JSON cache path for the autotuner, or NULL to tune without a cache.
+ * The problems must have phi set and outlive the batch. */
+vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32_t nprob,
+                            const char* tune_cache, vpp_batch* out);
+/* x, y: host arrays of sum(nrhs) device pointers, ordered problem-major. */
+vpp_status vpp_batch_apply(vpp_batch b, const double* const* x, double* const* y, void* stream);
+/* One PCG per (problem, rhs) pair (solved one after another with vpp_cg_solve);
+ * info: sum(nrhs) entries. */
+vpp_status vpp_batch_cg_solve(vpp_batch b, const double* const* rhs, double* const* x,
+                              const vpp_cg_opts* opts, vpp_cg_info* info, void* stream);
+vpp_status vpp_batch_get_config(vpp_batch b, vpp_kernel_config* cfg);
+vpp_status vpp_batch_destroy(vpp_batch b);
+
+const char* vpp_last_error(void);            /* thread-local message, never NULL */
+int32_t vpp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -78,6 +78,7 @@ def _load():
         "orc_grad_coef": (None, [P, _D, _D, _D]),
         "orc_grad_phi": (None, [P, _D, _D, _D]),
         "orc_num_threads": (C.c_int, []),
+        "orc_apply_rows": (None, [P, _D, _D, C.POINTER(C.c_int64), C.c_int64, _D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -242,6 +243,16 @@ def eval_qp(mesh, u, nq: Optional[int] = None) -> np.ndarray:
     d = desc_of(mesh)
     out = np.zeros(int(np.prod(mesh.ncells)) * nq ** 3)
     _load().orc_eval_qp(C.byref(d), nq, _ptr(_f64(u)), _ptr(out))
+    return out
+
+
+def apply_rows(mesh, phi, x, rows) -> np.ndarray:
+    """Rows `rows` of y = A_D x, assembled cell by cell around each node."""
+    d = desc_of(mesh)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros(rows.size)
+    _load().orc_apply_rows(C.byref(d), _ptr(_f64(phi)), _ptr(_f64(x)),
+                           rows.ctypes.data_as(C.POINTER(C.c_int64)), rows.size, _ptr(out))
     return out
 
 

@@ -711,6 +711,57 @@ void orc_grad_phi(const orc_desc* d, const double* phi, const double* gq, double
     }
 }
 
+/* Rows of y = A_D x for selected nodes, each assembled from the (at most 8)
+ * cells that contain the node; used to check full-size results one row at a
+ * time without assembling the whole matrix. */
+void orc_apply_rows(const orc_desc* d, const double* phi, const double* x, const int64_t* rows,
+                    int64_t nrows, double* out)
+{
+    lattice L;
+    make_lattice(d, &L);
+    const int n1 = L.n1, nb = n1 * n1 * n1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t g = rows[r];
+        if (is_dirichlet(d, &L, g)) { out[r] = x[g]; continue; }
+        const int64_t i = g % L.N[0], j = (g / L.N[0]) % L.N[1], l = g / (L.N[0] * L.N[1]);
+        int64_t lo[3], hi[3];
+        const int64_t idx[3] = {i, j, l};
+        for (int dd = 0; dd < 3; ++dd) {
+            int64_t a, b;
+            node_range(idx[dd], L.k, L.nc[dd], &a, &b);
+            lo[dd] = a / L.k;           /* first cell */
+            hi[dd] = b / L.k - 1;       /* last cell */
+        }
+        double s = 0.0;
+        for (int64_t cz = lo[2]; cz <= hi[2]; ++cz)
+            for (int64_t cy = lo[1]; cy <= hi[1]; ++cy)
+                for (int64_t cx = lo[0]; cx <= hi[0]; ++cx) {
+                    int64_t gg[MAXN * MAXN * MAXN];
+                    double N[MAXN * MAXN * MAXN], G0[MAXN * MAXN * MAXN], G1[MAXN * MAXN * MAXN],
+                           G2[MAXN * MAXN * MAXN];
+                    cell_dofs(&L, (int)cx, (int)cy, (int)cz, gg);
+                    int arow = -1;
+                    for (int a = 0; a < nb; ++a) if (gg[a] == g) arow = a;
+                    int q = 0;
+                    for (int q2 = 0; q2 < n1; ++q2)
+                        for (int q1 = 0; q1 < n1; ++q1)
+                            for (int q0 = 0; q0 < n1; ++q0, ++q) {
+                                basis_at_qp(&L, q0, q1, q2, N, G0, G1, G2);
+                                double ph = 0.0;
+                                for (int a = 0; a < nb; ++a) ph += N[a] * phi[gg[a]];
+                                const double W = L.gw[q0] * L.gw[q1] * L.gw[q2] * L.W3;
+                                const double cw = orc_coefficient(d, ph) * W;
+                                for (int b = 0; b < nb; ++b) {
+                                    if (is_dirichlet(d, &L, gg[b])) continue;
+                                    s += cw * (G0[arow] * G0[b] + G1[arow] * G1[b] + G2[arow] * G2[b]) * x[gg[b]];
+                                }
+                            }
+                }
+        out[r] = s;
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

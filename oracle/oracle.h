@@ -89,6 +89,10 @@ void orc_eval_qp(const orc_desc* d, int nq, const double* u, double* vals);
 void orc_grad_coef(const orc_desc* d, const double* p, const double* lam, double* gq);
 void orc_grad_phi(const orc_desc* d, const double* phi, const double* gq, double* gphi);
 
+/* Selected rows of y = A_D x, each from the cells around its node. */
+void orc_apply_rows(const orc_desc* d, const double* phi, const double* x, const int64_t* rows,
+                    int64_t nrows, double* out);
+
 int orc_num_threads(void);
 
 #ifdef __cplusplus

@@ -1,0 +1,265 @@
+"""Python face of the C ABI: problems, batches and the autograd Function.
+
+Torch provides device memory and streams only; every step of the operator,
+solver and adjoint runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+class VppError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != L.VPP_OK:
+        raise VppError(status, L.load().vpp_last_error().decode())
+
+
+def _stream(device: torch.device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _vec(t: torch.Tensor, n: int, dtype: torch.dtype, device: torch.device, name: str) -> C.c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous vector of {n} entries")
+    return C.c_void_p(t.data_ptr())
+
+
+def _info(ci: L.CgInfo) -> dict:
+    return {"iterations": ci.iterations, "outer_iterations": ci.outer_iterations, "status": ci.status,
+            "status_name": L.STATUS_NAMES.get(ci.status, str(ci.status)),
+            "rel_residual": ci.rel_residual, "true_rel_residual": ci.true_rel_residual}
+
+
+class Problem:
+    """One mesh + degree + material law on one GPU (vpp_create)."""
+
+    def __init__(self, ncells: Sequence[int], degree: int, origin=(0.0, 0.0, 0.0), extent=(1.0, 1.0, 1.0),
+                 bc=(0, 0, 0, 0, 0, 0), rho_l: float = 1000.0, rho_g: float = 1.0, heaviside: int = 0,
+                 device: int = 0):
+        lib = L.load()
+        d = L.Desc()
+        d.ncells[:] = [int(v) for v in ncells]
+        d.origin[:] = [float(v) for v in origin]
+        d.extent[:] = [float(v) for v in extent]
+        d.degree = int(degree)
+        d.bc[:] = [int(v) for v in bc]
+        d.rho_l = float(rho_l)
+        d.rho_g = float(rho_g)
+        d.heaviside = int(heaviside)
+        d.device = int(device)
+        self._h = C.c_void_p()
+        _check(lib.vpp_create(C.byref(d), C.byref(self._h)))
+        self.device = torch.device("cuda", int(device))
+        self.degree = int(degree)
+        self.ncells = tuple(int(v) for v in ncells)
+        self.n = lib.vpp_num_dofs(self._h)
+        self.nq = lib.vpp_num_qpoints(self._h)
+        self.last_grad_coef: Optional[torch.Tensor] = None
+        self._phi_version = 0
+
+    @classmethod
+    def from_mesh(cls, mesh, device: int = 0) -> "Problem":
+        """From any object with ncells, degree, origin, extent, bc, rho_l, rho_g, heaviside."""
+        return cls(mesh.ncells, mesh.degree, mesh.origin, mesh.extent, mesh.bc, mesh.rho_l, mesh.rho_g,
+                   mesh.heaviside, device)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and h.value and L._lib is not None:
+            L._lib.vpp_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def set_phi(self, phi: torch.Tensor):
+        _check(L.load().vpp_set_phi(self._h, _vec(phi, self.n, torch.float64, self.device, "phi"),
+                                    _stream(self.device)))
+        self._phi_version += 1
+
+    def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        prec = L.VPP_FP64 if x.dtype == torch.float64 else L.VPP_FP32
+        if x.dtype not in (torch.float64, torch.float32):
+            raise ValueError("x must be float64 or float32")
+        y = torch.empty_like(x) if out is None else out
+        _check(L.load().vpp_apply(self._h, prec, _vec(x, self.n, x.dtype, self.device, "x"),
+                                  _vec(y, self.n, x.dtype, self.device, "y"), _stream(self.device)))
+        return y
+
+    def diagonal(self) -> torch.Tensor:
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(L.load().vpp_diagonal(self._h, _vec(d, self.n, torch.float64, self.device, "diag"),
+                                     _stream(self.device)))
+        return d
+
+    def cg_solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, rtol: float = 1e-8,
+                 atol: float = 0.0, max_iter: int = 100000, precision: str = "fp64",
+                 inner_rtol: float = 1e-3, inner_max_iter: int = 0, check_every: int = 0,
+                 raise_on_failure: bool = True):
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        o = L.CgOpts(rtol, atol, int(max_iter), L.VPP_MIXED if precision == "mixed" else L.VPP_FP64,
+                     inner_rtol, int(inner_max_iter), int(check_every))
+        ci = L.CgInfo()
+        st = L.load().vpp_cg_solve(self._h, _vec(b, self.n, torch.float64, self.device, "b"),
+                                   _vec(x, self.n, torch.float64, self.device, "x"), C.byref(o),
+                                   C.byref(ci), _stream(self.device))
+        if st != L.VPP_OK and (raise_on_failure or st not in (5, 6)):
+            _check(st)
+        return x, _info(ci)
+
+    def grad_coef(self, p: torch.Tensor, lam: torch.Tensor) -> torch.Tensor:
+        g = torch.empty(self.nq, dtype=torch.float64, device=self.device)
+        _check(L.load().vpp_grad_coef(self._h, _vec(p, self.n, torch.float64, self.device, "p"),
+                                      _vec(lam, self.n, torch.float64, self.device, "lam"),
+                                      _vec(g, self.nq, torch.float64, self.device, "g_q"),
+                                      _stream(self.device)))
+        return g
+
+    def grad_phi(self, g_q: torch.Tensor) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(L.load().vpp_grad_phi(self._h, _vec(g_q, self.nq, torch.float64, self.device, "g_q"),
+                                     _vec(out, self.n, torch.float64, self.device, "g_phi"),
+                                     _stream(self.device)))
+        return out
+
+    @property
+    def config(self) -> dict:
+        c = L.KernelConfig()
+        _check(L.load().vpp_get_config(self._h, C.byref(c)))
+        return {"variant": c.variant, "tile": tuple(c.tile)}
+
+    def set_config(self, variant: int, tile: Sequence[int]):
+        c = L.KernelConfig()
+        c.variant = int(variant)
+        c.tile[:] = [int(v) for v in tile]
+        _check(L.load().vpp_set_config(self._h, C.byref(c)))
+
+    def tune(self, cache_path: Optional[str] = None) -> dict:
+        _check(L.load().vpp_tune(self._h, cache_path.encode() if cache_path else None, _stream(self.device)))
+        return self.config
+
+
+def config_candidates(degree: int) -> list:
+    lib = L.load()
+    n = lib.vpp_config_candidates(int(degree), None, 0)
+    arr = (L.KernelConfig * max(n, 1))()
+    lib.vpp_config_candidates(int(degree), arr, n)
+    return [{"variant": arr[i].variant, "tile": tuple(arr[i].tile)} for i in range(n)]
+
+
+class Batch:
+    """Independent problems applied together by one persistent graph launch."""
+
+    def __init__(self, problems: Sequence[Problem], nrhs: Sequence[int], tune_cache: Optional[str] = None):
+        lib = L.load()
+        self.problems = list(problems)
+        self.nrhs = [int(v) for v in nrhs]
+        hs = (C.c_void_p * len(problems))(*[p.handle.value for p in problems])
+        nr = (C.c_int32 * len(problems))(*self.nrhs)
+        self._h = C.c_void_p()
+        _check(lib.vpp_batch_create(hs, nr, len(problems), tune_cache.encode() if tune_cache else None,
+                                    C.byref(self._h)))
+        self.device = problems[0].device
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and h.value and L._lib is not None:
+            L._lib.vpp_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _tables(self, xs, ys):
+        ptr_x, ptr_y = [], []
+        i = 0
+        for p, nr in zip(self.problems, self.nrhs):
+            for _ in range(nr):
+                ptr_x.append(_vec(xs[i], p.n, torch.float64, self.device, "x").value)
+                ptr_y.append(_vec(ys[i], p.n, torch.float64, self.device, "y").value)
+                i += 1
+        if i != len(xs) or i != len(ys):
+            raise ValueError("one vector per (problem, rhs) pair expected")
+        tx = (C.c_void_p * i)(*ptr_x)
+        ty = (C.c_void_p * i)(*ptr_y)
+        return tx, ty
+
+    def apply(self, xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor]):
+        tx, ty = self._tables(xs, ys)
+        _check(L.load().vpp_batch_apply(self._h, tx, ty, _stream(self.device)))
+
+    def cg_solve(self, bs, xs, rtol=1e-8, atol=0.0, max_iter=100000, precision="fp64", inner_rtol=1e-3):
+        tb, tx = self._tables(bs, xs)
+        n = len(bs)
+        o = L.CgOpts(rtol, atol, int(max_iter), L.VPP_MIXED if precision == "mixed" else L.VPP_FP64,
+                     inner_rtol, 0, 0)
+        infos = (L.CgInfo * n)()
+        _check(L.load().vpp_batch_cg_solve(self._h, tb, tx, C.byref(o), infos, _stream(self.device)))
+        return [_info(infos[i]) for i in range(n)]
+
+    @property
+    def config(self) -> dict:
+        c = L.KernelConfig()
+        _check(L.load().vpp_batch_get_config(self._h, C.byref(c)))
+        return {"variant": c.variant, "tile": tuple(c.tile)}
+
+
+class PoissonSolve(torch.autograd.Function):
+    """p = A_D(phi)^{-1} b with a hand-written adjoint.
+
+    backward: lam = A_D^{-1} dJ/dp (A_D symmetric), dJ/dc_q from vpp_grad_coef (kept
+    on problem.last_grad_coef), dJ/dphi from vpp_grad_phi, dJ/db = lam."""
+
+    @staticmethod
+    def forward(ctx, phi: torch.Tensor, b: torch.Tensor, problem: Problem, opts: Optional[dict] = None):
+        opts = dict(opts or {})
+        problem.set_phi(phi.detach())
+        p, info = problem.cg_solve(b.detach(), **opts)
+        ctx.problem = problem
+        ctx.opts = opts
+        ctx.version = problem._phi_version
+        ctx.save_for_backward(phi.detach(), p)
+        return p
+
+    @staticmethod
+    def backward(ctx, gp: torch.Tensor):
+        phi, p = ctx.saved_tensors
+        problem: Problem = ctx.problem
+        if problem._phi_version != ctx.version:
+            problem.set_phi(phi)
+            ctx.version = problem._phi_version
+        lam, _ = problem.cg_solve(gp.contiguous().to(torch.float64), **ctx.opts)
+        g_q = problem.grad_coef(p, lam)
+        problem.last_grad_coef = g_q
+        g_phi = problem.grad_phi(g_q)
+        return g_phi, lam, None, None
+
+
+def poisson_solve(phi: torch.Tensor, b: torch.Tensor, problem: Problem, **opts) -> torch.Tensor:
+    return PoissonSolve.apply(phi, b, problem, opts)

@@ -1,0 +1,1013 @@
+// C ABI of the library (include/vpp.h): problem set-up, apply, diagonal,
+// Jacobi PCG (FP64 and FP64/FP32 defect correction), adjoint, batches and the
+// autotuner.  Host side only; the kernels live in the .hip files.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/vpp.h"
+#include "blas.h"
+#include "kernels.h"
+
+using namespace vpp;
+
+namespace {
+
+thread_local std::string g_err;
+
+vpp_status fail(vpp_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define VPP_HIP(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(VPP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+LaunchCfg default_config(int k)
+{
+    if (k == 2) return LaunchCfg{0, {8, 4, 4}};
+    if (k == 3) return LaunchCfg{1, {4, 4, 2}};
+    return LaunchCfg{1, {4, 2, 2}};
+}
+
+template <typename T>
+vpp_status dev_alloc(T** p, size_t n, const char* what)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(VPP_ERR_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what);
+    }
+    return VPP_OK;
+}
+
+template <typename T>
+void dev_free(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+struct CgWork {
+    // FP64 solver vectors
+    double *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+    // FP32 inner solver vectors
+    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    CgState* st = nullptr;        // device
+    CgState* st32 = nullptr;      // device
+    CgState* hst = nullptr;       // pinned host mirror
+    double* rr = nullptr;         // device scalar for residual norms
+    double* hrr = nullptr;        // pinned host mirror
+    hipGraphExec_t g64 = nullptr, g32 = nullptr;
+    int graph_iters = 0;
+    LaunchCfg graph_cfg{-1, {0, 0, 0}};
+};
+
+struct vpp_problem_s {
+    vpp_desc desc;
+    int k = 2;
+    int64_t N = 0, NQ = 0, ncell = 0;
+    MeshArgs m{};
+    LaunchCfg cfg{};
+    double* phi64 = nullptr;
+    float* phi32 = nullptr;
+    double* diag = nullptr;
+    double* inv64 = nullptr;
+    float* inv32 = nullptr;
+    bool phi_set = false;
+    hipStream_t stream = nullptr;   // library stream for solves and graph capture
+    CgWork w;
+};
+
+struct vpp_batch_s {
+    std::vector<vpp_problem> probs;
+    std::vector<int> nrhs;
+    int k = 2;
+    int total_rhs = 0;
+    int nitems = 0;
+    int64_t total_dofs = 0;
+    LaunchCfg cfg{};
+    int nblocks = 0;
+    BatchProblem* d_probs = nullptr;
+    double** d_x = nullptr;
+    double** d_y = nullptr;
+    int64_t* d_off = nullptr;
+    int* d_queue = nullptr;
+    std::vector<const double*> cur_x;
+    std::vector<double*> cur_y;
+    hipGraphExec_t graph = nullptr;
+    hipStream_t stream = nullptr;
+    int device = 0;
+};
+
+static void set_tiles(MeshArgs& m, const LaunchCfg& c)
+{
+    for (int d = 0; d < 3; ++d) m.ntile[d] = (m.nc[d] + c.tile[d] - 1) / c.tile[d];
+}
+
+static int tile_count(const MeshArgs& m) { return m.ntile[0] * m.ntile[1] * m.ntile[2]; }
+
+static MeshArgs make_mesh_args(const vpp_desc& d)
+{
+    MeshArgs m{};
+    const int k = d.degree;
+    double h[3];
+    for (int i = 0; i < 3; ++i) {
+        m.nc[i] = d.ncells[i];
+        m.nn[i] = k * d.ncells[i] + 1;
+        h[i] = d.extent[i] / d.ncells[i];
+    }
+    m.bcmask = 0;
+    for (int f = 0; f < 6; ++f)
+        if (d.bc[f] == VPP_BC_DIRICHLET) m.bcmask |= 1 << f;
+    m.heaviside = d.heaviside;
+    // W_q h_d^-2 = wref_q hx hy hz / h_d^2 = wref_q r0 rd[d]
+    m.r0 = h[1] * h[2] / h[0];
+    m.rd[0] = 1.0;
+    m.rd[1] = (h[0] * h[0]) / (h[1] * h[1]);
+    m.rd[2] = (h[0] * h[0]) / (h[2] * h[2]);
+    const double il = 1.0 / d.rho_l, ig = 1.0 / d.rho_g;
+    // linear H = (phi+1)/2:  c = ig + (il - ig)(phi+1)/2
+    m.ca = m.r0 * (ig + 0.5 * (il - ig));
+    m.cb = m.r0 * 0.5 * (il - ig);
+    // sine ramp:  c = ig + (il - ig) H
+    m.cg = m.r0 * ig;
+    m.cd = m.r0 * (il - ig);
+    m.dcdphi = il - ig;
+    return m;
+}
+
+static int hip_blocks(const vpp_problem p) { return tile_count(p->m); }
+
+// y = A x on `s` (y zeroed first).
+static vpp_status do_apply64(vpp_problem p, const double* x, double* y, double* dot, const int* done, hipStream_t s)
+{
+    VPP_HIP(launch_fill<double>(y, p->N, 0.0, s));
+    ApplyArgs<double> a{p->m, x, y, p->phi64, dot, done};
+    VPP_HIP(launch_apply_f64(p->cfg, p->k, a, hip_blocks(p), s));
+    return VPP_OK;
+}
+
+static vpp_status do_apply32(vpp_problem p, const float* x, float* y, double* dot, const int* done, hipStream_t s)
+{
+    VPP_HIP(launch_fill<float>(y, p->N, 0.0f, s));
+    ApplyArgs<float> a{p->m, x, y, p->phi32, dot, done};
+    VPP_HIP(launch_apply_f32(p->cfg, p->k, a, hip_blocks(p), s));
+    return VPP_OK;
+}
+
+static void free_graphs(CgWork& w)
+{
+    if (w.g64) (void)hipGraphExecDestroy(w.g64);
+    if (w.g32) (void)hipGraphExecDestroy(w.g32);
+    w.g64 = w.g32 = nullptr;
+}
+
+static void free_work(CgWork& w)
+{
+    free_graphs(w);
+    dev_free(w.x); dev_free(w.b); dev_free(w.r); dev_free(w.p); dev_free(w.q);
+    dev_free(w.x32); dev_free(w.r32); dev_free(w.p32); dev_free(w.q32);
+    dev_free(w.st); dev_free(w.st32); dev_free(w.rr);
+    if (w.hst) (void)hipHostFree(w.hst);
+    if (w.hrr) (void)hipHostFree(w.hrr);
+    w.hst = nullptr;
+    w.hrr = nullptr;
+}
+
+static vpp_status ensure_work(vpp_problem p, bool mixed)
+{
+    CgWork& w = p->w;
+    vpp_status s;
+    const size_t n = (size_t)p->N;
+    if (!w.x) {
+        if ((s = dev_alloc(&w.x, n, "cg x")) || (s = dev_alloc(&w.b, n, "cg b")) ||
+            (s = dev_alloc(&w.r, n, "cg r")) || (s = dev_alloc(&w.p, n, "cg p")) ||
+            (s = dev_alloc(&w.q, n, "cg q")) || (s = dev_alloc(&w.st, 1, "cg state")) ||
+            (s = dev_alloc(&w.st32, 1, "cg state")) || (s = dev_alloc(&w.rr, 1, "norm")))
+            return s;
+        VPP_HIP(hipHostMalloc((void**)&w.hst, sizeof(CgState), hipHostMallocDefault));
+        VPP_HIP(hipHostMalloc((void**)&w.hrr, sizeof(double), hipHostMallocDefault));
+    }
+    if (mixed && !w.x32) {
+        if ((s = dev_alloc(&w.x32, n, "cg x32")) || (s = dev_alloc(&w.r32, n, "cg r32")) ||
+            (s = dev_alloc(&w.p32, n, "cg p32")) || (s = dev_alloc(&w.q32, n, "cg q32")))
+            return s;
+    }
+    return VPP_OK;
+}
+
+// Record `iters` (even) PCG iterations on the library stream into a graph.
+template <typename T>
+static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
+{
+    CgWork& w = p->w;
+    hipStream_t s = p->stream;
+    hipGraph_t g = nullptr;
+    VPP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int it = 0; it < iters && err == hipSuccess; ++it) {
+        const int par = it & 1;
+        if constexpr (sizeof(T) == 8) {
+            ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, &w.st->pAp, &w.st->done};
+            err = launch_apply_f64(p->cfg, p->k, a, hip_blocks(p), s);
+            if (err == hipSuccess) err = launch_cg_update<double>(w.st, par, w.x, w.r, w.p, w.q, p->inv64, p->N, s);
+            if (err == hipSuccess) err = launch_cg_pupdate<double>(w.st, par, w.r, w.p, w.q, p->inv64, p->N, s);
+        } else {
+            ApplyArgs<float> a{p->m, w.p32, w.q32, p->phi32, &w.st32->pAp, &w.st32->done};
+            err = launch_apply_f32(p->cfg, p->k, a, hip_blocks(p), s);
+            if (err == hipSuccess)
+                err = launch_cg_update<float>(w.st32, par, w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
+            if (err == hipSuccess)
+                err = launch_cg_pupdate<float>(w.st32, par, w.r32, w.p32, w.q32, p->inv32, p->N, s);
+        }
+    }
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(VPP_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(err));
+    }
+    VPP_HIP(e2);
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    VPP_HIP(e3);
+    *out = ex;
+    return VPP_OK;
+}
+
+static bool same_cfg(const LaunchCfg& a, const LaunchCfg& b)
+{
+    return a.variant == b.variant && a.tile[0] == b.tile[0] && a.tile[1] == b.tile[1] && a.tile[2] == b.tile[2];
+}
+
+static vpp_status ensure_graphs(vpp_problem p, int iters, bool mixed)
+{
+    CgWork& w = p->w;
+    if (w.graph_iters != iters || !same_cfg(w.graph_cfg, p->cfg)) {
+        free_graphs(w);
+        w.graph_iters = iters;
+        w.graph_cfg = p->cfg;
+    }
+    vpp_status s;
+    if (!w.g64 && (s = build_cg_graph<double>(p, iters, &w.g64))) return s;
+    if (mixed && !w.g32 && (s = build_cg_graph<float>(p, iters, &w.g32))) return s;
+    return VPP_OK;
+}
+
+// Run graph chunks until the device flags `done`; returns the final state in *hs.
+static vpp_status run_until_done(vpp_problem p, hipGraphExec_t g, CgState* st, CgState* hs, int max_iter)
+{
+    hipStream_t s = p->stream;
+    const int chunk = p->w.graph_iters;
+    const int max_launch = max_iter / chunk + 2;
+    for (int l = 0; l < max_launch; ++l) {
+        VPP_HIP(hipGraphLaunch(g, s));
+        VPP_HIP(hipMemcpyAsync(hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        VPP_HIP(hipStreamSynchronize(s));
+        if (hs->done) break;
+    }
+    return VPP_OK;
+}
+
+// FP64 PCG on the workspace vectors (w.b, w.x in; w.x out).
+static vpp_status pcg64(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& info, double* r0_out)
+{
+    CgWork& w = p->w;
+    hipStream_t s = p->stream;
+    vpp_status st;
+    if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) return st;
+    CgState* hs = w.hst;
+    std::memset(hs, 0, sizeof(CgState));
+    VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
+    VPP_HIP(launch_cg_init<double>(w.st, w.b, w.q, w.r, w.p, p->inv64, p->N, s));
+    VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    const double rr0 = hs->rr_last, rz0 = hs->rz[0];
+    const double r0 = std::sqrt(rr0);
+    *r0_out = r0;
+    info.iterations = 0;
+    info.rel_residual = r0 > 0 ? 1.0 : 0.0;
+    if (!std::isfinite(rr0) || !std::isfinite(rz0)) {
+        info.status = VPP_ERR_BREAKDOWN;
+        return VPP_OK;
+    }
+    const double thr = std::max(o.rtol * r0, o.atol);
+    if (r0 == 0.0 || r0 < o.atol) {
+        info.status = VPP_OK;
+        return VPP_OK;
+    }
+    CgState init{};
+    init.rz[0] = rz0;
+    init.tol2 = thr * thr;
+    init.max_iter = o.max_iter;
+    *hs = init;
+    VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
+    VPP_HIP(launch_fill<double>(w.q, p->N, 0.0, s));
+    if ((st = run_until_done(p, w.g64, w.st, hs, o.max_iter))) return st;
+    info.iterations = hs->iters;
+    info.rel_residual = std::sqrt(hs->rr_last) / r0;
+    if (hs->breakdown) info.status = VPP_ERR_BREAKDOWN;
+    else if (hs->rr_last < init.tol2) info.status = VPP_OK;
+    else info.status = VPP_ERR_NOT_CONVERGED;
+    return VPP_OK;
+}
+
+// ||b - A x||^2 in FP64 on the workspace (r := b - A x).
+static vpp_status residual64(vpp_problem p, double* rr)
+{
+    CgWork& w = p->w;
+    hipStream_t s = p->stream;
+    vpp_status st;
+    if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) return st;
+    VPP_HIP(hipMemsetAsync(w.rr, 0, sizeof(double), s));
+    VPP_HIP(launch_residual(w.b, w.q, w.r, p->N, w.rr, s));
+    VPP_HIP(hipMemcpyAsync(w.hrr, w.rr, sizeof(double), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    *rr = *w.hrr;
+    return VPP_OK;
+}
+
+// Defect correction: FP64 residual and update, FP32 inner PCG with FP64 scalars.
+static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& info, double* r0_out)
+{
+    CgWork& w = p->w;
+    hipStream_t s = p->stream;
+    vpp_status st;
+    double rr;
+    if ((st = residual64(p, &rr))) return st;
+    const double r0 = std::sqrt(rr);
+    *r0_out = r0;
+    info.iterations = 0;
+    info.outer_iterations = 0;
+    info.rel_residual = r0 > 0 ? 1.0 : 0.0;
+    if (!std::isfinite(rr)) {
+        info.status = VPP_ERR_BREAKDOWN;
+        return VPP_OK;
+    }
+    const double thr = std::max(o.rtol * r0, o.atol);
+    const double inner_rtol = o.inner_rtol > 0 ? o.inner_rtol : 1e-3;
+    const int inner_max = o.inner_max_iter > 0 ? o.inner_max_iter : o.max_iter;
+    int total = 0;
+    double rn = r0;
+    info.status = VPP_OK;
+    const int max_outer = 200;
+    while (!(rn < thr) && rn > 0.0) {
+        if (info.outer_iterations >= max_outer || total >= o.max_iter) {
+            info.status = VPP_ERR_NOT_CONVERGED;
+            break;
+        }
+        const double scale = 1.0 / rn;
+        VPP_HIP(launch_demote(w.r, scale, w.r32, w.x32, p->N, s));
+        CgState* hs = w.hst;
+        std::memset(hs, 0, sizeof(CgState));
+        hs->tol2 = inner_rtol * inner_rtol;   // the inner right-hand side has unit norm
+        hs->max_iter = std::min(inner_max, o.max_iter - total);
+        const int inner_cap = hs->max_iter;
+        VPP_HIP(hipMemcpyAsync(w.st32, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
+        // zero initial guess: r = b, p = D^-1 b; rz[0] is accumulated on the device
+        VPP_HIP(launch_cg_init<float>(w.st32, w.r32, nullptr, w.r32, w.p32, p->inv32, p->N, s));
+        VPP_HIP(launch_fill<float>(w.q32, p->N, 0.0f, s));
+        if ((st = run_until_done(p, w.g32, w.st32, hs, inner_cap))) return st;
+        total += hs->iters;
+        VPP_HIP(launch_promote_add(w.x, w.x32, rn, p->N, s));
+        if ((st = residual64(p, &rr))) return st;
+        const double rn_new = std::sqrt(rr);
+        info.outer_iterations += 1;
+        if (!std::isfinite(rn_new)) {
+            info.status = VPP_ERR_BREAKDOWN;
+            break;
+        }
+        if (hs->iters == 0 && !(rn_new < rn)) {      // inner solver made no progress
+            info.status = hs->breakdown ? VPP_ERR_BREAKDOWN : VPP_ERR_NOT_CONVERGED;
+            rn = rn_new;
+            break;
+        }
+        rn = rn_new;
+    }
+    info.iterations = total;
+    info.rel_residual = r0 > 0 ? rn / r0 : 0.0;
+    return VPP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner cache: a JSON file {"entries": [{"key": ..., "variant": v,
+// "tile": [tx, ty, tz], "us": t}, ...]} keyed by architecture, degree and
+// problem-size bucket.
+
+static std::string size_bucket_key(const char* what, int k, int64_t n)
+{
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n) ++b;
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "gfx950/%s/k%d/n2^%d", what, k, b);
+    return buf;
+}
+
+struct CacheEntry {
+    std::string key;
+    LaunchCfg cfg;
+    double us;
+};
+
+static std::vector<CacheEntry> read_cache(const char* path)
+{
+    std::vector<CacheEntry> out;
+    if (!path) return out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t pos = 0;
+    while ((pos = s.find("\"key\"", pos)) != std::string::npos) {
+        CacheEntry e{};
+        size_t q1 = s.find('"', s.find(':', pos) + 1);
+        size_t q2 = s.find('"', q1 + 1);
+        if (q1 == std::string::npos || q2 == std::string::npos) break;
+        e.key = s.substr(q1 + 1, q2 - q1 - 1);
+        size_t v = s.find("\"variant\"", q2);
+        size_t t = s.find("\"tile\"", q2);
+        size_t u = s.find("\"us\"", q2);
+        if (v == std::string::npos || t == std::string::npos || u == std::string::npos) break;
+        e.cfg.variant = std::atoi(s.c_str() + s.find(':', v) + 1);
+        const char* tp = s.c_str() + s.find('[', t) + 1;
+        char* end = nullptr;
+        e.cfg.tile[0] = (int)std::strtol(tp, &end, 10);
+        e.cfg.tile[1] = (int)std::strtol(end + 1, &end, 10);
+        e.cfg.tile[2] = (int)std::strtol(end + 1, &end, 10);
+        e.us = std::atof(s.c_str() + s.find(':', u) + 1);
+        out.push_back(e);
+        pos = u;
+    }
+    return out;
+}
+
+static void write_cache(const char* path, const std::vector<CacheEntry>& es)
+{
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        f << "{\"entries\": [\n";
+        for (size_t i = 0; i < es.size(); ++i) {
+            f << "  {\"key\": \"" << es[i].key << "\", \"variant\": " << es[i].cfg.variant << ", \"tile\": ["
+              << es[i].cfg.tile[0] << ", " << es[i].cfg.tile[1] << ", " << es[i].cfg.tile[2]
+              << "], \"us\": " << es[i].us << "}" << (i + 1 < es.size() ? "," : "") << "\n";
+        }
+        f << "]}\n";
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+static bool cache_lookup(const char* path, const std::string& key, LaunchCfg* cfg)
+{
+    for (const auto& e : read_cache(path))
+        if (e.key == key) {
+            *cfg = e.cfg;
+            return true;
+        }
+    return false;
+}
+
+static void cache_store(const char* path, const std::string& key, const LaunchCfg& cfg, double us)
+{
+    if (!path) return;
+    auto es = read_cache(path);
+    bool found = false;
+    for (auto& e : es)
+        if (e.key == key) {
+            e.cfg = cfg;
+            e.us = us;
+            found = true;
+        }
+    if (!found) es.push_back(CacheEntry{key, cfg, us});
+    write_cache(path, es);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* vpp_last_error(void) { return g_err.c_str(); }
+int32_t vpp_abi_version(void) { return VPP_ABI_VERSION; }
+
+vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
+{
+    if (!d || !out) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (d->degree < 2 || d->degree > 4) return fail(VPP_ERR_INVALID_ARG, "degree must be 2, 3 or 4");
+    for (int i = 0; i < 3; ++i) {
+        if (d->ncells[i] < 1) return fail(VPP_ERR_INVALID_ARG, "ncells must be >= 1");
+        if (!(d->extent[i] > 0.0) || !std::isfinite(d->extent[i]))
+            return fail(VPP_ERR_INVALID_ARG, "extent must be positive");
+        if (!std::isfinite(d->origin[i])) return fail(VPP_ERR_INVALID_ARG, "origin must be finite");
+    }
+    if (!(d->rho_l > 0.0) || !(d->rho_g > 0.0) || !std::isfinite(d->rho_l) || !std::isfinite(d->rho_g))
+        return fail(VPP_ERR_INVALID_ARG, "densities must be positive");
+    for (int f = 0; f < 6; ++f)
+        if (d->bc[f] != VPP_BC_DIRICHLET && d->bc[f] != VPP_BC_NEUMANN)
+            return fail(VPP_ERR_INVALID_ARG, "bc must be VPP_BC_DIRICHLET or VPP_BC_NEUMANN");
+    if (d->heaviside != VPP_H_LINEAR && d->heaviside != VPP_H_PAPER)
+        return fail(VPP_ERR_INVALID_ARG, "unknown heaviside");
+    const int64_t k = d->degree;
+    const int64_t N = (k * d->ncells[0] + 1) * (k * d->ncells[1] + 1) * (k * d->ncells[2] + 1);
+    const int64_t ncell = (int64_t)d->ncells[0] * d->ncells[1] * d->ncells[2];
+    if (N > (int64_t)1 << 40 || ncell > (int64_t)INT32_MAX / 2)
+        return fail(VPP_ERR_INVALID_ARG, "mesh too large");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(VPP_ERR_HIP, "no HIP device available");
+    }
+    if (d->device < 0 || d->device >= ndev) return fail(VPP_ERR_INVALID_ARG, "device ordinal out of range");
+    DeviceGuard dg(d->device);
+    vpp_problem p = new vpp_problem_s();
+    p->desc = *d;
+    p->k = d->degree;
+    p->N = N;
+    p->ncell = ncell;
+    p->NQ = ncell * (k + 1) * (k + 1) * (k + 1);
+    p->m = make_mesh_args(*d);
+    p->cfg = default_config(p->k);
+    set_tiles(p->m, p->cfg);
+    vpp_status s;
+    if ((s = dev_alloc(&p->phi64, N, "phi")) || (s = dev_alloc(&p->phi32, N, "phi32")) ||
+        (s = dev_alloc(&p->diag, N, "diag")) || (s = dev_alloc(&p->inv64, N, "invdiag")) ||
+        (s = dev_alloc(&p->inv32, N, "invdiag32"))) {
+        vpp_destroy(p);
+        return s;
+    }
+    if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+        vpp_destroy(p);
+        return fail(VPP_ERR_HIP, "hipStreamCreate failed");
+    }
+    *out = p;
+    return VPP_OK;
+}
+
+vpp_status vpp_destroy(vpp_problem p)
+{
+    if (!p) return VPP_OK;
+    DeviceGuard dg(p->desc.device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    free_work(p->w);
+    dev_free(p->phi64); dev_free(p->phi32); dev_free(p->diag); dev_free(p->inv64); dev_free(p->inv32);
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+    return VPP_OK;
+}
+
+int64_t vpp_num_dofs(vpp_problem p) { return p ? p->N : -1; }
+int64_t vpp_num_qpoints(vpp_problem p) { return p ? p->NQ : -1; }
+
+vpp_status vpp_set_phi(vpp_problem p, const double* phi, void* stream)
+{
+    if (!p || !phi) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    DeviceGuard dg(p->desc.device);
+    hipStream_t s = (hipStream_t)stream;
+    VPP_HIP(hipMemcpyAsync(p->phi64, phi, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    VPP_HIP(launch_convert(p->phi64, p->phi32, p->N, s));
+    VPP_HIP(launch_fill<double>(p->diag, p->N, 0.0, s));
+    VPP_HIP(launch_diag(p->k, p->m, p->phi64, p->diag, s));
+    VPP_HIP(launch_fix_diagonal(p->m, p->diag, p->inv64, p->inv32, s));
+    p->phi_set = true;
+    return VPP_OK;
+}
+
+vpp_status vpp_apply(vpp_problem p, int32_t prec, const void* x, void* y, void* stream)
+{
+    if (!p || !x || !y) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (x == y) return fail(VPP_ERR_INVALID_ARG, "x and y must not alias");
+    if (prec != VPP_FP64 && prec != VPP_FP32) return fail(VPP_ERR_INVALID_ARG, "precision must be FP64 or FP32");
+    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    DeviceGuard dg(p->desc.device);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == VPP_FP64) return do_apply64(p, (const double*)x, (double*)y, nullptr, nullptr, s);
+    return do_apply32(p, (const float*)x, (float*)y, nullptr, nullptr, s);
+}
+
+vpp_status vpp_diagonal(vpp_problem p, double* diag, void* stream)
+{
+    if (!p || !diag) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(hipMemcpyAsync(diag, p->diag, p->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+vpp_status vpp_cg_solve(vpp_problem p, const double* b, double* x, const vpp_cg_opts* opts, vpp_cg_info* info,
+                        void* stream)
+{
+    if (!p || !b || !x || !opts) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (!(opts->rtol >= 0.0) || !(opts->atol >= 0.0) || opts->max_iter < 0)
+        return fail(VPP_ERR_INVALID_ARG, "tolerances must be >= 0 and max_iter >= 0");
+    if (opts->precision != VPP_FP64 && opts->precision != VPP_MIXED)
+        return fail(VPP_ERR_INVALID_ARG, "precision must be VPP_FP64 or VPP_MIXED");
+    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    DeviceGuard dg(p->desc.device);
+    const bool mixed = opts->precision == VPP_MIXED;
+    vpp_status st;
+    if ((st = ensure_work(p, mixed))) return st;
+    int chunk = opts->check_every > 0 ? opts->check_every : 32;
+    chunk = std::max(2, std::min(chunk, 512));
+    chunk += chunk & 1;
+    if ((st = ensure_graphs(p, chunk, mixed))) return st;
+    // Order after the caller's stream, then work on the library stream.
+    VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    hipStream_t s = p->stream;
+    CgWork& w = p->w;
+    VPP_HIP(hipMemcpyAsync(w.b, b, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    VPP_HIP(hipMemcpyAsync(w.x, x, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    vpp_cg_info inf{};
+    double r0 = 0.0;
+    if (mixed) st = pcg_mixed(p, *opts, inf, &r0);
+    else st = pcg64(p, *opts, inf, &r0);
+    if (st) return st;
+    VPP_HIP(hipMemcpyAsync(x, w.x, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double rr_true = 0.0;
+    if ((st = residual64(p, &rr_true))) return st;
+    inf.true_rel_residual = r0 > 0 ? std::sqrt(rr_true) / r0 : 0.0;
+    if (info) *info = inf;
+    if (inf.status == VPP_ERR_NOT_CONVERGED) return fail(VPP_ERR_NOT_CONVERGED, "CG did not converge");
+    if (inf.status == VPP_ERR_BREAKDOWN) return fail(VPP_ERR_BREAKDOWN, "CG breakdown (p.Ap <= 0 or non-finite)");
+    return VPP_OK;
+}
+
+vpp_status vpp_grad_coef(vpp_problem p, const double* pv, const double* lam, double* g_q, void* stream)
+{
+    if (!p || !pv || !lam || !g_q) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(launch_grad_coef(p->k, p->m, pv, lam, g_q, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* stream)
+{
+    if (!p || !g_q || !g_phi) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    DeviceGuard dg(p->desc.device);
+    hipStream_t s = (hipStream_t)stream;
+    VPP_HIP(launch_fill<double>(g_phi, p->N, 0.0, s));
+    VPP_HIP(launch_grad_phi(p->k, p->m, p->phi64, g_q, g_phi, s));
+    return VPP_OK;
+}
+
+vpp_status vpp_get_config(vpp_problem p, vpp_kernel_config* cfg)
+{
+    if (!p || !cfg) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    cfg->variant = p->cfg.variant;
+    for (int d = 0; d < 3; ++d) cfg->tile[d] = p->cfg.tile[d];
+    return VPP_OK;
+}
+
+vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg)
+{
+    if (!p || !cfg) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    LaunchCfg c{cfg->variant, {cfg->tile[0], cfg->tile[1], cfg->tile[2]}};
+    if (!apply_config_supported(c, p->k)) return fail(VPP_ERR_UNSUPPORTED, "kernel configuration not available");
+    p->cfg = c;
+    set_tiles(p->m, c);
+    return VPP_OK;
+}
+
+int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap)
+{
+    LaunchCfg tmp[64];
+    const int n = list_apply_configs(degree, tmp, 64);
+    for (int i = 0; i < n && i < cap && out; ++i) {
+        out[i].variant = tmp[i].variant;
+        for (int d = 0; d < 3; ++d) out[i].tile[d] = tmp[i].tile[d];
+    }
+    return n;
+}
+
+vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
+{
+    if (!p) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    DeviceGuard dg(p->desc.device);
+    const std::string key = size_bucket_key("apply", p->k, p->N);
+    LaunchCfg c;
+    if (cache_lookup(cache_path, key, &c) && apply_config_supported(c, p->k)) {
+        p->cfg = c;
+        set_tiles(p->m, c);
+        return VPP_OK;
+    }
+    VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    vpp_status st;
+    if ((st = ensure_work(p, false))) return st;
+    hipStream_t s = p->stream;
+    CgWork& w = p->w;
+    VPP_HIP(launch_fill<double>(w.x, p->N, 1.0, s));
+    LaunchCfg cands[64];
+    const int n = list_apply_configs(p->k, cands, 64);
+    hipEvent_t e0, e1;
+    VPP_HIP(hipEventCreate(&e0));
+    VPP_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    LaunchCfg best_cfg = p->cfg;
+    const int reps = 10;
+    for (int i = 0; i < n; ++i) {
+        p->cfg = cands[i];
+        set_tiles(p->m, cands[i]);
+        if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) break;
+        VPP_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r)
+            if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) break;
+        VPP_HIP(hipEventRecord(e1, s));
+        VPP_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        VPP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1000.0 * ms / reps;
+        if (us < best) {
+            best = us;
+            best_cfg = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->cfg = best_cfg;
+    set_tiles(p->m, best_cfg);
+    if (st) return st;
+    cache_store(cache_path, key, best_cfg, best);
+    return VPP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+
+static vpp_status batch_build_table(vpp_batch b)
+{
+    std::vector<BatchProblem> tab(b->probs.size());
+    int item = 0, rhs = 0;
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+        MeshArgs m = b->probs[i]->m;
+        set_tiles(m, b->cfg);
+        tab[i].m = m;
+        tab[i].phi = b->probs[i]->phi64;
+        tab[i].tile_begin = item;
+        tab[i].nrhs = b->nrhs[i];
+        tab[i].rhs_begin = rhs;
+        item += tile_count(m);
+        rhs += b->nrhs[i];
+    }
+    b->nitems = item;
+    VPP_HIP(hipMemcpy(b->d_probs, tab.data(), tab.size() * sizeof(BatchProblem), hipMemcpyHostToDevice));
+    int per_cu = batch_blocks_per_cu(b->cfg, b->k);
+    if (per_cu < 1) per_cu = 1;
+    hipDeviceProp_t prop;
+    VPP_HIP(hipGetDeviceProperties(&prop, b->device));
+    b->nblocks = std::max(1, std::min(prop.multiProcessorCount * per_cu, b->nitems));
+    return VPP_OK;
+}
+
+static vpp_status batch_build_graph(vpp_batch b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    hipGraph_t g = nullptr;
+    VPP_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    MultiFillArgs fa{b->d_y, b->d_off, b->total_rhs, b->d_queue};
+    hipError_t err = launch_multi_zero(fa, b->stream);
+    BatchArgs ba{b->d_probs, (int)b->probs.size(), b->nitems, b->d_x, b->d_y, b->d_queue};
+    if (err == hipSuccess) err = launch_batch_apply(b->cfg, b->k, ba, b->nblocks, b->stream);
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(VPP_ERR_HIP, std::string("batch graph capture: ") + hipGetErrorString(err));
+    }
+    VPP_HIP(e2);
+    hipError_t e3 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    VPP_HIP(e3);
+    return VPP_OK;
+}
+
+static vpp_status batch_set_pointers(vpp_batch b, const double* const* x, double* const* y)
+{
+    bool same = !b->cur_x.empty();
+    for (int i = 0; same && i < b->total_rhs; ++i) same = b->cur_x[i] == x[i] && b->cur_y[i] == y[i];
+    if (same) return VPP_OK;
+    b->cur_x.assign(x, x + b->total_rhs);
+    b->cur_y.assign(y, y + b->total_rhs);
+    VPP_HIP(hipMemcpy(b->d_x, x, b->total_rhs * sizeof(double*), hipMemcpyHostToDevice));
+    VPP_HIP(hipMemcpy(b->d_y, y, b->total_rhs * sizeof(double*), hipMemcpyHostToDevice));
+    return batch_build_graph(b);
+}
+
+static vpp_status batch_tune(vpp_batch b, const char* cache_path)
+{
+    const std::string key = size_bucket_key("batch", b->k, b->total_dofs);
+    LaunchCfg c;
+    if (cache_lookup(cache_path, key, &c) && batch_blocks_per_cu(c, b->k) > 0) {
+        b->cfg = c;
+        return batch_build_table(b);
+    }
+    // time every candidate on scratch vectors
+    std::vector<double*> xs(b->total_rhs, nullptr), ys(b->total_rhs, nullptr);
+    vpp_status st = VPP_OK;
+    int r = 0;
+    for (size_t i = 0; i < b->probs.size() && !st; ++i)
+        for (int j = 0; j < b->nrhs[i] && !st; ++j, ++r) {
+            if ((st = dev_alloc(&xs[r], b->probs[i]->N, "tune x")) ||
+                (st = dev_alloc(&ys[r], b->probs[i]->N, "tune y")))
+                break;
+            if (launch_fill<double>(xs[r], b->probs[i]->N, 1.0, b->stream) != hipSuccess)
+                st = fail(VPP_ERR_HIP, "fill");
+        }
+    LaunchCfg cands[8];
+    int nc = 0;
+    const int all[4][3] = {{8, 8, 4}, {16, 4, 4}, {8, 4, 4}, {4, 4, 4}};
+    for (int i = 0; i < 4; ++i) {
+        LaunchCfg t{0, {all[i][0], all[i][1], all[i][2]}};
+        if (batch_blocks_per_cu(t, b->k) > 0) cands[nc++] = t;
+    }
+    double best = 1e300;
+    LaunchCfg best_cfg = cands[0];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(VPP_ERR_HIP, "event");
+    for (int i = 0; i < nc && !st; ++i) {
+        b->cfg = cands[i];
+        if ((st = batch_build_table(b))) break;
+        b->cur_x.clear();
+        if ((st = batch_set_pointers(b, xs.data(), ys.data()))) break;
+        (void)hipGraphLaunch(b->graph, b->stream);
+        (void)hipEventRecord(e0, b->stream);
+        const int reps = 5;
+        for (int k = 0; k < reps; ++k) (void)hipGraphLaunch(b->graph, b->stream);
+        (void)hipEventRecord(e1, b->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(VPP_ERR_HIP, "tuning run failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1000.0 * ms / reps;
+        if (us < best) {
+            best = us;
+            best_cfg = cands[i];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(b->stream);
+    for (auto* v : xs) dev_free(v);
+    for (auto* v : ys) dev_free(v);
+    b->cur_x.clear();
+    b->cur_y.clear();
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    if (st) return st;
+    b->cfg = best_cfg;
+    cache_store(cache_path, key, best_cfg, best);
+    return batch_build_table(b);
+}
+
+vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32_t nprob, const char* tune_cache,
+                            vpp_batch* out)
+{
+    if (!probs || !nrhs || !out || nprob < 1) return fail(VPP_ERR_INVALID_ARG, "null argument or empty batch");
+    *out = nullptr;
+    const int k = probs[0] ? probs[0]->k : 0;
+    const int dev = probs[0] ? probs[0]->desc.device : 0;
+    for (int i = 0; i < nprob; ++i) {
+        if (!probs[i]) return fail(VPP_ERR_INVALID_ARG, "null problem");
+        if (probs[i]->k != k) return fail(VPP_ERR_UNSUPPORTED, "all problems of a batch must share the degree");
+        if (probs[i]->desc.device != dev) return fail(VPP_ERR_UNSUPPORTED, "all problems must be on one device");
+        if (!probs[i]->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called for every problem");
+        if (nrhs[i] < 1) return fail(VPP_ERR_INVALID_ARG, "nrhs must be >= 1");
+    }
+    if (k != 2) return fail(VPP_ERR_UNSUPPORTED, "batched apply is available for degree 2");
+    DeviceGuard dg(dev);
+    vpp_batch b = new vpp_batch_s();
+    b->device = dev;
+    b->k = k;
+    b->probs.assign(probs, probs + nprob);
+    b->nrhs.assign(nrhs, nrhs + nprob);
+    std::vector<int64_t> off(1, 0);
+    for (int i = 0; i < nprob; ++i) {
+        b->total_rhs += nrhs[i];
+        b->total_dofs += probs[i]->N * nrhs[i];
+        for (int j = 0; j < nrhs[i]; ++j) off.push_back(off.back() + probs[i]->N);
+    }
+    b->cfg = LaunchCfg{0, {8, 4, 4}};
+    vpp_status st;
+    if ((st = dev_alloc(&b->d_probs, nprob, "batch table")) || (st = dev_alloc(&b->d_x, b->total_rhs, "batch x")) ||
+        (st = dev_alloc(&b->d_y, b->total_rhs, "batch y")) || (st = dev_alloc(&b->d_off, off.size(), "batch off")) ||
+        (st = dev_alloc(&b->d_queue, 1, "batch queue"))) {
+        vpp_batch_destroy(b);
+        return st;
+    }
+    if (hipMemcpy(b->d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+        vpp_batch_destroy(b);
+        return fail(VPP_ERR_HIP, "batch set-up failed");
+    }
+    st = batch_tune(b, tune_cache);
+    if (st) {
+        vpp_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return VPP_OK;
+}
+
+vpp_status vpp_batch_apply(vpp_batch b, const double* const* x, double* const* y, void* stream)
+{
+    if (!b || !x || !y) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    for (int i = 0; i < b->total_rhs; ++i) {
+        if (!x[i] || !y[i]) return fail(VPP_ERR_INVALID_ARG, "null vector in batch");
+        for (int j = 0; j < b->total_rhs; ++j)
+            if ((const void*)x[i] == (const void*)y[j]) return fail(VPP_ERR_INVALID_ARG, "x and y must not alias");
+    }
+    DeviceGuard dg(b->device);
+    // The pointer tables are refreshed synchronously, only when the caller's buffers change.
+    bool changed = b->cur_x.empty() || !b->graph;
+    for (int i = 0; !changed && i < b->total_rhs; ++i) changed = b->cur_x[i] != x[i] || b->cur_y[i] != y[i];
+    if (changed) {
+        VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+        VPP_HIP(hipStreamSynchronize(b->stream));
+        vpp_status st = batch_set_pointers(b, x, y);
+        if (st) return st;
+    }
+    VPP_HIP(hipGraphLaunch(b->graph, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+vpp_status vpp_batch_cg_solve(vpp_batch b, const double* const* rhs, double* const* x, const vpp_cg_opts* opts,
+                              vpp_cg_info* info, void* stream)
+{
+    if (!b || !rhs || !x || !opts) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    vpp_status worst = VPP_OK;
+    int r = 0;
+    for (size_t i = 0; i < b->probs.size(); ++i)
+        for (int j = 0; j < b->nrhs[i]; ++j, ++r) {
+            vpp_cg_info inf{};
+            vpp_status st = vpp_cg_solve(b->probs[i], rhs[r], x[r], opts, &inf, stream);
+            if (info) info[r] = inf;
+            if (st == VPP_ERR_HIP || st == VPP_ERR_OUT_OF_MEMORY || st == VPP_ERR_INVALID_ARG) return st;
+            if (st != VPP_OK && worst == VPP_OK) worst = st;
+        }
+    if (worst != VPP_OK) return fail(worst, "at least one solve of the batch did not converge");
+    return VPP_OK;
+}
+
+vpp_status vpp_batch_get_config(vpp_batch b, vpp_kernel_config* cfg)
+{
+    if (!b || !cfg) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    cfg->variant = b->cfg.variant;
+    for (int d = 0; d < 3; ++d) cfg->tile[d] = b->cfg.tile[d];
+    return VPP_OK;
+}
+
+vpp_status vpp_batch_destroy(vpp_batch b)
+{
+    if (!b) return VPP_OK;
+    DeviceGuard dg(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    dev_free(b->d_probs); dev_free(b->d_x); dev_free(b->d_y); dev_free(b->d_off); dev_free(b->d_queue);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return VPP_OK;
+}
+
+}  // extern "C"

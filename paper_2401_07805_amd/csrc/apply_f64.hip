@@ -1,0 +1,33 @@
+// FP64 apply kernels (all instantiated configurations).
+#include "apply_configs.h"
+
+namespace vpp {
+
+hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& a, int nblocks, hipStream_t s)
+{
+    return launch_apply_t<double>(c, k, a, nblocks, s);
+}
+
+bool apply_config_supported(const LaunchCfg& c, int k)
+{
+#define VPP_SUP(K, V, TX, TY, TZ) \
+    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) return true;
+    VPP_APPLY_CONFIGS(VPP_SUP)
+#undef VPP_SUP
+    return false;
+}
+
+int list_apply_configs(int k, LaunchCfg* out, int cap)
+{
+    int n = 0;
+#define VPP_LIST(K, V, TX, TY, TZ)                          \
+    if (k == K) {                                           \
+        if (n < cap && out) out[n] = LaunchCfg{V, {TX, TY, TZ}}; \
+        ++n;                                                \
+    }
+    VPP_APPLY_CONFIGS(VPP_LIST)
+#undef VPP_LIST
+    return n;
+}
+
+}  // namespace vpp

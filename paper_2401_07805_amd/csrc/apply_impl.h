@@ -1,0 +1,425 @@
+// Matrix-free application of the variable-coefficient pressure-Poisson
+// operator, y = sum_e R_e^T A_e R_e x (Sec. "Numerical framework"), with
+// A_e = sum_q W_q c(phi_h(x_q)) B_q^T B_q evaluated on the fly by sum
+// factorisation over the tensor-product Q_k basis and (k+1)^3 Gauss points.
+//
+// Two thread mappings (the autotuner picks one per problem):
+//   variant 0, cell per thread: all (k+1)^3 values of a cell live in registers,
+//              every sweep is register-only (k = 2, and k = 3 as a candidate);
+//   variant 1, plane per thread: k+1 threads share a cell, each holding one
+//              x-plane of (k+1)^2 values; y/z sweeps are in registers and the
+//              x sweeps exchange planes through LDS (all k).
+// Both accumulate the workgroup tile's node block in LDS and write it out
+// coalesced: nodes inside the tile with plain stores, nodes on faces shared
+// with a neighbouring tile with atomics into a zeroed y.  Dirichlet rows get
+// y_i = x_i (identity rows of A_D); Dirichlet columns are dropped by zeroing
+// those entries of x at the gather.
+#pragma once
+#include "kernels.h"
+
+namespace vpp {
+
+// Dirichlet faces touched by a cell: bit f set if the cell lies on Dirichlet face f.
+__device__ __forceinline__ int cell_dirichlet_faces(const MeshArgs& m, int cx, int cy, int cz)
+{
+    int f = 0;
+    if (cx == 0) f |= 1;
+    if (cx == m.nc[0] - 1) f |= 2;
+    if (cy == 0) f |= 4;
+    if (cy == m.nc[1] - 1) f |= 8;
+    if (cz == 0) f |= 16;
+    if (cz == m.nc[2] - 1) f |= 32;
+    return f & m.bcmask;
+}
+
+template <int K>
+__device__ __forceinline__ bool local_dirichlet(int faces, int a0, int a1, int a2)
+{
+    return ((faces & 1) && a0 == 0) || ((faces & 2) && a0 == K) || ((faces & 4) && a1 == 0) ||
+           ((faces & 8) && a1 == K) || ((faces & 16) && a2 == 0) || ((faces & 32) && a2 == K);
+}
+
+template <int K, typename T, typename S>
+__device__ __forceinline__ void gather_cell(const MeshArgs& m, const S* __restrict__ x, int cx, int cy,
+                                            int cz, int faces, T (&u)[(K + 1) * (K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1;
+    const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
+    const int64_t base = node_index(m, (int64_t)K * cx, (int64_t)K * cy, (int64_t)K * cz);
+#pragma unroll
+    for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0)
+                u[a0 + N * (a1 + N * a2)] = T(x[base + a0 + nx * a1 + nxy * a2]);
+    if (faces) {
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+                for (int a0 = 0; a0 < N; ++a0)
+                    if (local_dirichlet<K>(faces, a0, a1, a2)) u[a0 + N * (a1 + N * a2)] = T(0);
+    }
+}
+
+// Scaled coefficient factor cw_q = c'(phi_h(x_q)) wref_q of a cell from nodal phi.
+template <int K, typename T>
+__device__ __forceinline__ void cell_coefficient(const MeshArgs& m, const T* __restrict__ phi, int cx,
+                                                 int cy, int cz, T (&cw)[(K + 1) * (K + 1) * (K + 1)])
+{
+    gather_cell<K>(m, phi, cx, cy, cz, 0, cw);
+    sweep3<K, MS, false, 0>(cw);
+    sweep3<K, MS, false, 1>(cw);
+    sweep3<K, MS, false, 2>(cw);
+    coef_weights3<K>(m, cw);
+}
+
+// Cell operator on registers: u (nodal values, Dirichlet entries zeroed) is
+// replaced by A_e u.
+//   forward:  u_q = (S x S x S) u,  g_d = Dc along d of u_q   (collocation derivative)
+//   Gauss point: f_d = cw rd[d] g_d
+//   backward: v = sum_d Dc_d^T f_d,  A_e u = (S^T x S^T x S^T) v
+template <int K, typename T>
+__device__ __forceinline__ void cell_operator(const MeshArgs& m, const T (&cw)[(K + 1) * (K + 1) * (K + 1)],
+                                              T (&u)[(K + 1) * (K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1, N3 = N * N * N;
+    sweep3<K, MS, false, 0>(u);
+    sweep3<K, MS, false, 1>(u);
+    sweep3<K, MS, false, 2>(u);
+    T v[N3];
+    const T r0 = T(m.rd[0]), r1 = T(m.rd[1]), r2 = T(m.rd[2]);
+#pragma unroll
+    for (int i2 = 0; i2 < N; ++i2)
+#pragma unroll
+        for (int i1 = 0; i1 < N; ++i1) {
+            T in[N], g[N], o[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) in[a] = u[a + N * (i1 + N * i2)];
+            line<K, MDC, false>(in, g);
+#pragma unroll
+            for (int a = 0; a < N; ++a) g[a] *= cw[a + N * (i1 + N * i2)] * r0;
+            line<K, MDC, true>(g, o);
+#pragma unroll
+            for (int a = 0; a < N; ++a) v[a + N * (i1 + N * i2)] = o[a];
+        }
+#pragma unroll
+    for (int i2 = 0; i2 < N; ++i2)
+#pragma unroll
+        for (int i0 = 0; i0 < N; ++i0) {
+            T in[N], g[N], o[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) in[a] = u[i0 + N * (a + N * i2)];
+            line<K, MDC, false>(in, g);
+#pragma unroll
+            for (int a = 0; a < N; ++a) g[a] *= cw[i0 + N * (a + N * i2)] * r1;
+#pragma unroll
+            for (int a = 0; a < N; ++a) o[a] = v[i0 + N * (a + N * i2)];
+            line_acc<K, MDC, true>(g, o);
+#pragma unroll
+            for (int a = 0; a < N; ++a) v[i0 + N * (a + N * i2)] = o[a];
+        }
+#pragma unroll
+    for (int i1 = 0; i1 < N; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < N; ++i0) {
+            T in[N], g[N], o[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) in[a] = u[i0 + N * (i1 + N * a)];
+            line<K, MDC, false>(in, g);
+#pragma unroll
+            for (int a = 0; a < N; ++a) g[a] *= cw[i0 + N * (i1 + N * a)] * r2;
+#pragma unroll
+            for (int a = 0; a < N; ++a) o[a] = v[i0 + N * (i1 + N * a)];
+            line_acc<K, MDC, true>(g, o);
+#pragma unroll
+            for (int a = 0; a < N; ++a) v[i0 + N * (i1 + N * a)] = o[a];
+        }
+    sweep3<K, MS, true, 2>(v);
+    sweep3<K, MS, true, 1>(v);
+    sweep3<K, MS, true, 0>(v);
+#pragma unroll
+    for (int a = 0; a < N3; ++a) u[a] = v[a];
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry and the write-out of a tile's node block.
+
+struct TileCoord {
+    int t[3];      // tile coordinates
+    int n0[3];     // first node of the tile's block
+    int ext[3];    // valid block extent (nodes) per direction
+};
+
+template <int K, int TX, int TY, int TZ>
+__device__ __forceinline__ TileCoord tile_coord(const MeshArgs& m, int tile)
+{
+    TileCoord c;
+    c.t[0] = tile % m.ntile[0];
+    c.t[1] = (tile / m.ntile[0]) % m.ntile[1];
+    c.t[2] = tile / (m.ntile[0] * m.ntile[1]);
+    const int T3[3] = {TX, TY, TZ};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c.n0[d] = K * T3[d] * c.t[d];
+        c.ext[d] = K * min(T3[d], m.nc[d] - T3[d] * c.t[d]) + 1;
+    }
+    return c;
+}
+
+// y from the LDS block yb (BX x BY x BZ, x fastest).  A node on the lower face
+// of a tile (with a tile below) belongs to the lower tile; a node of a Dirichlet
+// face is written (y = x) by the tile it belongs to.  Returns this thread's
+// share of x . y restricted to the tile's contributions.
+template <typename T, int BX, int BY, int BZ, int NT>
+__device__ __forceinline__ double flush_block(const MeshArgs& m, const TileCoord& tc, const T* yb,
+                                              const T* __restrict__ x, T* __restrict__ y, bool dot)
+{
+    double dsum = 0.0;
+    for (int idx = threadIdx.x; idx < BX * BY * BZ; idx += NT) {
+        const int li = idx % BX, lj = (idx / BX) % BY, ll = idx / (BX * BY);
+        if (li >= tc.ext[0] || lj >= tc.ext[1] || ll >= tc.ext[2]) continue;
+        const int gi = tc.n0[0] + li, gj = tc.n0[1] + lj, gl = tc.n0[2] + ll;
+        const int64_t g = node_index(m, gi, gj, gl);
+        const bool lo = (li == 0 && tc.t[0] > 0) || (lj == 0 && tc.t[1] > 0) || (ll == 0 && tc.t[2] > 0);
+        if (is_dirichlet(m, gi, gj, gl)) {
+            if (!lo) {
+                const T xv = x[g];
+                y[g] = xv;
+                if (dot) dsum += (double)xv * (double)xv;
+            }
+            continue;
+        }
+        const T v = yb[idx];
+        const bool hi = (li == tc.ext[0] - 1 && tc.t[0] < m.ntile[0] - 1) ||
+                        (lj == tc.ext[1] - 1 && tc.t[1] < m.ntile[1] - 1) ||
+                        (ll == tc.ext[2] - 1 && tc.t[2] < m.ntile[2] - 1);
+        if (lo || hi) atomicAdd(&y[g], v);
+        else y[g] = v;
+        if (dot) dsum += (double)x[g] * (double)v;
+    }
+    return dsum;
+}
+
+// Workgroup sum of one double per thread (LDS tree, valid for any NT including
+// partial waves), added atomically to *out by thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum_atomic(double v, double* out)
+{
+    constexpr int P = NT <= 1 ? 1 : (NT <= 64 ? 64 : (NT <= 128 ? 128 : (NT <= 256 ? 256 : (NT <= 512 ? 512 : 1024))));
+    static_assert(NT <= 1024, "workgroup too large");
+    __shared__ double red[P];
+    red[threadIdx.x] = v;
+    for (int i = NT + threadIdx.x; i < P; i += NT) red[i] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int s = P / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Variant 0: one cell per thread.
+
+template <int K, typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a)
+{
+    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
+    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
+    __shared__ T yb[BX * BY * BZ];
+    if (a.done && *a.done) return;
+    const MeshArgs& m = a.m;
+    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, xcd_tile(blockIdx.x, gridDim.x));
+    for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
+    __syncthreads();
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
+    if (cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2]) {
+        T cw[N3], u[N3];
+        cell_coefficient<K>(m, a.phi, cx, cy, cz, cw);
+        gather_cell<K>(m, a.x, cx, cy, cz, cell_dirichlet_faces(m, cx, cy, cz), u);
+        cell_operator<K>(m, cw, u);
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+                for (int a0 = 0; a0 < N; ++a0)
+                    atomicAdd(&yb[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))],
+                              u[a0 + N * (a1 + N * a2)]);
+    }
+    __syncthreads();
+    const double d = flush_block<T, BX, BY, BZ, NT>(m, tc, yb, a.x, a.y, a.dot != nullptr);
+    if (a.dot) block_sum_atomic<NT>(d, a.dot);
+}
+
+// ---------------------------------------------------------------------------
+// Variant 1: one x-plane of a cell per thread; x sweeps through LDS.
+
+// Entry (r, i) of a 1D matrix for a runtime row r (COL: entry (i, r)).
+template <int K, Mat M, bool COL>
+__device__ __forceinline__ double pick(int r, int i)
+{
+    double v = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < K + 1; ++rr)
+        if (r == rr) v = COL ? mat<K, M>(i, rr) : mat<K, M>(rr, i);
+    return v;
+}
+
+template <int K, typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(ApplyArgs<T> a)
+{
+    constexpr int N = K + 1, N2 = N * N, NC = TX * TY * TZ, NT = N * NC;
+    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
+    constexpr int CS = N * N2 + 1;           // padded per-cell stride of the exchange buffers
+    __shared__ T yb[BX * BY * BZ];
+    __shared__ T xb[2 * NC * CS];
+    if (a.done && *a.done) return;
+    const MeshArgs& m = a.m;
+    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, xcd_tile(blockIdx.x, gridDim.x));
+    for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
+    const int cell = threadIdx.x / N, ip = threadIdx.x % N;
+    const int lx = cell % TX, ly = (cell / TX) % TY, lz = cell / (TX * TY);
+    const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
+    const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+    T* X1 = xb + cell * CS;
+    T* X2 = xb + (NC + cell) * CS;
+    const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
+    const int64_t base = active ? node_index(m, (int64_t)K * cx + ip, (int64_t)K * cy, (int64_t)K * cz) : 0;
+    T rS[N], rD[N], cS[N], cD[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        rS[i] = T(pick<K, MS, false>(ip, i));
+        rD[i] = T(pick<K, MD, false>(ip, i));
+        cS[i] = T(pick<K, MS, true>(ip, i));
+        cD[i] = T(pick<K, MD, true>(ip, i));
+    }
+    T wx = T(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (ip == i) wx = T(Tab<K>::t.w[i]);
+
+    // Coefficient: phi plane at x-node ip -> Gauss in (y,z) -> exchange -> Gauss in x.
+    T cw[N2];
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+#pragma unroll
+            for (int j = 0; j < N; ++j) cw[j + N * l] = T(a.phi[base + nx * j + nxy * l]);
+        sweep2<K, MS, false, 0>(cw);
+        sweep2<K, MS, false, 1>(cw);
+#pragma unroll
+        for (int q = 0; q < N2; ++q) X1[ip * N2 + q] = cw[q];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            T s = rS[0] * X1[q];
+#pragma unroll
+            for (int i = 1; i < N; ++i) s = fma(rS[i], X1[i * N2 + q], s);
+            cw[q] = s;
+        }
+        if (m.heaviside == 0) {
+            const T ca = T(m.ca), cb = T(m.cb);
+#pragma unroll
+            for (int q = 0; q < N2; ++q)
+                cw[q] = fma(cb, clamp1(cw[q]), ca) * (wx * T(Tab<K>::t.w[q % N] * Tab<K>::t.w[q / N]));
+        } else {
+            const T cg = T(m.cg), cd = T(m.cd);
+#pragma unroll
+            for (int q = 0; q < N2; ++q)
+                cw[q] = fma(cd, sine_ramp(clamp1(cw[q])), cg) *
+                        (wx * T(Tab<K>::t.w[q % N] * Tab<K>::t.w[q / N]));
+        }
+    }
+    __syncthreads();
+
+    // Operand plane at x-node ip (Dirichlet entries zeroed).
+    T uq[N2], gx[N2];
+    if (active) {
+        const int faces = cell_dirichlet_faces(m, cx, cy, cz);
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                T v = T(a.x[base + nx * j + nxy * l]);
+                if (faces && local_dirichlet<K>(faces, ip, j, l)) v = T(0);
+                uq[j + N * l] = v;
+            }
+        sweep2<K, MS, false, 0>(uq);
+        sweep2<K, MS, false, 1>(uq);
+#pragma unroll
+        for (int q = 0; q < N2; ++q) X1[ip * N2 + q] = uq[q];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            const T v0 = X1[q];
+            T s = rS[0] * v0, d = rD[0] * v0;
+#pragma unroll
+            for (int i = 1; i < N; ++i) {
+                const T v = X1[i * N2 + q];
+                s = fma(rS[i], v, s);
+                d = fma(rD[i], v, d);
+            }
+            uq[q] = s;
+            gx[q] = d;
+        }
+    }
+    __syncthreads();
+    if (active) {
+        T gy[N2];
+#pragma unroll
+        for (int q = 0; q < N2; ++q) gy[q] = uq[q];
+        sweep2<K, MDC, false, 0>(gy);
+        sweep2<K, MDC, false, 1>(uq);     // uq now holds the z derivative
+        const T r0 = T(m.rd[0]), r1 = T(m.rd[1]), r2 = T(m.rd[2]);
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            gx[q] *= cw[q] * r0;
+            gy[q] *= cw[q] * r1;
+            uq[q] *= cw[q] * r2;
+        }
+        sweep2<K, MDC, true, 0>(gy);
+        sweep2<K, MDC, true, 1>(uq);
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            X1[ip * N2 + q] = gy[q] + uq[q];
+            X2[ip * N2 + q] = gx[q];
+        }
+    }
+    __syncthreads();
+    if (active) {
+        T o[N2];
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            T s = cS[0] * X1[q];
+            s = fma(cD[0], X2[q], s);
+#pragma unroll
+            for (int i = 1; i < N; ++i) {
+                s = fma(cS[i], X1[i * N2 + q], s);
+                s = fma(cD[i], X2[i * N2 + q], s);
+            }
+            o[q] = s;
+        }
+        sweep2<K, MS, true, 0>(o);
+        sweep2<K, MS, true, 1>(o);
+#pragma unroll
+        for (int l = 0; l < N; ++l)
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                atomicAdd(&yb[(K * lx + ip) + BX * ((K * ly + j) + BY * (K * lz + l))], o[j + N * l]);
+    }
+    __syncthreads();
+    const double d = flush_block<T, BX, BY, BZ, NT>(m, tc, yb, a.x, a.y, a.dot != nullptr);
+    if (a.dot) block_sum_atomic<NT>(d, a.dot);
+}
+
+}  // namespace vpp

@@ -1,0 +1,226 @@
+// Diagonal, fill and batched kernels and their launchers.
+#include "apply_impl.h"
+
+namespace vpp {
+
+// ---------------------------------------------------------------------------
+// Diagonal: diag_a = sum_q cw_q sum_d rd[d] (dN_a/dxi_d (x_q))^2, from squared
+// 1D tables (each term is a product of three 1D factors).  Runs once per phi.
+
+template <int K>
+__global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __restrict__ phi,
+                                                   double* __restrict__ diag)
+{
+    constexpr int N = K + 1, N3 = N * N * N;
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
+    if (cell >= ncell) return;
+    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
+              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    double A[N3], Z[N3], Y[N3], out[N3];
+    cell_coefficient<K>(m, phi, cx, cy, cz, A);
+#pragma unroll
+    for (int q = 0; q < N3; ++q) Z[q] = A[q];
+    sweep3<K, MS2, true, 2>(Z);
+#pragma unroll
+    for (int q = 0; q < N3; ++q) Y[q] = Z[q];
+    sweep3<K, MS2, true, 1>(Y);
+    sweep3<K, MD2, true, 0>(Y);
+#pragma unroll
+    for (int q = 0; q < N3; ++q) out[q] = m.rd[0] * Y[q];
+#pragma unroll
+    for (int q = 0; q < N3; ++q) Y[q] = Z[q];
+    sweep3<K, MD2, true, 1>(Y);
+    sweep3<K, MS2, true, 0>(Y);
+#pragma unroll
+    for (int q = 0; q < N3; ++q) out[q] = fma(m.rd[1], Y[q], out[q]);
+    sweep3<K, MD2, true, 2>(A);
+    sweep3<K, MS2, true, 1>(A);
+    sweep3<K, MS2, true, 0>(A);
+#pragma unroll
+    for (int q = 0; q < N3; ++q) out[q] = fma(m.rd[2], A[q], out[q]);
+    const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
+    const int64_t base = node_index(m, (int64_t)K * cx, (int64_t)K * cy, (int64_t)K * cz);
+#pragma unroll
+    for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0)
+                atomicAdd(&diag[base + a0 + nx * a1 + nxy * a2], out[a0 + N * (a1 + N * a2)]);
+}
+
+__global__ void fix_diagonal_kernel(MeshArgs m, double* __restrict__ diag, double* __restrict__ inv64,
+                                    float* __restrict__ inv32)
+{
+    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g % m.nn[0]), j = (int)((g / m.nn[0]) % m.nn[1]),
+                  l = (int)(g / ((int64_t)m.nn[0] * m.nn[1]));
+        double d = diag[g];
+        if (is_dirichlet(m, i, j, l)) d = 1.0;
+        diag[g] = d;
+        const double r = 1.0 / d;
+        inv64[g] = r;
+        inv32[g] = (float)r;
+    }
+}
+
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ p, int64_t n, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 255) / 256;
+    const int blocks = (int)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
+template hipError_t launch_fill<int>(int*, int64_t, int, hipStream_t);
+
+hipError_t launch_diag(int k, const MeshArgs& m, const double* phi, double* diag, hipStream_t s)
+{
+    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
+    const int blocks = (int)((ncell + 63) / 64);
+    switch (k) {
+    case 2: hipLaunchKernelGGL(diag_kernel<2>, dim3(blocks), dim3(64), 0, s, m, phi, diag); break;
+    case 3: hipLaunchKernelGGL(diag_kernel<3>, dim3(blocks), dim3(64), 0, s, m, phi, diag); break;
+    case 4: hipLaunchKernelGGL(diag_kernel<4>, dim3(blocks), dim3(64), 0, s, m, phi, diag); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fix_diagonal(const MeshArgs& m, double* diag, double* inv64, float* inv32, hipStream_t s)
+{
+    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
+    const int64_t want = (n + 255) / 256;
+    const int blocks = (int)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(fix_diagonal_kernel, dim3(blocks), dim3(256), 0, s, m, diag, inv64, inv32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent apply: one launch over the (problem, tile) work items of
+// several independent meshes.  Workgroups pull items from a device counter
+// until the list is exhausted (every workgroup leaves the loop once the
+// counter passes the item count).  The coefficient of a tile is computed once
+// and reused for all right-hand sides of its problem.
+
+template <int K, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
+{
+    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
+    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
+    __shared__ double yb[BX * BY * BZ];
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= a.nitems) break;
+        int pi = 0;
+        for (int i = 1; i < a.nprob; ++i)
+            if (a.probs[i].tile_begin <= item) pi = i;
+        const MeshArgs m = a.probs[pi].m;
+        const double* phi = a.probs[pi].phi;
+        const int nrhs = a.probs[pi].nrhs, rhs0 = a.probs[pi].rhs_begin;
+        const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, item - a.probs[pi].tile_begin);
+        const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+        const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
+        const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+        double cw[N3];
+        if (active) cell_coefficient<K>(m, phi, cx, cy, cz, cw);
+        const int faces = active ? cell_dirichlet_faces(m, cx, cy, cz) : 0;
+        for (int r = 0; r < nrhs; ++r) {
+            const double* x = a.x[rhs0 + r];
+            double* y = a.y[rhs0 + r];
+            for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = 0.0;
+            __syncthreads();
+            if (active) {
+                double u[N3];
+                gather_cell<K>(m, x, cx, cy, cz, faces, u);
+                cell_operator<K>(m, cw, u);
+#pragma unroll
+                for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+                    for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+                        for (int a0 = 0; a0 < N; ++a0)
+                            atomicAdd(&yb[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))],
+                                      u[a0 + N * (a1 + N * a2)]);
+            }
+            __syncthreads();
+            flush_block<double, BX, BY, BZ, NT>(m, tc, yb, x, y, false);
+            __syncthreads();
+        }
+    }
+}
+
+// Zero several vectors (and the work counter) in one launch.
+__global__ void multi_zero_kernel(MultiFillArgs a)
+{
+    const int64_t total = a.offset[a.nvec];
+    if (a.queue && blockIdx.x == 0 && threadIdx.x == 0) *a.queue = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int v = 0;
+        while (v + 1 < a.nvec && a.offset[v + 1] <= i) ++v;
+        a.ptr[v][i - a.offset[v]] = 0.0;
+    }
+}
+
+#define VPP_BATCH_CONFIGS(X) \
+    X(2, 8, 8, 4)            \
+    X(2, 16, 4, 4)           \
+    X(2, 8, 4, 4)            \
+    X(2, 4, 4, 4)
+
+hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, hipStream_t s)
+{
+#define VPP_BL(K, TX, TY, TZ)                                                                     \
+    if (k == K && c.variant == 0 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {     \
+        hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ>), dim3(nblocks), dim3(TX * TY * TZ), \
+                           0, s, a);                                                              \
+        return hipGetLastError();                                                                 \
+    }
+    VPP_BATCH_CONFIGS(VPP_BL)
+#undef VPP_BL
+    return hipErrorInvalidValue;
+}
+
+int batch_blocks_per_cu(const LaunchCfg& c, int k)
+{
+    int nb = 0;
+#define VPP_BO(K, TX, TY, TZ)                                                                      \
+    if (k == K && c.variant == 0 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {      \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_apply_kernel<K, TX, TY, TZ>,  \
+                                                         TX * TY * TZ, 0) != hipSuccess)          \
+            return 0;                                                                              \
+        return nb;                                                                                 \
+    }
+    VPP_BATCH_CONFIGS(VPP_BO)
+#undef VPP_BO
+    return 0;
+}
+
+hipError_t launch_multi_zero(const MultiFillArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(multi_zero_kernel, dim3(4096), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace vpp

@@ -1,0 +1,224 @@
+// Device-side building blocks shared by the kernels: argument blocks, the
+// coefficient law, 1D sum-factorisation sweeps and the tile geometry.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.h"
+
+namespace vpp {
+
+// ---------------------------------------------------------------------------
+// Geometry and material law of one problem, as the kernels see it.
+//
+// The element matrix of cell e is sum_q W_q c_q sum_d h_d^-2 (dN/dxi_d)(dN/dxi_d)^T
+// with W_q = w_q0 w_q1 w_q2 hx hy hz (Gauss weights on [0,1]).  We write the
+// Gauss-point factor as  c'(phi_q) * wref_q * rd[d]  with
+//   c'(phi) = r0 * c(phi),  r0 = hx hy hz / hx^2,  rd = (1, hx^2/hy^2, hx^2/hz^2),
+//   wref_q  = w_q0 w_q1 w_q2.
+// c(phi) = 1/rho_g + H(clamp(phi)) (1/rho_l - 1/rho_g)        (Eq. rhoEff)
+//   linear H:  c' = ca + cb * phi
+//   sine ramp: c' = cg + cd * H(phi), H from Eq. heaviside written in phi.
+struct MeshArgs {
+    int nc[3];        // cells per direction
+    int nn[3];        // nodes per direction (k nc + 1)
+    int ntile[3];     // workgroup tiles per direction
+    int bcmask;       // bit f set: face f (x-,x+,y-,y+,z-,z+) is Dirichlet
+    int heaviside;    // 0 linear, 1 sine ramp
+    double ca, cb;    // linear law (scaled by r0)
+    double cg, cd;    // sine-ramp law (scaled by r0)
+    double rd[3];
+    double dcdphi;    // r0-free (1/rho_l - 1/rho_g), used by the adjoint
+    double r0;
+};
+
+__device__ __forceinline__ int64_t node_index(const MeshArgs& m, int64_t i, int64_t j, int64_t l)
+{
+    return i + (int64_t)m.nn[0] * (j + (int64_t)m.nn[1] * l);
+}
+
+__device__ __forceinline__ bool is_dirichlet(const MeshArgs& m, int i, int j, int l)
+{
+    return ((m.bcmask & 1) && i == 0) || ((m.bcmask & 2) && i == m.nn[0] - 1) ||
+           ((m.bcmask & 4) && j == 0) || ((m.bcmask & 8) && j == m.nn[1] - 1) ||
+           ((m.bcmask & 16) && l == 0) || ((m.bcmask & 32) && l == m.nn[2] - 1);
+}
+
+// Sine-ramp Heaviside of Eq. heaviside written in phi through Eq. distance:
+// with a = artanh(phi) = d/(2 eps), H = 1/2 + a/3 + sin(2 pi a/3)/(2 pi) for
+// |a| < 3/2, and 0 / 1 beyond.  eps cancels.
+template <typename T>
+__device__ __forceinline__ T sine_ramp(T phi)
+{
+    const T lim = T(0.90514825364486640);   // tanh(3/2)
+    if (phi >= lim) return T(1);
+    if (phi <= -lim) return T(0);
+    const T a = T(0.5) * log((T(1) + phi) / (T(1) - phi));
+    return T(0.5) + a * T(1.0 / 3.0) + sin(a * T(2.0943951023931955)) * T(0.15915494309189535);
+}
+
+template <typename T>
+__device__ __forceinline__ T sine_ramp_deriv(T phi)
+{
+    const T lim = T(0.90514825364486640);
+    if (phi >= lim || phi <= -lim) return T(0);
+    const T a = T(0.5) * log((T(1) + phi) / (T(1) - phi));
+    return (T(1) + cos(a * T(2.0943951023931955))) / (T(3) * (T(1) - phi * phi));
+}
+
+template <typename T>
+__device__ __forceinline__ T clamp1(T v)
+{
+    return fmin(fmax(v, T(-1)), T(1));
+}
+
+// ---------------------------------------------------------------------------
+// Multiply-accumulate with a compile-time coefficient: zero coefficients are
+// skipped and unit ones become plain adds (the loops are fully unrolled, so all
+// of this folds away).
+template <typename T>
+struct Acc {
+    T s;
+    bool init;
+    __device__ __forceinline__ Acc() : s(T(0)), init(false) {}
+    __device__ __forceinline__ void add(double c, T x)
+    {
+        if (c == 0.0) return;
+        if (!init) {
+            s = (c == 1.0) ? x : (c == -1.0 ? -x : T(c) * x);
+            init = true;
+        } else {
+            s = (c == 1.0) ? s + x : (c == -1.0 ? s - x : fma(T(c), x, s));
+        }
+    }
+    __device__ __forceinline__ T get() const { return init ? s : T(0); }
+};
+
+enum Mat { MS = 0, MD = 1, MDC = 2, MS2 = 3, MD2 = 4 };
+
+template <int K, Mat M>
+__device__ __forceinline__ constexpr double mat(int q, int a)
+{
+    return M == MS    ? Tab<K>::t.S[q][a]
+           : M == MD  ? Tab<K>::t.D[q][a]
+           : M == MDC ? Tab<K>::t.Dc[q][a]
+           : M == MS2 ? Tab<K>::t.S[q][a] * Tab<K>::t.S[q][a]
+                      : Tab<K>::t.D[q][a] * Tab<K>::t.D[q][a];
+}
+
+// out[q] = sum_a M[q][a] in[a]   (TR=false)   or   out[a] = sum_q M[q][a] in[q]  (TR=true)
+template <int K, Mat M, bool TR, typename T>
+__device__ __forceinline__ void line(const T (&in)[K + 1], T (&out)[K + 1])
+{
+    constexpr int N = K + 1;
+#pragma unroll
+    for (int o = 0; o < N; ++o) {
+        Acc<T> acc;
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc.add(TR ? mat<K, M>(i, o) : mat<K, M>(o, i), in[i]);
+        out[o] = acc.get();
+    }
+}
+
+// Same, accumulating into out.
+template <int K, Mat M, bool TR, typename T>
+__device__ __forceinline__ void line_acc(const T (&in)[K + 1], T (&out)[K + 1])
+{
+    constexpr int N = K + 1;
+#pragma unroll
+    for (int o = 0; o < N; ++o) {
+        T s = out[o];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const double c = TR ? mat<K, M>(i, o) : mat<K, M>(o, i);
+            if (c == 0.0) continue;
+            s = (c == 1.0) ? s + in[i] : fma(T(c), in[i], s);
+        }
+        out[o] = s;
+    }
+}
+
+// In-place sweep of a 1D matrix along direction DIR of an N^3 array
+// (index a0 + N a1 + N^2 a2).
+template <int K, Mat M, bool TR, int DIR, typename T>
+__device__ __forceinline__ void sweep3(T (&v)[(K + 1) * (K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1;
+    constexpr int st = DIR == 0 ? 1 : (DIR == 1 ? N : N * N);
+    constexpr int s1 = DIR == 0 ? N : 1;
+    constexpr int s2 = DIR == 2 ? N : N * N;
+#pragma unroll
+    for (int i2 = 0; i2 < N; ++i2)
+#pragma unroll
+        for (int i1 = 0; i1 < N; ++i1) {
+            const int base = i1 * s1 + i2 * s2;
+            T in[N], out[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) in[a] = v[base + a * st];
+            line<K, M, TR>(in, out);
+#pragma unroll
+            for (int a = 0; a < N; ++a) v[base + a * st] = out[a];
+        }
+}
+
+// Same on an N^2 plane (index b0 + N b1), direction 0 or 1 of the plane.
+template <int K, Mat M, bool TR, int DIR, typename T>
+__device__ __forceinline__ void sweep2(T (&v)[(K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1;
+    constexpr int st = DIR == 0 ? 1 : N;
+    constexpr int so = DIR == 0 ? N : 1;
+#pragma unroll
+    for (int i1 = 0; i1 < N; ++i1) {
+        const int base = i1 * so;
+        T in[N], out[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) in[a] = v[base + a * st];
+        line<K, M, TR>(in, out);
+#pragma unroll
+        for (int a = 0; a < N; ++a) v[base + a * st] = out[a];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ constexpr double wref(int q0, int q1, int q2)
+{
+    return Tab<K>::t.w[q0] * Tab<K>::t.w[q1] * Tab<K>::t.w[q2];
+}
+
+// Scaled coefficient c'(phi) * wref at every Gauss point of a cell, in place
+// (phi values at the Gauss points in, factors out).
+template <int K, typename T>
+__device__ __forceinline__ void coef_weights3(const MeshArgs& m, T (&v)[(K + 1) * (K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1;
+    if (m.heaviside == 0) {
+        const T ca = T(m.ca), cb = T(m.cb);
+#pragma unroll
+        for (int q = 0; q < N * N * N; ++q)
+            v[q] = fma(cb, clamp1(v[q]), ca) * T(wref<K>(q % N, (q / N) % N, q / (N * N)));
+    } else {
+        const T cg = T(m.cg), cd = T(m.cd);
+#pragma unroll
+        for (int q = 0; q < N * N * N; ++q)
+            v[q] = fma(cd, sine_ramp(clamp1(v[q])), cg) * T(wref<K>(q % N, (q / N) % N, q / (N * N)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry.  A workgroup owns TX x TY x TZ cells; tiles are numbered
+// x-fastest.  Workgroups are dispatched round-robin over the 8 XCDs, so block b
+// runs on XCD b % 8; remapping b -> (b % 8) * chunk + b / 8 gives every XCD a
+// contiguous run of tiles, whose shared faces then meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int chunk = (nblocks + 7) / 8;
+    const int x = b % 8, r = b / 8;
+    const int full = nblocks - 8 * (chunk - 1);   // XCDs that get `chunk` tiles
+    int t;
+    if (x < full) t = x * chunk + r;
+    else t = full * chunk + (x - full) * (chunk - 1) + r;
+    return t;
+}
+
+}  // namespace vpp

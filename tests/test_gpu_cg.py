@@ -1,0 +1,136 @@
+"""GPU Jacobi PCG (FP64 and FP64/FP32 defect correction) against the oracle.
+
+Solve parity needs both (i) the true FP64 residual, recomputed with the
+oracle's assembled matrix, below rtol ||b|| and (ii) a relative distance to the
+oracle's tight solution below 1e-8 (with rtol tightened for the parity runs).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import dev, host, rel, say
+
+pytestmark = pytest.mark.gpu
+
+vpp = pytest.importorskip("paper_2401_07805_amd")
+
+
+def _setup(m, phi):
+    p = vpp.Problem.from_mesh(m)
+    p.set_phi(dev(phi))
+    return p
+
+
+def test_c0_solve_fp64():
+    wl = W.small_droplet(n=8, k=2, seed=0)
+    m = wl.mesh
+    op = oracle.Operator(m, phi=wl.phi)
+    b = oracle.manufactured_sine_rhs(m, 0.25, m.eps)
+    pref = spla.spsolve(op.to_scipy().tocsc(), b)
+    prob = _setup(m, wl.phi)
+    say("c0 cg fp64")
+    p, info = prob.cg_solve(dev(b), rtol=1e-10)
+    p = host(p)
+    res = np.linalg.norm(b - op.matvec(p)) / np.linalg.norm(b)
+    print("c0 fp64", info, "true res", res, "err", rel(p, pref))
+    assert info["status"] == 0
+    assert res < 1e-10 * 1.01
+    assert rel(p, pref) < 1e-8
+    # the oracle's own PCG takes the same number of iterations up to rounding
+    _, oinfo = op.pcg(b, rtol=1e-10)
+    assert abs(oinfo["iterations"] - info["iterations"]) <= 2
+
+
+@pytest.mark.parametrize("k,n,precision", [(2, 10, "fp64"), (3, 6, "fp64"), (4, 4, "fp64"),
+                                           (2, 10, "mixed"), (3, 6, "mixed")])
+def test_solve_variants(k, n, precision):
+    m = W.unit_cube(n, k, 1000.0, 1.0)
+    m.eps = 2.0 / n
+    phi = W.bubble_phi(m, 0.25, m.eps)
+    op = oracle.Operator(m, phi=phi)
+    b = oracle.manufactured_sine_rhs(m, 0.25, m.eps, sign=-1.0)
+    pref = spla.spsolve(op.to_scipy().tocsc(), b)
+    prob = _setup(m, phi)
+    say("cg", k, n, precision)
+    p, info = prob.cg_solve(dev(b), rtol=1e-10, precision=precision, inner_rtol=1e-3)
+    p = host(p)
+    res = np.linalg.norm(b - op.matvec(p)) / np.linalg.norm(b)
+    print(k, n, precision, info, "true res", res, "err", rel(p, pref))
+    assert info["status"] == 0
+    assert res < 1e-10 * 1.01
+    assert abs(info["true_rel_residual"] - res) < 1e-3 * res + 1e-14
+    assert rel(p, pref) < 1e-8
+
+
+def test_mixed_spheres_small_levels():
+    """Union of 20 spheres, density ratio 1e4 (7430/0.743), eps = 1.5h, Q3: the
+    mixed solver reaches the FP64 solution at each small refinement level."""
+    for n in (6, 12):
+        wl = W.spheres_mixed(n=n, k=3)
+        m = wl.mesh
+        op = oracle.Operator(m, phi=wl.phi)
+        pstar = W.sine_field(m)
+        b = oracle.discrete_manufactured_rhs(op, m, pstar)
+        pref = spla.spsolve(op.to_scipy().tocsc(), b)
+        prob = _setup(m, wl.phi)
+        say("mixed spheres", n)
+        p, info = prob.cg_solve(dev(b), rtol=1e-8, precision="mixed")
+        p = host(p)
+        res = np.linalg.norm(b - op.matvec(p)) / np.linalg.norm(b)
+        print("spheres", n, info, "res", res, "err vs ref", rel(p, pref))
+        assert info["status"] == 0 and res < 1e-8 * 1.01
+        assert rel(p, pref) < 1e-5
+
+
+def test_warm_start_and_failures():
+    wl = W.small_droplet(n=6, k=2)
+    m = wl.mesh
+    prob = _setup(m, wl.phi)
+    b = dev(oracle.sine_load(m))
+    say("failures")
+    p, info = prob.cg_solve(b, rtol=1e-6)
+    assert info["status"] == 0
+    # warm start from the solution: converges at once relative to the new r0? No:
+    # the rule is relative to the initial residual, so it keeps iterating.
+    p2, info2 = prob.cg_solve(b, x0=p, rtol=1e-6)
+    assert info2["status"] == 0 and info2["iterations"] >= 1
+    # max_iter
+    _, info3 = prob.cg_solve(b, rtol=1e-14, max_iter=3, raise_on_failure=False)
+    assert info3["status"] == 5 and info3["iterations"] == 3
+    with pytest.raises(vpp.VppError) as e:
+        prob.cg_solve(b, rtol=1e-14, max_iter=3)
+    assert e.value.status == 5
+    # NaN right-hand side: breakdown, no hang
+    bn = b.clone()
+    bn[50] = float("nan")
+    _, info4 = prob.cg_solve(bn, rtol=1e-10, raise_on_failure=False)
+    assert info4["status"] == 6
+    # zero right-hand side: converged with zero iterations
+    x0, info5 = prob.cg_solve(torch.zeros_like(b), rtol=1e-10)
+    assert info5["iterations"] == 0 and float(x0.abs().max()) == 0.0
+    # absolute tolerance
+    _, info6 = prob.cg_solve(b, rtol=0.0, atol=1e300)
+    assert info6["iterations"] == 0
+
+
+def test_argument_errors():
+    wl = W.small_droplet(n=4, k=2)
+    m = wl.mesh
+    prob = vpp.Problem.from_mesh(m)
+    x = dev(np.zeros(m.ndofs))
+    say("errors")
+    with pytest.raises(vpp.VppError) as e:
+        prob.apply(x)                       # phi not set
+    assert e.value.status == 7
+    prob.set_phi(dev(wl.phi))
+    with pytest.raises(ValueError):
+        prob.apply(dev(np.zeros(m.ndofs + 1)))
+    with pytest.raises(vpp.VppError) as e:
+        prob.set_config(1, (3, 3, 3))       # not instantiated
+    assert e.value.status == 2
+    with pytest.raises(vpp.VppError) as e:
+        vpp.Problem((2, 2, 2), 2, rho_l=-1.0)
+    assert e.value.status == 1

@@ -152,3 +152,13 @@ def test_patch_exactness(k, n):
     X, Y, Z = m.node_grid()
     ref = sum(px(X) * py(Y) * pz(Z) for px, py, pz in terms).ravel()
     assert np.abs(p - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k,n,bc", [(2, (5, 4, 3), (0,) * 6), (3, (3, 2, 4), (0, 1, 0, 1, 1, 0)), (4, (2, 3, 2), NEU)])
+def test_apply_rows_match_matrix(k, n, bc):
+    m, phi = droplet_mesh(n, k, bc=bc)
+    op = oracle.Operator(m, phi=phi)
+    x = np.random.default_rng(9).uniform(-1, 1, m.ndofs)
+    y = op.matvec(x)
+    rows = np.arange(m.ndofs)
+    np.testing.assert_allclose(oracle.apply_rows(m, phi, x, rows), y, rtol=0, atol=1e-13 * np.abs(y).max())
