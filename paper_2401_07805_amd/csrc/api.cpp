@@ -108,6 +108,10 @@ struct vpp_problem_s {
     double* diag = nullptr;
     double* inv64 = nullptr;
     float* inv32 = nullptr;
+    double* part = nullptr;         // shared-face partials of the apply (sized for cfg)
+    size_t part_bytes = 0;
+    double* dot_part = nullptr;     // per-workgroup partial dot products
+    size_t dot_part_n = 0;
     bool phi_set = false;
     hipStream_t stream = nullptr;   // library stream for solves and graph capture
     CgWork w;
@@ -125,7 +129,8 @@ struct vpp_batch_s {
     BatchProblem* d_probs = nullptr;
     double** d_x = nullptr;
     double** d_y = nullptr;
-    int64_t* d_off = nullptr;
+    double* d_part = nullptr;
+    size_t part_n = 0;
     int* d_queue = nullptr;
     std::vector<const double*> cur_x;
     std::vector<double*> cur_y;
@@ -171,22 +176,46 @@ static MeshArgs make_mesh_args(const vpp_desc& d)
     return m;
 }
 
-static int hip_blocks(const vpp_problem p) { return tile_count(p->m); }
+// Scratch of the apply for the current configuration: the partial slots of
+// shared-face nodes (tiles x block nodes, FP64-sized so both precisions fit)
+// and one partial dot product per tile.
+static vpp_status ensure_apply_scratch(vpp_problem p)
+{
+    const size_t need = (size_t)std::max<int64_t>(1, 8 * shared_node_count(p->m)) * sizeof(double);
+    if (need > p->part_bytes) {
+        if (p->part) (void)hipFree(p->part);
+        p->part = nullptr;
+        p->part_bytes = 0;
+        vpp_status s = dev_alloc(&p->part, need / sizeof(double), "apply partials");
+        if (s) return s;
+        p->part_bytes = need;
+    }
+    const size_t nd = (size_t)tile_count(p->m);
+    if (nd > p->dot_part_n) {
+        if (p->dot_part) (void)hipFree(p->dot_part);
+        p->dot_part = nullptr;
+        p->dot_part_n = 0;
+        vpp_status s = dev_alloc(&p->dot_part, nd, "dot partials");
+        if (s) return s;
+        p->dot_part_n = nd;
+    }
+    return VPP_OK;
+}
 
-// y = A x on `s` (y zeroed first).
+// y = A x on `s`; with `dot`, also x . y (written by the assembly kernel).
 static vpp_status do_apply64(vpp_problem p, const double* x, double* y, double* dot, const int* done, hipStream_t s)
 {
-    VPP_HIP(launch_fill<double>(y, p->N, 0.0, s));
-    ApplyArgs<double> a{p->m, x, y, p->phi64, dot, done};
-    VPP_HIP(launch_apply_f64(p->cfg, p->k, a, hip_blocks(p), s));
+    ApplyArgs<double> a{p->m, x, y, p->phi64, p->part, shared_node_count(p->m), dot ? p->dot_part : nullptr, dot,
+                        done};
+    VPP_HIP(launch_apply_f64(p->cfg, p->k, a, s));
     return VPP_OK;
 }
 
 static vpp_status do_apply32(vpp_problem p, const float* x, float* y, double* dot, const int* done, hipStream_t s)
 {
-    VPP_HIP(launch_fill<float>(y, p->N, 0.0f, s));
-    ApplyArgs<float> a{p->m, x, y, p->phi32, dot, done};
-    VPP_HIP(launch_apply_f32(p->cfg, p->k, a, hip_blocks(p), s));
+    ApplyArgs<float> a{p->m, x, y, p->phi32, reinterpret_cast<float*>(p->part), shared_node_count(p->m),
+                       dot ? p->dot_part : nullptr, dot, done};
+    VPP_HIP(launch_apply_f32(p->cfg, p->k, a, s));
     return VPP_OK;
 }
 
@@ -243,13 +272,15 @@ static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
     for (int it = 0; it < iters && err == hipSuccess; ++it) {
         const int par = it & 1;
         if constexpr (sizeof(T) == 8) {
-            ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, &w.st->pAp, &w.st->done};
-            err = launch_apply_f64(p->cfg, p->k, a, hip_blocks(p), s);
+            ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, p->part, shared_node_count(p->m), p->dot_part,
+                                &w.st->pAp, &w.st->done};
+            err = launch_apply_f64(p->cfg, p->k, a, s);
             if (err == hipSuccess) err = launch_cg_update<double>(w.st, par, w.x, w.r, w.p, w.q, p->inv64, p->N, s);
             if (err == hipSuccess) err = launch_cg_pupdate<double>(w.st, par, w.r, w.p, w.q, p->inv64, p->N, s);
         } else {
-            ApplyArgs<float> a{p->m, w.p32, w.q32, p->phi32, &w.st32->pAp, &w.st32->done};
-            err = launch_apply_f32(p->cfg, p->k, a, hip_blocks(p), s);
+            ApplyArgs<float> a{p->m, w.p32, w.q32, p->phi32, reinterpret_cast<float*>(p->part),
+                               shared_node_count(p->m), p->dot_part, &w.st32->pAp, &w.st32->done};
+            err = launch_apply_f32(p->cfg, p->k, a, s);
             if (err == hipSuccess)
                 err = launch_cg_update<float>(w.st32, par, w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
             if (err == hipSuccess)
@@ -337,7 +368,6 @@ static vpp_status pcg64(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& info, 
     init.max_iter = o.max_iter;
     *hs = init;
     VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
-    VPP_HIP(launch_fill<double>(w.q, p->N, 0.0, s));
     if ((st = run_until_done(p, w.g64, w.st, hs, o.max_iter))) return st;
     info.iterations = hs->iters;
     info.rel_residual = std::sqrt(hs->rr_last) / r0;
@@ -401,7 +431,6 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
         VPP_HIP(hipMemcpyAsync(w.st32, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
         // zero initial guess: r = b, p = D^-1 b; rz[0] is accumulated on the device
         VPP_HIP(launch_cg_init<float>(w.st32, w.r32, nullptr, w.r32, w.p32, p->inv32, p->N, s));
-        VPP_HIP(launch_fill<float>(w.q32, p->N, 0.0f, s));
         if ((st = run_until_done(p, w.g32, w.st32, hs, inner_cap))) return st;
         total += hs->iters;
         VPP_HIP(launch_promote_add(w.x, w.x32, rn, p->N, s));
@@ -549,8 +578,8 @@ vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
     const int64_t k = d->degree;
     const int64_t N = (k * d->ncells[0] + 1) * (k * d->ncells[1] + 1) * (k * d->ncells[2] + 1);
     const int64_t ncell = (int64_t)d->ncells[0] * d->ncells[1] * d->ncells[2];
-    if (N > (int64_t)1 << 40 || ncell > (int64_t)INT32_MAX / 2)
-        return fail(VPP_ERR_INVALID_ARG, "mesh too large");
+    if (N > (int64_t)INT32_MAX || ncell > (int64_t)INT32_MAX / 2)
+        return fail(VPP_ERR_INVALID_ARG, "mesh too large (at most 2^31-1 nodes)");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -574,6 +603,10 @@ vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
         vpp_destroy(p);
         return s;
     }
+    if ((s = ensure_apply_scratch(p))) {
+        vpp_destroy(p);
+        return s;
+    }
     if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
         vpp_destroy(p);
         return fail(VPP_ERR_HIP, "hipStreamCreate failed");
@@ -589,6 +622,7 @@ vpp_status vpp_destroy(vpp_problem p)
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     free_work(p->w);
     dev_free(p->phi64); dev_free(p->phi32); dev_free(p->diag); dev_free(p->inv64); dev_free(p->inv32);
+    dev_free(p->part); dev_free(p->dot_part);
     if (p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
     return VPP_OK;
@@ -702,9 +736,11 @@ vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg)
     if (!p || !cfg) return fail(VPP_ERR_INVALID_ARG, "null argument");
     LaunchCfg c{cfg->variant, {cfg->tile[0], cfg->tile[1], cfg->tile[2]}};
     if (!apply_config_supported(c, p->k)) return fail(VPP_ERR_UNSUPPORTED, "kernel configuration not available");
+    DeviceGuard dg(p->desc.device);
+    if (p->stream) VPP_HIP(hipStreamSynchronize(p->stream));
     p->cfg = c;
     set_tiles(p->m, c);
-    return VPP_OK;
+    return ensure_apply_scratch(p);
 }
 
 int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap)
@@ -728,7 +764,7 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
     if (cache_lookup(cache_path, key, &c) && apply_config_supported(c, p->k)) {
         p->cfg = c;
         set_tiles(p->m, c);
-        return VPP_OK;
+        return ensure_apply_scratch(p);
     }
     VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
     vpp_status st;
@@ -747,6 +783,7 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
     for (int i = 0; i < n; ++i) {
         p->cfg = cands[i];
         set_tiles(p->m, cands[i]);
+        if ((st = ensure_apply_scratch(p))) break;
         if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) break;
         VPP_HIP(hipEventRecord(e0, s));
         for (int r = 0; r < reps; ++r)
@@ -767,7 +804,7 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
     set_tiles(p->m, best_cfg);
     if (st) return st;
     cache_store(cache_path, key, best_cfg, best);
-    return VPP_OK;
+    return ensure_apply_scratch(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +814,7 @@ static vpp_status batch_build_table(vpp_batch b)
 {
     std::vector<BatchProblem> tab(b->probs.size());
     int item = 0, rhs = 0;
+    int64_t part = 0;
     for (size_t i = 0; i < b->probs.size(); ++i) {
         MeshArgs m = b->probs[i]->m;
         set_tiles(m, b->cfg);
@@ -785,10 +823,20 @@ static vpp_status batch_build_table(vpp_batch b)
         tab[i].tile_begin = item;
         tab[i].nrhs = b->nrhs[i];
         tab[i].rhs_begin = rhs;
+        tab[i].part_begin = part;
+        tab[i].nshared = shared_node_count(m);
         item += tile_count(m);
         rhs += b->nrhs[i];
+        part += 8 * std::max<int64_t>(1, tab[i].nshared) * b->nrhs[i];
     }
     b->nitems = item;
+    if ((size_t)part > b->part_n) {
+        dev_free(b->d_part);
+        b->part_n = 0;
+        vpp_status st = dev_alloc(&b->d_part, (size_t)part, "batch partials");
+        if (st) return st;
+        b->part_n = (size_t)part;
+    }
     VPP_HIP(hipMemcpy(b->d_probs, tab.data(), tab.size() * sizeof(BatchProblem), hipMemcpyHostToDevice));
     int per_cu = batch_blocks_per_cu(b->cfg, b->k);
     if (per_cu < 1) per_cu = 1;
@@ -804,10 +852,9 @@ static vpp_status batch_build_graph(vpp_batch b)
     b->graph = nullptr;
     hipGraph_t g = nullptr;
     VPP_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    MultiFillArgs fa{b->d_y, b->d_off, b->total_rhs, b->d_queue};
-    hipError_t err = launch_multi_zero(fa, b->stream);
-    BatchArgs ba{b->d_probs, (int)b->probs.size(), b->nitems, b->d_x, b->d_y, b->d_queue};
-    if (err == hipSuccess) err = launch_batch_apply(b->cfg, b->k, ba, b->nblocks, b->stream);
+    BatchArgs ba{b->d_probs, (int)b->probs.size(), b->nitems, b->d_x, b->d_y, b->d_part, b->d_queue,
+                 b->probs[0]->desc.heaviside};
+    hipError_t err = launch_batch_apply(b->cfg, b->k, ba, b->nblocks, b->total_rhs, b->stream);
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (err != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -912,6 +959,8 @@ vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32
         if (!probs[i]) return fail(VPP_ERR_INVALID_ARG, "null problem");
         if (probs[i]->k != k) return fail(VPP_ERR_UNSUPPORTED, "all problems of a batch must share the degree");
         if (probs[i]->desc.device != dev) return fail(VPP_ERR_UNSUPPORTED, "all problems must be on one device");
+        if (probs[i]->desc.heaviside != probs[0]->desc.heaviside)
+            return fail(VPP_ERR_UNSUPPORTED, "all problems of a batch must share the Heaviside law");
         if (!probs[i]->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called for every problem");
         if (nrhs[i] < 1) return fail(VPP_ERR_INVALID_ARG, "nrhs must be >= 1");
     }
@@ -922,21 +971,19 @@ vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32
     b->k = k;
     b->probs.assign(probs, probs + nprob);
     b->nrhs.assign(nrhs, nrhs + nprob);
-    std::vector<int64_t> off(1, 0);
     for (int i = 0; i < nprob; ++i) {
         b->total_rhs += nrhs[i];
         b->total_dofs += probs[i]->N * nrhs[i];
-        for (int j = 0; j < nrhs[i]; ++j) off.push_back(off.back() + probs[i]->N);
     }
     b->cfg = LaunchCfg{0, {8, 4, 4}};
     vpp_status st;
     if ((st = dev_alloc(&b->d_probs, nprob, "batch table")) || (st = dev_alloc(&b->d_x, b->total_rhs, "batch x")) ||
-        (st = dev_alloc(&b->d_y, b->total_rhs, "batch y")) || (st = dev_alloc(&b->d_off, off.size(), "batch off")) ||
-        (st = dev_alloc(&b->d_queue, 1, "batch queue"))) {
+        (st = dev_alloc(&b->d_y, b->total_rhs, "batch y")) || (st = dev_alloc(&b->d_queue, 1, "batch queue"))) {
         vpp_batch_destroy(b);
         return st;
     }
-    if (hipMemcpy(b->d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+    // the work counter starts at zero; the assembly launch resets it after every pass
+    if (hipMemset(b->d_queue, 0, sizeof(int)) != hipSuccess ||
         hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
         vpp_batch_destroy(b);
         return fail(VPP_ERR_HIP, "batch set-up failed");
@@ -1004,7 +1051,7 @@ vpp_status vpp_batch_destroy(vpp_batch b)
     DeviceGuard dg(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    dev_free(b->d_probs); dev_free(b->d_x); dev_free(b->d_y); dev_free(b->d_off); dev_free(b->d_queue);
+    dev_free(b->d_probs); dev_free(b->d_x); dev_free(b->d_y); dev_free(b->d_part); dev_free(b->d_queue);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return VPP_OK;

@@ -3,9 +3,9 @@
 
 namespace vpp {
 
-hipError_t launch_apply_f32(const LaunchCfg& c, int k, const ApplyArgs<float>& a, int nblocks, hipStream_t s)
+hipError_t launch_apply_f32(const LaunchCfg& c, int k, const ApplyArgs<float>& a, hipStream_t s)
 {
-    return launch_apply_t<float>(c, k, a, nblocks, s);
+    return launch_apply_t<float>(c, k, a, s);
 }
 
 }  // namespace vpp

@@ -3,9 +3,9 @@
 
 namespace vpp {
 
-hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& a, int nblocks, hipStream_t s)
+hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& a, hipStream_t s)
 {
-    return launch_apply_t<double>(c, k, a, nblocks, s);
+    return launch_apply_t<double>(c, k, a, s);
 }
 
 bool apply_config_supported(const LaunchCfg& c, int k)

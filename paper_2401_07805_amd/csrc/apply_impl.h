@@ -16,6 +16,7 @@
 // those entries of x at the gather.
 #pragma once
 #include "kernels.h"
+#include "shared_nodes.h"
 
 namespace vpp {
 
@@ -65,7 +66,7 @@ __device__ __forceinline__ void gather_cell(const MeshArgs& m, const S* __restri
 }
 
 // Scaled coefficient factor cw_q = c'(phi_h(x_q)) wref_q of a cell from nodal phi.
-template <int K, typename T>
+template <int K, int HV, typename T>
 __device__ __forceinline__ void cell_coefficient(const MeshArgs& m, const T* __restrict__ phi, int cx,
                                                  int cy, int cz, T (&cw)[(K + 1) * (K + 1) * (K + 1)])
 {
@@ -73,7 +74,7 @@ __device__ __forceinline__ void cell_coefficient(const MeshArgs& m, const T* __r
     sweep3<K, MS, false, 0>(cw);
     sweep3<K, MS, false, 1>(cw);
     sweep3<K, MS, false, 2>(cw);
-    coef_weights3<K>(m, cw);
+    coef_weights3<K, HV>(m, cw);
 }
 
 // Cell operator on registers: u (nodal values, Dirichlet entries zeroed) is
@@ -90,7 +91,8 @@ __device__ __forceinline__ void cell_operator(const MeshArgs& m, const T (&cw)[(
     sweep3<K, MS, false, 1>(u);
     sweep3<K, MS, false, 2>(u);
     T v[N3];
-    const T r0 = T(m.rd[0]), r1 = T(m.rd[1]), r2 = T(m.rd[2]);
+    // rd[0] is 1 by construction (the x spacing is the reference length)
+    const T r1 = T(m.rd[1]), r2 = T(m.rd[2]);
 #pragma unroll
     for (int i2 = 0; i2 < N; ++i2)
 #pragma unroll
@@ -100,7 +102,7 @@ __device__ __forceinline__ void cell_operator(const MeshArgs& m, const T (&cw)[(
             for (int a = 0; a < N; ++a) in[a] = u[a + N * (i1 + N * i2)];
             line<K, MDC, false>(in, g);
 #pragma unroll
-            for (int a = 0; a < N; ++a) g[a] *= cw[a + N * (i1 + N * i2)] * r0;
+            for (int a = 0; a < N; ++a) g[a] *= cw[a + N * (i1 + N * i2)];
             line<K, MDC, true>(g, o);
 #pragma unroll
             for (int a = 0; a < N; ++a) v[a + N * (i1 + N * i2)] = o[a];
@@ -169,48 +171,15 @@ __device__ __forceinline__ TileCoord tile_coord(const MeshArgs& m, int tile)
     return c;
 }
 
-// y from the LDS block yb (BX x BY x BZ, x fastest).  A node on the lower face
-// of a tile (with a tile below) belongs to the lower tile; a node of a Dirichlet
-// face is written (y = x) by the tile it belongs to.  Returns this thread's
-// share of x . y restricted to the tile's contributions.
-template <typename T, int BX, int BY, int BZ, int NT>
-__device__ __forceinline__ double flush_block(const MeshArgs& m, const TileCoord& tc, const T* yb,
-                                              const T* __restrict__ x, T* __restrict__ y, bool dot)
-{
-    double dsum = 0.0;
-    for (int idx = threadIdx.x; idx < BX * BY * BZ; idx += NT) {
-        const int li = idx % BX, lj = (idx / BX) % BY, ll = idx / (BX * BY);
-        if (li >= tc.ext[0] || lj >= tc.ext[1] || ll >= tc.ext[2]) continue;
-        const int gi = tc.n0[0] + li, gj = tc.n0[1] + lj, gl = tc.n0[2] + ll;
-        const int64_t g = node_index(m, gi, gj, gl);
-        const bool lo = (li == 0 && tc.t[0] > 0) || (lj == 0 && tc.t[1] > 0) || (ll == 0 && tc.t[2] > 0);
-        if (is_dirichlet(m, gi, gj, gl)) {
-            if (!lo) {
-                const T xv = x[g];
-                y[g] = xv;
-                if (dot) dsum += (double)xv * (double)xv;
-            }
-            continue;
-        }
-        const T v = yb[idx];
-        const bool hi = (li == tc.ext[0] - 1 && tc.t[0] < m.ntile[0] - 1) ||
-                        (lj == tc.ext[1] - 1 && tc.t[1] < m.ntile[1] - 1) ||
-                        (ll == tc.ext[2] - 1 && tc.t[2] < m.ntile[2] - 1);
-        if (lo || hi) atomicAdd(&y[g], v);
-        else y[g] = v;
-        if (dot) dsum += (double)x[g] * (double)v;
-    }
-    return dsum;
-}
-
-// Workgroup sum of one double per thread (LDS tree, valid for any NT including
-// partial waves), added atomically to *out by thread 0.
+// Workgroup sum of one double per thread (LDS tree in a fixed order, valid for
+// any NT including partial waves); the result is returned to thread 0.
 template <int NT>
-__device__ __forceinline__ void block_sum_atomic(double v, double* out)
+__device__ __forceinline__ double block_sum(double v)
 {
-    constexpr int P = NT <= 1 ? 1 : (NT <= 64 ? 64 : (NT <= 128 ? 128 : (NT <= 256 ? 256 : (NT <= 512 ? 512 : 1024))));
+    constexpr int P = NT <= 64 ? 64 : (NT <= 128 ? 128 : (NT <= 256 ? 256 : (NT <= 512 ? 512 : 1024)));
     static_assert(NT <= 1024, "workgroup too large");
     __shared__ double red[P];
+    __syncthreads();
     red[threadIdx.x] = v;
     for (int i = NT + threadIdx.x; i < P; i += NT) red[i] = 0.0;
     __syncthreads();
@@ -219,13 +188,99 @@ __device__ __forceinline__ void block_sum_atomic(double v, double* out)
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+    return red[0];
+}
+
+// Write-out by cell ownership: a cell writes the nodes of its block with local
+// index a_d in [0, K-1] along each direction, and also a_d = K when it is the
+// last cell of the tile along d; every node of the tile block then has exactly
+// one writer and all offsets are compile-time except the cell base.
+//  - a node only this tile touches: y[g] = value;
+//  - a node on a face shared with neighbouring tiles: this tile's partial value
+//    goes to part[rank * nshared + f], where f is the node's position in the
+//    enumeration of shared nodes (z planes, then y planes, then x planes; see
+//    shared_nodes.h) and rank orders the 2, 4 or 8 tiles holding it (lower tile
+//    first along each shared direction); the assembly kernel sums them;
+//  - a node of a Dirichlet face: y[g] = x[g] (identity row), written by the
+//    lowest-index tile that holds it.
+// Both f and the rank follow from the tile coordinates and the face flags, with
+// no division.  A0 restricts the x index to one plane (plane-per-thread
+// kernels); -1 = all.  Returns this thread's share of x . (A x).
+template <int K, typename T, int TX, int TY, int TZ>
+__device__ __forceinline__ double flush_owned(const MeshArgs& m, const TileCoord& tc, const T* yb, int lx, int ly,
+                                              int lz, int cx, int cy, int cz, int a0_only,
+                                              const T* __restrict__ x, T* __restrict__ y, T* __restrict__ part,
+                                              int64_t nshared, bool dot)
+{
+    constexpr int BX = K * TX + 1, BY = K * TY + 1;
+    const int faces = cell_dirichlet_faces(m, cx, cy, cz);
+    const bool last[3] = {K * (lx + 1) == tc.ext[0] - 1, K * (ly + 1) == tc.ext[1] - 1, K * (lz + 1) == tc.ext[2] - 1};
+    const bool has_lo[3] = {lx == 0 && tc.t[0] > 0, ly == 0 && tc.t[1] > 0, lz == 0 && tc.t[2] > 0};
+    const bool has_hi[3] = {last[0] && tc.t[0] < m.ntile[0] - 1, last[1] && tc.t[1] < m.ntile[1] - 1,
+                            last[2] && tc.t[2] < m.ntile[2] - 1};
+    const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
+    const int i0 = K * cx, j0 = K * cy, l0 = K * cz;
+    const int64_t gbase = node_index(m, i0, j0, l0);
+    const int lbase = K * lx + BX * (K * ly + BY * K * lz);
+    double dsum = 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 <= K; ++a2) {
+        if (a2 == K && !last[2]) continue;
+#pragma unroll
+        for (int a1 = 0; a1 <= K; ++a1) {
+            if (a1 == K && !last[1]) continue;
+#pragma unroll
+            for (int a0 = 0; a0 <= K; ++a0) {
+                if (a0_only >= 0 && a0 != a0_only) continue;
+                if (a0 == K && !last[0]) continue;
+                const int64_t g = gbase + a0 + nx * a1 + nxy * a2;
+                const bool lo0 = a0 == 0 && has_lo[0], lo1 = a1 == 0 && has_lo[1], lo2 = a2 == 0 && has_lo[2];
+                const bool hi0 = a0 == K && has_hi[0], hi1 = a1 == K && has_hi[1], hi2 = a2 == K && has_hi[2];
+                const bool lo = lo0 || lo1 || lo2;
+                if (faces && local_dirichlet<K>(faces, a0, a1, a2)) {
+                    if (!lo) {
+                        const T xv = x[g];
+                        y[g] = xv;
+                        if (dot) dsum += (double)xv * (double)xv;
+                    }
+                    continue;
+                }
+                const T v = yb[lbase + a0 + BX * (a1 + BY * a2)];
+                const bool s0 = lo0 || hi0, s1 = lo1 || hi1, s2 = lo2 || hi2;
+                if (s0 || s1 || s2) {
+                    int64_t f;
+                    int rank;
+                    shared_from_tile(m, tc.t, lo0, lo1, lo2, hi0, hi1, hi2, i0 + a0, j0 + a1, l0 + a2, f, rank);
+                    part[rank * nshared + f] = v;
+                } else {
+                    y[g] = v;
+                }
+                if (dot) dsum += (double)x[g] * (double)v;
+            }
+        }
+    }
+    return dsum;
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void scatter_cell_lds(T* yb, int BX, int BY, int lx, int ly, int lz,
+                                                 const T (&u)[(K + 1) * (K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1;
+#pragma unroll
+    for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0)
+                atomicAdd(&yb[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))], u[a0 + N * (a1 + N * a2)]);
 }
 
 // ---------------------------------------------------------------------------
-// Variant 0: one cell per thread.
+// Variant 0: one cell per thread, operands gathered straight from global memory,
+// one tile per workgroup.
 
-template <int K, typename T, int TX, int TY, int TZ>
+template <int K, typename T, int TX, int TY, int TZ, int HV>
 __global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a)
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
@@ -233,28 +288,175 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a
     __shared__ T yb[BX * BY * BZ];
     if (a.done && *a.done) return;
     const MeshArgs& m = a.m;
-    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, xcd_tile(blockIdx.x, gridDim.x));
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
     for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
     __syncthreads();
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
     if (cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2]) {
         T cw[N3], u[N3];
-        cell_coefficient<K>(m, a.phi, cx, cy, cz, cw);
+        cell_coefficient<K, HV>(m, a.phi, cx, cy, cz, cw);
         gather_cell<K>(m, a.x, cx, cy, cz, cell_dirichlet_faces(m, cx, cy, cz), u);
         cell_operator<K>(m, cw, u);
-#pragma unroll
-        for (int a2 = 0; a2 < N; ++a2)
-#pragma unroll
-            for (int a1 = 0; a1 < N; ++a1)
-#pragma unroll
-                for (int a0 = 0; a0 < N; ++a0)
-                    atomicAdd(&yb[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))],
-                              u[a0 + N * (a1 + N * a2)]);
+        scatter_cell_lds<K>(yb, BX, BY, lx, ly, lz, u);
     }
     __syncthreads();
-    const double d = flush_block<T, BX, BY, BZ, NT>(m, tc, yb, a.x, a.y, a.dot != nullptr);
-    if (a.dot) block_sum_atomic<NT>(d, a.dot);
+    double d = 0.0;
+    if (cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2])
+        d = flush_owned<K, T, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, -1, a.x, a.y, a.part, a.nshared,
+                                          a.dot_part != nullptr);
+    if (a.dot_part) {
+        const double s = block_sum<NT>(d);
+        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Variant 2: one cell per thread in a persistent workgroup that walks its tiles
+// in order.  The x and phi node blocks of a tile are staged into LDS by
+// global->LDS DMA (global_load_lds, 4 bytes per lane, coalesced along x rows);
+// the blocks of the next tile are requested as soon as the current ones have
+// been read into registers, so the loads overlap the arithmetic.
+
+// Rows of the block (fixed lj, ll) are contiguous in global memory: a wave
+// instruction moves R = 64 / (BX * DW) whole rows (lanes past R rows idle), so
+// a lane's offset inside its row group is fixed for the whole kernel and the
+// row bases are wave-uniform.  Rows of a ragged tile beyond the mesh are
+// clamped onto the last valid row/column (their values are never used).
+template <typename T, int BX, int BY, int BZ>
+struct RowStage {
+    static constexpr int DW = (int)(sizeof(T) / 4);
+    static constexpr int RW = BX * DW;                 // dwords per row
+    static constexpr int R = RW <= 64 ? 64 / RW : 1;   // rows per wave instruction
+    static constexpr int CHUNKS = (RW + 63) / 64;      // instructions per row when RW > 64
+    static constexpr int ROWS = BY * BZ;
+    static constexpr int GROUPS = (ROWS + R - 1) / R;
+    // LDS footprint in dwords: every instruction writes a whole 64-dword line
+    static constexpr int LDS_DW = (GROUPS - 1) * R * RW + (CHUNKS * 64 > R * RW ? CHUNKS * 64 : R * RW) + 64;
+};
+
+template <typename T, int BX, int BY, int BZ, int NT>
+__device__ __forceinline__ void stage_block(const MeshArgs& m, const TileCoord& tc, const T* __restrict__ g,
+                                            T* lds)
+{
+    using RS = RowStage<T, BX, BY, BZ>;
+    static_assert(NT % 64 == 0, "staging needs whole waves");
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int rsub = lane / RS::RW;                      // row inside the group (R > 1)
+    const int dw = lane - rsub * RS::RW;                 // dword inside the row
+    const int xi = min(dw / RS::DW, tc.ext[0] - 1);      // clamp columns of a ragged tile
+    const int part = dw % RS::DW;
+    const unsigned* gw = reinterpret_cast<const unsigned*>(g);
+    const int64_t tile0 = node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]);
+    unsigned* l32 = reinterpret_cast<unsigned*>(lds);
+    if constexpr (RS::CHUNKS == 1) {
+        for (int grp = wave; grp < RS::GROUPS; grp += NT / 64) {
+            const int row = grp * RS::R + rsub;
+            const int rr = row < RS::ROWS ? row : RS::ROWS - 1;
+            const int lj = min(rr % BY, tc.ext[1] - 1), ll = min(rr / BY, tc.ext[2] - 1);
+            const int64_t gi = tile0 + xi + (int64_t)m.nn[0] * (lj + (int64_t)m.nn[1] * ll);
+            if (rsub < RS::R)
+                __builtin_amdgcn_global_load_lds(
+                    (const void __attribute__((address_space(1)))*)(gw + gi * RS::DW + part),
+                    (void __attribute__((address_space(3)))*)(l32 + grp * RS::R * RS::RW), 4, 0, 0);
+        }
+    } else {
+        for (int it = wave; it < RS::ROWS * RS::CHUNKS; it += NT / 64) {
+            const int row = it / RS::CHUNKS, c = it % RS::CHUNKS;
+            const int d = c * 64 + lane;
+            const int xc = min(min(d, RS::RW - 1) / RS::DW, tc.ext[0] - 1);
+            const int pc = d % RS::DW;
+            const int lj = min(row % BY, tc.ext[1] - 1), ll = min(row / BY, tc.ext[2] - 1);
+            const int64_t gi = tile0 + xc + (int64_t)m.nn[0] * (lj + (int64_t)m.nn[1] * ll);
+            if (d < RS::RW)
+                __builtin_amdgcn_global_load_lds(
+                (const void __attribute__((address_space(1)))*)(gw + gi * RS::DW + pc),
+                (void __attribute__((address_space(3)))*)(l32 + row * RS::RW + c * 64), 4, 0, 0);
+        }
+    }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void read_cell_lds(const T* lds, int BX, int BY, int lx, int ly, int lz, int faces,
+                                              T (&u)[(K + 1) * (K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1;
+#pragma unroll
+    for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0) {
+                T v = lds[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))];
+                if (faces && local_dirichlet<K>(faces, a0, a1, a2)) v = T(0);
+                u[a0 + N * (a1 + N * a2)] = v;
+            }
+}
+
+template <int K, typename T, int TX, int TY, int TZ, int HV>
+__global__ void __launch_bounds__(TX * TY * TZ) apply_stream_kernel(ApplyArgs<T> a)
+{
+    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
+    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
+    constexpr int PAD = RowStage<T, BX, BY, BZ>::LDS_DW * 4 / (int)sizeof(T);
+    __shared__ T sx[PAD];
+    __shared__ T sp[PAD];
+    __shared__ T yb[BX * BY * BZ];
+    if (a.done && *a.done) return;
+    const MeshArgs& m = a.m;
+    const int ntiles = m.ntile[0] * m.ntile[1] * m.ntile[2];
+    const int G = gridDim.x;
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
+    int v = blockIdx.x;
+    int tile = v < ntiles ? xcd_tile(v, ntiles) : 0;
+    TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
+    if (v < ntiles) {
+        stage_block<T, BX, BY, BZ, NT>(m, tc, a.x, sx);
+        stage_block<T, BX, BY, BZ, NT>(m, tc, a.phi, sp);
+    }
+    double dsum = 0.0;
+    while (v < ntiles) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
+        const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+        T cw[N3], u[N3];
+        if (active) {
+            read_cell_lds<K>(sp, BX, BY, lx, ly, lz, 0, cw);
+            read_cell_lds<K>(sx, BX, BY, lx, ly, lz, cell_dirichlet_faces(m, cx, cy, cz), u);
+        }
+        __syncthreads();
+        const int vn = v + G;
+        const int tile_n = vn < ntiles ? xcd_tile(vn, ntiles) : 0;
+        const TileCoord tcn = tile_coord<K, TX, TY, TZ>(m, tile_n);
+        if (vn < ntiles) {
+            stage_block<T, BX, BY, BZ, NT>(m, tcn, a.x, sx);
+            stage_block<T, BX, BY, BZ, NT>(m, tcn, a.phi, sp);
+        }
+        if (active) {
+            sweep3<K, MS, false, 0>(cw);
+            sweep3<K, MS, false, 1>(cw);
+            sweep3<K, MS, false, 2>(cw);
+            coef_weights3<K, HV>(m, cw);
+            cell_operator<K>(m, cw, u);
+            scatter_cell_lds<K>(yb, BX, BY, lx, ly, lz, u);
+        }
+        __syncthreads();
+        if (active)
+            dsum += flush_owned<K, T, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, -1, a.x, a.y, a.part,
+                                                  a.nshared, a.dot_part != nullptr);
+        __syncthreads();
+        for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
+        v = vn;
+        tile = tile_n;
+        tc = tcn;
+    }
+    if (a.dot_part) {
+        const double s = block_sum<NT>(dsum);
+        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -271,7 +473,7 @@ __device__ __forceinline__ double pick(int r, int i)
     return v;
 }
 
-template <int K, typename T, int TX, int TY, int TZ>
+template <int K, typename T, int TX, int TY, int TZ, int HV>
 __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(ApplyArgs<T> a)
 {
     constexpr int N = K + 1, N2 = N * N, NC = TX * TY * TZ, NT = N * NC;
@@ -281,7 +483,8 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     __shared__ T xb[2 * NC * CS];
     if (a.done && *a.done) return;
     const MeshArgs& m = a.m;
-    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, xcd_tile(blockIdx.x, gridDim.x));
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
     for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
     const int cell = threadIdx.x / N, ip = threadIdx.x % N;
     const int lx = cell % TX, ly = (cell / TX) % TY, lz = cell / (TX * TY);
@@ -325,18 +528,9 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
             for (int i = 1; i < N; ++i) s = fma(rS[i], X1[i * N2 + q], s);
             cw[q] = s;
         }
-        if (m.heaviside == 0) {
-            const T ca = T(m.ca), cb = T(m.cb);
 #pragma unroll
-            for (int q = 0; q < N2; ++q)
-                cw[q] = fma(cb, clamp1(cw[q]), ca) * (wx * T(Tab<K>::t.w[q % N] * Tab<K>::t.w[q / N]));
-        } else {
-            const T cg = T(m.cg), cd = T(m.cd);
-#pragma unroll
-            for (int q = 0; q < N2; ++q)
-                cw[q] = fma(cd, sine_ramp(clamp1(cw[q])), cg) *
-                        (wx * T(Tab<K>::t.w[q % N] * Tab<K>::t.w[q / N]));
-        }
+        for (int q = 0; q < N2; ++q)
+            cw[q] = coef_scaled<HV>(m, cw[q]) * (wx * T(Tab<K>::t.w[q % N] * Tab<K>::t.w[q / N]));
     }
     __syncthreads();
 
@@ -380,10 +574,10 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
         for (int q = 0; q < N2; ++q) gy[q] = uq[q];
         sweep2<K, MDC, false, 0>(gy);
         sweep2<K, MDC, false, 1>(uq);     // uq now holds the z derivative
-        const T r0 = T(m.rd[0]), r1 = T(m.rd[1]), r2 = T(m.rd[2]);
+        const T r1 = T(m.rd[1]), r2 = T(m.rd[2]);
 #pragma unroll
         for (int q = 0; q < N2; ++q) {
-            gx[q] *= cw[q] * r0;
+            gx[q] *= cw[q];
             gy[q] *= cw[q] * r1;
             uq[q] *= cw[q] * r2;
         }
@@ -418,8 +612,14 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
                 atomicAdd(&yb[(K * lx + ip) + BX * ((K * ly + j) + BY * (K * lz + l))], o[j + N * l]);
     }
     __syncthreads();
-    const double d = flush_block<T, BX, BY, BZ, NT>(m, tc, yb, a.x, a.y, a.dot != nullptr);
-    if (a.dot) block_sum_atomic<NT>(d, a.dot);
+    double d = 0.0;
+    if (active)
+        d = flush_owned<K, T, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, ip, a.x, a.y, a.part, a.nshared,
+                                          a.dot_part != nullptr);
+    if (a.dot_part) {
+        const double s = block_sum<NT>(d);
+        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+    }
 }
 
 }  // namespace vpp

@@ -1,5 +1,6 @@
 // Diagonal, fill and batched kernels and their launchers.
 #include "apply_impl.h"
+#include "shared_nodes.h"
 
 namespace vpp {
 
@@ -7,7 +8,7 @@ namespace vpp {
 // Diagonal: diag_a = sum_q cw_q sum_d rd[d] (dN_a/dxi_d (x_q))^2, from squared
 // 1D tables (each term is a product of three 1D factors).  Runs once per phi.
 
-template <int K>
+template <int K, int HV>
 __global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __restrict__ phi,
                                                    double* __restrict__ diag)
 {
@@ -18,7 +19,7 @@ __global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __re
     const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
               cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
     double A[N3], Z[N3], Y[N3], out[N3];
-    cell_coefficient<K>(m, phi, cx, cy, cz, A);
+    cell_coefficient<K, HV>(m, phi, cx, cy, cz, A);
 #pragma unroll
     for (int q = 0; q < N3; ++q) Z[q] = A[q];
     sweep3<K, MS2, true, 2>(Z);
@@ -94,12 +95,16 @@ hipError_t launch_diag(int k, const MeshArgs& m, const double* phi, double* diag
 {
     const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
     const int blocks = (int)((ncell + 63) / 64);
+#define VPP_DIAG(K)                                                                              \
+    if (m.heaviside == 0) hipLaunchKernelGGL((diag_kernel<K, 0>), dim3(blocks), dim3(64), 0, s, m, phi, diag); \
+    else hipLaunchKernelGGL((diag_kernel<K, 1>), dim3(blocks), dim3(64), 0, s, m, phi, diag);
     switch (k) {
-    case 2: hipLaunchKernelGGL(diag_kernel<2>, dim3(blocks), dim3(64), 0, s, m, phi, diag); break;
-    case 3: hipLaunchKernelGGL(diag_kernel<3>, dim3(blocks), dim3(64), 0, s, m, phi, diag); break;
-    case 4: hipLaunchKernelGGL(diag_kernel<4>, dim3(blocks), dim3(64), 0, s, m, phi, diag); break;
+    case 2: VPP_DIAG(2) break;
+    case 3: VPP_DIAG(3) break;
+    case 4: VPP_DIAG(4) break;
     default: return hipErrorInvalidValue;
     }
+#undef VPP_DIAG
     return hipGetLastError();
 }
 
@@ -113,13 +118,76 @@ hipError_t launch_fix_diagonal(const MeshArgs& m, double* diag, double* inv64, f
 }
 
 // ---------------------------------------------------------------------------
+// Assembly of shared-face nodes.  A node lies in one or two tiles along each
+// direction (two when it sits on an interior tile boundary); its value is the
+// sum of the partial slots of all tiles holding it, taken in a fixed order
+// (z, y, x tile index ascending), so the result is deterministic.
+
+// Shared nodes, streamed in the order of their enumeration f: the value is the
+// sum of the partials the 2, 4 or 8 tiles holding the node wrote to
+// part[rank * nshared + f], taken in rank order (so the result is deterministic).
+template <typename T>
+__global__ void __launch_bounds__(256) assemble_kernel(AssembleArgs<T> a)
+{
+    if (a.done && *a.done) return;
+    if (a.dot && blockIdx.x == 0) {
+        // x . y from the per-workgroup partials, summed in a fixed order
+        __shared__ double red[256];
+        double s = 0.0;
+        for (int i = threadIdx.x; i < a.ndot; i += 256) s += a.dot_part[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *a.dot = red[0];
+    }
+    const SharedEnum e = shared_enum(a.m, a.k, a.tile);
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < a.nshared; f += (int64_t)gridDim.x * 256) {
+        int i, j, l;
+        shared_node(e, f, i, j, l);
+        if (is_dirichlet(a.m, i, j, l)) continue;
+        const int n = sharer_count(e, i, j, l);
+        T s = a.part[f] + a.part[a.nshared + f];
+        for (int c = 2; c < n; ++c) s += a.part[c * a.nshared + f];
+        a.y[i + (int64_t)a.m.nn[0] * (j + (int64_t)a.m.nn[1] * l)] = s;
+    }
+}
+
+template <typename T>
+hipError_t launch_assemble(const AssembleArgs<T>& a, hipStream_t s)
+{
+    const int64_t want = (a.nshared + 255) / 256;
+    const int blocks = (int)(want < 1 ? 1 : (want < 8192 ? want : 8192));
+    hipLaunchKernelGGL(assemble_kernel<T>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_assemble<double>(const AssembleArgs<double>&, hipStream_t);
+template hipError_t launch_assemble<float>(const AssembleArgs<float>&, hipStream_t);
+
+int device_cu_count()
+{
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 1;
+        cached = n;
+    }
+    return cached;
+}
+
+// ---------------------------------------------------------------------------
 // Batched persistent apply: one launch over the (problem, tile) work items of
 // several independent meshes.  Workgroups pull items from a device counter
 // until the list is exhausted (every workgroup leaves the loop once the
 // counter passes the item count).  The coefficient of a tile is computed once
-// and reused for all right-hand sides of its problem.
+// and reused for all right-hand sides of its problem.  A second launch
+// assembles the shared-face nodes of every (problem, rhs) and resets the counter.
 
-template <int K, int TX, int TY, int TZ>
+template <int K, int TX, int TY, int TZ, int HV>
 __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
@@ -138,48 +206,69 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
         const MeshArgs m = a.probs[pi].m;
         const double* phi = a.probs[pi].phi;
         const int nrhs = a.probs[pi].nrhs, rhs0 = a.probs[pi].rhs_begin;
-        const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, item - a.probs[pi].tile_begin);
+        const int tile = item - a.probs[pi].tile_begin;
+        const int ntiles = m.ntile[0] * m.ntile[1] * m.ntile[2];
+        const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
         const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
         const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
         const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
         double cw[N3];
-        if (active) cell_coefficient<K>(m, phi, cx, cy, cz, cw);
+        if (active) cell_coefficient<K, HV>(m, phi, cx, cy, cz, cw);
         const int faces = active ? cell_dirichlet_faces(m, cx, cy, cz) : 0;
         for (int r = 0; r < nrhs; ++r) {
             const double* x = a.x[rhs0 + r];
             double* y = a.y[rhs0 + r];
+            double* part = a.part + a.probs[pi].part_begin + (int64_t)r * 8 * a.probs[pi].nshared;
             for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = 0.0;
             __syncthreads();
             if (active) {
                 double u[N3];
                 gather_cell<K>(m, x, cx, cy, cz, faces, u);
                 cell_operator<K>(m, cw, u);
-#pragma unroll
-                for (int a2 = 0; a2 < N; ++a2)
-#pragma unroll
-                    for (int a1 = 0; a1 < N; ++a1)
-#pragma unroll
-                        for (int a0 = 0; a0 < N; ++a0)
-                            atomicAdd(&yb[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))],
-                                      u[a0 + N * (a1 + N * a2)]);
+                scatter_cell_lds<K>(yb, BX, BY, lx, ly, lz, u);
             }
             __syncthreads();
-            flush_block<double, BX, BY, BZ, NT>(m, tc, yb, x, y, false);
+            if (active)
+                flush_owned<K, double, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, -1, x, y, part,
+                                                   a.probs[pi].nshared, false);
             __syncthreads();
         }
     }
 }
 
-// Zero several vectors (and the work counter) in one launch.
-__global__ void multi_zero_kernel(MultiFillArgs a)
+struct BatchAssembleArgs {
+    const BatchProblem* probs;
+    int nprob;
+    int k;
+    int tile[3];
+    double* const* y;
+    double* part;
+    int* queue;
+};
+
+// grid.y = (problem, rhs) pair; grid.x strides over that pair's shared nodes.
+__global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a)
 {
-    const int64_t total = a.offset[a.nvec];
-    if (a.queue && blockIdx.x == 0 && threadIdx.x == 0) *a.queue = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int v = 0;
-        while (v + 1 < a.nvec && a.offset[v + 1] <= i) ++v;
-        a.ptr[v][i - a.offset[v]] = 0.0;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.queue = 0;
+    int pr = blockIdx.y, pi = 0;
+    for (; pi < a.nprob; ++pi) {
+        if (pr < a.probs[pi].nrhs) break;
+        pr -= a.probs[pi].nrhs;
+    }
+    if (pi >= a.nprob) return;
+    const BatchProblem& P = a.probs[pi];
+    const int64_t ns = P.nshared;
+    const double* part = a.part + P.part_begin + (int64_t)pr * 8 * ns;
+    double* y = a.y[P.rhs_begin + pr];
+    const SharedEnum e = shared_enum(P.m, a.k, a.tile);
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < ns; f += (int64_t)gridDim.x * 256) {
+        int i, j, l;
+        shared_node(e, f, i, j, l);
+        if (is_dirichlet(P.m, i, j, l)) continue;
+        const int n = sharer_count(e, i, j, l);
+        double s = part[f] + part[ns + f];
+        for (int c = 2; c < n; ++c) s += part[c * ns + f];
+        y[i + (int64_t)P.m.nn[0] * (j + (int64_t)P.m.nn[1] * l)] = s;
     }
 }
 
@@ -189,13 +278,22 @@ __global__ void multi_zero_kernel(MultiFillArgs a)
     X(2, 8, 4, 4)            \
     X(2, 4, 4, 4)
 
-hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, hipStream_t s)
+hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
+                              hipStream_t s)
 {
-#define VPP_BL(K, TX, TY, TZ)                                                                     \
-    if (k == K && c.variant == 0 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {     \
-        hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ>), dim3(nblocks), dim3(TX * TY * TZ), \
-                           0, s, a);                                                              \
-        return hipGetLastError();                                                                 \
+#define VPP_BL(K, TX, TY, TZ)                                                                       \
+    if (k == K && c.variant == 0 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {       \
+        if (a.heaviside == 0)                                                                       \
+            hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, 0>), dim3(nblocks),                \
+                               dim3(TX * TY * TZ), 0, s, a);                                        \
+        else                                                                                        \
+            hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, 1>), dim3(nblocks),                \
+                               dim3(TX * TY * TZ), 0, s, a);                                        \
+        hipError_t e = hipGetLastError();                                                           \
+        if (e != hipSuccess) return e;                                                              \
+        BatchAssembleArgs b{a.probs, a.nprob, K, {TX, TY, TZ}, a.y, a.part, a.queue};               \
+        hipLaunchKernelGGL(batch_assemble_kernel, dim3(512, (unsigned)total_rhs), dim3(256), 0, s, b);  \
+        return hipGetLastError();                                                                   \
     }
     VPP_BATCH_CONFIGS(VPP_BL)
 #undef VPP_BL
@@ -207,7 +305,7 @@ int batch_blocks_per_cu(const LaunchCfg& c, int k)
     int nb = 0;
 #define VPP_BO(K, TX, TY, TZ)                                                                      \
     if (k == K && c.variant == 0 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {      \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_apply_kernel<K, TX, TY, TZ>,  \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_apply_kernel<K, TX, TY, TZ, 0>,\
                                                          TX * TY * TZ, 0) != hipSuccess)          \
             return 0;                                                                              \
         return nb;                                                                                 \
@@ -215,12 +313,6 @@ int batch_blocks_per_cu(const LaunchCfg& c, int k)
     VPP_BATCH_CONFIGS(VPP_BO)
 #undef VPP_BO
     return 0;
-}
-
-hipError_t launch_multi_zero(const MultiFillArgs& a, hipStream_t s)
-{
-    hipLaunchKernelGGL(multi_zero_kernel, dim3(4096), dim3(256), 0, s, a);
-    return hipGetLastError();
 }
 
 }  // namespace vpp

@@ -8,7 +8,7 @@ namespace vpp {
 // Device-resident scalars of one PCG (FP64 for every precision).
 struct CgState {
     double rz[2];     // r.D^-1 r at the start of the iteration of parity 0 / 1
-    double pAp;       // accumulated by the apply of the current iteration
+    double pAp;       // p.Ap, written by the apply of the current iteration
     double rr[2];     // accumulated r.r of the new residual (by iteration parity)
     double rznew[2];  // accumulated r.D^-1 r of the new residual (by iteration parity)
     double tol2;      // convergence threshold on r.r

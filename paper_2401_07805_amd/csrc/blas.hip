@@ -4,10 +4,10 @@
 // All CG scalars live on the device in FP64 (CgState) so that a chunk of
 // iterations can be recorded once in a hipGraph and replayed without host
 // round trips.  One iteration is three kernels:
-//   apply:    q = A p, accumulating p.q into pAp           (apply kernels)
+//   apply:    q = A p and pAp = p.q                         (apply kernels)
 //   update:   alpha = rz/pAp; x += alpha p; r -= alpha q;
 //             accumulate r.r and r.(D^-1 r)
-//   pupdate:  beta = rz_new/rz; p = D^-1 r + beta p; q = 0 (for the next apply);
+//   pupdate:  beta = rz_new/rz; p = D^-1 r + beta p;
 //             block 0 records the iteration and the convergence flag and
 //             clears the accumulators of the next iteration.
 // The accumulated scalars are double-buffered by iteration parity, so no
@@ -105,7 +105,6 @@ __global__ void __launch_bounds__(BT) cg_pupdate_kernel(CgState* st, int par, co
         st->rz[1 - par] = rznew;
         st->rr[1 - par] = 0.0;
         st->rznew[1 - par] = 0.0;
-        st->pAp = 0.0;
         if (!isfinite(rr) || !isfinite(rznew)) {
             st->breakdown = 1;
             st->done = 1;
@@ -114,10 +113,8 @@ __global__ void __launch_bounds__(BT) cg_pupdate_kernel(CgState* st, int par, co
         }
     }
     const T beta = T(beta_d);
-    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT)
         p[i] = fma(beta, p[i], r[i] * invd[i]);
-        q[i] = T(0);
-    }
 }
 
 // r = b - q in FP64 and its squared norm (outer residual of the mixed solver and

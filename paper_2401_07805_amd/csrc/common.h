@@ -32,12 +32,12 @@ struct MeshArgs {
     double r0;
 };
 
-__device__ __forceinline__ int64_t node_index(const MeshArgs& m, int64_t i, int64_t j, int64_t l)
+__host__ __device__ inline int64_t node_index(const MeshArgs& m, int64_t i, int64_t j, int64_t l)
 {
     return i + (int64_t)m.nn[0] * (j + (int64_t)m.nn[1] * l);
 }
 
-__device__ __forceinline__ bool is_dirichlet(const MeshArgs& m, int i, int j, int l)
+__host__ __device__ inline bool is_dirichlet(const MeshArgs& m, int i, int j, int l)
 {
     return ((m.bcmask & 1) && i == 0) || ((m.bcmask & 2) && i == m.nn[0] - 1) ||
            ((m.bcmask & 4) && j == 0) || ((m.bcmask & 8) && j == m.nn[1] - 1) ||
@@ -186,23 +186,24 @@ __device__ __forceinline__ constexpr double wref(int q0, int q1, int q2)
     return Tab<K>::t.w[q0] * Tab<K>::t.w[q1] * Tab<K>::t.w[q2];
 }
 
+// Scaled coefficient c'(phi) at one Gauss point; HV selects the Heaviside
+// (0 linear, 1 sine ramp) at compile time so that each kernel carries one law.
+template <int HV, typename T>
+__device__ __forceinline__ T coef_scaled(const MeshArgs& m, T phi)
+{
+    if constexpr (HV == 0) return fma(T(m.cb), clamp1(phi), T(m.ca));
+    else return fma(T(m.cd), sine_ramp(clamp1(phi)), T(m.cg));
+}
+
 // Scaled coefficient c'(phi) * wref at every Gauss point of a cell, in place
 // (phi values at the Gauss points in, factors out).
-template <int K, typename T>
+template <int K, int HV, typename T>
 __device__ __forceinline__ void coef_weights3(const MeshArgs& m, T (&v)[(K + 1) * (K + 1) * (K + 1)])
 {
     constexpr int N = K + 1;
-    if (m.heaviside == 0) {
-        const T ca = T(m.ca), cb = T(m.cb);
 #pragma unroll
-        for (int q = 0; q < N * N * N; ++q)
-            v[q] = fma(cb, clamp1(v[q]), ca) * T(wref<K>(q % N, (q / N) % N, q / (N * N)));
-    } else {
-        const T cg = T(m.cg), cd = T(m.cd);
-#pragma unroll
-        for (int q = 0; q < N * N * N; ++q)
-            v[q] = fma(cd, sine_ramp(clamp1(v[q])), cg) * T(wref<K>(q % N, (q / N) % N, q / (N * N)));
-    }
+    for (int q = 0; q < N * N * N; ++q)
+        v[q] = coef_scaled<HV>(m, v[q]) * T(wref<K>(q % N, (q / N) % N, q / (N * N)));
 }
 
 // ---------------------------------------------------------------------------

@@ -14,25 +14,57 @@ struct ApplyArgs {
     const T* x;
     T* y;
     const T* phi;
-    double* dot;        // optional: atomically accumulates x . y (FP64)
-    const int* done;    // optional: the kernel returns at once when *done != 0
+    T* part;            // partial values of shared nodes: 8 ranks x nshared entries
+    int64_t nshared;    // number of nodes shared by several tiles
+    double* dot_part;   // optional: per-workgroup partial sums of x . y (ntiles entries)
+    double* dot;        // optional: x . y, written by the assembly kernel
+    const int* done;    // optional: the kernels return at once when *done != 0
 };
 
 // Per-problem launch configuration.
 struct LaunchCfg {
-    int variant;        // 0 cell per thread, 1 plane per thread
+    int variant;        // 0 cell per thread, 1 plane per thread, 2 cell per thread + LDS DMA staging
     int tile[3];
 };
 
-// y = A_D x (y must be zeroed before: nodes on shared tile faces are added
-// atomically).  Returns hipErrorInvalidValue for a configuration that is not
+inline int block_nodes(const LaunchCfg& c, int k)
+{
+    return (k * c.tile[0] + 1) * (k * c.tile[1] + 1) * (k * c.tile[2] + 1);
+}
+
+// Nodes lying in more than one tile (on interior tile boundary planes).
+inline int64_t shared_node_count(const MeshArgs& m)
+{
+    const int64_t nbx = m.ntile[0] - 1, nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
+    return nbz * m.nn[1] * m.nn[0] + nby * (m.nn[2] - nbz) * m.nn[0] + nbx * (m.nn[1] - nby) * (m.nn[2] - nbz);
+}
+
+// y = A_D x as two launches on s: the tile kernel (interior nodes of y, partials
+// of shared nodes) and the assembly of the shared nodes.  y needs no
+// initialisation.  hipErrorInvalidValue for a configuration that is not
 // instantiated.
-hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& a, int nblocks,
-                            hipStream_t s);
-hipError_t launch_apply_f32(const LaunchCfg& c, int k, const ApplyArgs<float>& a, int nblocks,
-                            hipStream_t s);
+hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& a, hipStream_t s);
+hipError_t launch_apply_f32(const LaunchCfg& c, int k, const ApplyArgs<float>& a, hipStream_t s);
 bool apply_config_supported(const LaunchCfg& c, int k);
 int list_apply_configs(int k, LaunchCfg* out, int cap);
+
+// Assembly of shared-face nodes from the tile partials (and of x . y).
+template <typename T>
+struct AssembleArgs {
+    MeshArgs m;
+    int k;
+    int tile[3];
+    const T* part;
+    int64_t nshared;
+    T* y;
+    const double* dot_part;
+    int ndot;
+    double* dot;
+    const int* done;
+};
+template <typename T>
+hipError_t launch_assemble(const AssembleArgs<T>& a, hipStream_t s);
+int device_cu_count();
 
 // Diagonal of A_D: accumulates into diag (zeroed before), then fix_diagonal
 // writes 1 on Dirichlet rows and the FP64 / FP32 inverses.
@@ -56,6 +88,8 @@ struct BatchProblem {
     int tile_begin;      // first global work item of this problem
     int nrhs;
     int rhs_begin;       // first entry in the pointer tables
+    int64_t part_begin;  // first partial entry of this problem's first right-hand side
+    int64_t nshared;     // shared nodes of this problem (8 * nshared partial entries per rhs)
 };
 
 struct BatchArgs {
@@ -64,18 +98,15 @@ struct BatchArgs {
     int nitems;
     const double* const* x;
     double* const* y;
-    int* queue;          // work counter, zero at launch
+    double* part;        // partial slots of every (problem, rhs)
+    int* queue;          // work counter, zero at launch (reset by the assembly kernel)
+    int heaviside;       // shared by every problem of the batch
 };
 
-hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, hipStream_t s);
+// Persistent tile kernel over all work items, then one assembly launch over all
+// (problem, rhs) vectors.
+hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
+                              hipStream_t s);
 int batch_blocks_per_cu(const LaunchCfg& c, int k);
-
-struct MultiFillArgs {
-    double* const* ptr;
-    const int64_t* offset;   // prefix sums of the lengths, nvec + 1 entries
-    int nvec;
-    int* queue;              // also zeroed (may be null)
-};
-hipError_t launch_multi_zero(const MultiFillArgs& a, hipStream_t s);
 
 }  // namespace vpp
