@@ -70,9 +70,14 @@ typedef struct {
 
 /* CG controls.  Convergence (Table tab:solver_settings): ||r||_2 < atol or
  * ||r||_2 / ||r0||_2 < rtol, r0 the initial residual.  precision VPP_MIXED runs
- * FP64 defect correction around an FP32 inner PCG solved to inner_rtol;
- * check_every = number of iterations between host-side convergence checks
- * (0 = library default).  Scalars of every CG are FP64. */
+ * the PCG recurrences with the FP32 operator and FP32 vectors and keeps the
+ * solution, the residual that decides convergence and every CG scalar in FP64:
+ * each time the FP32 residual has dropped by inner_rtol (0 = 1e-3) since the
+ * last replacement, the FP32 correction is added to the FP64 solution and the
+ * FP32 residual is replaced by the FP64 residual b - A x (the search direction
+ * is kept).  inner_max_iter (0 = none) caps the FP32 iterations between two
+ * replacements.  check_every = iterations between host-side checks of the
+ * device stop flag (0 = 32).  Scalars of every CG are FP64. */
 typedef struct {
     double rtol, atol;
     int32_t max_iter, precision;
@@ -81,8 +86,8 @@ typedef struct {
 } vpp_cg_opts;
 
 typedef struct {
-    int32_t iterations;        /* CG iterations (inner iterations summed for VPP_MIXED) */
-    int32_t outer_iterations;  /* defect-correction steps (0 unless VPP_MIXED) */
+    int32_t iterations;        /* CG iterations (FP32 iterations for VPP_MIXED) */
+    int32_t outer_iterations;  /* FP64 residual replacements (0 unless VPP_MIXED) */
     int32_t status;            /* vpp_status of the solve */
     double rel_residual;       /* ||r|| / ||r0|| as tracked by the (outer) iteration */
     double true_rel_residual;  /* ||b - A x|| / ||b - A x0|| recomputed in FP64 at the end */
@@ -91,7 +96,8 @@ typedef struct {
 /* Kernel configuration: cells of one workgroup tile (tx, ty, tz). */
 typedef struct {
     int32_t tile[3];
-    int32_t variant;           /* 0 = cell-per-thread, 1 = plane-per-thread */
+    int32_t variant;           /* 0 = cell per thread, 1 = plane per thread, 2 = cell per thread in a
+                                  persistent workgroup, 3 = cell per thread with LDS-staged blocks */
 } vpp_kernel_config;
 
 /* Create a problem on desc->device (host call, allocates device workspace and
@@ -132,12 +138,18 @@ vpp_status vpp_grad_coef(vpp_problem p, const double* pv, const double* lam, dou
                          void* stream);
 vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* stream);
 
-/* Kernel configuration of a problem (what the autotuner chooses).  Setting an
- * unsupported one returns VPP_ERR_UNSUPPORTED.  vpp_tune times the candidates on
- * this problem (synchronises) and keeps the fastest; with a non-NULL cache path
- * the choice is read from / added to that JSON file. */
+/* Kernel configuration of a problem (what the autotuner chooses), held per
+ * precision: the FP64 and the FP32 apply may use different kernels and tiles.
+ * Setting an unsupported one returns VPP_ERR_UNSUPPORTED.  vpp_get_config /
+ * vpp_set_config read the FP64 choice / set both.  vpp_tune times the
+ * candidates of both precisions on this problem (synchronises) and keeps the
+ * fastest of each; with a non-NULL cache path the choices are read from /
+ * added to that JSON file. */
 vpp_status vpp_get_config(vpp_problem p, vpp_kernel_config* cfg);
 vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg);
+/* precision: VPP_FP64 or VPP_FP32 (VPP_ERR_INVALID_ARG otherwise). */
+vpp_status vpp_get_config_for(vpp_problem p, int32_t precision, vpp_kernel_config* cfg);
+vpp_status vpp_set_config_for(vpp_problem p, int32_t precision, const vpp_kernel_config* cfg);
 vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream);
 /* Candidate list for a degree: writes up to `cap` configs, returns the count. */
 int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap);

@@ -61,6 +61,8 @@ def load() -> C.CDLL:
         "vpp_grad_phi": (C.c_int, [vp, vp, vp, vp]),
         "vpp_get_config": (C.c_int, [vp, C.POINTER(KernelConfig)]),
         "vpp_set_config": (C.c_int, [vp, C.POINTER(KernelConfig)]),
+        "vpp_get_config_for": (C.c_int, [vp, C.c_int32, C.POINTER(KernelConfig)]),
+        "vpp_set_config_for": (C.c_int, [vp, C.c_int32, C.POINTER(KernelConfig)]),
         "vpp_tune": (C.c_int, [vp, C.c_char_p, vp]),
         "vpp_config_candidates": (C.c_int32, [C.c_int32, C.POINTER(KernelConfig), C.c_int32]),
         "vpp_batch_create": (C.c_int, [PP, C.POINTER(C.c_int32), C.c_int32, C.c_char_p, PP]),

@@ -19,6 +19,9 @@ class VppError(RuntimeError):
         self.status = status
 
 
+_PREC = {"fp64": L.VPP_FP64, "fp32": L.VPP_FP32}
+
+
 def _check(status: int):
     if status != L.VPP_OK:
         raise VppError(status, L.load().vpp_last_error().decode())
@@ -147,17 +150,26 @@ class Problem:
 
     @property
     def config(self) -> dict:
+        """Kernel configuration of the FP64 apply."""
+        return self.config_for("fp64")
+
+    def config_for(self, precision: str) -> dict:
         c = L.KernelConfig()
-        _check(L.load().vpp_get_config(self._h, C.byref(c)))
+        _check(L.load().vpp_get_config_for(self._h, _PREC[precision], C.byref(c)))
         return {"variant": c.variant, "tile": tuple(c.tile)}
 
-    def set_config(self, variant: int, tile: Sequence[int]):
+    def set_config(self, variant: int, tile: Sequence[int], precision: Optional[str] = None):
+        """Sets the kernel configuration of one precision ("fp64", "fp32") or of both (None)."""
         c = L.KernelConfig()
         c.variant = int(variant)
         c.tile[:] = [int(v) for v in tile]
-        _check(L.load().vpp_set_config(self._h, C.byref(c)))
+        if precision is None:
+            _check(L.load().vpp_set_config(self._h, C.byref(c)))
+        else:
+            _check(L.load().vpp_set_config_for(self._h, _PREC[precision], C.byref(c)))
 
     def tune(self, cache_path: Optional[str] = None) -> dict:
+        """Autotunes both precisions; returns the FP64 choice."""
         _check(L.load().vpp_tune(self._h, cache_path.encode() if cache_path else None, _stream(self.device)))
         return self.config
 

@@ -52,7 +52,7 @@ struct DeviceGuard {
 
 LaunchCfg default_config(int k)
 {
-    if (k == 2) return LaunchCfg{0, {8, 4, 4}};
+    if (k == 2) return LaunchCfg{4, {8, 8, 4}};
     if (k == 3) return LaunchCfg{1, {4, 4, 2}};
     return LaunchCfg{1, {4, 2, 2}};
 }
@@ -91,18 +91,22 @@ struct CgWork {
     CgState* st32 = nullptr;      // device
     CgState* hst = nullptr;       // pinned host mirror
     double* rr = nullptr;         // device scalar for residual norms
+    double* red = nullptr;        // per-workgroup partial sums of the reductions
     double* hrr = nullptr;        // pinned host mirror
     hipGraphExec_t g64 = nullptr, g32 = nullptr;
     int graph_iters = 0;
     LaunchCfg graph_cfg{-1, {0, 0, 0}};
+    LaunchCfg graph_cfg32{-1, {0, 0, 0}};
 };
 
 struct vpp_problem_s {
     vpp_desc desc;
     int k = 2;
     int64_t N = 0, NQ = 0, ncell = 0;
-    MeshArgs m{};
+    MeshArgs m{};                   // FP64 apply (tile counts of cfg)
     LaunchCfg cfg{};
+    MeshArgs m32{};                 // FP32 apply (tile counts of cfg32)
+    LaunchCfg cfg32{};
     double* phi64 = nullptr;
     float* phi32 = nullptr;
     double* diag = nullptr;
@@ -176,12 +180,13 @@ static MeshArgs make_mesh_args(const vpp_desc& d)
     return m;
 }
 
-// Scratch of the apply for the current configuration: the partial slots of
-// shared-face nodes (tiles x block nodes, FP64-sized so both precisions fit)
-// and one partial dot product per tile.
+// Scratch of the apply for the current configurations of both precisions: the
+// partials of shared-face nodes (8 ranks x shared nodes, FP64-sized) and one
+// partial dot product per tile.
 static vpp_status ensure_apply_scratch(vpp_problem p)
 {
-    const size_t need = (size_t)std::max<int64_t>(1, 8 * shared_node_count(p->m)) * sizeof(double);
+    const int64_t ns = std::max(shared_node_count(p->m), shared_node_count(p->m32));
+    const size_t need = (size_t)std::max<int64_t>(1, 8 * ns) * sizeof(double);
     if (need > p->part_bytes) {
         if (p->part) (void)hipFree(p->part);
         p->part = nullptr;
@@ -190,7 +195,7 @@ static vpp_status ensure_apply_scratch(vpp_problem p)
         if (s) return s;
         p->part_bytes = need;
     }
-    const size_t nd = (size_t)tile_count(p->m);
+    const size_t nd = (size_t)std::max(tile_count(p->m), tile_count(p->m32));
     if (nd > p->dot_part_n) {
         if (p->dot_part) (void)hipFree(p->dot_part);
         p->dot_part = nullptr;
@@ -213,9 +218,9 @@ static vpp_status do_apply64(vpp_problem p, const double* x, double* y, double* 
 
 static vpp_status do_apply32(vpp_problem p, const float* x, float* y, double* dot, const int* done, hipStream_t s)
 {
-    ApplyArgs<float> a{p->m, x, y, p->phi32, reinterpret_cast<float*>(p->part), shared_node_count(p->m),
+    ApplyArgs<float> a{p->m32, x, y, p->phi32, reinterpret_cast<float*>(p->part), shared_node_count(p->m32),
                        dot ? p->dot_part : nullptr, dot, done};
-    VPP_HIP(launch_apply_f32(p->cfg, p->k, a, s));
+    VPP_HIP(launch_apply_f32(p->cfg32, p->k, a, s));
     return VPP_OK;
 }
 
@@ -231,7 +236,7 @@ static void free_work(CgWork& w)
     free_graphs(w);
     dev_free(w.x); dev_free(w.b); dev_free(w.r); dev_free(w.p); dev_free(w.q);
     dev_free(w.x32); dev_free(w.r32); dev_free(w.p32); dev_free(w.q32);
-    dev_free(w.st); dev_free(w.st32); dev_free(w.rr);
+    dev_free(w.st); dev_free(w.st32); dev_free(w.rr); dev_free(w.red);
     if (w.hst) (void)hipHostFree(w.hst);
     if (w.hrr) (void)hipHostFree(w.hrr);
     w.hst = nullptr;
@@ -247,7 +252,8 @@ static vpp_status ensure_work(vpp_problem p, bool mixed)
         if ((s = dev_alloc(&w.x, n, "cg x")) || (s = dev_alloc(&w.b, n, "cg b")) ||
             (s = dev_alloc(&w.r, n, "cg r")) || (s = dev_alloc(&w.p, n, "cg p")) ||
             (s = dev_alloc(&w.q, n, "cg q")) || (s = dev_alloc(&w.st, 1, "cg state")) ||
-            (s = dev_alloc(&w.st32, 1, "cg state")) || (s = dev_alloc(&w.rr, 1, "norm")))
+            (s = dev_alloc(&w.st32, 1, "cg state")) || (s = dev_alloc(&w.rr, 1, "norm")) ||
+            (s = dev_alloc(&w.red, kRedDoubles, "reduction partials")))
             return s;
         VPP_HIP(hipHostMalloc((void**)&w.hst, sizeof(CgState), hipHostMallocDefault));
         VPP_HIP(hipHostMalloc((void**)&w.hrr, sizeof(double), hipHostMallocDefault));
@@ -273,18 +279,19 @@ static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
         const int par = it & 1;
         if constexpr (sizeof(T) == 8) {
             ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, p->part, shared_node_count(p->m), p->dot_part,
-                                &w.st->pAp, &w.st->done};
+                                &w.st->pAp, &w.st->halt[par]};
             err = launch_apply_f64(p->cfg, p->k, a, s);
-            if (err == hipSuccess) err = launch_cg_update<double>(w.st, par, w.x, w.r, w.p, w.q, p->inv64, p->N, s);
-            if (err == hipSuccess) err = launch_cg_pupdate<double>(w.st, par, w.r, w.p, w.q, p->inv64, p->N, s);
+            if (err == hipSuccess)
+                err = launch_cg_update<double>(w.st, par, w.red, w.x, w.r, w.p, w.q, p->inv64, p->N, s);
+            if (err == hipSuccess) err = launch_cg_pupdate<double>(w.st, par, w.red, w.r, w.p, p->inv64, p->N, s);
         } else {
-            ApplyArgs<float> a{p->m, w.p32, w.q32, p->phi32, reinterpret_cast<float*>(p->part),
-                               shared_node_count(p->m), p->dot_part, &w.st32->pAp, &w.st32->done};
-            err = launch_apply_f32(p->cfg, p->k, a, s);
+            ApplyArgs<float> a{p->m32, w.p32, w.q32, p->phi32, reinterpret_cast<float*>(p->part),
+                               shared_node_count(p->m32), p->dot_part, &w.st32->pAp, &w.st32->halt[par]};
+            err = launch_apply_f32(p->cfg32, p->k, a, s);
             if (err == hipSuccess)
-                err = launch_cg_update<float>(w.st32, par, w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
+                err = launch_cg_update<float>(w.st32, par, w.red, w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
             if (err == hipSuccess)
-                err = launch_cg_pupdate<float>(w.st32, par, w.r32, w.p32, w.q32, p->inv32, p->N, s);
+                err = launch_cg_pupdate<float>(w.st32, par, w.red, w.r32, w.p32, p->inv32, p->N, s);
         }
     }
     hipError_t e2 = hipStreamEndCapture(s, &g);
@@ -309,10 +316,11 @@ static bool same_cfg(const LaunchCfg& a, const LaunchCfg& b)
 static vpp_status ensure_graphs(vpp_problem p, int iters, bool mixed)
 {
     CgWork& w = p->w;
-    if (w.graph_iters != iters || !same_cfg(w.graph_cfg, p->cfg)) {
+    if (w.graph_iters != iters || !same_cfg(w.graph_cfg, p->cfg) || !same_cfg(w.graph_cfg32, p->cfg32)) {
         free_graphs(w);
         w.graph_iters = iters;
         w.graph_cfg = p->cfg;
+        w.graph_cfg32 = p->cfg32;
     }
     vpp_status s;
     if (!w.g64 && (s = build_cg_graph<double>(p, iters, &w.g64))) return s;
@@ -320,7 +328,7 @@ static vpp_status ensure_graphs(vpp_problem p, int iters, bool mixed)
     return VPP_OK;
 }
 
-// Run graph chunks until the device flags `done`; returns the final state in *hs.
+// Run graph chunks until the device sets a stop flag; returns the final state in *hs.
 static vpp_status run_until_done(vpp_problem p, hipGraphExec_t g, CgState* st, CgState* hs, int max_iter)
 {
     hipStream_t s = p->stream;
@@ -330,7 +338,7 @@ static vpp_status run_until_done(vpp_problem p, hipGraphExec_t g, CgState* st, C
         VPP_HIP(hipGraphLaunch(g, s));
         VPP_HIP(hipMemcpyAsync(hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         VPP_HIP(hipStreamSynchronize(s));
-        if (hs->done) break;
+        if (hs->halt[0] || hs->halt[1]) break;
     }
     return VPP_OK;
 }
@@ -345,7 +353,7 @@ static vpp_status pcg64(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& info, 
     CgState* hs = w.hst;
     std::memset(hs, 0, sizeof(CgState));
     VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
-    VPP_HIP(launch_cg_init<double>(w.st, w.b, w.q, w.r, w.p, p->inv64, p->N, s));
+    VPP_HIP(launch_cg_init<double>(w.st, w.red, w.b, w.q, w.r, w.p, p->inv64, p->N, s));
     VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     VPP_HIP(hipStreamSynchronize(s));
     const double rr0 = hs->rr_last, rz0 = hs->rz[0];
@@ -384,15 +392,21 @@ static vpp_status residual64(vpp_problem p, double* rr)
     hipStream_t s = p->stream;
     vpp_status st;
     if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) return st;
-    VPP_HIP(hipMemsetAsync(w.rr, 0, sizeof(double), s));
-    VPP_HIP(launch_residual(w.b, w.q, w.r, p->N, w.rr, s));
+    VPP_HIP(launch_residual(w.b, w.q, w.r, p->N, w.red, w.rr, s));
     VPP_HIP(hipMemcpyAsync(w.hrr, w.rr, sizeof(double), hipMemcpyDeviceToHost, s));
     VPP_HIP(hipStreamSynchronize(s));
     *rr = *w.hrr;
     return VPP_OK;
 }
 
-// Defect correction: FP64 residual and update, FP32 inner PCG with FP64 scalars.
+// Mixed precision PCG with reliable updates.  The Jacobi-PCG recurrences run
+// in FP32 (operator, vectors) with FP64 scalars on a residual scaled to unit
+// norm; whenever the scaled FP32 residual has dropped by inner_rtol since the
+// last replacement, the FP32 correction is added to the FP64 solution, the
+// true residual b - A x is recomputed with the FP64 operator, and it replaces
+// the FP32 residual (rescaled) while the search direction is kept, so the
+// Krylov recurrence continues instead of restarting.  Convergence is decided
+// on the FP64 residual only.
 static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& info, double* r0_out)
 {
     CgWork& w = p->w;
@@ -405,50 +419,62 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
     info.iterations = 0;
     info.outer_iterations = 0;
     info.rel_residual = r0 > 0 ? 1.0 : 0.0;
+    info.status = VPP_OK;
     if (!std::isfinite(rr)) {
         info.status = VPP_ERR_BREAKDOWN;
         return VPP_OK;
     }
     const double thr = std::max(o.rtol * r0, o.atol);
-    const double inner_rtol = o.inner_rtol > 0 ? o.inner_rtol : 1e-3;
-    const int inner_max = o.inner_max_iter > 0 ? o.inner_max_iter : o.max_iter;
-    int total = 0;
+    if (!(r0 >= thr) || r0 == 0.0) return VPP_OK;
+    const double delta = o.inner_rtol > 0 ? o.inner_rtol : 1e-3;
+    CgState* hs = w.hst;
+    std::memset(hs, 0, sizeof(CgState));
+    hs->tol2 = delta * delta;   // the replaced residual has unit norm
+    hs->max_iter = o.max_iter;
+    VPP_HIP(hipMemcpyAsync(w.st32, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
     double rn = r0;
-    info.status = VPP_OK;
-    const int max_outer = 200;
-    while (!(rn < thr) && rn > 0.0) {
-        if (info.outer_iterations >= max_outer || total >= o.max_iter) {
-            info.status = VPP_ERR_NOT_CONVERGED;
-            break;
-        }
-        const double scale = 1.0 / rn;
-        VPP_HIP(launch_demote(w.r, scale, w.r32, w.x32, p->N, s));
-        CgState* hs = w.hst;
-        std::memset(hs, 0, sizeof(CgState));
-        hs->tol2 = inner_rtol * inner_rtol;   // the inner right-hand side has unit norm
-        hs->max_iter = std::min(inner_max, o.max_iter - total);
-        const int inner_cap = hs->max_iter;
-        VPP_HIP(hipMemcpyAsync(w.st32, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
-        // zero initial guess: r = b, p = D^-1 b; rz[0] is accumulated on the device
-        VPP_HIP(launch_cg_init<float>(w.st32, w.r32, nullptr, w.r32, w.p32, p->inv32, p->N, s));
-        if ((st = run_until_done(p, w.g32, w.st32, hs, inner_cap))) return st;
-        total += hs->iters;
+    VPP_HIP(launch_cg_replace32(w.st32, w.red, w.r, 1.0 / rn, 0.0, w.r32, w.p32, w.x32, p->inv32, p->N, s));
+    const int max_phases = 10000;
+    int last_iters = 0;
+    while (true) {
+        // per-phase iteration cap (inner_max_iter), within the overall max_iter
+        int cap = o.max_iter;
+        if (o.inner_max_iter > 0) cap = (int)std::min<int64_t>(cap, (int64_t)last_iters + o.inner_max_iter);
+        hs->max_iter = cap;
+        VPP_HIP(hipMemcpyAsync(&w.st32->max_iter, &hs->max_iter, sizeof(int), hipMemcpyHostToDevice, s));
+        if ((st = run_until_done(p, w.g32, w.st32, hs, o.max_iter))) return st;
+        const int phase_iters = hs->iters - last_iters;
+        last_iters = hs->iters;
         VPP_HIP(launch_promote_add(w.x, w.x32, rn, p->N, s));
         if ((st = residual64(p, &rr))) return st;
         const double rn_new = std::sqrt(rr);
         info.outer_iterations += 1;
         if (!std::isfinite(rn_new)) {
             info.status = VPP_ERR_BREAKDOWN;
-            break;
-        }
-        if (hs->iters == 0 && !(rn_new < rn)) {      // inner solver made no progress
-            info.status = hs->breakdown ? VPP_ERR_BREAKDOWN : VPP_ERR_NOT_CONVERGED;
             rn = rn_new;
             break;
         }
+        if (rn_new < thr) {
+            rn = rn_new;
+            break;
+        }
+        if (hs->breakdown) {
+            info.status = VPP_ERR_BREAKDOWN;
+            rn = rn_new;
+            break;
+        }
+        if (hs->iters >= o.max_iter || info.outer_iterations >= max_phases ||
+            (phase_iters == 0 && !(rn_new < rn))) {
+            info.status = VPP_ERR_NOT_CONVERGED;
+            rn = rn_new;
+            break;
+        }
+        // keep the direction: it was built on the residual scaled by 1/rn
+        VPP_HIP(launch_cg_replace32(w.st32, w.red, w.r, 1.0 / rn_new, rn / rn_new, w.r32, w.p32, w.x32, p->inv32,
+                                    p->N, s));
         rn = rn_new;
     }
-    info.iterations = total;
+    info.iterations = hs->iters;
     info.rel_residual = r0 > 0 ? rn / r0 : 0.0;
     return VPP_OK;
 }
@@ -596,6 +622,8 @@ vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
     p->m = make_mesh_args(*d);
     p->cfg = default_config(p->k);
     set_tiles(p->m, p->cfg);
+    p->m32 = p->m;
+    p->cfg32 = p->cfg;
     vpp_status s;
     if ((s = dev_alloc(&p->phi64, N, "phi")) || (s = dev_alloc(&p->phi32, N, "phi32")) ||
         (s = dev_alloc(&p->diag, N, "diag")) || (s = dev_alloc(&p->inv64, N, "invdiag")) ||
@@ -723,24 +751,48 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
     return VPP_OK;
 }
 
-vpp_status vpp_get_config(vpp_problem p, vpp_kernel_config* cfg)
+static void put_config(vpp_problem p, int prec, const LaunchCfg& c)
+{
+    if (prec == VPP_FP32) {
+        p->cfg32 = c;
+        set_tiles(p->m32, c);
+    } else {
+        p->cfg = c;
+        set_tiles(p->m, c);
+    }
+}
+
+vpp_status vpp_get_config_for(vpp_problem p, int32_t precision, vpp_kernel_config* cfg)
 {
     if (!p || !cfg) return fail(VPP_ERR_INVALID_ARG, "null argument");
-    cfg->variant = p->cfg.variant;
-    for (int d = 0; d < 3; ++d) cfg->tile[d] = p->cfg.tile[d];
+    if (precision != VPP_FP64 && precision != VPP_FP32)
+        return fail(VPP_ERR_INVALID_ARG, "precision must be VPP_FP64 or VPP_FP32");
+    const LaunchCfg& c = precision == VPP_FP32 ? p->cfg32 : p->cfg;
+    cfg->variant = c.variant;
+    for (int d = 0; d < 3; ++d) cfg->tile[d] = c.tile[d];
     return VPP_OK;
 }
 
-vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg)
+vpp_status vpp_set_config_for(vpp_problem p, int32_t precision, const vpp_kernel_config* cfg)
 {
     if (!p || !cfg) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (precision != VPP_FP64 && precision != VPP_FP32)
+        return fail(VPP_ERR_INVALID_ARG, "precision must be VPP_FP64 or VPP_FP32");
     LaunchCfg c{cfg->variant, {cfg->tile[0], cfg->tile[1], cfg->tile[2]}};
     if (!apply_config_supported(c, p->k)) return fail(VPP_ERR_UNSUPPORTED, "kernel configuration not available");
     DeviceGuard dg(p->desc.device);
     if (p->stream) VPP_HIP(hipStreamSynchronize(p->stream));
-    p->cfg = c;
-    set_tiles(p->m, c);
+    put_config(p, precision, c);
     return ensure_apply_scratch(p);
+}
+
+vpp_status vpp_get_config(vpp_problem p, vpp_kernel_config* cfg) { return vpp_get_config_for(p, VPP_FP64, cfg); }
+
+vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg)
+{
+    vpp_status s = vpp_set_config_for(p, VPP_FP64, cfg);
+    if (s) return s;
+    return vpp_set_config_for(p, VPP_FP32, cfg);
 }
 
 int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap)
@@ -754,40 +806,40 @@ int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t ca
     return n;
 }
 
-vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
+// Times every candidate configuration of one precision and keeps the fastest.
+static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path)
 {
-    if (!p) return fail(VPP_ERR_INVALID_ARG, "null argument");
-    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
-    DeviceGuard dg(p->desc.device);
-    const std::string key = size_bucket_key("apply", p->k, p->N);
+    const std::string key = size_bucket_key(prec == VPP_FP32 ? "apply32" : "apply", p->k, p->N);
     LaunchCfg c;
     if (cache_lookup(cache_path, key, &c) && apply_config_supported(c, p->k)) {
-        p->cfg = c;
-        set_tiles(p->m, c);
+        put_config(p, prec, c);
         return ensure_apply_scratch(p);
     }
-    VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
     vpp_status st;
-    if ((st = ensure_work(p, false))) return st;
+    if ((st = ensure_work(p, prec == VPP_FP32))) return st;
     hipStream_t s = p->stream;
     CgWork& w = p->w;
-    VPP_HIP(launch_fill<double>(w.x, p->N, 1.0, s));
+    if (prec == VPP_FP32) VPP_HIP(launch_fill<float>(w.p32, p->N, 1.0f, s));
+    else VPP_HIP(launch_fill<double>(w.x, p->N, 1.0, s));
     LaunchCfg cands[64];
     const int n = list_apply_configs(p->k, cands, 64);
     hipEvent_t e0, e1;
     VPP_HIP(hipEventCreate(&e0));
     VPP_HIP(hipEventCreate(&e1));
     double best = 1e300;
-    LaunchCfg best_cfg = p->cfg;
+    LaunchCfg best_cfg = prec == VPP_FP32 ? p->cfg32 : p->cfg;
     const int reps = 10;
-    for (int i = 0; i < n; ++i) {
-        p->cfg = cands[i];
-        set_tiles(p->m, cands[i]);
+    auto one = [&]() {
+        return prec == VPP_FP32 ? do_apply32(p, w.p32, w.q32, nullptr, nullptr, s)
+                                : do_apply64(p, w.x, w.q, nullptr, nullptr, s);
+    };
+    for (int i = 0; i < n && !st; ++i) {
+        put_config(p, prec, cands[i]);
         if ((st = ensure_apply_scratch(p))) break;
-        if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) break;
+        if ((st = one())) break;
         VPP_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r)
-            if ((st = do_apply64(p, w.x, w.q, nullptr, nullptr, s))) break;
+        for (int r = 0; r < reps && !st; ++r) st = one();
+        if (st) break;
         VPP_HIP(hipEventRecord(e1, s));
         VPP_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -800,11 +852,21 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    p->cfg = best_cfg;
-    set_tiles(p->m, best_cfg);
+    put_config(p, prec, best_cfg);
     if (st) return st;
     cache_store(cache_path, key, best_cfg, best);
     return ensure_apply_scratch(p);
+}
+
+vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
+{
+    if (!p) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    vpp_status st = tune_precision(p, VPP_FP64, cache_path);
+    if (st) return st;
+    return tune_precision(p, VPP_FP32, cache_path);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,6 +6,12 @@ namespace vpp {
 
 // Instantiated configurations: (k, variant, tile).
 #define VPP_APPLY_CONFIGS(X)  \
+    X(2, 4, 16, 4, 4)         \
+    X(2, 4, 8, 8, 4)          \
+    X(2, 4, 8, 4, 4)          \
+    X(2, 3, 16, 4, 4)         \
+    X(2, 3, 8, 8, 4)          \
+    X(2, 3, 8, 4, 4)          \
     X(2, 2, 8, 8, 4)          \
     X(2, 2, 16, 4, 4)         \
     X(2, 2, 8, 4, 4)          \
@@ -25,7 +31,9 @@ inline auto kernel_ptr()
 {
     if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV>;
     else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV>;
-    else return &apply_stream_kernel<K, T, TX, TY, TZ, HV>;
+    else if constexpr (V == 2) return &apply_stream_kernel<K, T, TX, TY, TZ, HV>;
+    else if constexpr (V == 3) return &apply_lds_kernel<K, T, TX, TY, TZ, HV>;
+    else return &apply_slot_kernel<K, T, TX, TY, TZ, HV>;
 }
 
 // Workgroups that stay resident per CU for a kernel (queried once).

@@ -206,13 +206,12 @@ __device__ __forceinline__ double block_sum(double v)
 // Both f and the rank follow from the tile coordinates and the face flags, with
 // no division.  A0 restricts the x index to one plane (plane-per-thread
 // kernels); -1 = all.  Returns this thread's share of x . (A x).
-template <int K, typename T, int TX, int TY, int TZ>
-__device__ __forceinline__ double flush_owned(const MeshArgs& m, const TileCoord& tc, const T* yb, int lx, int ly,
-                                              int lz, int cx, int cy, int cz, int a0_only,
-                                              const T* __restrict__ x, T* __restrict__ y, T* __restrict__ part,
-                                              int64_t nshared, bool dot)
+template <int K, typename T, int TX, int TY, int TZ, typename Get>
+__device__ __forceinline__ double flush_owned_get(const MeshArgs& m, const TileCoord& tc, const Get& get, int lx,
+                                                  int ly, int lz, int cx, int cy, int cz, int a0_only,
+                                                  const T* __restrict__ x, T* __restrict__ y, T* __restrict__ part,
+                                                  int64_t nshared, bool dot)
 {
-    constexpr int BX = K * TX + 1, BY = K * TY + 1;
     const int faces = cell_dirichlet_faces(m, cx, cy, cz);
     const bool last[3] = {K * (lx + 1) == tc.ext[0] - 1, K * (ly + 1) == tc.ext[1] - 1, K * (lz + 1) == tc.ext[2] - 1};
     const bool has_lo[3] = {lx == 0 && tc.t[0] > 0, ly == 0 && tc.t[1] > 0, lz == 0 && tc.t[2] > 0};
@@ -221,7 +220,6 @@ __device__ __forceinline__ double flush_owned(const MeshArgs& m, const TileCoord
     const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
     const int i0 = K * cx, j0 = K * cy, l0 = K * cz;
     const int64_t gbase = node_index(m, i0, j0, l0);
-    const int lbase = K * lx + BX * (K * ly + BY * K * lz);
     double dsum = 0.0;
 #pragma unroll
     for (int a2 = 0; a2 <= K; ++a2) {
@@ -245,7 +243,7 @@ __device__ __forceinline__ double flush_owned(const MeshArgs& m, const TileCoord
                     }
                     continue;
                 }
-                const T v = yb[lbase + a0 + BX * (a1 + BY * a2)];
+                const T v = get(a0, a1, a2, last);
                 const bool s0 = lo0 || hi0, s1 = lo1 || hi1, s2 = lo2 || hi2;
                 if (s0 || s1 || s2) {
                     int64_t f;
@@ -260,6 +258,19 @@ __device__ __forceinline__ double flush_owned(const MeshArgs& m, const TileCoord
         }
     }
     return dsum;
+}
+
+// flush_owned_get reading the accumulated tile block yb.
+template <int K, typename T, int TX, int TY, int TZ>
+__device__ __forceinline__ double flush_owned(const MeshArgs& m, const TileCoord& tc, const T* yb, int lx, int ly,
+                                              int lz, int cx, int cy, int cz, int a0_only,
+                                              const T* __restrict__ x, T* __restrict__ y, T* __restrict__ part,
+                                              int64_t nshared, bool dot)
+{
+    constexpr int BX = K * TX + 1, BY = K * TY + 1;
+    const int lbase = K * lx + BX * (K * ly + BY * K * lz);
+    auto get = [&](int a0, int a1, int a2, const bool*) { return yb[lbase + a0 + BX * (a1 + BY * a2)]; };
+    return flush_owned_get<K, T, TX, TY, TZ>(m, tc, get, lx, ly, lz, cx, cy, cz, a0_only, x, y, part, nshared, dot);
 }
 
 template <int K, typename T>
@@ -460,6 +471,214 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_stream_kernel(ApplyArgs<T>
 }
 
 // ---------------------------------------------------------------------------
+// Variant 4: one cell per thread, operands gathered straight from global
+// memory, and the cell results exchanged through LDS without atomics: every
+// cell stores its (k+1)^3 local results in its own column of a slot array
+// (slot q of cell c at q * (NT + 1) + c, so a wave's stores and loads hit
+// consecutive words), then sums, for each node it owns, the slots of the up to
+// eight cells of the tile that touch the node.  Column NT stays zero and stands
+// in for a neighbour cell below the tile.
+
+// Value of an owned node of cell `c` (local index a0, a1, a2) from the slot
+// array: the cell's own slot plus, for every direction with a_d = 0, the slot
+// of the cell below along d (local index K there), or the zero column ZERO when
+// that cell lies outside the tile.
+template <int K, typename T, int TX, int TY>
+struct SlotGet {
+    static constexpr int N = K + 1;
+    const T* slot;
+    int cs, c, nb0, nb1, nb2, nb01, nb02, nb12, nb012;
+    __device__ __forceinline__ SlotGet(const T* s, int cs_, int c_, int lx, int ly, int lz, int zero)
+        : slot(s), cs(cs_), c(c_)
+    {
+        nb0 = lx > 0 ? c - 1 : zero;
+        nb1 = ly > 0 ? c - TX : zero;
+        nb2 = lz > 0 ? c - TX * TY : zero;
+        nb01 = lx > 0 && ly > 0 ? c - 1 - TX : zero;
+        nb02 = lx > 0 && lz > 0 ? c - 1 - TX * TY : zero;
+        nb12 = ly > 0 && lz > 0 ? c - TX - TX * TY : zero;
+        nb012 = lx > 0 && ly > 0 && lz > 0 ? c - 1 - TX - TX * TY : zero;
+    }
+    __device__ __forceinline__ T operator()(int a0, int a1, int a2, const bool*) const
+    {
+        const bool s0 = a0 == 0, s1 = a1 == 0, s2 = a2 == 0;
+        T v = slot[(a0 + N * (a1 + N * a2)) * cs + c];
+        if (s0) v += slot[(K + N * (a1 + N * a2)) * cs + nb0];
+        if (s1) v += slot[(a0 + N * (K + N * a2)) * cs + nb1];
+        if (s2) v += slot[(a0 + N * (a1 + N * K)) * cs + nb2];
+        if (s0 && s1) v += slot[(K + N * (K + N * a2)) * cs + nb01];
+        if (s0 && s2) v += slot[(K + N * (a1 + N * K)) * cs + nb02];
+        if (s1 && s2) v += slot[(a0 + N * (K + N * K)) * cs + nb12];
+        if (s0 && s1 && s2) v += slot[(K + N * (K + N * K)) * cs + nb012];
+        return v;
+    }
+};
+
+template <int K, typename T, int TX, int TY, int TZ, int HV>
+__global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a)
+{
+    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ, CS = NT + 1;
+    __shared__ T slot[N3 * CS];
+    if (a.done && *a.done) return;
+    const MeshArgs& m = a.m;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
+    const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+    for (int q = tid; q < N3; q += NT) slot[q * CS + NT] = T(0);
+    if (active) {
+        T cw[N3], u[N3];
+        cell_coefficient<K, HV>(m, a.phi, cx, cy, cz, cw);
+        gather_cell<K>(m, a.x, cx, cy, cz, cell_dirichlet_faces(m, cx, cy, cz), u);
+        cell_operator<K>(m, cw, u);
+#pragma unroll
+        for (int q = 0; q < N3; ++q) slot[q * CS + tid] = u[q];
+    }
+    __syncthreads();
+    double d = 0.0;
+    if (active) {
+        const SlotGet<K, T, TX, TY> get(slot, CS, tid, lx, ly, lz, NT);
+        d = flush_owned_get<K, T, TX, TY, TZ>(m, tc, get, lx, ly, lz, cx, cy, cz, -1, a.x, a.y, a.part, a.nshared,
+                                              a.dot_part != nullptr);
+    }
+    if (a.dot_part) {
+        const double s = block_sum<NT>(d);
+        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Variant 3: one cell per thread with the tile's x and phi node blocks staged
+// in LDS by coalesced row loads.  Every node of the block is read from global
+// memory once per tile (instead of once per cell touching it), the cell
+// gathers become LDS reads at compile-time offsets, and the write-out walks
+// the block node by node so that consecutive lanes store consecutive nodes.
+
+// Copies the x and phi node blocks of a tile into LDS (block layout: x fastest,
+// extents BX, BY, BZ).  Block nodes past the mesh end of a ragged tile are
+// clamped onto the last valid node; their values are never used.
+template <typename T, int BX, int BY, int BZ, int NT>
+__device__ __forceinline__ void stage_blocks(const MeshArgs& m, const TileCoord& tc, const T* __restrict__ x,
+                                             const T* __restrict__ phi, T* sx, T* sp)
+{
+    constexpr int NB = BX * BY * BZ, IT = (NB + NT - 1) / NT;
+    const int64_t tile0 = node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]);
+    const T* __restrict__ xt = x + tile0;
+    const T* __restrict__ pt = phi + tile0;
+    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+    T vx[IT], vp[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int n = threadIdx.x + it * NT;
+        if (NB % NT == 0 || n < NB) {
+            const int i = min(n % BX, tc.ext[0] - 1);
+            const int j = min((n / BX) % BY, tc.ext[1] - 1);
+            const int l = min(n / (BX * BY), tc.ext[2] - 1);
+            const int off = i + nx * j + nxy * l;
+            vx[it] = xt[off];
+            vp[it] = pt[off];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int n = threadIdx.x + it * NT;
+        if (NB % NT == 0 || n < NB) {
+            sx[n] = vx[it];
+            sp[n] = vp[it];
+        }
+    }
+}
+
+// Write-out of a tile's accumulated block yb, node by node (same ownership
+// rules as flush_owned: plain stores for nodes of this tile only, partials for
+// nodes on faces shared with neighbouring tiles, identity rows y = x on
+// Dirichlet nodes by the lowest tile holding them).  xb is the staged x block.
+// Returns this thread's share of x . (A x).
+template <typename T, int BX, int BY, int BZ, int NT>
+__device__ __forceinline__ double flush_block(const MeshArgs& m, const TileCoord& tc, const T* yb, const T* xb,
+                                              T* __restrict__ y, T* __restrict__ part, int64_t nshared, bool dot)
+{
+    constexpr int NB = BX * BY * BZ, IT = (NB + NT - 1) / NT;
+    const int64_t tile0 = node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]);
+    T* __restrict__ yt = y + tile0;
+    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+    const bool tlo0 = tc.t[0] > 0, tlo1 = tc.t[1] > 0, tlo2 = tc.t[2] > 0;
+    const bool thi0 = tc.t[0] < m.ntile[0] - 1, thi1 = tc.t[1] < m.ntile[1] - 1, thi2 = tc.t[2] < m.ntile[2] - 1;
+    double dsum = 0.0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int n = threadIdx.x + it * NT;
+        if (NB % NT != 0 && n >= NB) continue;
+        const int i = n % BX, j = (n / BX) % BY, l = n / (BX * BY);
+        if (i >= tc.ext[0] || j >= tc.ext[1] || l >= tc.ext[2]) continue;
+        const int off = i + nx * j + nxy * l;
+        const int gi = tc.n0[0] + i, gj = tc.n0[1] + j, gl = tc.n0[2] + l;
+        const bool lo0 = i == 0 && tlo0, lo1 = j == 0 && tlo1, lo2 = l == 0 && tlo2;
+        const bool hi0 = i == tc.ext[0] - 1 && thi0, hi1 = j == tc.ext[1] - 1 && thi1;
+        const bool hi2 = l == tc.ext[2] - 1 && thi2;
+        const T xv = xb[n];
+        if (is_dirichlet(m, gi, gj, gl)) {
+            if (!(lo0 || lo1 || lo2)) {
+                yt[off] = xv;
+                if (dot) dsum += (double)xv * (double)xv;
+            }
+            continue;
+        }
+        const T v = yb[n];
+        if (lo0 || lo1 || lo2 || hi0 || hi1 || hi2) {
+            int64_t f;
+            int rank;
+            shared_from_tile(m, tc.t, lo0, lo1, lo2, hi0, hi1, hi2, gi, gj, gl, f, rank);
+            part[rank * nshared + f] = v;
+        } else {
+            yt[off] = v;
+        }
+        if (dot) dsum += (double)xv * (double)v;
+    }
+    return dsum;
+}
+
+template <int K, typename T, int TX, int TY, int TZ, int HV>
+__global__ void __launch_bounds__(TX * TY * TZ) apply_lds_kernel(ApplyArgs<T> a)
+{
+    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
+    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1, NB = BX * BY * BZ;
+    __shared__ T sx[NB];
+    __shared__ T sb[NB];      // phi block, then the accumulation block of A x
+    if (a.done && *a.done) return;
+    const MeshArgs& m = a.m;
+    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, xcd_tile(blockIdx.x, gridDim.x));
+    stage_blocks<T, BX, BY, BZ, NT>(m, tc, a.x, a.phi, sx, sb);
+    __syncthreads();
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
+    const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+    T u[N3];
+    if (active) {
+        T cw[N3];
+        read_cell_lds<K>(sb, BX, BY, lx, ly, lz, 0, cw);
+        sweep3<K, MS, false, 0>(cw);
+        sweep3<K, MS, false, 1>(cw);
+        sweep3<K, MS, false, 2>(cw);
+        coef_weights3<K, HV>(m, cw);
+        read_cell_lds<K>(sx, BX, BY, lx, ly, lz, cell_dirichlet_faces(m, cx, cy, cz), u);
+        cell_operator<K>(m, cw, u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NB; i += NT) sb[i] = T(0);
+    __syncthreads();
+    if (active) scatter_cell_lds<K>(sb, BX, BY, lx, ly, lz, u);
+    __syncthreads();
+    const double d = flush_block<T, BX, BY, BZ, NT>(m, tc, sb, sx, a.y, a.part, a.nshared, a.dot_part != nullptr);
+    if (a.dot_part) {
+        const double s = block_sum<NT>(d);
+        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Variant 1: one x-plane of a cell per thread; x sweeps through LDS.
 
 // Entry (r, i) of a 1D matrix for a runtime row r (COL: entry (i, r)).
@@ -479,13 +698,13 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     constexpr int N = K + 1, N2 = N * N, NC = TX * TY * TZ, NT = N * NC;
     constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
     constexpr int CS = N * N2 + 1;           // padded per-cell stride of the exchange buffers
-    __shared__ T yb[BX * BY * BZ];
+    constexpr int SS = NC + 1;               // slot column stride (column NC stays zero)
+    static_assert(N * N2 * SS <= 2 * NC * CS, "slots must fit in the exchange buffers");
     __shared__ T xb[2 * NC * CS];
     if (a.done && *a.done) return;
     const MeshArgs& m = a.m;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
-    for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
     const int cell = threadIdx.x / N, ip = threadIdx.x % N;
     const int lx = cell % TX, ly = (cell / TX) % TY, lz = cell / (TX * TY);
     const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
@@ -590,8 +809,8 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
         }
     }
     __syncthreads();
+    T o[N2];
     if (active) {
-        T o[N2];
 #pragma unroll
         for (int q = 0; q < N2; ++q) {
             T s = cS[0] * X1[q];
@@ -605,17 +824,24 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
         }
         sweep2<K, MS, true, 0>(o);
         sweep2<K, MS, true, 1>(o);
+    }
+    // exchange of the cell results through slots (no atomics), on the x buffers
+    __syncthreads();
+    T* slot = xb;
+    for (int q = threadIdx.x; q < N * N2; q += NT) slot[q * SS + NC] = T(0);
+    if (active) {
 #pragma unroll
         for (int l = 0; l < N; ++l)
 #pragma unroll
-            for (int j = 0; j < N; ++j)
-                atomicAdd(&yb[(K * lx + ip) + BX * ((K * ly + j) + BY * (K * lz + l))], o[j + N * l]);
+            for (int j = 0; j < N; ++j) slot[(ip + N * (j + N * l)) * SS + cell] = o[j + N * l];
     }
     __syncthreads();
     double d = 0.0;
-    if (active)
-        d = flush_owned<K, T, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, ip, a.x, a.y, a.part, a.nshared,
-                                          a.dot_part != nullptr);
+    if (active) {
+        const SlotGet<K, T, TX, TY> get(slot, SS, cell, lx, ly, lz, NC);
+        d = flush_owned_get<K, T, TX, TY, TZ>(m, tc, get, lx, ly, lz, cx, cy, cz, ip, a.x, a.y, a.part, a.nshared,
+                                              a.dot_part != nullptr);
+    }
     if (a.dot_part) {
         const double s = block_sum<NT>(d);
         if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;

@@ -9,28 +9,40 @@ namespace vpp {
 struct CgState {
     double rz[2];     // r.D^-1 r at the start of the iteration of parity 0 / 1
     double pAp;       // p.Ap, written by the apply of the current iteration
-    double rr[2];     // accumulated r.r of the new residual (by iteration parity)
-    double rznew[2];  // accumulated r.D^-1 r of the new residual (by iteration parity)
+    double rr[2];     // r.r of the new residual (by iteration parity)
+    double rznew[2];  // r.D^-1 r of the new residual (by iteration parity)
     double tol2;      // convergence threshold on r.r
     double rr_last;   // r.r after the last completed iteration (initial r.r after init)
-    int done;         // converged, broke down or hit max_iter
-    int breakdown;
+    int halt[2];      // stop flag read by the kernels of the iteration of parity 0 / 1
+    int breakdown;    // p.Ap <= 0 or a non-finite scalar
     int iters;
     int max_iter;
 };
 
+// Reduction workspace: per-workgroup partial sums of two quantities, summed in
+// a fixed order by the consumer (no atomics, bit-reproducible results).
+constexpr int kMaxRedBlocks = 1024;
+constexpr int kRedDoubles = 2 * kMaxRedBlocks;
+
 template <typename T>
-hipError_t launch_cg_init(CgState* st, const T* b, const T* q, T* r, T* p, const T* invd, int64_t n,
+hipError_t launch_cg_init(CgState* st, double* red, const T* b, const T* q, T* r, T* p, const T* invd, int64_t n,
                           hipStream_t s);
 template <typename T>
-hipError_t launch_cg_update(CgState* st, int par, T* x, T* r, const T* p, const T* q, const T* invd,
+hipError_t launch_cg_update(CgState* st, int par, double* red, T* x, T* r, const T* p, const T* q, const T* invd,
                             int64_t n, hipStream_t s);
 template <typename T>
-hipError_t launch_cg_pupdate(CgState* st, int par, const T* r, T* p, T* q, const T* invd, int64_t n,
+hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, const T* r, T* p, const T* invd, int64_t n,
                              hipStream_t s);
 
-hipError_t launch_residual(const double* b, const double* q, double* r, int64_t n, double* rr, hipStream_t s);
-hipError_t launch_demote(const double* r, double scale, float* r32, float* x32, int64_t n, hipStream_t s);
+// r = b - q in FP64 (r may be null) and *rr = r.r.
+hipError_t launch_residual(const double* b, const double* q, double* r, int64_t n, double* red, double* rr,
+                           hipStream_t s);
+// Residual replacement of the FP32 inner PCG: r32 = (float)(scale r64),
+// x32 = 0, and p32 = D^-1 r32 (pscale == 0: fresh start) or p32 *= pscale
+// (search direction kept across the replacement); then the state restarts at
+// parity 0 with rz[0] = r32.D^-1 r32, rr_last = r32.r32 and done = 0.
+hipError_t launch_cg_replace32(CgState* st, double* red, const double* r64, double scale, double pscale,
+                               float* r32, float* p32, float* x32, const float* invd, int64_t n, hipStream_t s);
 hipError_t launch_convert(const double* a, float* b, int64_t n, hipStream_t s);
 hipError_t launch_promote_add(double* x, const float* d, double scale, int64_t n, hipStream_t s);
 

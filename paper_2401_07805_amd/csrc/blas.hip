@@ -6,49 +6,91 @@
 // round trips.  One iteration is three kernels:
 //   apply:    q = A p and pAp = p.q                         (apply kernels)
 //   update:   alpha = rz/pAp; x += alpha p; r -= alpha q;
-//             accumulate r.r and r.(D^-1 r)
-//   pupdate:  beta = rz_new/rz; p = D^-1 r + beta p;
-//             block 0 records the iteration and the convergence flag and
-//             clears the accumulators of the next iteration.
-// The accumulated scalars are double-buffered by iteration parity, so no
-// kernel ever reads a scalar that the same kernel writes.  Once `done` is set, every
-// kernel returns immediately, so replays past convergence change nothing.
+//             per-workgroup partial sums of r.r and r.(D^-1 r)
+//   pupdate:  every workgroup sums the partials in the same fixed order,
+//             beta = rz_new/rz; p = D^-1 r + beta p; workgroup 0 records the
+//             iteration and the stop decision.
+// Reductions use no atomics: a producer writes one partial per workgroup and
+// the consumer sums them in a fixed order, so every run gives the same bits.
+//
+// Stop flags are double-buffered by iteration parity: the kernels of the
+// iteration of parity `par` test halt[par], and pupdate(par) writes only
+// halt[1-par] (propagating a stop it sees), so no kernel reads a flag that the
+// same kernel writes.  Once a stop is set every later kernel returns at once.
 #include "blas.h"
 
 namespace vpp {
 
+constexpr int BT = 256;
+
+// 16-byte packet of T (two doubles or four floats): one dwordx4 access.
+template <typename T>
+struct alignas(16) Pack {
+    static constexpr int W = 16 / (int)sizeof(T);
+    T v[W];
+};
+
+// Workgroup sums of two doubles in a fixed order (butterfly inside each wave,
+// then the waves in index order); every thread receives the totals.
 template <int NT>
-__device__ __forceinline__ void block_sum2(double a, double b, double* outa, double* outb)
+__device__ __forceinline__ void block_sum2(double& a, double& b)
 {
+    static_assert(NT % 64 == 0, "whole waves only");
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o);
         b += __shfl_xor(b, o);
     }
     __shared__ double pa[NT / 64], pb[NT / 64];
-    const int w = threadIdx.x / 64;
+    __syncthreads();
     if ((threadIdx.x & 63) == 0) {
-        pa[w] = a;
-        pb[w] = b;
+        pa[threadIdx.x / 64] = a;
+        pb[threadIdx.x / 64] = b;
     }
     __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        sa += pa[i];
+        sb += pb[i];
+    }
+    a = sa;
+    b = sb;
+}
+
+// Totals of the ng partials of both quantities (every thread receives them).
+__device__ __forceinline__ void sum_partials(const double* red, int ng, double& a, double& b)
+{
+    a = 0.0;
+    b = 0.0;
+    for (int i = threadIdx.x; i < ng; i += BT) {
+        a += red[i];
+        b += red[kMaxRedBlocks + i];
+    }
+    block_sum2<BT>(a, b);
+}
+
+__device__ __forceinline__ void write_partials(double* red, double a, double b)
+{
     if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
-        for (int i = 0; i < NT / 64; ++i) {
-            sa += pa[i];
-            sb += pb[i];
-        }
-        if (outa) atomicAdd(outa, sa);
-        if (outb) atomicAdd(outb, sb);
+        red[blockIdx.x] = a;
+        red[kMaxRedBlocks + blockIdx.x] = b;
     }
 }
 
-constexpr int BT = 256;
-
-// r = b - q (q may be null: zero initial guess), p = D^-1 r; the initial r.r is
-// accumulated into rr_last and r.D^-1 r into rz[0] (both zeroed by the host).
+// Number of workgroups of the streaming kernels (about 4 packets per thread).
 template <typename T>
-__global__ void __launch_bounds__(BT) cg_init_kernel(CgState* st, const T* __restrict__ b, const T* __restrict__ q,
+static int grid_for(int64_t n)
+{
+    const int64_t packets = (n + Pack<T>::W - 1) / Pack<T>::W;
+    const int64_t want = (packets + 4 * BT - 1) / (4 * BT);
+    return (int)(want < 1 ? 1 : (want > kMaxRedBlocks ? kMaxRedBlocks : want));
+}
+
+// r = b - q (q may be null: zero initial guess), p = D^-1 r; partials of r.r
+// and r.D^-1 r.
+template <typename T>
+__global__ void __launch_bounds__(BT) cg_init_kernel(double* red, const T* __restrict__ b, const T* __restrict__ q,
                                                      T* __restrict__ r, T* __restrict__ p,
                                                      const T* __restrict__ invd, int64_t n)
 {
@@ -61,83 +103,160 @@ __global__ void __launch_bounds__(BT) cg_init_kernel(CgState* st, const T* __res
         rr += (double)ri * (double)ri;
         rz += (double)ri * (double)zi;
     }
-    block_sum2<BT>(rr, rz, &st->rr_last, &st->rz[0]);
+    block_sum2<BT>(rr, rz);
+    write_partials(red, rr, rz);
+}
+
+// One workgroup: rr_last = r.r, rz[0] = r.D^-1 r.
+__global__ void __launch_bounds__(BT) cg_init_finish_kernel(CgState* st, const double* red, int ng)
+{
+    double rr, rz;
+    sum_partials(red, ng, rr, rz);
+    if (threadIdx.x == 0) {
+        st->rr_last = rr;
+        st->rz[0] = rz;
+    }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BT) cg_update_kernel(CgState* st, int par, T* __restrict__ x, T* __restrict__ r,
-                                                       const T* __restrict__ p, const T* __restrict__ q,
-                                                       const T* __restrict__ invd, int64_t n)
+__global__ void __launch_bounds__(BT) cg_update_kernel(CgState* st, int par, double* red, T* __restrict__ x,
+                                                       T* __restrict__ r, const T* __restrict__ p,
+                                                       const T* __restrict__ q, const T* __restrict__ invd,
+                                                       int64_t n)
 {
-    if (st->done) return;
+    if (st->halt[par]) return;
     const double pAp = st->pAp;
     if (!(pAp > 0.0) || !isfinite(pAp)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->breakdown = 1;
-            st->done = 1;
-        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->breakdown = 1;
         return;
     }
-    const double alpha_d = st->rz[par] / pAp;
-    const T alpha = T(alpha_d);
+    const T alpha = T(st->rz[par] / pAp);
     double rr = 0.0, rz = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
-        x[i] = fma(alpha, p[i], x[i]);
-        const T ri = fma(-alpha, q[i], r[i]);
-        r[i] = ri;
-        rr += (double)ri * (double)ri;
-        rz += (double)ri * (double)(ri * invd[i]);
+    using P = Pack<T>;
+    const int64_t np = n / P::W;
+    for (int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x; c < np; c += (int64_t)gridDim.x * BT) {
+        P xv = reinterpret_cast<const P*>(x)[c];
+        P rv = reinterpret_cast<const P*>(r)[c];
+        const P pv = reinterpret_cast<const P*>(p)[c];
+        const P qv = reinterpret_cast<const P*>(q)[c];
+        const P dv = reinterpret_cast<const P*>(invd)[c];
+#pragma unroll
+        for (int j = 0; j < P::W; ++j) {
+            xv.v[j] = fma(alpha, pv.v[j], xv.v[j]);
+            const T ri = fma(-alpha, qv.v[j], rv.v[j]);
+            rv.v[j] = ri;
+            rr += (double)ri * (double)ri;
+            rz += (double)ri * (double)(ri * dv.v[j]);
+        }
+        reinterpret_cast<P*>(x)[c] = xv;
+        reinterpret_cast<P*>(r)[c] = rv;
     }
-    block_sum2<BT>(rr, rz, &st->rr[par], &st->rznew[par]);
+    if (blockIdx.x == 0)
+        for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) {
+            x[i] = fma(alpha, p[i], x[i]);
+            const T ri = fma(-alpha, q[i], r[i]);
+            r[i] = ri;
+            rr += (double)ri * (double)ri;
+            rz += (double)ri * (double)(ri * invd[i]);
+        }
+    block_sum2<BT>(rr, rz);
+    write_partials(red, rr, rz);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BT) cg_pupdate_kernel(CgState* st, int par, const T* __restrict__ r, T* __restrict__ p,
-                                                        T* __restrict__ q, const T* __restrict__ invd, int64_t n)
+__global__ void __launch_bounds__(BT) cg_pupdate_kernel(CgState* st, int par, const double* red, int ng,
+                                                        const T* __restrict__ r, T* __restrict__ p,
+                                                        const T* __restrict__ invd, int64_t n)
 {
-    if (st->done) return;
-    const double rznew = st->rznew[par];
-    const double beta_d = rznew / st->rz[par];
+    if (st->halt[par] || st->breakdown) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->halt[1 - par] = 1;
+        return;
+    }
+    double rr, rzn;
+    sum_partials(red, ng, rr, rzn);
+    const double beta_d = rzn / st->rz[par];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const double rr = st->rr[par];
-        st->iters += 1;
+        const int it = st->iters + 1;
+        st->iters = it;
         st->rr_last = rr;
-        st->rz[1 - par] = rznew;
-        st->rr[1 - par] = 0.0;
-        st->rznew[1 - par] = 0.0;
-        if (!isfinite(rr) || !isfinite(rznew)) {
+        st->rr[par] = rr;
+        st->rznew[par] = rzn;
+        st->rz[1 - par] = rzn;
+        if (!isfinite(rr) || !isfinite(rzn)) {
             st->breakdown = 1;
-            st->done = 1;
-        } else if (rr < st->tol2 || st->iters >= st->max_iter) {
-            st->done = 1;
+            st->halt[1 - par] = 1;
+        } else if (rr < st->tol2 || it >= st->max_iter) {
+            st->halt[1 - par] = 1;
         }
     }
     const T beta = T(beta_d);
-    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT)
-        p[i] = fma(beta, p[i], r[i] * invd[i]);
+    using P = Pack<T>;
+    const int64_t np = n / P::W;
+    for (int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x; c < np; c += (int64_t)gridDim.x * BT) {
+        const P rv = reinterpret_cast<const P*>(r)[c];
+        const P dv = reinterpret_cast<const P*>(invd)[c];
+        P pv = reinterpret_cast<const P*>(p)[c];
+#pragma unroll
+        for (int j = 0; j < P::W; ++j) pv.v[j] = fma(beta, pv.v[j], rv.v[j] * dv.v[j]);
+        reinterpret_cast<P*>(p)[c] = pv;
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) p[i] = fma(beta, p[i], r[i] * invd[i]);
 }
 
-// r = b - q in FP64 and its squared norm (outer residual of the mixed solver and
+// r = b - q in FP64 and partials of r.r (outer residual of the mixed solver and
 // the true residual at the end of every solve).
 __global__ void __launch_bounds__(BT) residual_kernel(const double* __restrict__ b, const double* __restrict__ q,
-                                                      double* __restrict__ r, int64_t n, double* rr)
+                                                      double* __restrict__ r, int64_t n, double* red)
 {
-    double s = 0.0;
+    double s = 0.0, unused = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
         const double v = b[i] - q[i];
         if (r) r[i] = v;
         s += v * v;
     }
-    block_sum2<BT>(s, 0.0, rr, nullptr);
+    block_sum2<BT>(s, unused);
+    write_partials(red, s, 0.0);
 }
 
-// r32 = (float)(scale r64); the FP32 inner iterate starts at zero.
-__global__ void __launch_bounds__(BT) demote_kernel(const double* __restrict__ r, double scale, float* __restrict__ r32,
-                                                    float* __restrict__ x32, int64_t n)
+__global__ void __launch_bounds__(BT) sum_finish_kernel(const double* red, int ng, double* out)
 {
+    double a, b;
+    sum_partials(red, ng, a, b);
+    if (threadIdx.x == 0) *out = a;
+}
+
+__global__ void __launch_bounds__(BT) cg_replace32_kernel(const double* __restrict__ r64, double scale,
+                                                          double pscale, float* __restrict__ r32,
+                                                          float* __restrict__ p32, float* __restrict__ x32,
+                                                          const float* __restrict__ invd, int64_t n, double* red)
+{
+    double rr = 0.0, rz = 0.0;
+    const float ps = (float)pscale;
     for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
-        r32[i] = (float)(scale * r[i]);
+        const float ri = (float)(scale * r64[i]);
+        const float zi = ri * invd[i];
+        r32[i] = ri;
         x32[i] = 0.0f;
+        p32[i] = pscale == 0.0 ? zi : ps * p32[i];
+        rr += (double)ri * (double)ri;
+        rz += (double)ri * (double)zi;
+    }
+    block_sum2<BT>(rr, rz);
+    write_partials(red, rr, rz);
+}
+
+// One workgroup: restart the inner state at parity 0 after a replacement.
+__global__ void __launch_bounds__(BT) cg_resume_kernel(CgState* st, const double* red, int ng)
+{
+    double rr, rz;
+    sum_partials(red, ng, rr, rz);
+    if (threadIdx.x == 0) {
+        st->rz[0] = rz;
+        st->rr_last = rr;
+        st->halt[0] = 0;
+        st->halt[1] = 0;
+        st->breakdown = 0;
     }
 }
 
@@ -154,65 +273,78 @@ __global__ void __launch_bounds__(BT) promote_add_kernel(double* __restrict__ x,
         x[i] = fma(scale, (double)d[i], x[i]);
 }
 
-static int grid_for(int64_t n)
+template <typename T>
+hipError_t launch_cg_init(CgState* st, double* red, const T* b, const T* q, T* r, T* p, const T* invd, int64_t n,
+                          hipStream_t s)
+{
+    const int g = grid_for<T>(n);
+    hipLaunchKernelGGL(cg_init_kernel<T>, dim3(g), dim3(BT), 0, s, red, b, q, r, p, invd, n);
+    hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(BT), 0, s, st, red, g);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_update(CgState* st, int par, double* red, T* x, T* r, const T* p, const T* q, const T* invd,
+                            int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid_for<T>(n)), dim3(BT), 0, s, st, par, red, x, r, p, q, invd, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, const T* r, T* p, const T* invd, int64_t n,
+                             hipStream_t s)
+{
+    const int g = grid_for<T>(n);
+    hipLaunchKernelGGL(cg_pupdate_kernel<T>, dim3(g), dim3(BT), 0, s, st, par, red, g, r, p, invd, n);
+    return hipGetLastError();
+}
+
+#define VPP_INST(T)                                                                                          \
+    template hipError_t launch_cg_init<T>(CgState*, double*, const T*, const T*, T*, T*, const T*, int64_t,  \
+                                          hipStream_t);                                                      \
+    template hipError_t launch_cg_update<T>(CgState*, int, double*, T*, T*, const T*, const T*, const T*,    \
+                                            int64_t, hipStream_t);                                           \
+    template hipError_t launch_cg_pupdate<T>(CgState*, int, const double*, const T*, T*, const T*, int64_t, \
+                                             hipStream_t);
+VPP_INST(double)
+VPP_INST(float)
+#undef VPP_INST
+
+hipError_t launch_residual(const double* b, const double* q, double* r, int64_t n, double* red, double* rr,
+                           hipStream_t s)
+{
+    const int g = grid_for<double>(n);
+    hipLaunchKernelGGL(residual_kernel, dim3(g), dim3(BT), 0, s, b, q, r, n, red);
+    hipLaunchKernelGGL(sum_finish_kernel, dim3(1), dim3(BT), 0, s, red, g, rr);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_replace32(CgState* st, double* red, const double* r64, double scale, double pscale,
+                               float* r32, float* p32, float* x32, const float* invd, int64_t n, hipStream_t s)
+{
+    const int g = grid_for<float>(n);
+    hipLaunchKernelGGL(cg_replace32_kernel, dim3(g), dim3(BT), 0, s, r64, scale, pscale, r32, p32, x32, invd, n,
+                       red);
+    hipLaunchKernelGGL(cg_resume_kernel, dim3(1), dim3(BT), 0, s, st, red, g);
+    return hipGetLastError();
+}
+
+static int grid_plain(int64_t n)
 {
     const int64_t want = (n + BT - 1) / BT;
     return (int)(want < 2048 ? (want < 1 ? 1 : want) : 2048);
 }
 
-template <typename T>
-hipError_t launch_cg_init(CgState* st, const T* b, const T* q, T* r, T* p, const T* invd, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(cg_init_kernel<T>, dim3(grid_for(n)), dim3(BT), 0, s, st, b, q, r, p, invd, n);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_cg_update(CgState* st, int par, T* x, T* r, const T* p, const T* q, const T* invd, int64_t n,
-                            hipStream_t s)
-{
-    hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid_for(n)), dim3(BT), 0, s, st, par, x, r, p, q, invd, n);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_cg_pupdate(CgState* st, int par, const T* r, T* p, T* q, const T* invd, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(cg_pupdate_kernel<T>, dim3(grid_for(n)), dim3(BT), 0, s, st, par, r, p, q, invd, n);
-    return hipGetLastError();
-}
-
-#define VPP_INST(T)                                                                                       \
-    template hipError_t launch_cg_init<T>(CgState*, const T*, const T*, T*, T*, const T*, int64_t,        \
-                                          hipStream_t);                                                   \
-    template hipError_t launch_cg_update<T>(CgState*, int, T*, T*, const T*, const T*, const T*, int64_t, \
-                                            hipStream_t);                                                 \
-    template hipError_t launch_cg_pupdate<T>(CgState*, int, const T*, T*, T*, const T*, int64_t, hipStream_t);
-VPP_INST(double)
-VPP_INST(float)
-#undef VPP_INST
-
-hipError_t launch_residual(const double* b, const double* q, double* r, int64_t n, double* rr, hipStream_t s)
-{
-    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n)), dim3(BT), 0, s, b, q, r, n, rr);
-    return hipGetLastError();
-}
-
-hipError_t launch_demote(const double* r, double scale, float* r32, float* x32, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(demote_kernel, dim3(grid_for(n)), dim3(BT), 0, s, r, scale, r32, x32, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_convert(const double* a, float* b, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(convert_kernel, dim3(grid_for(n)), dim3(BT), 0, s, a, b, n);
+    hipLaunchKernelGGL(convert_kernel, dim3(grid_plain(n)), dim3(BT), 0, s, a, b, n);
     return hipGetLastError();
 }
 
 hipError_t launch_promote_add(double* x, const float* d, double scale, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(promote_add_kernel, dim3(grid_for(n)), dim3(BT), 0, s, x, d, scale, n);
+    hipLaunchKernelGGL(promote_add_kernel, dim3(grid_plain(n)), dim3(BT), 0, s, x, d, scale, n);
     return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ struct ApplyArgs {
 
 // Per-problem launch configuration.
 struct LaunchCfg {
-    int variant;        // 0 cell per thread, 1 plane per thread, 2 cell per thread + LDS DMA staging
+    int variant;        // 0 cell per thread, 1 plane per thread, 2 cell per thread + LDS DMA staging,
+                        // 3 cell per thread with the tile's node blocks staged in LDS
     int tile[3];
 };
 

@@ -75,11 +75,13 @@ def test_apply_fp32_error(k, n):
     x = W.uniform_vectors(0, 1, m.ndofs)[0]
     yref = oracle.Operator(m, phi=phi).matvec(x)
     prob = setup_problem(m, phi)
-    say("fp32 apply", k, n)
-    y = host(prob.apply(dev(x, dtype=__import__("torch").float32)))
-    err = rel(y, yref)
-    print(f"fp32 apply k={k} n={n}: rel err {err:.3e}")
-    assert err < 2e-6
+    for cfg in vpp.config_candidates(k):
+        say("fp32 apply", k, n, cfg)
+        prob.set_config(cfg["variant"], cfg["tile"])
+        y = host(prob.apply(dev(x, dtype=__import__("torch").float32)))
+        err = rel(y, yref)
+        print(f"fp32 apply k={k} n={n} {cfg}: rel err {err:.3e}")
+        assert err < 2e-6, cfg
 
 
 @pytest.mark.parametrize("k,n,bc", [(2, (6, 5, 4), (0,) * 6), (3, (3, 4, 2), (1, 0, 1, 0, 1, 0)),
