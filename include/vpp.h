@@ -96,8 +96,8 @@ typedef struct {
 /* Kernel configuration: cells of one workgroup tile (tx, ty, tz). */
 typedef struct {
     int32_t tile[3];
-    int32_t variant;           /* 0 = cell per thread, 1 = plane per thread, 2 = cell per thread in a
-                                  persistent workgroup, 3 = cell per thread with LDS-staged blocks */
+    int32_t variant;           /* 0 = cell per thread (LDS atomic accumulation), 1 = plane per thread,
+                                  4 = cell per thread (LDS slot exchange) */
 } vpp_kernel_config;
 
 /* Create a problem on desc->device (host call, allocates device workspace and

@@ -186,6 +186,8 @@ static MeshArgs make_mesh_args(const vpp_desc& d)
 static vpp_status ensure_apply_scratch(vpp_problem p)
 {
     const int64_t ns = std::max(shared_node_count(p->m), shared_node_count(p->m32));
+    if (8 * ns >= (int64_t(1) << 32))
+        return fail(VPP_ERR_UNSUPPORTED, "mesh too large for 32-bit partial indices with this tile configuration");
     const size_t need = (size_t)std::max<int64_t>(1, 8 * ns) * sizeof(double);
     if (need > p->part_bytes) {
         if (p->part) (void)hipFree(p->part);
@@ -606,6 +608,9 @@ vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
     const int64_t ncell = (int64_t)d->ncells[0] * d->ncells[1] * d->ncells[2];
     if (N > (int64_t)INT32_MAX || ncell > (int64_t)INT32_MAX / 2)
         return fail(VPP_ERR_INVALID_ARG, "mesh too large (at most 2^31-1 nodes)");
+    for (int i = 0; i < 3; ++i)
+        if ((int64_t)k * d->ncells[i] + 1 >= (int64_t(1) << 20))
+            return fail(VPP_ERR_INVALID_ARG, "mesh too large (at most 2^20-1 nodes per direction)");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -887,6 +892,7 @@ static vpp_status batch_build_table(vpp_batch b)
         tab[i].rhs_begin = rhs;
         tab[i].part_begin = part;
         tab[i].nshared = shared_node_count(m);
+        tab[i].se = shared_enum(m, b->k, b->cfg.tile);
         item += tile_count(m);
         rhs += b->nrhs[i];
         part += 8 * std::max<int64_t>(1, tab[i].nshared) * b->nrhs[i];

@@ -9,13 +9,6 @@ namespace vpp {
     X(2, 4, 16, 4, 4)         \
     X(2, 4, 8, 8, 4)          \
     X(2, 4, 8, 4, 4)          \
-    X(2, 3, 16, 4, 4)         \
-    X(2, 3, 8, 8, 4)          \
-    X(2, 3, 8, 4, 4)          \
-    X(2, 2, 8, 8, 4)          \
-    X(2, 2, 16, 4, 4)         \
-    X(2, 2, 8, 4, 4)          \
-    X(2, 2, 32, 2, 2)         \
     X(2, 0, 16, 4, 4)         \
     X(2, 0, 8, 4, 4)          \
     X(2, 1, 8, 4, 2)          \
@@ -31,43 +24,19 @@ inline auto kernel_ptr()
 {
     if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV>;
     else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV>;
-    else if constexpr (V == 2) return &apply_stream_kernel<K, T, TX, TY, TZ, HV>;
-    else if constexpr (V == 3) return &apply_lds_kernel<K, T, TX, TY, TZ, HV>;
     else return &apply_slot_kernel<K, T, TX, TY, TZ, HV>;
-}
-
-// Workgroups that stay resident per CU for a kernel (queried once).
-template <int K, typename T, int V, int TX, int TY, int TZ, int HV>
-inline int resident_blocks()
-{
-    static int cached = -1;
-    if (cached < 0) {
-        constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : TX * TY * TZ;
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_ptr<K, T, V, TX, TY, TZ, HV>(), threads, 0) !=
-                hipSuccess ||
-            nb < 1)
-            nb = 1;
-        cached = nb;
-    }
-    return cached;
 }
 
 template <int K, typename T, int V, int TX, int TY, int TZ, int HV>
 inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
 {
-    const int ntiles = a.m.ntile[0] * a.m.ntile[1] * a.m.ntile[2];
-    int nblocks = ntiles;
-    if constexpr (V == 2) {
-        // persistent: as many workgroups as stay resident, a multiple of the 8 XCDs
-        const int resident = resident_blocks<K, T, V, TX, TY, TZ, HV>() * device_cu_count();
-        if (resident < nblocks) nblocks = resident >= 8 ? resident / 8 * 8 : resident;
-    }
+    const int nblocks = a.m.ntile[0] * a.m.ntile[1] * a.m.ntile[2];
     constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : TX * TY * TZ;
     hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV>()), dim3(nblocks), dim3(threads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    AssembleArgs<T> b{a.m, K, {TX, TY, TZ}, a.part, a.nshared, a.y, a.dot_part, nblocks, a.dot, a.done};
+    const int tile[3] = {TX, TY, TZ};
+    AssembleArgs<T> b{a.m, shared_enum(a.m, K, tile), a.part, a.nshared, a.y, a.dot_part, nblocks, a.dot, a.done};
     return launch_assemble<T>(b, s);
 }
 

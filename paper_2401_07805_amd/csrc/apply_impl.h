@@ -3,17 +3,22 @@
 // A_e = sum_q W_q c(phi_h(x_q)) B_q^T B_q evaluated on the fly by sum
 // factorisation over the tensor-product Q_k basis and (k+1)^3 Gauss points.
 //
-// Two thread mappings (the autotuner picks one per problem):
-//   variant 0, cell per thread: all (k+1)^3 values of a cell live in registers,
-//              every sweep is register-only (k = 2, and k = 3 as a candidate);
+// A workgroup owns a tile of TX x TY x TZ cells.  Thread mappings (the
+// autotuner picks one per problem and precision):
+//   variant 4, cell per thread: all (k+1)^3 values of a cell live in registers,
+//              every sweep is register-only; the cell results are exchanged
+//              through an LDS slot array without atomics (k = 2);
+//   variant 0, cell per thread with the tile's node block accumulated by LDS
+//              atomic adds (k = 2);
 //   variant 1, plane per thread: k+1 threads share a cell, each holding one
 //              x-plane of (k+1)^2 values; y/z sweeps are in registers and the
 //              x sweeps exchange planes through LDS (all k).
-// Both accumulate the workgroup tile's node block in LDS and write it out
-// coalesced: nodes inside the tile with plain stores, nodes on faces shared
-// with a neighbouring tile with atomics into a zeroed y.  Dirichlet rows get
-// y_i = x_i (identity rows of A_D); Dirichlet columns are dropped by zeroing
-// those entries of x at the gather.
+// Nodes that only this tile touches are written with plain stores; nodes on
+// planes shared with neighbouring tiles are written as per-tile partials and
+// summed, in a fixed order, by the assembly kernel (apply_misc.hip), so the
+// result does not depend on scheduling.  Dirichlet rows get y_i = x_i
+// (identity rows of A_D); Dirichlet columns are dropped by zeroing those
+// entries of x at the gather.
 #pragma once
 #include "kernels.h"
 #include "shared_nodes.h"
@@ -54,6 +59,53 @@ __device__ __forceinline__ void gather_cell(const MeshArgs& m, const S* __restri
 #pragma unroll
             for (int a0 = 0; a0 < N; ++a0)
                 u[a0 + N * (a1 + N * a2)] = T(x[base + a0 + nx * a1 + nxy * a2]);
+    if (faces) {
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+                for (int a0 = 0; a0 < N; ++a0)
+                    if (local_dirichlet<K>(faces, a0, a1, a2)) u[a0 + N * (a1 + N * a2)] = T(0);
+    }
+}
+
+// A wave-uniform 64-bit value moved into scalar registers, so that addresses
+// built from it use the scalar-base + 32-bit-lane-offset form of global memory
+// instructions (no 64-bit vector address arithmetic per access).
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename S>
+__device__ __forceinline__ S* at_byte(S* base, unsigned off)
+{
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + off);
+}
+template <typename S>
+__device__ __forceinline__ const S* at_byte(const S* base, unsigned off)
+{
+    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off);
+}
+
+// Gather of a cell's nodal values from a wave-uniform tile base `tb` (node of
+// the tile's first cell) and the lane's byte offset `lane_b` of its cell; row
+// offsets are uniform, so every load shares one offset register.
+template <int K, typename T, typename S>
+__device__ __forceinline__ void gather_cell_t(const S* __restrict__ tb, unsigned lane_b, int nx, int nxy, int faces,
+                                              T (&u)[(K + 1) * (K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1;
+#pragma unroll
+    for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0)
+                u[a0 + N * (a1 + N * a2)] = T(*at_byte(tb + (a0 + nx * a1 + nxy * a2), lane_b));
     if (faces) {
 #pragma unroll
         for (int a2 = 0; a2 < N; ++a2)
@@ -217,9 +269,25 @@ __device__ __forceinline__ double flush_owned_get(const MeshArgs& m, const TileC
     const bool has_lo[3] = {lx == 0 && tc.t[0] > 0, ly == 0 && tc.t[1] > 0, lz == 0 && tc.t[2] > 0};
     const bool has_hi[3] = {last[0] && tc.t[0] < m.ntile[0] - 1, last[1] && tc.t[1] < m.ntile[1] - 1,
                             last[2] && tc.t[2] < m.ntile[2] - 1};
-    const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
+    // 32-bit offsets: nodes relative to the tile's first node, f within the
+    // shared-node enumeration (both < 2^31 since N < 2^31)
+    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+    const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+    const T* __restrict__ xt = x + tile0;
+    T* __restrict__ yt = y + tile0;
     const int i0 = K * cx, j0 = K * cy, l0 = K * cz;
-    const int64_t gbase = node_index(m, i0, j0, l0);
+    const unsigned lane_b = (unsigned)(K * lx + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(T);
+    // bases of the shared-node enumeration (z planes, y planes, x planes) for
+    // the planes this cell can touch, lower (lo) or upper (hi) face of the tile
+    const int t0 = tc.t[0], t1 = tc.t[1], t2 = tc.t[2];
+    const int nbx = m.ntile[0] - 1, nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
+    const int cz_n = nbz * nxy;
+    const int cy_n = nby * (m.nn[2] - nbz) * nx;
+    const int ny_free = m.nn[1] - nby;
+    const int fz = i0 + nx * j0 + nxy * (t2 - 1);                       // + nxy on the upper face
+    const int fy = cz_n + i0 + nx * ((t1 - 1) + nby * (l0 - t2));        // + nx on the upper face
+    const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));   // + 1 on the upper face
+    const unsigned nsh = (unsigned)nshared;   // 8 nshared < 2^32 (checked on the host)
     double dsum = 0.0;
 #pragma unroll
     for (int a2 = 0; a2 <= K; ++a2) {
@@ -231,29 +299,29 @@ __device__ __forceinline__ double flush_owned_get(const MeshArgs& m, const TileC
             for (int a0 = 0; a0 <= K; ++a0) {
                 if (a0_only >= 0 && a0 != a0_only) continue;
                 if (a0 == K && !last[0]) continue;
-                const int64_t g = gbase + a0 + nx * a1 + nxy * a2;
+                const int row = a0 + nx * a1 + nxy * a2;   // uniform
                 const bool lo0 = a0 == 0 && has_lo[0], lo1 = a1 == 0 && has_lo[1], lo2 = a2 == 0 && has_lo[2];
                 const bool hi0 = a0 == K && has_hi[0], hi1 = a1 == K && has_hi[1], hi2 = a2 == K && has_hi[2];
-                const bool lo = lo0 || lo1 || lo2;
                 if (faces && local_dirichlet<K>(faces, a0, a1, a2)) {
-                    if (!lo) {
-                        const T xv = x[g];
-                        y[g] = xv;
-                        if (dot) dsum += (double)xv * (double)xv;
-                    }
+                    // identity row: every tile holding the node writes the same x
+                    const T xv = *at_byte(xt + row, lane_b);
+                    *at_byte(yt + row, lane_b) = xv;
+                    if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                     continue;
                 }
                 const T v = get(a0, a1, a2, last);
                 const bool s0 = lo0 || hi0, s1 = lo1 || hi1, s2 = lo2 || hi2;
                 if (s0 || s1 || s2) {
-                    int64_t f;
-                    int rank;
-                    shared_from_tile(m, tc.t, lo0, lo1, lo2, hi0, hi1, hi2, i0 + a0, j0 + a1, l0 + a2, f, rank);
-                    part[rank * nshared + f] = v;
+                    int f;
+                    if (s2) f = fz + (hi2 ? nxy : 0) + a0 + nx * a1;
+                    else if (s1) f = fy + (hi1 ? nx : 0) + a0 + nx * nby * a2;
+                    else f = fx + (hi0 ? 1 : 0) + nbx * (a1 + ny_free * a2);
+                    const int rank = (lo0 ? 1 : 0) + (s0 ? 2 : 1) * ((lo1 ? 1 : 0) + (s1 ? 2 : 1) * (lo2 ? 1 : 0));
+                    part[(unsigned)rank * nsh + (unsigned)f] = v;
                 } else {
-                    y[g] = v;
+                    *at_byte(yt + row, lane_b) = v;
                 }
-                if (dot) dsum += (double)x[g] * (double)v;
+                if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)v;
             }
         }
     }
@@ -324,150 +392,160 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a
 }
 
 // ---------------------------------------------------------------------------
-// Variant 2: one cell per thread in a persistent workgroup that walks its tiles
-// in order.  The x and phi node blocks of a tile are staged into LDS by
-// global->LDS DMA (global_load_lds, 4 bytes per lane, coalesced along x rows);
-// the blocks of the next tile are requested as soon as the current ones have
-// been read into registers, so the loads overlap the arithmetic.
-
-// Rows of the block (fixed lj, ll) are contiguous in global memory: a wave
-// instruction moves R = 64 / (BX * DW) whole rows (lanes past R rows idle), so
-// a lane's offset inside its row group is fixed for the whole kernel and the
-// row bases are wave-uniform.  Rows of a ragged tile beyond the mesh are
-// clamped onto the last valid row/column (their values are never used).
-template <typename T, int BX, int BY, int BZ>
-struct RowStage {
-    static constexpr int DW = (int)(sizeof(T) / 4);
-    static constexpr int RW = BX * DW;                 // dwords per row
-    static constexpr int R = RW <= 64 ? 64 / RW : 1;   // rows per wave instruction
-    static constexpr int CHUNKS = (RW + 63) / 64;      // instructions per row when RW > 64
-    static constexpr int ROWS = BY * BZ;
-    static constexpr int GROUPS = (ROWS + R - 1) / R;
-    // LDS footprint in dwords: every instruction writes a whole 64-dword line
-    static constexpr int LDS_DW = (GROUPS - 1) * R * RW + (CHUNKS * 64 > R * RW ? CHUNKS * 64 : R * RW) + 64;
-};
-
-template <typename T, int BX, int BY, int BZ, int NT>
-__device__ __forceinline__ void stage_block(const MeshArgs& m, const TileCoord& tc, const T* __restrict__ g,
-                                            T* lds)
+// Write-out of a one-cell-per-thread tile from the slot array in two passes
+// with little divergence:
+//   pass 1: every cell writes the K^3 nodes with local index a_d < K (its own
+//           result from registers plus the slots of the cells below it in the
+//           tile) - the same straight-line code for every lane;
+//   pass 2: the nodes of the tile block's three upper faces (local index K of
+//           the last cells), walked node by node by all threads, whose
+//           contributions all lie in slots.
+// Each node goes to y (node of this tile only), to the partial array (node on
+// a plane shared with a neighbouring tile: part[rank * nshared + f], see
+// shared_nodes.h), or is an identity row y = x (Dirichlet node; every tile
+// holding it writes the same value).  Only the positions with some a_d = K need
+// to be in the slot array.  Returns this thread's share of x . (A x); identity
+// rows count once, from the lowest tile holding them.
+template <int K>
+__device__ __forceinline__ constexpr bool owned_pos(int a0, int a1, int a2)
 {
-    using RS = RowStage<T, BX, BY, BZ>;
-    static_assert(NT % 64 == 0, "staging needs whole waves");
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int rsub = lane / RS::RW;                      // row inside the group (R > 1)
-    const int dw = lane - rsub * RS::RW;                 // dword inside the row
-    const int xi = min(dw / RS::DW, tc.ext[0] - 1);      // clamp columns of a ragged tile
-    const int part = dw % RS::DW;
-    const unsigned* gw = reinterpret_cast<const unsigned*>(g);
-    const int64_t tile0 = node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]);
-    unsigned* l32 = reinterpret_cast<unsigned*>(lds);
-    if constexpr (RS::CHUNKS == 1) {
-        for (int grp = wave; grp < RS::GROUPS; grp += NT / 64) {
-            const int row = grp * RS::R + rsub;
-            const int rr = row < RS::ROWS ? row : RS::ROWS - 1;
-            const int lj = min(rr % BY, tc.ext[1] - 1), ll = min(rr / BY, tc.ext[2] - 1);
-            const int64_t gi = tile0 + xi + (int64_t)m.nn[0] * (lj + (int64_t)m.nn[1] * ll);
-            if (rsub < RS::R)
-                __builtin_amdgcn_global_load_lds(
-                    (const void __attribute__((address_space(1)))*)(gw + gi * RS::DW + part),
-                    (void __attribute__((address_space(3)))*)(l32 + grp * RS::R * RS::RW), 4, 0, 0);
-        }
-    } else {
-        for (int it = wave; it < RS::ROWS * RS::CHUNKS; it += NT / 64) {
-            const int row = it / RS::CHUNKS, c = it % RS::CHUNKS;
-            const int d = c * 64 + lane;
-            const int xc = min(min(d, RS::RW - 1) / RS::DW, tc.ext[0] - 1);
-            const int pc = d % RS::DW;
-            const int lj = min(row % BY, tc.ext[1] - 1), ll = min(row / BY, tc.ext[2] - 1);
-            const int64_t gi = tile0 + xc + (int64_t)m.nn[0] * (lj + (int64_t)m.nn[1] * ll);
-            if (d < RS::RW)
-                __builtin_amdgcn_global_load_lds(
-                (const void __attribute__((address_space(1)))*)(gw + gi * RS::DW + pc),
-                (void __attribute__((address_space(3)))*)(l32 + row * RS::RW + c * 64), 4, 0, 0);
-        }
-    }
+    return a0 < K && a1 < K && a2 < K;
 }
 
-template <int K, typename T>
-__device__ __forceinline__ void read_cell_lds(const T* lds, int BX, int BY, int lx, int ly, int lz, int faces,
-                                              T (&u)[(K + 1) * (K + 1) * (K + 1)])
+template <int K, typename T, int TX, int TY, int TZ>
+__device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCoord& tc, const T* slot, int cs,
+                                                 const T (&u)[(K + 1) * (K + 1) * (K + 1)], bool active, int lx,
+                                                 int ly, int lz, int cx, int cy, int cz, const T* __restrict__ x,
+                                                 T* __restrict__ y, T* __restrict__ part, int64_t nshared, bool dot)
 {
-    constexpr int N = K + 1;
-#pragma unroll
-    for (int a2 = 0; a2 < N; ++a2)
-#pragma unroll
-        for (int a1 = 0; a1 < N; ++a1)
-#pragma unroll
-            for (int a0 = 0; a0 < N; ++a0) {
-                T v = lds[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))];
-                if (faces && local_dirichlet<K>(faces, a0, a1, a2)) v = T(0);
-                u[a0 + N * (a1 + N * a2)] = v;
-            }
-}
-
-template <int K, typename T, int TX, int TY, int TZ, int HV>
-__global__ void __launch_bounds__(TX * TY * TZ) apply_stream_kernel(ApplyArgs<T> a)
-{
-    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
-    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
-    constexpr int PAD = RowStage<T, BX, BY, BZ>::LDS_DW * 4 / (int)sizeof(T);
-    __shared__ T sx[PAD];
-    __shared__ T sp[PAD];
-    __shared__ T yb[BX * BY * BZ];
-    if (a.done && *a.done) return;
-    const MeshArgs& m = a.m;
-    const int ntiles = m.ntile[0] * m.ntile[1] * m.ntile[2];
-    const int G = gridDim.x;
-    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
-    for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
-    int v = blockIdx.x;
-    int tile = v < ntiles ? xcd_tile(v, ntiles) : 0;
-    TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
-    if (v < ntiles) {
-        stage_block<T, BX, BY, BZ, NT>(m, tc, a.x, sx);
-        stage_block<T, BX, BY, BZ, NT>(m, tc, a.phi, sp);
-    }
+    constexpr int N = K + 1, NT = TX * TY * TZ;
+    const int tid = threadIdx.x;
+    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+    const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+    const T* __restrict__ xt = x + tile0;
+    T* __restrict__ yt = y + tile0;
+    const int t0 = tc.t[0], t1 = tc.t[1], t2 = tc.t[2];
+    const int nbx = m.ntile[0] - 1, nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
+    const int cz_n = nbz * nxy;
+    const int cy_n = nby * (m.nn[2] - nbz) * nx;
+    const int ny_free = m.nn[1] - nby;
+    const unsigned nsh = (unsigned)nshared;
     double dsum = 0.0;
-    while (v < ntiles) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
-        const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
-        T cw[N3], u[N3];
-        if (active) {
-            read_cell_lds<K>(sp, BX, BY, lx, ly, lz, 0, cw);
-            read_cell_lds<K>(sx, BX, BY, lx, ly, lz, cell_dirichlet_faces(m, cx, cy, cz), u);
-        }
-        __syncthreads();
-        const int vn = v + G;
-        const int tile_n = vn < ntiles ? xcd_tile(vn, ntiles) : 0;
-        const TileCoord tcn = tile_coord<K, TX, TY, TZ>(m, tile_n);
-        if (vn < ntiles) {
-            stage_block<T, BX, BY, BZ, NT>(m, tcn, a.x, sx);
-            stage_block<T, BX, BY, BZ, NT>(m, tcn, a.phi, sp);
-        }
-        if (active) {
-            sweep3<K, MS, false, 0>(cw);
-            sweep3<K, MS, false, 1>(cw);
-            sweep3<K, MS, false, 2>(cw);
-            coef_weights3<K, HV>(m, cw);
-            cell_operator<K>(m, cw, u);
-            scatter_cell_lds<K>(yb, BX, BY, lx, ly, lz, u);
-        }
-        __syncthreads();
-        if (active)
-            dsum += flush_owned<K, T, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, -1, a.x, a.y, a.part,
-                                                  a.nshared, a.dot_part != nullptr);
-        __syncthreads();
-        for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = T(0);
-        v = vn;
-        tile = tile_n;
-        tc = tcn;
+
+    // ---- pass 1: owned positions of every cell
+    if (active) {
+        const int zero = NT;
+        const int nb0 = lx > 0 ? tid - 1 : zero, nb1 = ly > 0 ? tid - TX : zero, nb2 = lz > 0 ? tid - TX * TY : zero;
+        const int nb01 = lx > 0 && ly > 0 ? tid - 1 - TX : zero;
+        const int nb02 = lx > 0 && lz > 0 ? tid - 1 - TX * TY : zero;
+        const int nb12 = ly > 0 && lz > 0 ? tid - TX - TX * TY : zero;
+        const int nb012 = lx > 0 && ly > 0 && lz > 0 ? tid - 1 - TX - TX * TY : zero;
+        const bool hl0 = lx == 0 && t0 > 0, hl1 = ly == 0 && t1 > 0, hl2 = lz == 0 && t2 > 0;
+        const int faces = cell_dirichlet_faces(m, cx, cy, cz);
+        const bool dl0 = faces & 1, dl1 = faces & 4, dl2 = faces & 16;
+        const int i0 = K * cx, j0 = K * cy, l0 = K * cz;
+        const unsigned lane_b = (unsigned)(K * lx + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(T);
+        const int fz = i0 + nx * j0 + nxy * (t2 - 1);
+        const int fy = cz_n + i0 + nx * ((t1 - 1) + nby * (l0 - t2));
+        const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));
+#pragma unroll
+        for (int a2 = 0; a2 < K; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 < K; ++a1)
+#pragma unroll
+                for (int a0 = 0; a0 < K; ++a0) {
+                    const bool z0 = a0 == 0, z1 = a1 == 0, z2 = a2 == 0;
+                    T v = u[a0 + N * (a1 + N * a2)];
+                    if (z0) v += slot[(K + N * (a1 + N * a2)) * cs + nb0];
+                    if (z1) v += slot[(a0 + N * (K + N * a2)) * cs + nb1];
+                    if (z2) v += slot[(a0 + N * (a1 + N * K)) * cs + nb2];
+                    if (z0 && z1) v += slot[(K + N * (K + N * a2)) * cs + nb01];
+                    if (z0 && z2) v += slot[(K + N * (a1 + N * K)) * cs + nb02];
+                    if (z1 && z2) v += slot[(a0 + N * (K + N * K)) * cs + nb12];
+                    if (z0 && z1 && z2) v += slot[(K + N * (K + N * K)) * cs + nb012];
+                    const int row = a0 + nx * a1 + nxy * a2;   // uniform
+                    const bool lo0 = z0 && hl0, lo1 = z1 && hl1, lo2 = z2 && hl2;
+                    const bool dir = (z0 && dl0) || (z1 && dl1) || (z2 && dl2);
+                    if (dir) {
+                        const T xv = *at_byte(xt + row, lane_b);
+                        *at_byte(yt + row, lane_b) = xv;
+                        if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
+                        continue;
+                    }
+                    T* dst = at_byte(yt + row, lane_b);
+                    if (lo0 || lo1 || lo2) {
+                        const int f = lo2 ? fz + a0 + nx * a1 : (lo1 ? fy + a0 + nx * nby * a2 : fx + nbx * (a1 + ny_free * a2));
+                        const int rank = (lo0 ? 1 : 0) + (lo0 ? 2 : 1) * ((lo1 ? 1 : 0) + (lo1 ? 2 : 1) * (lo2 ? 1 : 0));
+                        dst = part + ((unsigned)rank * nsh + (unsigned)f);
+                    }
+                    *dst = v;
+                    if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)v;
+                }
     }
-    if (a.dot_part) {
-        const double s = block_sum<NT>(dsum);
-        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+
+    // ---- pass 2: nodes on the upper faces of the tile block
+    const int E0 = tc.ext[0] - 1, E1 = tc.ext[1] - 1, E2 = tc.ext[2] - 1;
+    const int nfx = (E1 + 1) * (E2 + 1), nfy = E0 * (E2 + 1), nfz = E0 * E1;
+    const int total = nfx + nfy + nfz;
+    const int E[3] = {E0, E1, E2};
+    for (int n = tid; n < total; n += NT) {
+        int c[3];
+        if (n < nfx) {
+            c[0] = E0; c[1] = n % (E1 + 1); c[2] = n / (E1 + 1);
+        } else if (n < nfx + nfy) {
+            const int r = n - nfx;
+            c[0] = r % E0; c[1] = E1; c[2] = r / E0;
+        } else {
+            const int r = n - nfx - nfy;
+            c[0] = r % E0; c[1] = r / E0; c[2] = E2;
+        }
+        // contributing (cell, local index) per direction: one or two choices
+        int cc[3][2], aa[3][2];
+        bool ok1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int q = c[d] / K, r = c[d] - q * K;
+            if (c[d] == E[d]) {
+                cc[d][0] = q - 1; aa[d][0] = K; cc[d][1] = 0; aa[d][1] = 0; ok1[d] = false;
+            } else if (r == 0) {
+                cc[d][0] = q; aa[d][0] = 0; cc[d][1] = q - 1; aa[d][1] = K; ok1[d] = q > 0;
+            } else {
+                cc[d][0] = q; aa[d][0] = r; cc[d][1] = 0; aa[d][1] = 0; ok1[d] = false;
+            }
+        }
+        T v = T(0);
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+                for (int s0 = 0; s0 < 2; ++s0) {
+                    if ((s0 && !ok1[0]) || (s1 && !ok1[1]) || (s2 && !ok1[2])) continue;
+                    const int q = aa[0][s0] + N * (aa[1][s1] + N * aa[2][s2]);
+                    const int cell = cc[0][s0] + TX * (cc[1][s1] + TY * cc[2][s2]);
+                    v += slot[q * cs + cell];
+                }
+        const int gi = tc.n0[0] + c[0], gj = tc.n0[1] + c[1], gl = tc.n0[2] + c[2];
+        const int off = c[0] + nx * c[1] + nxy * c[2];
+        const bool lo0 = c[0] == 0 && t0 > 0, lo1 = c[1] == 0 && t1 > 0, lo2 = c[2] == 0 && t2 > 0;
+        const bool hi0 = c[0] == E0 && t0 < nbx, hi1 = c[1] == E1 && t1 < nby, hi2 = c[2] == E2 && t2 < nbz;
+        if (is_dirichlet(m, gi, gj, gl)) {
+            const T xv = xt[off];
+            yt[off] = xv;
+            if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
+            continue;
+        }
+        if (lo0 || lo1 || lo2 || hi0 || hi1 || hi2) {
+            int64_t f;
+            int rank;
+            shared_from_tile(m, tc.t, lo0, lo1, lo2, hi0, hi1, hi2, gi, gj, gl, f, rank);
+            part[(unsigned)rank * nsh + (unsigned)f] = v;
+        } else {
+            yt[off] = v;
+        }
+        if (dot) dsum += (double)xt[off] * (double)v;
     }
+    return dsum;
 }
 
 // ---------------------------------------------------------------------------
@@ -528,150 +606,26 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
     const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
     const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
     for (int q = tid; q < N3; q += NT) slot[q * CS + NT] = T(0);
-    if (active) {
-        T cw[N3], u[N3];
-        cell_coefficient<K, HV>(m, a.phi, cx, cy, cz, cw);
-        gather_cell<K>(m, a.x, cx, cy, cz, cell_dirichlet_faces(m, cx, cy, cz), u);
-        cell_operator<K>(m, cw, u);
-#pragma unroll
-        for (int q = 0; q < N3; ++q) slot[q * CS + tid] = u[q];
-    }
-    __syncthreads();
-    double d = 0.0;
-    if (active) {
-        const SlotGet<K, T, TX, TY> get(slot, CS, tid, lx, ly, lz, NT);
-        d = flush_owned_get<K, T, TX, TY, TZ>(m, tc, get, lx, ly, lz, cx, cy, cz, -1, a.x, a.y, a.part, a.nshared,
-                                              a.dot_part != nullptr);
-    }
-    if (a.dot_part) {
-        const double s = block_sum<NT>(d);
-        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Variant 3: one cell per thread with the tile's x and phi node blocks staged
-// in LDS by coalesced row loads.  Every node of the block is read from global
-// memory once per tile (instead of once per cell touching it), the cell
-// gathers become LDS reads at compile-time offsets, and the write-out walks
-// the block node by node so that consecutive lanes store consecutive nodes.
-
-// Copies the x and phi node blocks of a tile into LDS (block layout: x fastest,
-// extents BX, BY, BZ).  Block nodes past the mesh end of a ragged tile are
-// clamped onto the last valid node; their values are never used.
-template <typename T, int BX, int BY, int BZ, int NT>
-__device__ __forceinline__ void stage_blocks(const MeshArgs& m, const TileCoord& tc, const T* __restrict__ x,
-                                             const T* __restrict__ phi, T* sx, T* sp)
-{
-    constexpr int NB = BX * BY * BZ, IT = (NB + NT - 1) / NT;
-    const int64_t tile0 = node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]);
-    const T* __restrict__ xt = x + tile0;
-    const T* __restrict__ pt = phi + tile0;
-    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
-    T vx[IT], vp[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int n = threadIdx.x + it * NT;
-        if (NB % NT == 0 || n < NB) {
-            const int i = min(n % BX, tc.ext[0] - 1);
-            const int j = min((n / BX) % BY, tc.ext[1] - 1);
-            const int l = min(n / (BX * BY), tc.ext[2] - 1);
-            const int off = i + nx * j + nxy * l;
-            vx[it] = xt[off];
-            vp[it] = pt[off];
-        }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int n = threadIdx.x + it * NT;
-        if (NB % NT == 0 || n < NB) {
-            sx[n] = vx[it];
-            sp[n] = vp[it];
-        }
-    }
-}
-
-// Write-out of a tile's accumulated block yb, node by node (same ownership
-// rules as flush_owned: plain stores for nodes of this tile only, partials for
-// nodes on faces shared with neighbouring tiles, identity rows y = x on
-// Dirichlet nodes by the lowest tile holding them).  xb is the staged x block.
-// Returns this thread's share of x . (A x).
-template <typename T, int BX, int BY, int BZ, int NT>
-__device__ __forceinline__ double flush_block(const MeshArgs& m, const TileCoord& tc, const T* yb, const T* xb,
-                                              T* __restrict__ y, T* __restrict__ part, int64_t nshared, bool dot)
-{
-    constexpr int NB = BX * BY * BZ, IT = (NB + NT - 1) / NT;
-    const int64_t tile0 = node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]);
-    T* __restrict__ yt = y + tile0;
-    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
-    const bool tlo0 = tc.t[0] > 0, tlo1 = tc.t[1] > 0, tlo2 = tc.t[2] > 0;
-    const bool thi0 = tc.t[0] < m.ntile[0] - 1, thi1 = tc.t[1] < m.ntile[1] - 1, thi2 = tc.t[2] < m.ntile[2] - 1;
-    double dsum = 0.0;
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int n = threadIdx.x + it * NT;
-        if (NB % NT != 0 && n >= NB) continue;
-        const int i = n % BX, j = (n / BX) % BY, l = n / (BX * BY);
-        if (i >= tc.ext[0] || j >= tc.ext[1] || l >= tc.ext[2]) continue;
-        const int off = i + nx * j + nxy * l;
-        const int gi = tc.n0[0] + i, gj = tc.n0[1] + j, gl = tc.n0[2] + l;
-        const bool lo0 = i == 0 && tlo0, lo1 = j == 0 && tlo1, lo2 = l == 0 && tlo2;
-        const bool hi0 = i == tc.ext[0] - 1 && thi0, hi1 = j == tc.ext[1] - 1 && thi1;
-        const bool hi2 = l == tc.ext[2] - 1 && thi2;
-        const T xv = xb[n];
-        if (is_dirichlet(m, gi, gj, gl)) {
-            if (!(lo0 || lo1 || lo2)) {
-                yt[off] = xv;
-                if (dot) dsum += (double)xv * (double)xv;
-            }
-            continue;
-        }
-        const T v = yb[n];
-        if (lo0 || lo1 || lo2 || hi0 || hi1 || hi2) {
-            int64_t f;
-            int rank;
-            shared_from_tile(m, tc.t, lo0, lo1, lo2, hi0, hi1, hi2, gi, gj, gl, f, rank);
-            part[rank * nshared + f] = v;
-        } else {
-            yt[off] = v;
-        }
-        if (dot) dsum += (double)xv * (double)v;
-    }
-    return dsum;
-}
-
-template <int K, typename T, int TX, int TY, int TZ, int HV>
-__global__ void __launch_bounds__(TX * TY * TZ) apply_lds_kernel(ApplyArgs<T> a)
-{
-    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
-    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1, NB = BX * BY * BZ;
-    __shared__ T sx[NB];
-    __shared__ T sb[NB];      // phi block, then the accumulation block of A x
-    if (a.done && *a.done) return;
-    const MeshArgs& m = a.m;
-    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, xcd_tile(blockIdx.x, gridDim.x));
-    stage_blocks<T, BX, BY, BZ, NT>(m, tc, a.x, a.phi, sx, sb);
-    __syncthreads();
-    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
-    const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
-    const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
     T u[N3];
     if (active) {
+        const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+        const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+        const unsigned lane_b = (unsigned)(K * lx + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(T);
         T cw[N3];
-        read_cell_lds<K>(sb, BX, BY, lx, ly, lz, 0, cw);
+        gather_cell_t<K>(a.phi + tile0, lane_b, nx, nxy, 0, cw);
         sweep3<K, MS, false, 0>(cw);
         sweep3<K, MS, false, 1>(cw);
         sweep3<K, MS, false, 2>(cw);
         coef_weights3<K, HV>(m, cw);
-        read_cell_lds<K>(sx, BX, BY, lx, ly, lz, cell_dirichlet_faces(m, cx, cy, cz), u);
+        gather_cell_t<K>(a.x + tile0, lane_b, nx, nxy, cell_dirichlet_faces(m, cx, cy, cz), u);
         cell_operator<K>(m, cw, u);
+#pragma unroll
+        for (int q = 0; q < N3; ++q)
+            if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) slot[q * CS + tid] = u[q];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < NB; i += NT) sb[i] = T(0);
-    __syncthreads();
-    if (active) scatter_cell_lds<K>(sb, BX, BY, lx, ly, lz, u);
-    __syncthreads();
-    const double d = flush_block<T, BX, BY, BZ, NT>(m, tc, sb, sx, a.y, a.part, a.nshared, a.dot_part != nullptr);
+    const double d = flush_two_pass<K, T, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy, cz, a.x, a.y,
+                                                      a.part, a.nshared, a.dot_part != nullptr);
     if (a.dot_part) {
         const double s = block_sum<NT>(d);
         if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;

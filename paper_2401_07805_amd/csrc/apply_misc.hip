@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(256) assemble_kernel(AssembleArgs<T> a)
         }
         if (threadIdx.x == 0) *a.dot = red[0];
     }
-    const SharedEnum e = shared_enum(a.m, a.k, a.tile);
+    const SharedEnum& e = a.e;
     for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < a.nshared; f += (int64_t)gridDim.x * 256) {
         int i, j, l;
         shared_node(e, f, i, j, l);
@@ -239,8 +239,6 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
 struct BatchAssembleArgs {
     const BatchProblem* probs;
     int nprob;
-    int k;
-    int tile[3];
     double* const* y;
     double* part;
     int* queue;
@@ -260,7 +258,7 @@ __global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a
     const int64_t ns = P.nshared;
     const double* part = a.part + P.part_begin + (int64_t)pr * 8 * ns;
     double* y = a.y[P.rhs_begin + pr];
-    const SharedEnum e = shared_enum(P.m, a.k, a.tile);
+    const SharedEnum& e = P.se;
     for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < ns; f += (int64_t)gridDim.x * 256) {
         int i, j, l;
         shared_node(e, f, i, j, l);
@@ -291,7 +289,7 @@ hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int
                                dim3(TX * TY * TZ), 0, s, a);                                        \
         hipError_t e = hipGetLastError();                                                           \
         if (e != hipSuccess) return e;                                                              \
-        BatchAssembleArgs b{a.probs, a.nprob, K, {TX, TY, TZ}, a.y, a.part, a.queue};               \
+        BatchAssembleArgs b{a.probs, a.nprob, a.y, a.part, a.queue};                                \
         hipLaunchKernelGGL(batch_assemble_kernel, dim3(512, (unsigned)total_rhs), dim3(256), 0, s, b);  \
         return hipGetLastError();                                                                   \
     }

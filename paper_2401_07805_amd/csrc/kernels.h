@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "common.h"
+#include "shared_nodes.h"
 
 namespace vpp {
 
@@ -23,8 +24,7 @@ struct ApplyArgs {
 
 // Per-problem launch configuration.
 struct LaunchCfg {
-    int variant;        // 0 cell per thread, 1 plane per thread, 2 cell per thread + LDS DMA staging,
-                        // 3 cell per thread with the tile's node blocks staged in LDS
+    int variant;        // 0 cell per thread (LDS atomics), 1 plane per thread, 4 cell per thread (LDS slots)
     int tile[3];
 };
 
@@ -53,8 +53,7 @@ int list_apply_configs(int k, LaunchCfg* out, int cap);
 template <typename T>
 struct AssembleArgs {
     MeshArgs m;
-    int k;
-    int tile[3];
+    SharedEnum e;        // enumeration of the shared nodes (built on the host)
     const T* part;
     int64_t nshared;
     T* y;
@@ -91,6 +90,7 @@ struct BatchProblem {
     int rhs_begin;       // first entry in the pointer tables
     int64_t part_begin;  // first partial entry of this problem's first right-hand side
     int64_t nshared;     // shared nodes of this problem (8 * nshared partial entries per rhs)
+    SharedEnum se;       // their enumeration
 };
 
 struct BatchArgs {

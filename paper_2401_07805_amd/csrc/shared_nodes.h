@@ -7,15 +7,26 @@
 
 namespace vpp {
 
+// a / b for 0 <= a < 2^31 and 1 <= b < 2^20 through a double reciprocal (a few
+// instructions instead of an integer division): (a + 0.5) / b lies at least
+// 0.5 / b from an integer, and the product's rounding error is below
+// 2^31 * 2^-52 < 0.5 / b, so truncation gives the exact quotient.
+__host__ __device__ inline int qdiv(int a, int b, double inv_b)
+{
+    (void)b;
+    return (int)(((double)a + 0.5) * inv_b);
+}
+
 // The r-th index in [0, n) that is not an interior tile boundary (multiples s,
 // 2s, ..., (nt-1)s of the tile span s): the first group [0, s) has s entries,
 // the middle groups ((g+1)s, (g+2)s) s-1 each, the last one runs to n-1.
-__host__ __device__ inline int nth_free(int r, int s, int nt)
+// inv_s1 = 1 / (s - 1).
+__host__ __device__ inline int nth_free(int r, int s, int nt, double inv_s1)
 {
     if (r < s || nt <= 1) return r;
     const int rr = r - s;
     if (s > 1) {
-        const int g = rr / (s - 1);
+        const int g = qdiv(rr, s - 1, inv_s1);
         if (g < nt - 2) return (g + 1) * s + 1 + (rr - g * (s - 1));
         return (nt - 1) * s + 1 + (rr - (nt - 2) * (s - 1));
     }
@@ -29,6 +40,7 @@ __host__ __device__ inline int nth_free(int r, int s, int nt)
 struct SharedEnum {
     int s[3], nb[3], nn[3], nt[3];
     int64_t cz, cy, cx;
+    double inv_s[3], inv_s1[3], inv_nn[3], inv_nb[3], inv_nyf;   // reciprocals for qdiv
 };
 
 __host__ __device__ inline SharedEnum shared_enum(const MeshArgs& m, int k, const int (&tile)[3])
@@ -40,38 +52,48 @@ __host__ __device__ inline SharedEnum shared_enum(const MeshArgs& m, int k, cons
         e.nb[d] = m.ntile[d] - 1;
         e.nn[d] = m.nn[d];
     }
+    for (int d = 0; d < 3; ++d) {
+        e.inv_s[d] = 1.0 / e.s[d];
+        e.inv_s1[d] = e.s[d] > 1 ? 1.0 / (e.s[d] - 1) : 0.0;
+        e.inv_nn[d] = 1.0 / e.nn[d];
+        e.inv_nb[d] = e.nb[d] > 0 ? 1.0 / e.nb[d] : 0.0;
+    }
+    e.inv_nyf = 1.0 / (e.nn[1] - e.nb[1]);
     e.cz = (int64_t)e.nb[2] * e.nn[1] * e.nn[0];
     e.cy = (int64_t)e.nb[1] * (e.nn[2] - e.nb[2]) * e.nn[0];
     e.cx = (int64_t)e.nb[0] * (e.nn[1] - e.nb[1]) * (e.nn[2] - e.nb[2]);
     return e;
 }
 
-// f < 2^31 (checked by the host): 32-bit unsigned division throughout.
+// Node (i, j, l) of enumeration position f (f < 2^31, every divisor < 2^20:
+// checked by the host), with reciprocal divisions.
 __host__ __device__ inline void shared_node(const SharedEnum& e, int64_t f64, int& i, int& j, int& l)
 {
-    unsigned f = (unsigned)f64;
-    if (f < (unsigned)e.cz) {
-        i = (int)(f % (unsigned)e.nn[0]);
-        const unsigned r = f / (unsigned)e.nn[0];
-        j = (int)(r % (unsigned)e.nn[1]);
-        l = ((int)(r / (unsigned)e.nn[1]) + 1) * e.s[2];
+    int f = (int)f64;
+    if (f < e.cz) {
+        const int r = qdiv(f, e.nn[0], e.inv_nn[0]);
+        i = f - r * e.nn[0];
+        const int p = qdiv(r, e.nn[1], e.inv_nn[1]);
+        j = r - p * e.nn[1];
+        l = (p + 1) * e.s[2];
         return;
     }
-    f -= (unsigned)e.cz;
-    if (f < (unsigned)e.cy) {
-        i = (int)(f % (unsigned)e.nn[0]);
-        const unsigned r = f / (unsigned)e.nn[0];
-        j = ((int)(r % (unsigned)e.nb[1]) + 1) * e.s[1];
-        l = nth_free((int)(r / (unsigned)e.nb[1]), e.s[2], e.nt[2]);
+    f -= (int)e.cz;
+    if (f < e.cy) {
+        const int r = qdiv(f, e.nn[0], e.inv_nn[0]);
+        i = f - r * e.nn[0];
+        const int lf = qdiv(r, e.nb[1], e.inv_nb[1]);
+        j = (r - lf * e.nb[1] + 1) * e.s[1];
+        l = nth_free(lf, e.s[2], e.nt[2], e.inv_s1[2]);
         return;
     }
-    f -= (unsigned)e.cy;
-    const int ib = (int)(f % (unsigned)e.nb[0]);
-    const unsigned r = f / (unsigned)e.nb[0];
-    i = (ib + 1) * e.s[0];
-    const unsigned ny = (unsigned)(e.nn[1] - e.nb[1]);
-    j = nth_free((int)(r % ny), e.s[1], e.nt[1]);
-    l = nth_free((int)(r / ny), e.s[2], e.nt[2]);
+    f -= (int)e.cy;
+    const int r = qdiv(f, e.nb[0], e.inv_nb[0]);
+    i = (f - r * e.nb[0] + 1) * e.s[0];
+    const int ny = e.nn[1] - e.nb[1];
+    const int lf = qdiv(r, ny, e.inv_nyf);
+    j = nth_free(r - lf * ny, e.s[1], e.nt[1], e.inv_s1[1]);
+    l = nth_free(lf, e.s[2], e.nt[2], e.inv_s1[2]);
 }
 
 // Number of tiles holding node (i, j, l) and this tile's rank among them (the
@@ -150,42 +172,10 @@ __host__ __device__ inline int sharer_count(const SharedEnum& e, int i, int j, i
     const int idx[3] = {i, j, l};
     int n = 1;
     for (int d = 0; d < 3; ++d) {
-        const int a = idx[d] / e.s[d];
+        const int a = qdiv(idx[d], e.s[d], e.inv_s[d]);
         if (idx[d] == a * e.s[d] && a > 0 && a < e.nt[d]) n *= 2;
     }
     return n;
-}
-
-// Rows (fixed j, l) that hold shared nodes: the z family (l on a z plane, every
-// j), the y family (j on a y plane, l free) and the x family (j and l free,
-// only the nodes whose i is on an x plane).  full = every node of the row is
-// shared.
-__host__ __device__ inline int shared_row_count(const MeshArgs& m)
-{
-    const int nbx = m.ntile[0] - 1, nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
-    return nbz * m.nn[1] + nby * (m.nn[2] - nbz) + (nbx > 0 ? (m.nn[1] - nby) * (m.nn[2] - nbz) : 0);
-}
-
-__host__ __device__ inline void shared_row(const MeshArgs& m, int k, const int (&tile)[3], int r, int& j, int& l,
-                                           bool& full)
-{
-    const int sy = k * tile[1], sz = k * tile[2];
-    const int nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
-    const int rz = nbz * m.nn[1], ry = nby * (m.nn[2] - nbz);
-    full = true;
-    if (r < rz) {
-        j = r % m.nn[1];
-        l = (r / m.nn[1] + 1) * sz;
-    } else if ((r -= rz) < ry) {
-        j = (r % nby + 1) * sy;
-        l = nth_free(r / nby, sz, m.ntile[2]);
-    } else {
-        r -= ry;
-        const int fy = m.nn[1] - nby;
-        j = nth_free(r % fy, sy, m.ntile[1]);
-        l = nth_free(r / fy, sz, m.ntile[2]);
-        full = false;
-    }
 }
 
 // Partial slots (tile * block size + local index) of node (i, j, l), in the

@@ -113,23 +113,6 @@ static void check(int k, const int (&nc)[3], const int (&tile)[3], int bcmask)
                             CHECK(rank == rk && rank >= 0 && rank < cnt, "tile-side rank %d vs %d\n", rank, rk);
                         }
             }
-    // row enumeration used by the assembly kernel
-    std::set<std::tuple<int, int, int>> rows_got;
-    const int nrows = shared_row_count(m);
-    for (int r = 0; r < nrows; ++r) {
-        int j, l;
-        bool full;
-        shared_row(m, k, tile, r, j, l, full);
-        CHECK(j >= 0 && j < m.nn[1] && l >= 0 && l < m.nn[2], "row out of range %d %d\n", j, l);
-        const int cnt = full ? m.nn[0] : m.ntile[0] - 1;
-        for (int t = 0; t < cnt; ++t) {
-            const int i = full ? t : (t + 1) * k * tile[0];
-            CHECK(i >= 0 && i < m.nn[0], "row node out of range\n");
-            CHECK(rows_got.insert({i, j, l}).second, "row duplicate %d %d %d\n", i, j, l);
-        }
-    }
-    CHECK(rows_got == ref, "row set mismatch k=%d nc=%d,%d,%d tile=%d,%d,%d\n", k, nc[0], nc[1], nc[2], tile[0],
-          tile[1], tile[2]);
 }
 
 int main()
