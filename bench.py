@@ -5,19 +5,24 @@ Workload (the configuration the headline metric is quoted on): unit cube,
 eps = 2h, rho_l/rho_g = 1000/1, Dirichlet faces.
 
 One step = 100 FP64 operator applies on seed-1 uniform[-1,1] vectors (every
-apply reads its own x and phi copy and writes its own y, so the 1.7 GB working
-set streams from HBM instead of the 256 MB Infinity Cache), then one FP64
-Jacobi-PCG solve and one FP64/FP32 defect-correction solve to rtol 1e-8 with
-the manufactured right-hand side b = A_D p*, p* = sin(pi x) sin(pi y) sin(pi z).
+apply reads its own x and phi copy and writes its own y, so the working set
+streams from HBM instead of the 256 MB Infinity Cache), then one FP64 Jacobi-PCG
+solve and one FP32/FP64 mixed-precision solve to rtol 1e-8 with the
+manufactured right-hand side b = A_D p*, p* = sin(pi x) sin(pi y) sin(pi z).
 
-value = operator MDoF/s of the applies (N * applies / apply time).
+value = operator MDoF/s of the applies (N * applies / apply time), timed with
+HIP events on the stream the kernels run on.  One apply is two launches: the
+tile kernel and the shared-node assembly; `roofline` prices the pair against
+24 algorithmic bytes per DoF (x and phi read, y written once).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -28,6 +33,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_DOF_F64 = 24.0      # x read, phi read, y written once per DoF
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_q2_64cube_traffic.md")
+KERNEL_SOURCES = ["apply_impl.h", "apply_configs.h", "apply_misc.hip", "apply_f64.hip", "common.h", "tables.h",
+                  "shared_nodes.h", "kernels.h"]
 
 
 def parse():
@@ -37,12 +45,36 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--applies", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time Q3/Q4 and FP32 applies")
+    ap.add_argument("--extras", action="store_true", help="also time FP32, Q3/Q4, hot-cache applies, bubble solves")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, run a plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2401_07805_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per apply from the committed counter summary, if it was taken on
+    the current kernel sources (else None)."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    mh = re.search(r"kernel sources hash:\s*([0-9a-f]+)", text)
+    mb = re.search(r"HBM bytes per apply:\s*([0-9.eE+]+)", text)
+    if not mh or not mb or mh.group(1) != kernel_hash():
+        return None
+    return float(mb.group(1))
 
 
 def cpu_baseline():
@@ -69,6 +101,67 @@ def cpu_baseline():
                       f"({m.ndofs} DoFs, nnz {op.nnz}); assembly {t_asm:.2f} s not included"}
 
 
+def timed_applies(torch, probs, xs, ys, napp, stream, prec_tensor=None):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    npool = len(probs)
+    e0.record(stream)
+    for i in range(napp):
+        probs[i % npool].apply(xs[i], out=ys[i])
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def extras(torch, vpp, W, dev, cache):
+    """Secondary figures: FP32 and hot-cache applies at Q2, Q3/Q4 applies, bubble solves."""
+    out = {}
+    for k in (2, 3, 4):
+        wl = W.droplet_at_scale(k=k, nvec=1, seed=1)
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(torch.from_numpy(wl.phi).to(dev))
+        p.tune(cache)
+        x = torch.from_numpy(wl.vectors[0]).to(dev)
+        for tag, xx in (("f64", x), ("f32", x.float())):
+            yy = torch.empty_like(xx)
+            for _ in range(3):
+                p.apply(xx, out=yy)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(50):
+                p.apply(xx, out=yy)
+            e1.record()
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 50
+            out[f"q{k}_{tag}_hot_apply_us"] = us
+            out[f"q{k}_{tag}_hot_mdofs"] = wl.mesh.ndofs / us
+        if k == 3:
+            ps = torch.from_numpy(W.sine_field(wl.mesh)).to(dev)
+            ps[torch.from_numpy(wl.mesh.boundary_mask()).to(dev)] = 0.0
+            b = p.apply(ps)
+            for prec in ("fp64", "mixed"):
+                t0 = time.perf_counter()
+                _, info = p.cg_solve(b, rtol=1e-8, precision=prec)
+                out[f"q3_cg_{prec}_s"] = time.perf_counter() - t0
+                out[f"q3_cg_{prec}_iters"] = info["iterations"]
+    wl = W.droplet_at_scale(k=2, nvec=0, bubble=True)
+    p = vpp.Problem.from_mesh(wl.mesh)
+    p.set_phi(torch.from_numpy(wl.phi).to(dev))
+    p.tune(cache)
+    ps = torch.from_numpy(W.sine_field(wl.mesh)).to(dev)
+    ps[torch.from_numpy(wl.mesh.boundary_mask()).to(dev)] = 0.0
+    b = p.apply(ps)
+    for prec in ("fp64", "mixed"):
+        p.cg_solve(b, rtol=1e-8, precision=prec)
+        t0 = time.perf_counter()
+        _, info = p.cg_solve(b, rtol=1e-8, precision=prec)
+        out[f"bubble_q2_cg_{prec}_s"] = time.perf_counter() - t0
+        out[f"bubble_q2_cg_{prec}_iters"] = info["iterations"]
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -85,7 +178,8 @@ def main():
     N = m.ndofs
     napp = args.applies
     log(f"workload {wl.name} N={N}")
-    # one phi copy per problem handle; applies rotate over them
+    # one phi copy per problem handle; applies rotate over them so that x, phi
+    # and y of consecutive applies do not share cache lines
     npool = max(1, min(napp, math.ceil(600e6 / (BYTES_PER_DOF_F64 * N))))
     phi_t = torch.from_numpy(wl.phi).to(dev)
     probs = []
@@ -95,9 +189,11 @@ def main():
         probs.append(p)
     cache = os.path.join(ROOT, "paper_2401_07805_amd", "tune_cache.json")
     cfg = probs[0].tune(cache)
+    cfg32 = probs[0].config_for("fp32")
     for p in probs[1:]:
-        p.set_config(cfg["variant"], cfg["tile"])
-    log(f"kernel config {cfg}")
+        p.set_config(cfg["variant"], cfg["tile"], "fp64")
+        p.set_config(cfg32["variant"], cfg32["tile"], "fp32")
+    log(f"kernel config fp64 {cfg} fp32 {cfg32}")
     xs_host = W.uniform_vectors(1, napp, N)
     xs = torch.from_numpy(xs_host).to(dev)
     del xs_host
@@ -106,23 +202,15 @@ def main():
     pstar[torch.from_numpy(m.boundary_mask()).to(dev)] = 0.0
     b = probs[0].apply(pstar)
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream(dev)
 
     def step():
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for i in range(napp):
-            probs[i % npool].apply(xs[i], out=ys[i])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_apply = e0.elapsed_time(e1) / 1e3
+        t_apply = timed_applies(torch, probs, xs, ys, napp, stream)
         t0 = time.perf_counter()
         p64, i64 = probs[0].cg_solve(b, rtol=1e-8)
         t_cg64 = time.perf_counter() - t0
         t0 = time.perf_counter()
-        pmx, imx = probs[0].cg_solve(b, rtol=1e-8, precision="mixed", inner_rtol=1e-3)
+        pmx, imx = probs[0].cg_solve(b, rtol=1e-8, precision="mixed", inner_rtol=1e-2)
         t_cgmx = time.perf_counter() - t0
         return t_apply, t_cg64, i64, p64, t_cgmx, imx, pmx
 
@@ -140,6 +228,7 @@ def main():
     last = res[-1]
     err64 = float(torch.linalg.norm(last[3] - pstar) / torch.linalg.norm(pstar))
     errmx = float(torch.linalg.norm(last[6] - pstar) / torch.linalg.norm(pstar))
+    traffic = measured_traffic()
     out = {
         "metric": "operator MDoF/s + CG time to rtol 1e-8, FP64 vs FP32-mixed, Q2/Q3 hex",
         "value": value,
@@ -154,20 +243,35 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "droplet 64^3 cells Q2, rho 1000/1, eps=2h, 100 applies + FP64 and mixed PCG to 1e-8",
-                   "ndofs": N, "applies_per_step": napp, "kernel": cfg},
+                   "ndofs": N, "applies_per_step": napp, "kernel_fp64": cfg, "kernel_fp32": cfg32},
         "apply_us": per_apply * 1e6,
         "cg_fp64_s": float(np.median([r[1] for r in res])),
         "cg_fp64_iters": last[2]["iterations"],
         "cg_fp64_true_rel_res": last[2]["true_rel_residual"],
         "cg_fp64_err_vs_exact": err64,
         "cg_mixed_s": float(np.median([r[4] for r in res])),
-        "cg_mixed_inner_iters": last[5]["iterations"],
-        "cg_mixed_outer": last[5]["outer_iterations"],
+        "cg_mixed_fp32_iters": last[5]["iterations"],
+        "cg_mixed_replacements": last[5]["outer_iterations"],
         "cg_mixed_true_rel_res": last[5]["true_rel_residual"],
         "cg_mixed_err_vs_exact": errmx,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic / per_apply / 1e9,
+                     "kernel": "FP64 Q2 apply = tile kernel + shared-node assembly (2 launches)"},
     }
+    if traffic is not None:
+        out["roofline"]["traffic_bytes_per_apply"] = traffic
+    if args.copy_probe:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x copy of 512 MiB")
+    if args.extras:
+        log("extras")
+        out["extras"] = extras(torch, vpp, W, dev, cache)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline()

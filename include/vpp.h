@@ -72,11 +72,14 @@ typedef struct {
  * ||r||_2 / ||r0||_2 < rtol, r0 the initial residual.  precision VPP_MIXED runs
  * the PCG recurrences with the FP32 operator and FP32 vectors and keeps the
  * solution, the residual that decides convergence and every CG scalar in FP64:
- * each time the FP32 residual has dropped by inner_rtol (0 = 1e-3) since the
+ * each time the FP32 residual has dropped by inner_rtol (0 = 1e-2) since the
  * last replacement, the FP32 correction is added to the FP64 solution and the
  * FP32 residual is replaced by the FP64 residual b - A x (the search direction
- * is kept).  inner_max_iter (0 = none) caps the FP32 iterations between two
- * replacements.  check_every = iterations between host-side checks of the
+ * is kept).  A breakdown of the FP32 recurrence (p.Ap <= 0 from FP32 rounding,
+ * possible when inner_rtol asks for more than the FP32 operator can resolve)
+ * restarts it from the FP64 residual; a second one without progress hands the
+ * rest of the solve to FP64 PCG.  inner_max_iter (0 = none) caps the FP32
+ * iterations between two replacements.  check_every = iterations between host-side checks of the
  * device stop flag (0 = 32).  Scalars of every CG are FP64. */
 typedef struct {
     double rtol, atol;
@@ -86,7 +89,7 @@ typedef struct {
 } vpp_cg_opts;
 
 typedef struct {
-    int32_t iterations;        /* CG iterations (FP32 iterations for VPP_MIXED) */
+    int32_t iterations;        /* CG iterations (for VPP_MIXED: FP32 plus any FP64 fallback iterations) */
     int32_t outer_iterations;  /* FP64 residual replacements (0 unless VPP_MIXED) */
     int32_t status;            /* vpp_status of the solve */
     double rel_residual;       /* ||r|| / ||r0|| as tracked by the (outer) iteration */

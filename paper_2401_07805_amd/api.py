@@ -120,7 +120,7 @@ class Problem:
 
     def cg_solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, rtol: float = 1e-8,
                  atol: float = 0.0, max_iter: int = 100000, precision: str = "fp64",
-                 inner_rtol: float = 1e-3, inner_max_iter: int = 0, check_every: int = 0,
+                 inner_rtol: float = 1e-2, inner_max_iter: int = 0, check_every: int = 0,
                  raise_on_failure: bool = True):
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         o = L.CgOpts(rtol, atol, int(max_iter), L.VPP_MIXED if precision == "mixed" else L.VPP_FP64,
@@ -226,7 +226,7 @@ class Batch:
         tx, ty = self._tables(xs, ys)
         _check(L.load().vpp_batch_apply(self._h, tx, ty, _stream(self.device)))
 
-    def cg_solve(self, bs, xs, rtol=1e-8, atol=0.0, max_iter=100000, precision="fp64", inner_rtol=1e-3):
+    def cg_solve(self, bs, xs, rtol=1e-8, atol=0.0, max_iter=100000, precision="fp64", inner_rtol=1e-2):
         tb, tx = self._tables(bs, xs)
         n = len(bs)
         o = L.CgOpts(rtol, atol, int(max_iter), L.VPP_MIXED if precision == "mixed" else L.VPP_FP64,

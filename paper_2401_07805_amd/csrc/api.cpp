@@ -87,6 +87,7 @@ struct CgWork {
     double *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     // FP32 inner solver vectors
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    double* xb = nullptr;         // FP64 iterate kept across a mixed-precision phase
     CgState* st = nullptr;        // device
     CgState* st32 = nullptr;      // device
     CgState* hst = nullptr;       // pinned host mirror
@@ -237,7 +238,7 @@ static void free_work(CgWork& w)
 {
     free_graphs(w);
     dev_free(w.x); dev_free(w.b); dev_free(w.r); dev_free(w.p); dev_free(w.q);
-    dev_free(w.x32); dev_free(w.r32); dev_free(w.p32); dev_free(w.q32);
+    dev_free(w.x32); dev_free(w.r32); dev_free(w.p32); dev_free(w.q32); dev_free(w.xb);
     dev_free(w.st); dev_free(w.st32); dev_free(w.rr); dev_free(w.red);
     if (w.hst) (void)hipHostFree(w.hst);
     if (w.hrr) (void)hipHostFree(w.hrr);
@@ -262,7 +263,8 @@ static vpp_status ensure_work(vpp_problem p, bool mixed)
     }
     if (mixed && !w.x32) {
         if ((s = dev_alloc(&w.x32, n, "cg x32")) || (s = dev_alloc(&w.r32, n, "cg r32")) ||
-            (s = dev_alloc(&w.p32, n, "cg p32")) || (s = dev_alloc(&w.q32, n, "cg q32")))
+            (s = dev_alloc(&w.p32, n, "cg p32")) || (s = dev_alloc(&w.q32, n, "cg q32")) ||
+            (s = dev_alloc(&w.xb, n, "cg x kept")))
             return s;
     }
     return VPP_OK;
@@ -428,7 +430,7 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
     }
     const double thr = std::max(o.rtol * r0, o.atol);
     if (!(r0 >= thr) || r0 == 0.0) return VPP_OK;
-    const double delta = o.inner_rtol > 0 ? o.inner_rtol : 1e-3;
+    const double delta = o.inner_rtol > 0 ? o.inner_rtol : 1e-2;
     CgState* hs = w.hst;
     std::memset(hs, 0, sizeof(CgState));
     hs->tol2 = delta * delta;   // the replaced residual has unit norm
@@ -437,7 +439,7 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
     double rn = r0;
     VPP_HIP(launch_cg_replace32(w.st32, w.red, w.r, 1.0 / rn, 0.0, w.r32, w.p32, w.x32, p->inv32, p->N, s));
     const int max_phases = 10000;
-    int last_iters = 0;
+    int last_iters = 0, bad_phases = 0;
     while (true) {
         // per-phase iteration cap (inner_max_iter), within the overall max_iter
         int cap = o.max_iter;
@@ -445,35 +447,52 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
         hs->max_iter = cap;
         VPP_HIP(hipMemcpyAsync(&w.st32->max_iter, &hs->max_iter, sizeof(int), hipMemcpyHostToDevice, s));
         if ((st = run_until_done(p, w.g32, w.st32, hs, o.max_iter))) return st;
-        const int phase_iters = hs->iters - last_iters;
         last_iters = hs->iters;
+        const bool broke = hs->breakdown != 0;
+        // apply the phase's correction, keeping the previous iterate
+        VPP_HIP(hipMemcpyAsync(w.xb, w.x, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
         VPP_HIP(launch_promote_add(w.x, w.x32, rn, p->N, s));
         if ((st = residual64(p, &rr))) return st;
         const double rn_new = std::sqrt(rr);
         info.outer_iterations += 1;
-        if (!std::isfinite(rn_new)) {
-            info.status = VPP_ERR_BREAKDOWN;
-            rn = rn_new;
-            break;
-        }
         if (rn_new < thr) {
             rn = rn_new;
             break;
         }
-        if (hs->breakdown) {
-            info.status = VPP_ERR_BREAKDOWN;
-            rn = rn_new;
-            break;
+        if (!(rn_new < rn)) {
+            // no progress (or a non-finite correction from an FP32 breakdown):
+            // drop the phase, and hand over to FP64 PCG after two such phases
+            VPP_HIP(hipMemcpyAsync(w.x, w.xb, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if ((st = residual64(p, &rr))) return st;
+            if (++bad_phases >= 2 || hs->iters >= o.max_iter) {
+                vpp_cg_info f64{};
+                double r0f = 0.0;
+                vpp_cg_opts of = o;
+                of.max_iter = std::max(0, o.max_iter - hs->iters);
+                of.atol = std::max(o.atol, thr);
+                of.rtol = 0.0;
+                if ((st = pcg64(p, of, f64, &r0f))) return st;
+                info.iterations = hs->iters + f64.iterations;
+                info.status = f64.status;
+                double rr_end;
+                if ((st = residual64(p, &rr_end))) return st;
+                info.rel_residual = r0 > 0 ? std::sqrt(rr_end) / r0 : 0.0;
+                return VPP_OK;
+            }
+            // restart the FP32 recurrence from the kept iterate's residual
+            VPP_HIP(launch_cg_replace32(w.st32, w.red, w.r, 1.0 / rn, 0.0, w.r32, w.p32, w.x32, p->inv32, p->N, s));
+            continue;
         }
-        if (hs->iters >= o.max_iter || info.outer_iterations >= max_phases ||
-            (phase_iters == 0 && !(rn_new < rn))) {
+        bad_phases = 0;
+        if (hs->iters >= o.max_iter || info.outer_iterations >= max_phases) {
             info.status = VPP_ERR_NOT_CONVERGED;
             rn = rn_new;
             break;
         }
-        // keep the direction: it was built on the residual scaled by 1/rn
-        VPP_HIP(launch_cg_replace32(w.st32, w.red, w.r, 1.0 / rn_new, rn / rn_new, w.r32, w.p32, w.x32, p->inv32,
-                                    p->N, s));
+        // keep the direction (built on the residual scaled by 1/rn) unless the
+        // FP32 recurrence broke down (p.Ap <= 0 from rounding): then restart it
+        VPP_HIP(launch_cg_replace32(w.st32, w.red, w.r, 1.0 / rn_new, broke ? 0.0 : rn / rn_new, w.r32, w.p32, w.x32,
+                                    p->inv32, p->N, s));
         rn = rn_new;
     }
     info.iterations = hs->iters;

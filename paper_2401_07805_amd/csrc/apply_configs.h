@@ -19,20 +19,20 @@ namespace vpp {
     X(4, 1, 2, 2, 2)          \
     X(4, 1, 4, 4, 1)
 
-template <int K, typename T, int V, int TX, int TY, int TZ, int HV>
+template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT>
 inline auto kernel_ptr()
 {
-    if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV>;
-    else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV>;
-    else return &apply_slot_kernel<K, T, TX, TY, TZ, HV>;
+    if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV, DOT>;
+    else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV, DOT>;
+    else return &apply_slot_kernel<K, T, TX, TY, TZ, HV, DOT>;
 }
 
-template <int K, typename T, int V, int TX, int TY, int TZ, int HV>
+template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT>
 inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
 {
     const int nblocks = a.m.ntile[0] * a.m.ntile[1] * a.m.ntile[2];
     constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : TX * TY * TZ;
-    hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV>()), dim3(nblocks), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV, DOT>()), dim3(nblocks), dim3(threads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int tile[3] = {TX, TY, TZ};
@@ -43,8 +43,13 @@ inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
 template <int K, typename T, int V, int TX, int TY, int TZ>
 inline hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s)
 {
-    if (a.m.heaviside == 0) return launch_hv<K, T, V, TX, TY, TZ, 0>(a, s);
-    return launch_hv<K, T, V, TX, TY, TZ, 1>(a, s);
+    // the x . (A x) partials are a separate instantiation, used inside CG only
+    if (a.dot_part) {
+        if (a.m.heaviside == 0) return launch_hv<K, T, V, TX, TY, TZ, 0, true>(a, s);
+        return launch_hv<K, T, V, TX, TY, TZ, 1, true>(a, s);
+    }
+    if (a.m.heaviside == 0) return launch_hv<K, T, V, TX, TY, TZ, 0, false>(a, s);
+    return launch_hv<K, T, V, TX, TY, TZ, 1, false>(a, s);
 }
 
 template <typename T>

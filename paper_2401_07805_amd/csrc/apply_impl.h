@@ -359,7 +359,7 @@ __device__ __forceinline__ void scatter_cell_lds(T* yb, int BX, int BY, int lx, 
 // Variant 0: one cell per thread, operands gathered straight from global memory,
 // one tile per workgroup.
 
-template <int K, typename T, int TX, int TY, int TZ, int HV>
+template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT>
 __global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a)
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
@@ -384,8 +384,8 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a
     double d = 0.0;
     if (cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2])
         d = flush_owned<K, T, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, -1, a.x, a.y, a.part, a.nshared,
-                                          a.dot_part != nullptr);
-    if (a.dot_part) {
+                                          DOT);
+    if constexpr (DOT) {
         const double s = block_sum<NT>(d);
         if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
     }
@@ -592,7 +592,7 @@ struct SlotGet {
     }
 };
 
-template <int K, typename T, int TX, int TY, int TZ, int HV>
+template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT>
 __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a)
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ, CS = NT + 1;
@@ -625,8 +625,8 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
     }
     __syncthreads();
     const double d = flush_two_pass<K, T, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy, cz, a.x, a.y,
-                                                      a.part, a.nshared, a.dot_part != nullptr);
-    if (a.dot_part) {
+                                                      a.part, a.nshared, DOT);
+    if constexpr (DOT) {
         const double s = block_sum<NT>(d);
         if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
     }
@@ -646,7 +646,7 @@ __device__ __forceinline__ double pick(int r, int i)
     return v;
 }
 
-template <int K, typename T, int TX, int TY, int TZ, int HV>
+template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT>
 __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(ApplyArgs<T> a)
 {
     constexpr int N = K + 1, N2 = N * N, NC = TX * TY * TZ, NT = N * NC;
@@ -794,9 +794,9 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     if (active) {
         const SlotGet<K, T, TX, TY> get(slot, SS, cell, lx, ly, lz, NC);
         d = flush_owned_get<K, T, TX, TY, TZ>(m, tc, get, lx, ly, lz, cx, cy, cz, ip, a.x, a.y, a.part, a.nshared,
-                                              a.dot_part != nullptr);
+                                              DOT);
     }
-    if (a.dot_part) {
+    if constexpr (DOT) {
         const double s = block_sum<NT>(d);
         if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
     }

@@ -134,3 +134,60 @@ def test_argument_errors():
     with pytest.raises(vpp.VppError) as e:
         vpp.Problem((2, 2, 2), 2, rho_l=-1.0)
     assert e.value.status == 1
+
+
+def test_mixed_recovers_from_fp32_breakdown():
+    """A very small inner_rtol asks the FP32 recurrence for more than the FP32
+    operator resolves (p.Ap <= 0 from rounding on the smoothest modes); the solver
+    restarts / finishes in FP64 and still meets the FP64 residual criterion."""
+    m = W.unit_cube(32, 2, 1000.0, 1.0)
+    m.eps = 2.0 / 32
+    phi = W.droplet_phi(m, 0.25, m.eps)
+    op = oracle.Operator(m, phi=phi)
+    pstar = W.sine_field(m)
+    b = oracle.discrete_manufactured_rhs(op, m, pstar)
+    prob = _setup(m, phi)
+    for inner in (1e-2, 1e-7):
+        say("mixed inner_rtol", inner)
+        p, info = prob.cg_solve(dev(b), rtol=1e-8, precision="mixed", inner_rtol=inner)
+        res = np.linalg.norm(b - op.matvec(host(p))) / np.linalg.norm(b)
+        print("inner", inner, info, "res", res)
+        assert info["status"] == 0 and res < 1e-8 * 1.01
+
+
+def test_c2_mixed_levels_against_fp64():
+    """C2 at levels 24 and 48 (Q3, 20 spheres, ratio 1e4): mixed reaches the FP64
+    residual criterion and the tight FP64 GPU solve (itself oracle-pinned at the
+    small levels above) to within the error the rtol allows."""
+    for n in (24, 48):
+        wl = W.spheres_mixed(n=n, k=3)
+        m = wl.mesh
+        prob = _setup(m, wl.phi)
+        pstar = dev(W.sine_field(m))
+        pstar[dev(m.boundary_mask().astype(np.float64)) > 0] = 0.0
+        b = prob.apply(pstar)
+        say("c2 level", n)
+        pref, iref = prob.cg_solve(b, rtol=1e-12)
+        pm, im = prob.cg_solve(b, rtol=1e-8, precision="mixed")
+        p64, i64 = prob.cg_solve(b, rtol=1e-8)
+        em, e64 = rel(host(pm), host(pref)), rel(host(p64), host(pref))
+        print("c2", n, "mixed", im, "err", em, "fp64", i64, "err", e64)
+        assert im["status"] == 0 and im["true_rel_residual"] < 1e-8 * 1.01
+        assert em < 1e-5 and e64 < 1e-5
+
+
+def test_per_precision_configs():
+    wl = W.small_droplet(n=8, k=2)
+    m = wl.mesh
+    prob = _setup(m, wl.phi)
+    x = W.uniform_vectors(3, 1, m.ndofs)[0]
+    yref = oracle.Operator(m, phi=wl.phi).matvec(x)
+    cands = vpp.config_candidates(2)
+    prob.set_config(cands[0]["variant"], cands[0]["tile"], "fp64")
+    prob.set_config(cands[-1]["variant"], cands[-1]["tile"], "fp32")
+    assert prob.config_for("fp64") == cands[0] and prob.config_for("fp32") == cands[-1]
+    say("per-precision configs")
+    assert rel(host(prob.apply(dev(x))), yref) < 1e-12
+    assert rel(host(prob.apply(dev(x, dtype=torch.float32))), yref) < 2e-6
+    p, info = prob.cg_solve(dev(oracle.sine_load(m)), rtol=1e-8, precision="mixed")
+    assert info["status"] == 0
