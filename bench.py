@@ -146,6 +146,7 @@ def extras(torch, vpp, W, dev, cache):
                 _, info = p.cg_solve(b, rtol=1e-8, precision=prec)
                 out[f"q3_cg_{prec}_s"] = time.perf_counter() - t0
                 out[f"q3_cg_{prec}_iters"] = info["iterations"]
+    out.update(batch_figures(torch, vpp, W, dev, cache))
     wl = W.droplet_at_scale(k=2, nvec=0, bubble=True)
     p = vpp.Problem.from_mesh(wl.mesh)
     p.set_phi(torch.from_numpy(wl.phi).to(dev))
@@ -159,6 +160,47 @@ def extras(torch, vpp, W, dev, cache):
         _, info = p.cg_solve(b, rtol=1e-8, precision=prec)
         out[f"bubble_q2_cg_{prec}_s"] = time.perf_counter() - t0
         out[f"bubble_q2_cg_{prec}_iters"] = info["iterations"]
+    return out
+
+
+def batch_figures(torch, vpp, W, dev, cache):
+    """The batched workload: 8 independent single-sphere meshes of 16..64 cells per
+    side (Q2, 7.6M DoFs) with 4 right-hand sides each, applied by one persistent
+    graph launch; aggregate and per-mesh DoF-rhs rates."""
+    wls = W.batch_meshes()
+    probs, xs = [], []
+    for wl in wls:
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(torch.from_numpy(wl.phi).to(dev))
+        probs.append(p)
+        xs += [torch.from_numpy(v).to(dev) for v in wl.vectors]
+    ys = [torch.empty_like(x) for x in xs]
+    nrhs = [len(wl.vectors) for wl in wls]
+    bt = vpp.Batch(probs, nrhs, tune_cache=cache)
+
+    def rate(batch, xx, yy, dofs, reps=20):
+        batch.apply(xx, yy)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            batch.apply(xx, yy)
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        return t, dofs / t / 1e6
+
+    total = sum(wl.mesh.ndofs * len(wl.vectors) for wl in wls)
+    t, r = rate(bt, xs, ys, total)
+    out = {"batch_config": bt.config, "batch_dof_rhs": total, "batch_apply_us": t * 1e6,
+           "batch_aggregate_mdofs": r, "batch_per_mesh_mdofs": []}
+    i = 0
+    for p, wl, nr in zip(probs, wls, nrhs):
+        b1 = vpp.Batch([p], [nr], tune_cache=cache)
+        _, r1 = rate(b1, xs[i:i + nr], ys[i:i + nr], wl.mesh.ndofs * nr)
+        out["batch_per_mesh_mdofs"].append({"n": wl.mesh.ncells[0], "ratio": wl.extra["ratio"], "mdofs": r1})
+        i += nr
     return out
 
 

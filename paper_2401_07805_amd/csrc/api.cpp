@@ -990,7 +990,7 @@ static vpp_status batch_tune(vpp_batch b, const char* cache_path)
     int nc = 0;
     const int all[4][3] = {{8, 8, 4}, {16, 4, 4}, {8, 4, 4}, {4, 4, 4}};
     for (int i = 0; i < 4; ++i) {
-        LaunchCfg t{0, {all[i][0], all[i][1], all[i][2]}};
+        LaunchCfg t{4, {all[i][0], all[i][1], all[i][2]}};
         if (batch_blocks_per_cu(t, b->k) > 0) cands[nc++] = t;
     }
     double best = 1e300;
@@ -1062,7 +1062,7 @@ vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32
         b->total_rhs += nrhs[i];
         b->total_dofs += probs[i]->N * nrhs[i];
     }
-    b->cfg = LaunchCfg{0, {8, 4, 4}};
+    b->cfg = LaunchCfg{4, {8, 4, 4}};
     vpp_status st;
     if ((st = dev_alloc(&b->d_probs, nprob, "batch table")) || (st = dev_alloc(&b->d_x, b->total_rhs, "batch x")) ||
         (st = dev_alloc(&b->d_y, b->total_rhs, "batch y")) || (st = dev_alloc(&b->d_queue, 1, "batch queue"))) {

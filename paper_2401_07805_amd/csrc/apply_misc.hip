@@ -190,12 +190,14 @@ int device_cu_count()
 template <int K, int TX, int TY, int TZ, int HV>
 __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
 {
-    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
-    constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
-    __shared__ double yb[BX * BY * BZ];
+    constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ, CS = NT + 1;
+    __shared__ double slot[N3 * CS];
     __shared__ int item_s;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < N3; q += NT) slot[q * CS + NT] = 0.0;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     for (;;) {
-        if (threadIdx.x == 0) item_s = atomicAdd(a.queue, 1);
+        if (tid == 0) item_s = atomicAdd(a.queue, 1);
         __syncthreads();
         const int item = item_s;
         __syncthreads();
@@ -207,11 +209,10 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
         const double* phi = a.probs[pi].phi;
         const int nrhs = a.probs[pi].nrhs, rhs0 = a.probs[pi].rhs_begin;
         const int tile = item - a.probs[pi].tile_begin;
-        const int ntiles = m.ntile[0] * m.ntile[1] * m.ntile[2];
         const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
-        const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
         const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
         const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+        // the coefficient of the tile is computed once for all right-hand sides
         double cw[N3];
         if (active) cell_coefficient<K, HV>(m, phi, cx, cy, cz, cw);
         const int faces = active ? cell_dirichlet_faces(m, cx, cy, cz) : 0;
@@ -219,19 +220,20 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             const double* x = a.x[rhs0 + r];
             double* y = a.y[rhs0 + r];
             double* part = a.part + a.probs[pi].part_begin + (int64_t)r * 8 * a.probs[pi].nshared;
-            for (int i = threadIdx.x; i < BX * BY * BZ; i += NT) yb[i] = 0.0;
-            __syncthreads();
+            double u[N3];
             if (active) {
-                double u[N3];
                 gather_cell<K>(m, x, cx, cy, cz, faces, u);
                 cell_operator<K>(m, cw, u);
-                scatter_cell_lds<K>(yb, BX, BY, lx, ly, lz, u);
+            }
+            __syncthreads();   // the previous write-out has finished reading the slots
+            if (active) {
+#pragma unroll
+                for (int q = 0; q < N3; ++q)
+                    if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) slot[q * CS + tid] = u[q];
             }
             __syncthreads();
-            if (active)
-                flush_owned<K, double, TX, TY, TZ>(m, tc, yb, lx, ly, lz, cx, cy, cz, -1, x, y, part,
-                                                   a.probs[pi].nshared, false);
-            __syncthreads();
+            flush_two_pass<K, double, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy, cz, x, y, part,
+                                                  a.probs[pi].nshared, false);
         }
     }
 }
@@ -280,7 +282,7 @@ hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int
                               hipStream_t s)
 {
 #define VPP_BL(K, TX, TY, TZ)                                                                       \
-    if (k == K && c.variant == 0 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {       \
+    if (k == K && c.variant == 4 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {       \
         if (a.heaviside == 0)                                                                       \
             hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, 0>), dim3(nblocks),                \
                                dim3(TX * TY * TZ), 0, s, a);                                        \
@@ -302,7 +304,7 @@ int batch_blocks_per_cu(const LaunchCfg& c, int k)
 {
     int nb = 0;
 #define VPP_BO(K, TX, TY, TZ)                                                                      \
-    if (k == K && c.variant == 0 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {      \
+    if (k == K && c.variant == 4 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {      \
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_apply_kernel<K, TX, TY, TZ, 0>,\
                                                          TX * TY * TZ, 0) != hipSuccess)          \
             return 0;                                                                              \

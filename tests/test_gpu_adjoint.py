@@ -77,3 +77,44 @@ def test_autograd_function_c4_small():
         fm[j] -= h
         fd = (Jof(fp) - Jof(fm)) / (2 * h)
         assert abs(fd - gphi[j]) <= 1e-5 * np.abs(gphi).max() + 1e-7 * abs(fd), (j, fd, gphi[j])
+
+
+def test_autograd_c4_full_size_fd_32_nodes():
+    """48^3 Q2, droplet r=0.3 vs target r=0.28, ratio 1000: dJ/dphi from the
+    autograd Function against central differences (step 1e-6) of J at the 32
+    seeded nodes; the homogeneity identity at full size."""
+    m, phi, phit = W.adjoint_case(n=48, k=2)
+    b = dev(oracle.sine_load(m))
+    prob = vpp.Problem.from_mesh(m)
+    say("c4 48^3 target solve")
+    prob.set_phi(dev(phit))
+    pt, _ = prob.cg_solve(b, rtol=1e-13)
+    phi_t = dev(phi).requires_grad_(True)
+    say("c4 48^3 forward + adjoint")
+    p = vpp.poisson_solve(phi_t, b, prob, rtol=1e-13)
+    J = 0.5 * ((p - pt) ** 2).sum()
+    J.backward()
+    gphi = host(phi_t.grad)
+    g = prob.last_grad_coef
+    assert g is not None and g.numel() == prob.nq
+    # sum_q c_q g_q = -(p - p_t) . p  (A(alpha c) = alpha A(c))
+    cq = dev(oracle.coef_qp(m, phi))
+    lhs = float((cq * g).sum())
+    rhs = -float(((p - pt) * p).sum())
+    assert abs(lhs - rhs) < 1e-9 * abs(rhs)
+
+    def Jof(f):
+        prob.set_phi(dev(f))
+        x, _ = prob.cg_solve(b, rtol=1e-13)
+        return 0.5 * float(((x - pt) ** 2).sum())
+
+    nodes = W.fd_nodes(m, count=32, seed=4)
+    say("c4 48^3 finite differences at 32 nodes")
+    scale = np.abs(gphi).max()
+    for j in nodes:
+        h = 1e-6
+        fp, fm = phi.copy(), phi.copy()
+        fp[j] += h
+        fm[j] -= h
+        fd = (Jof(fp) - Jof(fm)) / (2 * h)
+        assert abs(fd - gphi[j]) <= 1e-5 * scale + 1e-6 * abs(fd), (j, fd, gphi[j])
