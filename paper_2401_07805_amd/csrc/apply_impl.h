@@ -412,6 +412,105 @@ __device__ __forceinline__ constexpr bool owned_pos(int a0, int a1, int a2)
     return a0 < K && a1 < K && a2 < K;
 }
 
+// Per-tile data of the upper-face write-out.
+template <typename T>
+struct FaceCtx {
+    const MeshArgs& m;
+    const TileCoord& tc;
+    const T* slot;
+    int cs;
+    const T* __restrict__ xt;
+    T* __restrict__ yt;
+    T* __restrict__ part;
+    unsigned nsh;
+    int nx, nxy, nbx, nby, nbz;
+};
+
+// The (cell, local index) pairs of the tile touching block coordinate c along
+// one direction: on the face (c == E) only the last cell with index K; else
+// cell c / K with index c % K, plus cell c / K - 1 with index K when c is a
+// multiple of K above 0 (the second pair reads the zero column ZERO otherwise).
+template <int K>
+__device__ __forceinline__ void contributors(int c, bool face, int ncell, int stride, int zero, int& cell0,
+                                             int& q0, int& cell1, int& q1)
+{
+    if (face) {
+        cell0 = (ncell - 1) * stride;
+        q0 = K;
+        cell1 = -1;
+        q1 = 0;
+        return;
+    }
+    const int q = c / K, r = c - q * K;
+    cell0 = q * stride;
+    q0 = r;
+    cell1 = (r == 0 && q > 0) ? (q - 1) * stride : -1;
+    q1 = K;
+}
+
+// Writes the nodes of the tile block's upper face normal to direction FACE
+// (the two other coordinates strictly below their upper faces for the faces
+// written later, so every node is written once: z face first, then y, then x).
+// FULL: the tile holds TX x TY x TZ cells (compile-time extents).
+template <int K, typename T, int TX, int TY, int TZ, int FACE, bool FULL>
+__device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
+{
+    constexpr int N = K + 1, NT = TX * TY * TZ;
+    const int E0 = FULL ? K * TX : f.tc.ext[0] - 1;
+    const int E1 = FULL ? K * TY : f.tc.ext[1] - 1;
+    const int E2 = FULL ? K * TZ : f.tc.ext[2] - 1;
+    // extents of the two free coordinates (a, b) of this face
+    const int na = FACE == 0 ? E1 + 1 : E0;
+    const int nb = FACE == 2 ? E1 : E2 + 1;
+    const int count = na * nb;
+    const int nc0 = E0 / K, nc1 = E1 / K, nc2 = E2 / K;
+    const int t0 = f.tc.t[0], t1 = f.tc.t[1], t2 = f.tc.t[2];
+    double dsum = 0.0;
+    for (int n = threadIdx.x; n < count; n += NT) {
+        const int ib = n / na, ia = n - ib * na;
+        const int c0 = FACE == 0 ? E0 : ia;
+        const int c1 = FACE == 0 ? ia : (FACE == 1 ? E1 : ib);
+        const int c2 = FACE == 2 ? E2 : ib;
+        int x0, p0, x1, p1, y0, r0, y1, r1, z0, s0, z1, s1;
+        contributors<K>(c0, FACE == 0, nc0, 1, NT, x0, p0, x1, p1);
+        contributors<K>(c1, FACE == 1 || (FACE == 0 && c1 == E1), nc1, TX, NT, y0, r0, y1, r1);
+        contributors<K>(c2, FACE == 2 || (FACE != 2 && c2 == E2), nc2, TX * TY, NT, z0, s0, z1, s1);
+        const int zero = NT;
+        auto rd = [&](int cx_, int qx, int cy_, int qy, int cz_, int qz) -> T {
+            const bool ok = cx_ >= 0 && cy_ >= 0 && cz_ >= 0;
+            return f.slot[(qx + N * (qy + N * qz)) * f.cs + (ok ? cx_ + cy_ + cz_ : zero)];
+        };
+        T v = rd(x0, p0, y0, r0, z0, s0);
+        v += rd(x1, p1, y0, r0, z0, s0);
+        v += rd(x0, p0, y1, r1, z0, s0);
+        v += rd(x1, p1, y1, r1, z0, s0);
+        v += rd(x0, p0, y0, r0, z1, s1);
+        v += rd(x1, p1, y0, r0, z1, s1);
+        v += rd(x0, p0, y1, r1, z1, s1);
+        v += rd(x1, p1, y1, r1, z1, s1);
+        const int gi = f.tc.n0[0] + c0, gj = f.tc.n0[1] + c1, gl = f.tc.n0[2] + c2;
+        const unsigned off = (unsigned)(c0 + f.nx * c1 + f.nxy * c2);
+        const bool lo0 = c0 == 0 && t0 > 0, lo1 = c1 == 0 && t1 > 0, lo2 = c2 == 0 && t2 > 0;
+        const bool hi0 = c0 == E0 && t0 < f.nbx, hi1 = c1 == E1 && t1 < f.nby, hi2 = c2 == E2 && t2 < f.nbz;
+        if (is_dirichlet(f.m, gi, gj, gl)) {
+            const T xv = f.xt[off];
+            f.yt[off] = xv;
+            if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
+            continue;
+        }
+        if (lo0 || lo1 || lo2 || hi0 || hi1 || hi2) {
+            int64_t fi;
+            int rank;
+            shared_from_tile(f.m, f.tc.t, lo0, lo1, lo2, hi0, hi1, hi2, gi, gj, gl, fi, rank);
+            f.part[(unsigned)rank * f.nsh + (unsigned)fi] = v;
+        } else {
+            f.yt[off] = v;
+        }
+        if (dot) dsum += (double)f.xt[off] * (double)v;
+    }
+    return dsum;
+}
+
 template <int K, typename T, int TX, int TY, int TZ>
 __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCoord& tc, const T* slot, int cs,
                                                  const T (&u)[(K + 1) * (K + 1) * (K + 1)], bool active, int lx,
@@ -484,66 +583,16 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
     }
 
     // ---- pass 2: nodes on the upper faces of the tile block
-    const int E0 = tc.ext[0] - 1, E1 = tc.ext[1] - 1, E2 = tc.ext[2] - 1;
-    const int nfx = (E1 + 1) * (E2 + 1), nfy = E0 * (E2 + 1), nfz = E0 * E1;
-    const int total = nfx + nfy + nfz;
-    const int E[3] = {E0, E1, E2};
-    for (int n = tid; n < total; n += NT) {
-        int c[3];
-        if (n < nfx) {
-            c[0] = E0; c[1] = n % (E1 + 1); c[2] = n / (E1 + 1);
-        } else if (n < nfx + nfy) {
-            const int r = n - nfx;
-            c[0] = r % E0; c[1] = E1; c[2] = r / E0;
-        } else {
-            const int r = n - nfx - nfy;
-            c[0] = r % E0; c[1] = r / E0; c[2] = E2;
-        }
-        // contributing (cell, local index) per direction: one or two choices
-        int cc[3][2], aa[3][2];
-        bool ok1[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int q = c[d] / K, r = c[d] - q * K;
-            if (c[d] == E[d]) {
-                cc[d][0] = q - 1; aa[d][0] = K; cc[d][1] = 0; aa[d][1] = 0; ok1[d] = false;
-            } else if (r == 0) {
-                cc[d][0] = q; aa[d][0] = 0; cc[d][1] = q - 1; aa[d][1] = K; ok1[d] = q > 0;
-            } else {
-                cc[d][0] = q; aa[d][0] = r; cc[d][1] = 0; aa[d][1] = 0; ok1[d] = false;
-            }
-        }
-        T v = T(0);
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-            for (int s1 = 0; s1 < 2; ++s1)
-#pragma unroll
-                for (int s0 = 0; s0 < 2; ++s0) {
-                    if ((s0 && !ok1[0]) || (s1 && !ok1[1]) || (s2 && !ok1[2])) continue;
-                    const int q = aa[0][s0] + N * (aa[1][s1] + N * aa[2][s2]);
-                    const int cell = cc[0][s0] + TX * (cc[1][s1] + TY * cc[2][s2]);
-                    v += slot[q * cs + cell];
-                }
-        const int gi = tc.n0[0] + c[0], gj = tc.n0[1] + c[1], gl = tc.n0[2] + c[2];
-        const int off = c[0] + nx * c[1] + nxy * c[2];
-        const bool lo0 = c[0] == 0 && t0 > 0, lo1 = c[1] == 0 && t1 > 0, lo2 = c[2] == 0 && t2 > 0;
-        const bool hi0 = c[0] == E0 && t0 < nbx, hi1 = c[1] == E1 && t1 < nby, hi2 = c[2] == E2 && t2 < nbz;
-        if (is_dirichlet(m, gi, gj, gl)) {
-            const T xv = xt[off];
-            yt[off] = xv;
-            if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
-            continue;
-        }
-        if (lo0 || lo1 || lo2 || hi0 || hi1 || hi2) {
-            int64_t f;
-            int rank;
-            shared_from_tile(m, tc.t, lo0, lo1, lo2, hi0, hi1, hi2, gi, gj, gl, f, rank);
-            part[(unsigned)rank * nsh + (unsigned)f] = v;
-        } else {
-            yt[off] = v;
-        }
-        if (dot) dsum += (double)xt[off] * (double)v;
+    const bool full = tc.ext[0] == K * TX + 1 && tc.ext[1] == K * TY + 1 && tc.ext[2] == K * TZ + 1;
+    FaceCtx<T> fc{m, tc, slot, cs, xt, yt, part, nsh, nx, nxy, nbx, nby, nbz};
+    if (full) {
+        dsum += upper_face<K, T, TX, TY, TZ, 2, true>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 1, true>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 0, true>(fc, dot);
+    } else {
+        dsum += upper_face<K, T, TX, TY, TZ, 2, false>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 1, false>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 0, false>(fc, dot);
     }
     return dsum;
 }
