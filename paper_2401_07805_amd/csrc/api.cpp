@@ -186,7 +186,7 @@ static MeshArgs make_mesh_args(const vpp_desc& d)
 // partial dot product per tile.
 static vpp_status ensure_apply_scratch(vpp_problem p)
 {
-    const int64_t ns = std::max(shared_node_count(p->m), shared_node_count(p->m32));
+    const int64_t ns = std::max(shared_stride(p->m), shared_stride(p->m32));
     if (8 * ns >= (int64_t(1) << 32))
         return fail(VPP_ERR_UNSUPPORTED, "mesh too large for 32-bit partial indices with this tile configuration");
     const size_t need = (size_t)std::max<int64_t>(1, 8 * ns) * sizeof(double);
@@ -213,7 +213,7 @@ static vpp_status ensure_apply_scratch(vpp_problem p)
 // y = A x on `s`; with `dot`, also x . y (written by the assembly kernel).
 static vpp_status do_apply64(vpp_problem p, const double* x, double* y, double* dot, const int* done, hipStream_t s)
 {
-    ApplyArgs<double> a{p->m, x, y, p->phi64, p->part, shared_node_count(p->m), dot ? p->dot_part : nullptr, dot,
+    ApplyArgs<double> a{p->m, x, y, p->phi64, p->part, shared_stride(p->m), dot ? p->dot_part : nullptr, dot,
                         done};
     VPP_HIP(launch_apply_f64(p->cfg, p->k, a, s));
     return VPP_OK;
@@ -221,7 +221,7 @@ static vpp_status do_apply64(vpp_problem p, const double* x, double* y, double* 
 
 static vpp_status do_apply32(vpp_problem p, const float* x, float* y, double* dot, const int* done, hipStream_t s)
 {
-    ApplyArgs<float> a{p->m32, x, y, p->phi32, reinterpret_cast<float*>(p->part), shared_node_count(p->m32),
+    ApplyArgs<float> a{p->m32, x, y, p->phi32, reinterpret_cast<float*>(p->part), shared_stride(p->m32),
                        dot ? p->dot_part : nullptr, dot, done};
     VPP_HIP(launch_apply_f32(p->cfg32, p->k, a, s));
     return VPP_OK;
@@ -282,7 +282,7 @@ static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
     for (int it = 0; it < iters && err == hipSuccess; ++it) {
         const int par = it & 1;
         if constexpr (sizeof(T) == 8) {
-            ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, p->part, shared_node_count(p->m), p->dot_part,
+            ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, p->part, shared_stride(p->m), p->dot_part,
                                 &w.st->pAp, &w.st->halt[par]};
             err = launch_apply_f64(p->cfg, p->k, a, s);
             if (err == hipSuccess)
@@ -290,7 +290,7 @@ static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
             if (err == hipSuccess) err = launch_cg_pupdate<double>(w.st, par, w.red, w.r, w.p, p->inv64, p->N, s);
         } else {
             ApplyArgs<float> a{p->m32, w.p32, w.q32, p->phi32, reinterpret_cast<float*>(p->part),
-                               shared_node_count(p->m32), p->dot_part, &w.st32->pAp, &w.st32->halt[par]};
+                               shared_stride(p->m32), p->dot_part, &w.st32->pAp, &w.st32->halt[par]};
             err = launch_apply_f32(p->cfg32, p->k, a, s);
             if (err == hipSuccess)
                 err = launch_cg_update<float>(w.st32, par, w.red, w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
@@ -910,7 +910,7 @@ static vpp_status batch_build_table(vpp_batch b)
         tab[i].nrhs = b->nrhs[i];
         tab[i].rhs_begin = rhs;
         tab[i].part_begin = part;
-        tab[i].nshared = shared_node_count(m);
+        tab[i].nshared = shared_stride(m);
         tab[i].se = shared_enum(m, b->k, b->cfg.tile);
         item += tile_count(m);
         rhs += b->nrhs[i];

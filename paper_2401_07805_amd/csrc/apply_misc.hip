@@ -123,9 +123,34 @@ hipError_t launch_fix_diagonal(const MeshArgs& m, double* diag, double* inv64, f
 // sum of the partial slots of all tiles holding it, taken in a fixed order
 // (z, y, x tile index ascending), so the result is deterministic.
 
-// Shared nodes, streamed in the order of their enumeration f: the value is the
-// sum of the partials the 2, 4 or 8 tiles holding the node wrote to
-// part[rank * nshared + f], taken in rank order (so the result is deterministic).
+// Shared nodes, streamed in the order of their enumeration f, two per thread:
+// the value is the sum of the partials the 2, 4 or 8 tiles holding the node
+// wrote to part[rank * stride + f], taken in rank order (so the result is
+// deterministic).  Every shared node has at least two sharers, so ranks 0 and 1
+// are read as 16-byte pairs (stride and f are even).
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+
+template <typename T>
+__device__ __forceinline__ void assemble_one(const SharedEnum& e, const MeshArgs& m, const T* __restrict__ part,
+                                             int64_t stride, int64_t f, T v, T* __restrict__ y)
+{
+    int i, j, l;
+    shared_node(e, f, i, j, l);
+    if (is_dirichlet(m, i, j, l)) return;
+    const int n = sharer_count(e, i, j, l);
+    for (int c = 2; c < n; ++c) v += part[c * stride + f];
+    y[i + (int64_t)m.nn[0] * (j + (int64_t)m.nn[1] * l)] = v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) assemble_kernel(AssembleArgs<T> a)
 {
@@ -144,21 +169,20 @@ __global__ void __launch_bounds__(256) assemble_kernel(AssembleArgs<T> a)
         if (threadIdx.x == 0) *a.dot = red[0];
     }
     const SharedEnum& e = a.e;
-    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < a.nshared; f += (int64_t)gridDim.x * 256) {
-        int i, j, l;
-        shared_node(e, f, i, j, l);
-        if (is_dirichlet(a.m, i, j, l)) continue;
-        const int n = sharer_count(e, i, j, l);
-        T s = a.part[f] + a.part[a.nshared + f];
-        for (int c = 2; c < n; ++c) s += a.part[c * a.nshared + f];
-        a.y[i + (int64_t)a.m.nn[0] * (j + (int64_t)a.m.nn[1] * l)] = s;
+    const int64_t count = e.cz + e.cy + e.cx;
+    using P = typename Pair<T>::type;
+    for (int64_t f = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); f < count; f += 2 * (int64_t)gridDim.x * 256) {
+        const P r0 = *reinterpret_cast<const P*>(a.part + f);
+        const P r1 = *reinterpret_cast<const P*>(a.part + a.nshared + f);
+        assemble_one(e, a.m, a.part, a.nshared, f, r0.x + r1.x, a.y);
+        if (f + 1 < count) assemble_one(e, a.m, a.part, a.nshared, f + 1, r0.y + r1.y, a.y);
     }
 }
 
 template <typename T>
 hipError_t launch_assemble(const AssembleArgs<T>& a, hipStream_t s)
 {
-    const int64_t want = (a.nshared + 255) / 256;
+    const int64_t want = (a.e.cz + a.e.cy + a.e.cx + 511) / 512;
     const int blocks = (int)(want < 1 ? 1 : (want < 8192 ? want : 8192));
     hipLaunchKernelGGL(assemble_kernel<T>, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -261,14 +285,12 @@ __global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a
     const double* part = a.part + P.part_begin + (int64_t)pr * 8 * ns;
     double* y = a.y[P.rhs_begin + pr];
     const SharedEnum& e = P.se;
-    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < ns; f += (int64_t)gridDim.x * 256) {
-        int i, j, l;
-        shared_node(e, f, i, j, l);
-        if (is_dirichlet(P.m, i, j, l)) continue;
-        const int n = sharer_count(e, i, j, l);
-        double s = part[f] + part[ns + f];
-        for (int c = 2; c < n; ++c) s += part[c * ns + f];
-        y[i + (int64_t)P.m.nn[0] * (j + (int64_t)P.m.nn[1] * l)] = s;
+    const int64_t count = e.cz + e.cy + e.cx;
+    for (int64_t f = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); f < count; f += 2 * (int64_t)gridDim.x * 256) {
+        const double2 r0 = *reinterpret_cast<const double2*>(part + f);
+        const double2 r1 = *reinterpret_cast<const double2*>(part + ns + f);
+        assemble_one(e, P.m, part, ns, f, r0.x + r1.x, y);
+        if (f + 1 < count) assemble_one(e, P.m, part, ns, f + 1, r0.y + r1.y, y);
     }
 }
 

@@ -15,8 +15,8 @@ struct ApplyArgs {
     const T* x;
     T* y;
     const T* phi;
-    T* part;            // partial values of shared nodes: 8 ranks x nshared entries
-    int64_t nshared;    // number of nodes shared by several tiles
+    T* part;            // partial values of shared nodes: part[rank * nshared + f]
+    int64_t nshared;    // stride of the rank arrays (shared_stride)
     double* dot_part;   // optional: per-workgroup partial sums of x . y (ntiles entries)
     double* dot;        // optional: x . y, written by the assembly kernel
     const int* done;    // optional: the kernels return at once when *done != 0
@@ -40,6 +40,10 @@ inline int64_t shared_node_count(const MeshArgs& m)
     return nbz * m.nn[1] * m.nn[0] + nby * (m.nn[2] - nbz) * m.nn[0] + nbx * (m.nn[1] - nby) * (m.nn[2] - nbz);
 }
 
+// Stride between the rank arrays of the partials: the count rounded up to a
+// multiple of 4, so that every rank array starts 32-byte aligned.
+inline int64_t shared_stride(const MeshArgs& m) { return (shared_node_count(m) + 3) & ~int64_t(3); }
+
 // y = A_D x as two launches on s: the tile kernel (interior nodes of y, partials
 // of shared nodes) and the assembly of the shared nodes.  y needs no
 // initialisation.  hipErrorInvalidValue for a configuration that is not
@@ -55,7 +59,7 @@ struct AssembleArgs {
     MeshArgs m;
     SharedEnum e;        // enumeration of the shared nodes (built on the host)
     const T* part;
-    int64_t nshared;
+    int64_t nshared;     // stride of the rank arrays (shared_stride); count = e.cz + e.cy + e.cx
     T* y;
     const double* dot_part;
     int ndot;
@@ -89,7 +93,7 @@ struct BatchProblem {
     int nrhs;
     int rhs_begin;       // first entry in the pointer tables
     int64_t part_begin;  // first partial entry of this problem's first right-hand side
-    int64_t nshared;     // shared nodes of this problem (8 * nshared partial entries per rhs)
+    int64_t nshared;     // stride of this problem's rank arrays (8 * nshared partial entries per rhs)
     SharedEnum se;       // their enumeration
 };
 
