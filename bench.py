@@ -147,6 +147,7 @@ def extras(torch, vpp, W, dev, cache):
                 out[f"q3_cg_{prec}_s"] = time.perf_counter() - t0
                 out[f"q3_cg_{prec}_iters"] = info["iterations"]
     out.update(batch_figures(torch, vpp, W, dev, cache))
+    out.update(c2_figures(torch, vpp, W, dev, cache))
     wl = W.droplet_at_scale(k=2, nvec=0, bubble=True)
     p = vpp.Problem.from_mesh(wl.mesh)
     p.set_phi(torch.from_numpy(wl.phi).to(dev))
@@ -160,6 +161,30 @@ def extras(torch, vpp, W, dev, cache):
         _, info = p.cg_solve(b, rtol=1e-8, precision=prec)
         out[f"bubble_q2_cg_{prec}_s"] = time.perf_counter() - t0
         out[f"bubble_q2_cg_{prec}_iters"] = info["iterations"]
+    return out
+
+
+def c2_figures(torch, vpp, W, dev, cache):
+    """Mixed precision at scale: 96^3 Q3 (24.1M DoFs), union of 20 spheres, ratio
+    1e4, eps = 1.5h; FP64 PCG and mixed PCG to rtol 1e-8 (same FP64 residual
+    criterion), errors against a tight FP64 solve (rtol 1e-11)."""
+    wl = W.spheres_mixed(n=96, k=3)
+    m = wl.mesh
+    p = vpp.Problem.from_mesh(m)
+    p.set_phi(torch.from_numpy(wl.phi).to(dev))
+    p.tune(cache)
+    ps = torch.from_numpy(W.sine_field(m)).to(dev)
+    ps[torch.from_numpy(m.boundary_mask()).to(dev)] = 0.0
+    b = p.apply(ps)
+    out = {"c2_ndofs": m.ndofs}
+    pref, iref = p.cg_solve(b, rtol=1e-11)
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        x, info = p.cg_solve(b, rtol=1e-8, precision=prec)
+        out[f"c2_cg_{prec}_s"] = time.perf_counter() - t0
+        out[f"c2_cg_{prec}_iters"] = info["iterations"]
+        out[f"c2_cg_{prec}_true_rel_res"] = info["true_rel_residual"]
+        out[f"c2_cg_{prec}_err_vs_tight_fp64"] = float(torch.linalg.norm(x - pref) / torch.linalg.norm(pref))
     return out
 
 
