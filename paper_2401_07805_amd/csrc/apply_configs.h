@@ -6,12 +6,16 @@ namespace vpp {
 
 // Instantiated configurations: (k, variant, tile).
 #define VPP_APPLY_CONFIGS(X)  \
+    X(2, 4, 8, 8, 8)          \
+    X(2, 4, 16, 8, 4)         \
     X(2, 4, 16, 4, 4)         \
     X(2, 4, 8, 8, 4)          \
     X(2, 4, 8, 4, 4)          \
     X(2, 0, 16, 4, 4)         \
     X(2, 0, 8, 4, 4)          \
     X(2, 1, 8, 4, 2)          \
+    X(3, 4, 8, 4, 4)          \
+    X(3, 4, 4, 4, 4)          \
     X(3, 1, 4, 4, 2)          \
     X(3, 1, 4, 2, 2)          \
     X(3, 1, 8, 2, 2)          \
