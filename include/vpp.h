@@ -99,8 +99,9 @@ typedef struct {
 /* Kernel configuration: cells of one workgroup tile (tx, ty, tz). */
 typedef struct {
     int32_t tile[3];
-    int32_t variant;           /* 0 = cell per thread (LDS atomic accumulation), 1 = plane per thread,
-                                  4 = cell per thread (LDS slot exchange) */
+    int32_t variant;           /* 0 = cell per thread, LDS atomic accumulation (k = 2);
+                                  1 = plane per thread (k = 2, 3, 4);
+                                  4 = cell per thread, LDS slot exchange (k = 2, 3) */
 } vpp_kernel_config;
 
 /* Create a problem on desc->device (host call, allocates device workspace and
@@ -157,10 +158,12 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream);
 /* Candidate list for a degree: writes up to `cap` configs, returns the count. */
 int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap);
 
-/* Batch of independent problems (same degree, FP64) with nrhs[i] right-hand sides
- * each, applied by ONE persistent kernel that pulls (problem, tile) work items
- * from a device queue; the coefficient of a tile is computed once and reused for
- * all right-hand sides of its problem.  The launch is recorded in a hipGraph.
+/* Batch of independent problems (same degree k = 2, FP64) with nrhs[i]
+ * right-hand sides each, applied by ONE persistent kernel that pulls
+ * (problem, tile) work items from a device queue (the coefficient of a tile is
+ * computed once and reused for all right-hand sides of its problem), followed
+ * by one assembly launch for the shared-face nodes of every (problem, rhs);
+ * both launches are recorded in one hipGraph.
  * tune_cache: JSON cache path for the autotuner, or NULL to tune without a cache.
  * The problems must have phi set and outlive the batch. */
 vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32_t nprob,
