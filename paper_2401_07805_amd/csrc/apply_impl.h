@@ -423,7 +423,7 @@ struct FaceCtx {
     T* __restrict__ yt;
     T* __restrict__ part;
     unsigned nsh;
-    int nx, nxy, nbx, nby, nbz;
+    int nx, nxy, nbx, nby, nbz, nyf;
 };
 
 // The (cell, local index) pairs of the tile touching block coordinate c along
@@ -511,6 +511,82 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
     return dsum;
 }
 
+// upper_face for a complete tile (compile-time extents), with 32-bit index
+// arithmetic and per-tile uniform bases.  Along a direction that is not FACE,
+// block coordinate c < E has the pairs (c / K, c % K) when c / K is a cell of
+// the tile and (c / K - 1, K) when c % K == 0 and c > 0; on the face (c == E)
+// only the second exists.  Along FACE only the last cell with index K holds the
+// node, so every node sums at most four slots.
+template <int K, typename T, int TX, int TY, int TZ, int FACE>
+__device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int (&fb)[3], const bool (&dlo)[3],
+                                                  const bool (&dhi)[3], bool dot)
+{
+    constexpr int N = K + 1, NT = TX * TY * TZ;
+    constexpr int E0 = K * TX, E1 = K * TY, E2 = K * TZ;
+    constexpr int NA = FACE == 0 ? E1 + 1 : E0;
+    constexpr int NB = FACE == 2 ? E1 : E2 + 1;
+    constexpr int T3[3] = {TX, TY, TZ};
+    constexpr int CST[3] = {1, TX, TX * TY};
+    const int t0 = f.tc.t[0], t1 = f.tc.t[1], t2 = f.tc.t[2];
+    const bool anyd = dlo[0] || dlo[1] || dlo[2] || dhi[0] || dhi[1] || dhi[2];
+    const bool hn[3] = {t0 < f.nbx, t1 < f.nby, t2 < f.nbz};   // a tile above along d
+    double dsum = 0.0;
+    for (int n = threadIdx.x; n < NA * NB; n += NT) {
+        const int ib = n / NA, ia = n - ib * NA;
+        const int c[3] = {FACE == 0 ? E0 : ia, FACE == 0 ? ia : (FACE == 1 ? E1 : ib), FACE == 2 ? E2 : ib};
+        // slot column and local index of the (up to) two cells along each direction
+        int ca[3], cb[3], qa[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (d == FACE) {
+                ca[d] = -1;
+                qa[d] = 0;
+                cb[d] = T3[d] - 1;
+                continue;
+            }
+            const int q = c[d] / K, r = c[d] - q * K;
+            ca[d] = q < T3[d] ? q : -1;
+            qa[d] = r;
+            cb[d] = (r == 0 && q > 0) ? q - 1 : -1;
+        }
+        T v = T(0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const bool b0 = s & 1, b1 = (s >> 1) & 1, b2 = (s >> 2) & 1;
+            if ((FACE == 0 && !b0) || (FACE == 1 && !b1) || (FACE == 2 && !b2)) continue;
+            const int x0 = b0 ? cb[0] : ca[0], x1 = b1 ? cb[1] : ca[1], x2 = b2 ? cb[2] : ca[2];
+            const int p = (b0 ? K : qa[0]) + N * ((b1 ? K : qa[1]) + N * (b2 ? K : qa[2]));
+            const bool ok = x0 >= 0 && x1 >= 0 && x2 >= 0;
+            v += f.slot[p * f.cs + (ok ? x0 * CST[0] + x1 * CST[1] + x2 * CST[2] : NT)];
+        }
+        const unsigned off = (unsigned)(c[0] + f.nx * c[1] + f.nxy * c[2]);
+        const bool lo0 = FACE != 0 && c[0] == 0 && t0 > 0;
+        const bool lo1 = FACE != 1 && c[1] == 0 && t1 > 0;
+        const bool lo2 = FACE != 2 && c[2] == 0 && t2 > 0;
+        const bool hi0 = c[0] == E0 && hn[0], hi1 = c[1] == E1 && hn[1], hi2 = c[2] == E2 && hn[2];
+        if (anyd && ((dlo[0] && c[0] == 0) || (dhi[0] && c[0] == E0) || (dlo[1] && c[1] == 0) ||
+                     (dhi[1] && c[1] == E1) || (dlo[2] && c[2] == 0) || (dhi[2] && c[2] == E2))) {
+            const T xv = f.xt[off];
+            f.yt[off] = xv;
+            if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
+            continue;
+        }
+        const bool s0 = lo0 || hi0, s1 = lo1 || hi1, s2 = lo2 || hi2;
+        if (s0 || s1 || s2) {
+            int fi;
+            if (s2) fi = fb[2] + c[0] + f.nx * c[1] + (hi2 ? f.nxy : 0);
+            else if (s1) fi = fb[1] + c[0] + f.nx * ((hi1 ? 1 : 0) + f.nby * c[2]);
+            else fi = fb[0] + (hi0 ? 1 : 0) + f.nbx * (c[1] + f.nyf * c[2]);
+            const int rank = (lo0 ? 1 : 0) + (s0 ? 2 : 1) * ((lo1 ? 1 : 0) + (s1 ? 2 : 1) * (lo2 ? 1 : 0));
+            f.part[(unsigned)rank * f.nsh + (unsigned)fi] = v;
+        } else {
+            f.yt[off] = v;
+        }
+        if (dot) dsum += (double)f.xt[off] * (double)v;
+    }
+    return dsum;
+}
+
 template <int K, typename T, int TX, int TY, int TZ>
 __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCoord& tc, const T* slot, int cs,
                                                  const T (&u)[(K + 1) * (K + 1) * (K + 1)], bool active, int lx,
@@ -584,11 +660,18 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
 
     // ---- pass 2: nodes on the upper faces of the tile block
     const bool full = tc.ext[0] == K * TX + 1 && tc.ext[1] == K * TY + 1 && tc.ext[2] == K * TZ + 1;
-    FaceCtx<T> fc{m, tc, slot, cs, xt, yt, part, nsh, nx, nxy, nbx, nby, nbz};
+    FaceCtx<T> fc{m, tc, slot, cs, xt, yt, part, nsh, nx, nxy, nbx, nby, nbz, ny_free};
     if (full) {
-        dsum += upper_face<K, T, TX, TY, TZ, 2, true>(fc, dot);
-        dsum += upper_face<K, T, TX, TY, TZ, 1, true>(fc, dot);
-        dsum += upper_face<K, T, TX, TY, TZ, 0, true>(fc, dot);
+        // shared-node enumeration bases of the tile's planes (lower plane of
+        // each family; the upper plane adds nxy, nx or 1)
+        const int n0x = tc.n0[0], n0y = tc.n0[1], n0z = tc.n0[2];
+        const int fb[3] = {cz_n + cy_n + (t0 - 1) + nbx * ((n0y - t1) + ny_free * (n0z - t2)),
+                           cz_n + n0x + nx * ((t1 - 1) + nby * (n0z - t2)), n0x + nx * n0y + nxy * (t2 - 1)};
+        const bool dlo[3] = {(m.bcmask & 1) && t0 == 0, (m.bcmask & 4) && t1 == 0, (m.bcmask & 16) && t2 == 0};
+        const bool dhi[3] = {(m.bcmask & 2) && t0 == nbx, (m.bcmask & 8) && t1 == nby, (m.bcmask & 32) && t2 == nbz};
+        dsum += upper_face_full<K, T, TX, TY, TZ, 2>(fc, fb, dlo, dhi, dot);
+        dsum += upper_face_full<K, T, TX, TY, TZ, 1>(fc, fb, dlo, dhi, dot);
+        dsum += upper_face_full<K, T, TX, TY, TZ, 0>(fc, fb, dlo, dhi, dot);
     } else {
         dsum += upper_face<K, T, TX, TY, TZ, 2, false>(fc, dot);
         dsum += upper_face<K, T, TX, TY, TZ, 1, false>(fc, dot);

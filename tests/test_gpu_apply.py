@@ -42,6 +42,9 @@ CASES = [
     ((9, 5, 7), 2, (0, 1, 1, 0, 0, 1), W.H_PAPER, (1.0, 0.6, 0.9)),
     ((1, 1, 1), 2, (0,) * 6, W.H_LINEAR, (1.0, 1.0, 1.0)),
     ((1, 1, 1), 2, (1,) * 6, W.H_LINEAR, (1.0, 1.0, 1.0)),
+    # several complete tiles of every instantiated shape, mixed boundary conditions
+    ((16, 8, 12), 2, (0, 1, 1, 0, 0, 1), W.H_PAPER, (1.0, 0.8, 1.1)),
+    ((8, 16, 4), 2, (1, 0, 0, 1, 1, 0), W.H_LINEAR, (0.7, 1.0, 1.0)),
     ((6, 3, 5), 3, (0,) * 6, W.H_LINEAR, (1.0, 1.0, 1.0)),
     ((3, 4, 2), 3, (1, 0, 1, 1, 0, 1), W.H_PAPER, (0.5, 1.0, 0.7)),
     ((1, 1, 1), 3, (0,) * 6, W.H_LINEAR, (1.0, 1.0, 1.0)),
@@ -143,3 +146,4 @@ def test_full_size_sampled_rows_q3_q4(k):
     rows = rng.choice(m.ndofs, 1500, replace=False)
     yr = oracle.apply_rows(m, wl.phi, x, rows)
     assert rel(y[rows], yr) < 1e-12
+
