@@ -281,19 +281,28 @@ static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
     hipError_t err = hipSuccess;
     for (int it = 0; it < iters && err == hipSuccess; ++it) {
         const int par = it & 1;
+        // tile kernel of q = A p (with p.q partials), then the update that also
+        // assembles the shared nodes of q, then the search-direction update
         if constexpr (sizeof(T) == 8) {
-            ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, p->part, shared_stride(p->m), p->dot_part,
-                                &w.st->pAp, &w.st->halt[par]};
+            const int64_t stride = shared_stride(p->m);
+            ApplyArgs<double> a{p->m, w.p, w.q, p->phi64, p->part, stride, p->dot_part, nullptr, &w.st->halt[par],
+                                true};
             err = launch_apply_f64(p->cfg, p->k, a, s);
             if (err == hipSuccess)
-                err = launch_cg_update<double>(w.st, par, w.red, w.x, w.r, w.p, w.q, p->inv64, p->N, s);
+                err = launch_cg_assemble_update<double>(w.st, par, w.red, p->dot_part, tile_count(p->m), p->m,
+                                                        shared_enum(p->m, p->k, p->cfg.tile), p->part, stride,
+                                                        w.x, w.r, w.p, w.q, p->inv64, p->N, s);
             if (err == hipSuccess) err = launch_cg_pupdate<double>(w.st, par, w.red, w.r, w.p, p->inv64, p->N, s);
         } else {
-            ApplyArgs<float> a{p->m32, w.p32, w.q32, p->phi32, reinterpret_cast<float*>(p->part),
-                               shared_stride(p->m32), p->dot_part, &w.st32->pAp, &w.st32->halt[par]};
+            const int64_t stride = shared_stride(p->m32);
+            const float* part = reinterpret_cast<float*>(p->part);
+            ApplyArgs<float> a{p->m32, w.p32, w.q32, p->phi32, reinterpret_cast<float*>(p->part), stride,
+                               p->dot_part, nullptr, &w.st32->halt[par], true};
             err = launch_apply_f32(p->cfg32, p->k, a, s);
             if (err == hipSuccess)
-                err = launch_cg_update<float>(w.st32, par, w.red, w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
+                err = launch_cg_assemble_update<float>(w.st32, par, w.red, p->dot_part, tile_count(p->m32), p->m32,
+                                                       shared_enum(p->m32, p->k, p->cfg32.tile), part, stride,
+                                                       w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
             if (err == hipSuccess)
                 err = launch_cg_pupdate<float>(w.st32, par, w.red, w.r32, w.p32, p->inv32, p->N, s);
         }

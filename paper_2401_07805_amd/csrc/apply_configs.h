@@ -38,7 +38,7 @@ inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
     constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : TX * TY * TZ;
     hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV, DOT>()), dim3(nblocks), dim3(threads), 0, s, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || a.tiles_only) return e;
     const int tile[3] = {TX, TY, TZ};
     AssembleArgs<T> b{a.m, shared_enum(a.m, K, tile), a.part, a.nshared, a.y, a.dot_part, nblocks, a.dot, a.done};
     return launch_assemble<T>(b, s);

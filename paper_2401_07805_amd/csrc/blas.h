@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "shared_nodes.h"
+
 namespace vpp {
 
 // Device-resident scalars of one PCG (FP64 for every precision).
@@ -27,9 +29,14 @@ constexpr int kRedDoubles = 2 * kMaxRedBlocks;
 template <typename T>
 hipError_t launch_cg_init(CgState* st, double* red, const T* b, const T* q, T* r, T* p, const T* invd, int64_t n,
                           hipStream_t s);
+// CG update after a tiles-only apply q = A p: p.Ap from the ndot per-workgroup
+// partials dot_part; the values of q on shared nodes assembled from the partial
+// array part (stride `stride`, enumeration e); alpha = rz / pAp, x += alpha p,
+// r -= alpha q, and per-workgroup partials of r.r and r.(D^-1 r).
 template <typename T>
-hipError_t launch_cg_update(CgState* st, int par, double* red, T* x, T* r, const T* p, const T* q, const T* invd,
-                            int64_t n, hipStream_t s);
+hipError_t launch_cg_assemble_update(CgState* st, int par, double* red, const double* dot_part, int ndot,
+                                     const MeshArgs& m, const SharedEnum& e, const T* part, int64_t stride, T* x,
+                                     T* r, const T* p, const T* q, const T* invd, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, const T* r, T* p, const T* invd, int64_t n,
                              hipStream_t s);

@@ -4,8 +4,10 @@
 // All CG scalars live on the device in FP64 (CgState) so that a chunk of
 // iterations can be recorded once in a hipGraph and replayed without host
 // round trips.  One iteration is three kernels:
-//   apply:    q = A p and pAp = p.q                         (apply kernels)
-//   update:   alpha = rz/pAp; x += alpha p; r -= alpha q;
+//   apply:    the tile kernel of q = A p with per-workgroup partials of p.q
+//             (apply kernels; the shared-node assembly is left to update)
+//   update:   pAp from those partials; alpha = rz/pAp; q on shared nodes from
+//             the apply's partials; x += alpha p; r -= alpha q;
 //             per-workgroup partial sums of r.r and r.(D^-1 r)
 //   pupdate:  every workgroup sums the partials in the same fixed order,
 //             beta = rz_new/rz; p = D^-1 r + beta p; workgroup 0 records the
@@ -18,6 +20,7 @@
 // halt[1-par] (propagating a stop it sees), so no kernel reads a flag that the
 // same kernel writes.  Once a stop is set every later kernel returns at once.
 #include "blas.h"
+#include "shared_nodes.h"
 
 namespace vpp {
 
@@ -87,6 +90,18 @@ static int grid_for(int64_t n)
     return (int)(want < 1 ? 1 : (want > kMaxRedBlocks ? kMaxRedBlocks : want));
 }
 
+// Number of workgroups of the fused update and of the search-direction update
+// (which sums the former's partials): one packet per thread up to the
+// partial-array capacity, since the shared-node lookups make the fused update
+// latency-bound rather than bandwidth-bound.
+template <typename T>
+static int grid_update(int64_t n)
+{
+    const int64_t packets = (n + Pack<T>::W - 1) / Pack<T>::W;
+    const int64_t want = (packets + BT - 1) / BT;
+    return (int)(want < 1 ? 1 : (want > kMaxRedBlocks ? kMaxRedBlocks : want));
+}
+
 // r = b - q (q may be null: zero initial guess), p = D^-1 r; partials of r.r
 // and r.D^-1 r.
 template <typename T>
@@ -118,14 +133,42 @@ __global__ void __launch_bounds__(BT) cg_init_finish_kernel(CgState* st, const d
     }
 }
 
+// update fused with the assembly of the apply's shared-node partials: q holds
+// A p on the nodes only one tile touches (and on Dirichlet rows); for a shared
+// node the value is the sum of its partials in rank order, as the assembly
+// kernel forms it.  p.Ap is summed from the apply's per-workgroup partials in
+// the same fixed order by every workgroup.
 template <typename T>
-__global__ void __launch_bounds__(BT) cg_update_kernel(CgState* st, int par, double* red, T* __restrict__ x,
-                                                       T* __restrict__ r, const T* __restrict__ p,
-                                                       const T* __restrict__ q, const T* __restrict__ invd,
-                                                       int64_t n)
+struct SharedParts {
+    SharedEnum e;
+    int bcmask;
+    const T* part;
+    int64_t stride;
+    const double* dot_part;
+    int ndot;
+};
+
+template <typename T>
+__device__ __forceinline__ T node_value(const SharedParts<T>& sp, const T* __restrict__ q, int64_t g)
+{
+    int f, cnt;
+    if (!shared_lookup(sp.e, sp.bcmask, (int)g, f, cnt)) return q[g];
+    T v = sp.part[f] + sp.part[sp.stride + f];
+    for (int c = 2; c < cnt; ++c) v += sp.part[c * sp.stride + f];
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BT) cg_assemble_update_kernel(CgState* st, int par, double* red, SharedParts<T> sp,
+                                                                T* __restrict__ x, T* __restrict__ r,
+                                                                const T* __restrict__ p, const T* __restrict__ q,
+                                                                const T* __restrict__ invd, int64_t n)
 {
     if (st->halt[par]) return;
-    const double pAp = st->pAp;
+    double pAp = 0.0, unused = 0.0;
+    for (int i = threadIdx.x; i < sp.ndot; i += BT) pAp += sp.dot_part[i];
+    block_sum2<BT>(pAp, unused);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->pAp = pAp;
     if (!(pAp > 0.0) || !isfinite(pAp)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->breakdown = 1;
         return;
@@ -138,12 +181,37 @@ __global__ void __launch_bounds__(BT) cg_update_kernel(CgState* st, int par, dou
         P xv = reinterpret_cast<const P*>(x)[c];
         P rv = reinterpret_cast<const P*>(r)[c];
         const P pv = reinterpret_cast<const P*>(p)[c];
-        const P qv = reinterpret_cast<const P*>(q)[c];
         const P dv = reinterpret_cast<const P*>(invd)[c];
+        P qv = reinterpret_cast<const P*>(q)[c];
+        // shared nodes of the packet: all partial loads issued before any use;
+        // the row part of the lookup is shared unless the packet wraps a row
+        int f[P::W], cnt[P::W];
+        const int g0 = (int)(c * P::W);
+        const int rw = qdiv(g0, sp.e.nn[0], sp.e.inv_nn[0]);
+        const int i0 = g0 - rw * sp.e.nn[0];
+        if (i0 + P::W <= sp.e.nn[0]) {
+            const int l = qdiv(rw, sp.e.nn[1], sp.e.inv_nn[1]);
+            const SharedRow w = shared_row(sp.e, sp.bcmask, rw - l * sp.e.nn[1], l);
+#pragma unroll
+            for (int j = 0; j < P::W; ++j)
+                if (!shared_in_row(sp.e, sp.bcmask, w, i0 + j, f[j], cnt[j])) cnt[j] = 0;
+        } else {
+#pragma unroll
+            for (int j = 0; j < P::W; ++j)
+                if (!shared_lookup(sp.e, sp.bcmask, g0 + j, f[j], cnt[j])) cnt[j] = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < P::W; ++j)
+            if (cnt[j]) {
+                T v = sp.part[f[j]] + sp.part[sp.stride + f[j]];
+                for (int k = 2; k < cnt[j]; ++k) v += sp.part[k * sp.stride + f[j]];
+                qv.v[j] = v;
+            }
 #pragma unroll
         for (int j = 0; j < P::W; ++j) {
+            const T qj = qv.v[j];
             xv.v[j] = fma(alpha, pv.v[j], xv.v[j]);
-            const T ri = fma(-alpha, qv.v[j], rv.v[j]);
+            const T ri = fma(-alpha, qj, rv.v[j]);
             rv.v[j] = ri;
             rr += (double)ri * (double)ri;
             rz += (double)ri * (double)(ri * dv.v[j]);
@@ -154,7 +222,7 @@ __global__ void __launch_bounds__(BT) cg_update_kernel(CgState* st, int par, dou
     if (blockIdx.x == 0)
         for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) {
             x[i] = fma(alpha, p[i], x[i]);
-            const T ri = fma(-alpha, q[i], r[i]);
+            const T ri = fma(-alpha, node_value(sp, q, i), r[i]);
             r[i] = ri;
             rr += (double)ri * (double)ri;
             rz += (double)ri * (double)(ri * invd[i]);
@@ -284,10 +352,13 @@ hipError_t launch_cg_init(CgState* st, double* red, const T* b, const T* q, T* r
 }
 
 template <typename T>
-hipError_t launch_cg_update(CgState* st, int par, double* red, T* x, T* r, const T* p, const T* q, const T* invd,
-                            int64_t n, hipStream_t s)
+hipError_t launch_cg_assemble_update(CgState* st, int par, double* red, const double* dot_part, int ndot,
+                                     const MeshArgs& m, const SharedEnum& e, const T* part, int64_t stride, T* x,
+                                     T* r, const T* p, const T* q, const T* invd, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid_for<T>(n)), dim3(BT), 0, s, st, par, red, x, r, p, q, invd, n);
+    SharedParts<T> sp{e, m.bcmask, part, stride, dot_part, ndot};
+    hipLaunchKernelGGL(cg_assemble_update_kernel<T>, dim3(grid_update<T>(n)), dim3(BT), 0, s, st, par, red, sp, x,
+                       r, p, q, invd, n);
     return hipGetLastError();
 }
 
@@ -295,7 +366,7 @@ template <typename T>
 hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, const T* r, T* p, const T* invd, int64_t n,
                              hipStream_t s)
 {
-    const int g = grid_for<T>(n);
+    const int g = grid_update<T>(n);   // also the number of partials the update wrote
     hipLaunchKernelGGL(cg_pupdate_kernel<T>, dim3(g), dim3(BT), 0, s, st, par, red, g, r, p, invd, n);
     return hipGetLastError();
 }
@@ -303,10 +374,11 @@ hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, const T* r
 #define VPP_INST(T)                                                                                          \
     template hipError_t launch_cg_init<T>(CgState*, double*, const T*, const T*, T*, T*, const T*, int64_t,  \
                                           hipStream_t);                                                      \
-    template hipError_t launch_cg_update<T>(CgState*, int, double*, T*, T*, const T*, const T*, const T*,    \
-                                            int64_t, hipStream_t);                                           \
     template hipError_t launch_cg_pupdate<T>(CgState*, int, const double*, const T*, T*, const T*, int64_t, \
-                                             hipStream_t);
+                                             hipStream_t);                                                   \
+    template hipError_t launch_cg_assemble_update<T>(CgState*, int, double*, const double*, int, const MeshArgs&, \
+                                                     const SharedEnum&, const T*, int64_t, T*, T*, const T*,      \
+                                                     const T*, const T*, int64_t, hipStream_t);
 VPP_INST(double)
 VPP_INST(float)
 #undef VPP_INST

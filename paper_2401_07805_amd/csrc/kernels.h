@@ -20,6 +20,7 @@ struct ApplyArgs {
     double* dot_part;   // optional: per-workgroup partial sums of x . y (ntiles entries)
     double* dot;        // optional: x . y, written by the assembly kernel
     const int* done;    // optional: the kernels return at once when *done != 0
+    bool tiles_only;    // launch the tile kernel only; the caller assembles the shared nodes
 };
 
 // Per-problem launch configuration.

@@ -137,6 +137,59 @@ __host__ __device__ inline int64_t shared_index(const SharedEnum& e, int i, int 
     return e.cz + e.cy + (i / e.s[0] - 1) + (int64_t)e.nb[0] * (jf + (int64_t)(e.nn[1] - e.nb[1]) * lf);
 }
 
+// Node-space lookup used where a streaming kernel visits every node: whether
+// global node g (< 2^31) is a shared node that is not a Dirichlet node (those
+// are written directly as identity rows), and if so its enumeration position
+// f (as shared_index) and the number of tiles holding it (as sharer_count).
+// Reciprocal divisions only.  The part that depends on the row (j, l) alone is
+// split off, so that consecutive nodes of a row share it.
+struct SharedRow {
+    int j, l, ay, lf, jf;
+    bool by, bz, dir;   // on a y plane, on a z plane, Dirichlet row
+};
+
+__host__ __device__ inline SharedRow shared_row(const SharedEnum& e, int bcmask, int j, int l)
+{
+    SharedRow w;
+    w.j = j;
+    w.l = l;
+    w.ay = qdiv(j, e.s[1], e.inv_s[1]);
+    const int az = qdiv(l, e.s[2], e.inv_s[2]);
+    w.by = j == w.ay * e.s[1] && w.ay > 0 && w.ay < e.nt[1];
+    w.bz = l == az * e.s[2] && az > 0 && az < e.nt[2];
+    w.dir = ((bcmask & 4) && j == 0) || ((bcmask & 8) && j == e.nn[1] - 1) || ((bcmask & 16) && l == 0) ||
+            ((bcmask & 32) && l == e.nn[2] - 1);
+    w.lf = l - (az < e.nt[2] - 1 ? az : e.nt[2] - 1);
+    w.jf = j - (w.ay < e.nt[1] - 1 ? w.ay : e.nt[1] - 1);
+    // on a z plane, lf is replaced by the plane index - 1 (see shared_in_row)
+    if (w.bz) w.lf = az - 1;
+    return w;
+}
+
+__host__ __device__ inline bool shared_in_row(const SharedEnum& e, int bcmask, const SharedRow& w, int i, int& f,
+                                              int& count)
+{
+    const int ax = qdiv(i, e.s[0], e.inv_s[0]);
+    const bool bx = i == ax * e.s[0] && ax > 0 && ax < e.nt[0];
+    if (!(bx || w.by || w.bz)) return false;
+    if (w.dir || ((bcmask & 1) && i == 0) || ((bcmask & 2) && i == e.nn[0] - 1)) return false;
+    count = (bx ? 2 : 1) * (w.by ? 2 : 1) * (w.bz ? 2 : 1);
+    if (w.bz)
+        f = i + e.nn[0] * (w.j + e.nn[1] * w.lf);
+    else if (w.by)
+        f = (int)e.cz + i + e.nn[0] * ((w.ay - 1) + e.nb[1] * w.lf);
+    else
+        f = (int)(e.cz + e.cy) + (ax - 1) + e.nb[0] * (w.jf + (e.nn[1] - e.nb[1]) * w.lf);
+    return true;
+}
+
+__host__ __device__ inline bool shared_lookup(const SharedEnum& e, int bcmask, int g, int& f, int& count)
+{
+    const int r = qdiv(g, e.nn[0], e.inv_nn[0]);
+    const int l = qdiv(r, e.nn[1], e.inv_nn[1]);
+    return shared_in_row(e, bcmask, shared_row(e, bcmask, r - l * e.nn[1], l), g - r * e.nn[0], f, count);
+}
+
 // Enumeration position and rank of node (gi, gj, gl) as seen from tile t, given
 // on which faces of that tile's block it lies (lo*: bottom face with a tile
 // below, hi*: top face with a tile above); at least one flag is set.  Needs no

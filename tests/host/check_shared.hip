@@ -83,6 +83,22 @@ static void check(int k, const int (&nc)[3], const int (&tile)[3], int bcmask)
         }
     }
     CHECK(got == ref, "set mismatch\n");
+    // node-space lookup: every node, shared or not, Dirichlet or not
+    for (int l = 0; l < m.nn[2]; ++l)
+        for (int j = 0; j < m.nn[1]; ++j)
+            for (int i = 0; i < m.nn[0]; ++i) {
+                const int g = i + m.nn[0] * (j + m.nn[1] * l);
+                const bool sh = ref.count({i, j, l}) > 0 && !is_dirichlet(m, i, j, l);
+                int f = -1, cnt = 0;
+                const bool got_sh = shared_lookup(e, m.bcmask, g, f, cnt);
+                CHECK(got_sh == sh, "shared_lookup(%d,%d,%d) = %d, expected %d\n", i, j, l, (int)got_sh, (int)sh);
+                if (sh && got_sh) {
+                    CHECK(f == shared_index(e, i, j, l), "shared_lookup f %d vs %lld\n", f,
+                          (long long)shared_index(e, i, j, l));
+                    CHECK(cnt == sharer_count(e, i, j, l), "shared_lookup count %d vs %d\n", cnt,
+                          sharer_count(e, i, j, l));
+                }
+            }
     // the tile-side formula used by the apply kernels' write-out: every node on a
     // shared face of every tile block maps to its enumeration index and rank
     for (int tz = 0; tz < m.ntile[2]; ++tz)
