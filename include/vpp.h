@@ -147,7 +147,9 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
  * Setting an unsupported one returns VPP_ERR_UNSUPPORTED.  vpp_get_config /
  * vpp_set_config read the FP64 choice / set both.  vpp_tune times the
  * candidates of both precisions on this problem (synchronises) and keeps the
- * fastest of each; with a non-NULL cache path the choices are read from /
+ * fastest of each; every timed apply follows a write of a 512 MiB scratch
+ * buffer (allocated for the call), so operands come from HBM rather than from
+ * the last-level cache.  With a non-NULL cache path the choices are read from /
  * added to that JSON file. */
 vpp_status vpp_get_config(vpp_problem p, vpp_kernel_config* cfg);
 vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg);

@@ -840,9 +840,13 @@ int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t ca
 }
 
 // Times every candidate configuration of one precision and keeps the fastest.
-static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path)
+// Each timed apply follows a write of `flush` (larger than the last-level
+// cache), so x, phi and y come from HBM as for applies on streaming data and
+// for problems larger than the cache; without a flush buffer the applies run
+// back to back.
+static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path, double* flush, int64_t nflush)
 {
-    const std::string key = size_bucket_key(prec == VPP_FP32 ? "apply32" : "apply", p->k, p->N);
+    const std::string key = size_bucket_key(prec == VPP_FP32 ? "apply32/hbm" : "apply/hbm", p->k, p->N);
     LaunchCfg c;
     if (cache_lookup(cache_path, key, &c) && apply_config_supported(c, p->k)) {
         put_config(p, prec, c);
@@ -856,35 +860,44 @@ static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path
     else VPP_HIP(launch_fill<double>(w.x, p->N, 1.0, s));
     LaunchCfg cands[64];
     const int n = list_apply_configs(p->k, cands, 64);
-    hipEvent_t e0, e1;
-    VPP_HIP(hipEventCreate(&e0));
-    VPP_HIP(hipEventCreate(&e1));
+    constexpr int reps = 6;
+    hipEvent_t ev[2 * reps] = {};
+    for (int r = 0; r < 2 * reps && !st; ++r)
+        if (hipEventCreate(&ev[r]) != hipSuccess) st = fail(VPP_ERR_HIP, "hipEventCreate failed");
     double best = 1e300;
     LaunchCfg best_cfg = prec == VPP_FP32 ? p->cfg32 : p->cfg;
-    const int reps = 10;
     auto one = [&]() {
         return prec == VPP_FP32 ? do_apply32(p, w.p32, w.q32, nullptr, nullptr, s)
                                 : do_apply64(p, w.x, w.q, nullptr, nullptr, s);
+    };
+    auto hip = [&](hipError_t e) {
+        if (e != hipSuccess && !st) st = fail(VPP_ERR_HIP, hipGetErrorString(e));
+        return st == VPP_OK;
     };
     for (int i = 0; i < n && !st; ++i) {
         put_config(p, prec, cands[i]);
         if ((st = ensure_apply_scratch(p))) break;
         if ((st = one())) break;
-        VPP_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps && !st; ++r) st = one();
-        if (st) break;
-        VPP_HIP(hipEventRecord(e1, s));
-        VPP_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        VPP_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const double us = 1000.0 * ms / reps;
-        if (us < best) {
+        for (int r = 0; r < reps && !st; ++r) {
+            if (flush && !hip(launch_fill<double>(flush, nflush, (double)r, s))) break;
+            if (!hip(hipEventRecord(ev[2 * r], s))) break;
+            if ((st = one())) break;
+            hip(hipEventRecord(ev[2 * r + 1], s));
+        }
+        if (st || !hip(hipEventSynchronize(ev[2 * reps - 1]))) break;
+        double us = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            if (!hip(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]))) break;
+            us += 1000.0 * ms / reps;
+        }
+        if (!st && us < best) {
             best = us;
             best_cfg = cands[i];
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (int r = 0; r < 2 * reps; ++r)
+        if (ev[r]) (void)hipEventDestroy(ev[r]);
     put_config(p, prec, best_cfg);
     if (st) return st;
     cache_store(cache_path, key, best_cfg, best);
@@ -897,9 +910,21 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
     if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
     DeviceGuard dg(p->desc.device);
     VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
-    vpp_status st = tune_precision(p, VPP_FP64, cache_path);
-    if (st) return st;
-    return tune_precision(p, VPP_FP32, cache_path);
+    // cache flush buffer: twice the 256 MB last-level cache (skipped if it
+    // cannot be allocated)
+    const int64_t nflush = (int64_t)64 << 20;
+    double* flush = nullptr;
+    if (hipMalloc((void**)&flush, (size_t)nflush * sizeof(double)) != hipSuccess) {
+        flush = nullptr;
+        (void)hipGetLastError();
+    }
+    vpp_status st = tune_precision(p, VPP_FP64, cache_path, flush, nflush);
+    if (!st) st = tune_precision(p, VPP_FP32, cache_path, flush, nflush);
+    if (flush) {
+        (void)hipStreamSynchronize(p->stream);
+        (void)hipFree(flush);
+    }
+    return st;
 }
 
 // ---------------------------------------------------------------------------
