@@ -32,7 +32,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
 BYTES_PER_DOF_F64 = 24.0      # x read, phi read, y written once per DoF
+# FP64 operations of the Q2 cell kernel per cell (coefficient: 3 value sweeps
+# and the material law; operator: 3 value sweeps, 3 collocation-derivative
+# line pairs with the Gauss-point scaling, 3 transposed value sweeps), counted
+# from the compiled tile kernel's instruction mix with an FMA as two
+# operations (625 FMAC + 50 FMA + 408 MUL); the slot sums of the write-out are
+# not counted.
+FLOPS_PER_CELL_Q2 = 1758.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_q2_64cube_traffic.md")
 KERNEL_SOURCES = ["apply_impl.h", "apply_configs.h", "apply_misc.hip", "apply_f64.hip", "common.h", "tables.h",
                   "shared_nodes.h", "kernels.h"]
@@ -328,6 +336,10 @@ def main():
     }
     if traffic is not None:
         out["roofline"]["traffic_bytes_per_apply"] = traffic
+    ncells = m.ncells[0] * m.ncells[1] * m.ncells[2]
+    tflops = FLOPS_PER_CELL_Q2 * ncells / per_apply / 1e12
+    out["valu"] = {"achieved": tflops, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": tflops / FP64_VALU_PEAK_TFLOPS, "flops_per_apply": FLOPS_PER_CELL_Q2 * ncells}
     if args.copy_probe:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         c = torch.empty_like(a)

@@ -7,6 +7,7 @@ namespace vpp {
 // Instantiated configurations: (k, variant, tile).
 #define VPP_APPLY_CONFIGS(X)  \
     X(2, 4, 8, 8, 8)          \
+    X(2, 4, 32, 4, 4)         \
     X(2, 4, 16, 8, 4)         \
     X(2, 4, 16, 4, 4)         \
     X(2, 4, 8, 8, 4)          \
