@@ -12,7 +12,9 @@
 //              atomic adds (k = 2);
 //   variant 1, plane per thread: k+1 threads share a cell, each holding one
 //              x-plane of (k+1)^2 values; y/z sweeps are in registers and the
-//              x sweeps exchange planes through LDS (all k).
+//              x sweeps exchange planes through LDS (all k), or for k = 3,
+//              where a cell's four threads form one lane quad, by DPP quad
+//              permutations.
 // Nodes that only this tile touches are written with plain stores; nodes on
 // planes shared with neighbouring tiles are written as per-tile partials and
 // summed, in a fixed order, by the assembly kernel (apply_misc.hip), so the
@@ -767,6 +769,35 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
 // ---------------------------------------------------------------------------
 // Variant 1: one x-plane of a cell per thread; x sweeps through LDS.
 
+// Value of lane L of this lane's quad (lanes 4q .. 4q+3), by a DPP quad
+// permutation: no LDS, no barrier.  Used where the k+1 = 4 threads of a cell
+// form one quad.
+template <int L>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    constexpr int ctrl = L * 0x55;   // quad_perm(L, L, L, L)
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+template <int L>
+__device__ __forceinline__ float quad_bcast(float v)
+{
+    constexpr int ctrl = L * 0x55;
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, true));
+}
+
+// out = sum_i c[i] v_i over the four x-planes of the cell, v_i the value of
+// quad lane i.
+template <typename T>
+__device__ __forceinline__ T quad_dot(const T (&c)[4], T v)
+{
+    T s = c[0] * quad_bcast<0>(v);
+    s = fma(c[1], quad_bcast<1>(v), s);
+    s = fma(c[2], quad_bcast<2>(v), s);
+    return fma(c[3], quad_bcast<3>(v), s);
+}
+
 // Entry (r, i) of a 1D matrix for a runtime row r (COL: entry (i, r)).
 template <int K, Mat M, bool COL>
 __device__ __forceinline__ double pick(int r, int i)
@@ -785,6 +816,9 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
     constexpr int CS = N * N2 + 1;           // padded per-cell stride of the exchange buffers
     constexpr int SS = NC + 1;               // slot column stride (column NC stays zero)
+    // k = 3: the four threads of a cell are one lane quad, and the x sweeps
+    // exchange planes by DPP quad permutations instead of through LDS
+    constexpr bool QUAD = N == 4;
     static_assert(N * N2 * SS <= 2 * NC * CS, "slots must fit in the exchange buffers");
     __shared__ T xb[2 * NC * CS];
     if (a.done && *a.done) return;
@@ -821,23 +855,37 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
             for (int j = 0; j < N; ++j) cw[j + N * l] = T(a.phi[base + nx * j + nxy * l]);
         sweep2<K, MS, false, 0>(cw);
         sweep2<K, MS, false, 1>(cw);
+        if constexpr (QUAD) {
+            // one value at a time (the scheduler would otherwise issue every
+            // permutation first and hold all results in registers)
 #pragma unroll
-        for (int q = 0; q < N2; ++q) X1[ip * N2 + q] = cw[q];
-    }
-    __syncthreads();
-    if (active) {
+            for (int q = 0; q < N2; ++q) {
+                cw[q] = quad_dot<T>(rS, cw[q]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
 #pragma unroll
-        for (int q = 0; q < N2; ++q) {
-            T s = rS[0] * X1[q];
-#pragma unroll
-            for (int i = 1; i < N; ++i) s = fma(rS[i], X1[i * N2 + q], s);
-            cw[q] = s;
+            for (int q = 0; q < N2; ++q) X1[ip * N2 + q] = cw[q];
         }
+    }
+    if constexpr (!QUAD) {
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < N2; ++q) {
+                T s = rS[0] * X1[q];
+#pragma unroll
+                for (int i = 1; i < N; ++i) s = fma(rS[i], X1[i * N2 + q], s);
+                cw[q] = s;
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
 #pragma unroll
         for (int q = 0; q < N2; ++q)
             cw[q] = coef_scaled<HV>(m, cw[q]) * (wx * T(Tab<K>::t.w[q % N] * Tab<K>::t.w[q / N]));
     }
-    __syncthreads();
 
     // Operand plane at x-node ip (Dirichlet entries zeroed).
     T uq[N2], gx[N2];
@@ -853,26 +901,47 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
             }
         sweep2<K, MS, false, 0>(uq);
         sweep2<K, MS, false, 1>(uq);
+        if constexpr (QUAD) {
 #pragma unroll
-        for (int q = 0; q < N2; ++q) X1[ip * N2 + q] = uq[q];
-    }
-    __syncthreads();
-    if (active) {
+            for (int q = 0; q < N2; ++q) {
+                const T v[4] = {quad_bcast<0>(uq[q]), quad_bcast<1>(uq[q]), quad_bcast<2>(uq[q]),
+                                quad_bcast<3>(uq[q])};
+                T s = rS[0] * v[0], d = rD[0] * v[0];
 #pragma unroll
-        for (int q = 0; q < N2; ++q) {
-            const T v0 = X1[q];
-            T s = rS[0] * v0, d = rD[0] * v0;
-#pragma unroll
-            for (int i = 1; i < N; ++i) {
-                const T v = X1[i * N2 + q];
-                s = fma(rS[i], v, s);
-                d = fma(rD[i], v, d);
+                for (int i = 1; i < 4; ++i) {
+                    s = fma(rS[i], v[i], s);
+                    d = fma(rD[i], v[i], d);
+                }
+                uq[q] = s;
+                gx[q] = d;
+                __builtin_amdgcn_sched_barrier(0);
             }
-            uq[q] = s;
-            gx[q] = d;
+        } else {
+#pragma unroll
+            for (int q = 0; q < N2; ++q) X1[ip * N2 + q] = uq[q];
         }
     }
-    __syncthreads();
+    if constexpr (!QUAD) {
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < N2; ++q) {
+                const T v0 = X1[q];
+                T s = rS[0] * v0, d = rD[0] * v0;
+#pragma unroll
+                for (int i = 1; i < N; ++i) {
+                    const T v = X1[i * N2 + q];
+                    s = fma(rS[i], v, s);
+                    d = fma(rD[i], v, d);
+                }
+                uq[q] = s;
+                gx[q] = d;
+            }
+        }
+        __syncthreads();
+    }
+    T o[N2];
+    if constexpr (QUAD) __syncthreads();   // bounds the scheduling region (register pressure)
     if (active) {
         T gy[N2];
 #pragma unroll
@@ -888,26 +957,37 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
         }
         sweep2<K, MDC, true, 0>(gy);
         sweep2<K, MDC, true, 1>(uq);
+        if constexpr (QUAD) {
 #pragma unroll
-        for (int q = 0; q < N2; ++q) {
-            X1[ip * N2 + q] = gy[q] + uq[q];
-            X2[ip * N2 + q] = gx[q];
+            for (int q = 0; q < N2; ++q) {
+                o[q] = quad_dot<T>(cS, gy[q] + uq[q]) + quad_dot<T>(cD, gx[q]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < N2; ++q) {
+                X1[ip * N2 + q] = gy[q] + uq[q];
+                X2[ip * N2 + q] = gx[q];
+            }
         }
     }
-    __syncthreads();
-    T o[N2];
-    if (active) {
+    if constexpr (!QUAD) {
+        __syncthreads();
+        if (active) {
 #pragma unroll
-        for (int q = 0; q < N2; ++q) {
-            T s = cS[0] * X1[q];
-            s = fma(cD[0], X2[q], s);
+            for (int q = 0; q < N2; ++q) {
+                T s = cS[0] * X1[q];
+                s = fma(cD[0], X2[q], s);
 #pragma unroll
-            for (int i = 1; i < N; ++i) {
-                s = fma(cS[i], X1[i * N2 + q], s);
-                s = fma(cD[i], X2[i * N2 + q], s);
+                for (int i = 1; i < N; ++i) {
+                    s = fma(cS[i], X1[i * N2 + q], s);
+                    s = fma(cD[i], X2[i * N2 + q], s);
+                }
+                o[q] = s;
             }
-            o[q] = s;
         }
+    }
+    if (active) {
         sweep2<K, MS, true, 0>(o);
         sweep2<K, MS, true, 1>(o);
     }
