@@ -15,6 +15,10 @@ namespace vpp {
     X(2, 0, 16, 4, 4)         \
     X(2, 0, 8, 4, 4)          \
     X(2, 1, 8, 4, 2)          \
+    X(3, 2, 8, 8, 4)          \
+    X(3, 2, 8, 4, 4)          \
+    X(3, 2, 4, 4, 4)          \
+    X(3, 2, 8, 4, 2)          \
     X(3, 4, 8, 4, 4)          \
     X(3, 4, 4, 4, 4)          \
     X(3, 1, 4, 4, 2)          \
@@ -29,6 +33,7 @@ inline auto kernel_ptr()
 {
     if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV, DOT>;
     else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV, DOT>;
+    else if constexpr (V == 2) return &apply_half_kernel<K, T, TX, TY, TZ, HV, DOT>;
     else return &apply_slot_kernel<K, T, TX, TY, TZ, HV, DOT>;
 }
 
@@ -36,7 +41,7 @@ template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT>
 inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
 {
     const int nblocks = a.m.ntile[0] * a.m.ntile[1] * a.m.ntile[2];
-    constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : TX * TY * TZ;
+    constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : (V == 2 ? 2 : 1) * TX * TY * TZ;
     hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV, DOT>()), dim3(nblocks), dim3(threads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.tiles_only) return e;

@@ -454,7 +454,7 @@ __device__ __forceinline__ void contributors(int c, bool face, int ncell, int st
 // (the two other coordinates strictly below their upper faces for the faces
 // written later, so every node is written once: z face first, then y, then x).
 // FULL: the tile holds TX x TY x TZ cells (compile-time extents).
-template <int K, typename T, int TX, int TY, int TZ, int FACE, bool FULL>
+template <int K, typename T, int TX, int TY, int TZ, int FACE, bool FULL, int NTH = TX * TY * TZ>
 __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
 {
     constexpr int N = K + 1, NT = TX * TY * TZ;
@@ -468,7 +468,7 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
     const int nc0 = E0 / K, nc1 = E1 / K, nc2 = E2 / K;
     const int t0 = f.tc.t[0], t1 = f.tc.t[1], t2 = f.tc.t[2];
     double dsum = 0.0;
-    for (int n = threadIdx.x; n < count; n += NT) {
+    for (int n = threadIdx.x; n < count; n += NTH) {
         const int ib = n / na, ia = n - ib * na;
         const int c0 = FACE == 0 ? E0 : ia;
         const int c1 = FACE == 0 ? ia : (FACE == 1 ? E1 : ib);
@@ -519,7 +519,7 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
 // the tile and (c / K - 1, K) when c % K == 0 and c > 0; on the face (c == E)
 // only the second exists.  Along FACE only the last cell with index K holds the
 // node, so every node sums at most four slots.
-template <int K, typename T, int TX, int TY, int TZ, int FACE>
+template <int K, typename T, int TX, int TY, int TZ, int FACE, int NTH = TX * TY * TZ>
 __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int (&fb)[3], const bool (&dlo)[3],
                                                   const bool (&dhi)[3], bool dot)
 {
@@ -533,7 +533,7 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
     const bool anyd = dlo[0] || dlo[1] || dlo[2] || dhi[0] || dhi[1] || dhi[2];
     const bool hn[3] = {t0 < f.nbx, t1 < f.nby, t2 < f.nbz};   // a tile above along d
     double dsum = 0.0;
-    for (int n = threadIdx.x; n < NA * NB; n += NT) {
+    for (int n = threadIdx.x; n < NA * NB; n += NTH) {
         const int ib = n / NA, ia = n - ib * NA;
         const int c[3] = {FACE == 0 ? E0 : ia, FACE == 0 ? ia : (FACE == 1 ? E1 : ib), FACE == 2 ? E2 : ib};
         // slot column and local index of the (up to) two cells along each direction
@@ -585,6 +585,42 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
             f.yt[off] = v;
         }
         if (dot) dsum += (double)f.xt[off] * (double)v;
+    }
+    return dsum;
+}
+
+// Pass 2 of the write-out: the nodes of the tile block's three upper faces,
+// whose contributions all lie in the slot array, walked by NTH threads.
+template <int K, typename T, int TX, int TY, int TZ, int NTH = TX * TY * TZ>
+__device__ __forceinline__ double upper_faces(const MeshArgs& m, const TileCoord& tc, const T* slot, int cs,
+                                              const T* __restrict__ x, T* __restrict__ y, T* __restrict__ part,
+                                              int64_t nshared, bool dot)
+{
+    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+    const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+    const int t0 = tc.t[0], t1 = tc.t[1], t2 = tc.t[2];
+    const int nbx = m.ntile[0] - 1, nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
+    const int cz_n = nbz * nxy;
+    const int cy_n = nby * (m.nn[2] - nbz) * nx;
+    const int ny_free = m.nn[1] - nby;
+    FaceCtx<T> fc{m, tc, slot, cs, x + tile0, y + tile0, part, (unsigned)nshared, nx, nxy, nbx, nby, nbz, ny_free};
+    double dsum = 0.0;
+    const bool full = tc.ext[0] == K * TX + 1 && tc.ext[1] == K * TY + 1 && tc.ext[2] == K * TZ + 1;
+    if (full) {
+        // shared-node enumeration bases of the tile's planes (lower plane of
+        // each family; the upper plane adds nxy, nx or 1)
+        const int n0x = tc.n0[0], n0y = tc.n0[1], n0z = tc.n0[2];
+        const int fb[3] = {cz_n + cy_n + (t0 - 1) + nbx * ((n0y - t1) + ny_free * (n0z - t2)),
+                           cz_n + n0x + nx * ((t1 - 1) + nby * (n0z - t2)), n0x + nx * n0y + nxy * (t2 - 1)};
+        const bool dlo[3] = {(m.bcmask & 1) && t0 == 0, (m.bcmask & 4) && t1 == 0, (m.bcmask & 16) && t2 == 0};
+        const bool dhi[3] = {(m.bcmask & 2) && t0 == nbx, (m.bcmask & 8) && t1 == nby, (m.bcmask & 32) && t2 == nbz};
+        dsum += upper_face_full<K, T, TX, TY, TZ, 2, NTH>(fc, fb, dlo, dhi, dot);
+        dsum += upper_face_full<K, T, TX, TY, TZ, 1, NTH>(fc, fb, dlo, dhi, dot);
+        dsum += upper_face_full<K, T, TX, TY, TZ, 0, NTH>(fc, fb, dlo, dhi, dot);
+    } else {
+        dsum += upper_face<K, T, TX, TY, TZ, 2, false, NTH>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 1, false, NTH>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 0, false, NTH>(fc, dot);
     }
     return dsum;
 }
@@ -660,26 +696,7 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
                 }
     }
 
-    // ---- pass 2: nodes on the upper faces of the tile block
-    const bool full = tc.ext[0] == K * TX + 1 && tc.ext[1] == K * TY + 1 && tc.ext[2] == K * TZ + 1;
-    FaceCtx<T> fc{m, tc, slot, cs, xt, yt, part, nsh, nx, nxy, nbx, nby, nbz, ny_free};
-    if (full) {
-        // shared-node enumeration bases of the tile's planes (lower plane of
-        // each family; the upper plane adds nxy, nx or 1)
-        const int n0x = tc.n0[0], n0y = tc.n0[1], n0z = tc.n0[2];
-        const int fb[3] = {cz_n + cy_n + (t0 - 1) + nbx * ((n0y - t1) + ny_free * (n0z - t2)),
-                           cz_n + n0x + nx * ((t1 - 1) + nby * (n0z - t2)), n0x + nx * n0y + nxy * (t2 - 1)};
-        const bool dlo[3] = {(m.bcmask & 1) && t0 == 0, (m.bcmask & 4) && t1 == 0, (m.bcmask & 16) && t2 == 0};
-        const bool dhi[3] = {(m.bcmask & 2) && t0 == nbx, (m.bcmask & 8) && t1 == nby, (m.bcmask & 32) && t2 == nbz};
-        dsum += upper_face_full<K, T, TX, TY, TZ, 2>(fc, fb, dlo, dhi, dot);
-        dsum += upper_face_full<K, T, TX, TY, TZ, 1>(fc, fb, dlo, dhi, dot);
-        dsum += upper_face_full<K, T, TX, TY, TZ, 0>(fc, fb, dlo, dhi, dot);
-    } else {
-        dsum += upper_face<K, T, TX, TY, TZ, 2, false>(fc, dot);
-        dsum += upper_face<K, T, TX, TY, TZ, 1, false>(fc, dot);
-        dsum += upper_face<K, T, TX, TY, TZ, 0, false>(fc, dot);
-    }
-    return dsum;
+    return dsum + upper_faces<K, T, TX, TY, TZ>(m, tc, slot, cs, x, y, part, nshared, dot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,6 +1028,289 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     if constexpr (DOT) {
         const double s = block_sum<NT>(d);
         if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Variant 2 (k = 3): half a cell per thread.  The two threads of a cell (an
+// even/odd lane pair) hold two z-planes each of the cell's (k+1)^3 values, so a
+// thread carries half the register state of the cell-per-thread kernel and
+// twice as many waves cover the mesh.  x and y sweeps stay in registers; z
+// sweeps combine the pair's planes by DPP lane swaps.  The odd thread stores
+// its planes mirrored in z (its local plane j is the cell's plane k - j), which
+// makes every z sweep the same compile-time code on both threads: the value
+// matrix and the Gauss weights are symmetric under z -> 1 - z, and the
+// collocation derivative changes sign, which cancels between the forward and
+// the transposed derivative (derivative values exchanged between the two
+// threads are negated, since each holds them in its own frame).
+
+template <int K>
+constexpr bool z_reflection_ok()
+{
+    constexpr int N = K + 1;
+    for (int q = 0; q < N; ++q) {
+        if (Tab<K>::t.w[N - 1 - q] - Tab<K>::t.w[q] > 1e-15 || Tab<K>::t.w[q] - Tab<K>::t.w[N - 1 - q] > 1e-15)
+            return false;
+        for (int a = 0; a < N; ++a) {
+            const double ds = Tab<K>::t.S[N - 1 - q][N - 1 - a] - Tab<K>::t.S[q][a];
+            const double dd = Tab<K>::t.Dc[N - 1 - q][N - 1 - a] + Tab<K>::t.Dc[q][a];
+            if (ds > 1e-14 || -ds > 1e-14 || dd > 1e-12 || -dd > 1e-12) return false;
+        }
+    }
+    return true;
+}
+static_assert(z_reflection_ok<3>(), "S even and Dc odd under reflection");
+
+// The partner lane's value (lanes 2i and 2i+1 swapped).
+__device__ __forceinline__ double pair_swap(double v)
+{
+    constexpr int ctrl = 0xB1;   // quad_perm(1, 0, 3, 2)
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float pair_swap(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+
+// z sweep of a 4 x 4 matrix over the pair's planes, in this thread's frame
+// (frame planes 0, 1 local; 2, 3 the partner's planes 1, 0).
+template <int K, Mat M, bool TR, typename T>
+__device__ __forceinline__ void zsweep_pair(T (&v)[2][(K + 1) * (K + 1)])
+{
+    constexpr int N = K + 1, N2 = N * N;
+    static_assert(N == 4, "two planes per thread");
+#pragma unroll
+    for (int q = 0; q < N2; ++q) {
+        const T f[4] = {v[0][q], v[1][q], pair_swap(v[1][q]), pair_swap(v[0][q])};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            Acc<T> acc;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc.add(TR ? mat<K, M>(a, j) : mat<K, M>(j, a), f[a]);
+            v[j][q] = acc.get();
+        }
+        __builtin_amdgcn_sched_barrier(0);   // one column at a time (register pressure)
+    }
+}
+
+// Pass 1 of the write-out for a half cell: the owned positions (every index
+// below K) of this thread's two planes pl[0], pl[1] (a runtime plane index
+// per thread), from its registers plus the slots of the cells below it in the
+// tile, as flush_two_pass does for a whole cell.
+template <int K, typename T, int TX, int TY, int TZ>
+__device__ __forceinline__ double flush_half_owned(const MeshArgs& m, const TileCoord& tc, const T* slot, int cs,
+                                                   const T (&v)[2][(K + 1) * (K + 1)], const int (&pl)[2], int lx,
+                                                   int ly, int lz, int cx, int cy, int cz, const T* __restrict__ x,
+                                                   T* __restrict__ y, T* __restrict__ part, int64_t nshared, bool dot)
+{
+    constexpr int N = K + 1, NC = TX * TY * TZ;
+    const int c = lx + TX * (ly + TY * lz), zero = NC;
+    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+    const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+    const T* __restrict__ xt = x + tile0;
+    T* __restrict__ yt = y + tile0;
+    const int t0 = tc.t[0], t1 = tc.t[1], t2 = tc.t[2];
+    const int nbx = m.ntile[0] - 1, nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
+    const int cz_n = nbz * nxy;
+    const int cy_n = nby * (m.nn[2] - nbz) * nx;
+    const int ny_free = m.nn[1] - nby;
+    const unsigned nsh = (unsigned)nshared;
+    const int nb0 = lx > 0 ? c - 1 : zero, nb1 = ly > 0 ? c - TX : zero, nb2 = lz > 0 ? c - TX * TY : zero;
+    const int nb01 = lx > 0 && ly > 0 ? c - 1 - TX : zero;
+    const int nb02 = lx > 0 && lz > 0 ? c - 1 - TX * TY : zero;
+    const int nb12 = ly > 0 && lz > 0 ? c - TX - TX * TY : zero;
+    const int nb012 = lx > 0 && ly > 0 && lz > 0 ? c - 1 - TX - TX * TY : zero;
+    const bool hl0 = lx == 0 && t0 > 0, hl1 = ly == 0 && t1 > 0, hl2 = lz == 0 && t2 > 0;
+    const int faces = cell_dirichlet_faces(m, cx, cy, cz);
+    const bool dl0 = faces & 1, dl1 = faces & 4, dl2 = faces & 16;
+    const int i0 = K * cx, j0 = K * cy, l0 = K * cz;
+    const unsigned lane_b = (unsigned)(K * lx + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(T);
+    const int fz = i0 + nx * j0 + nxy * (t2 - 1);
+    const int fy = cz_n + i0 + nx * ((t1 - 1) + nby * (l0 - t2));
+    const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));
+    auto pos = [](int b0, int b1, int b2) { return b0 + N * (b1 + N * b2); };
+    double dsum = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int a2 = pl[j];
+        if (a2 >= K) continue;
+        const bool z2 = a2 == 0;
+#pragma unroll
+        for (int a1 = 0; a1 < K; ++a1)
+#pragma unroll
+            for (int a0 = 0; a0 < K; ++a0) {
+                const bool z0 = a0 == 0, z1 = a1 == 0;
+                T val = v[j][a0 + N * a1];
+                if (z0) val += slot[pos(K, a1, a2) * cs + nb0];
+                if (z1) val += slot[pos(a0, K, a2) * cs + nb1];
+                if (z2) val += slot[pos(a0, a1, K) * cs + nb2];
+                if (z0 && z1) val += slot[pos(K, K, a2) * cs + nb01];
+                if (z0 && z2) val += slot[pos(K, a1, K) * cs + nb02];
+                if (z1 && z2) val += slot[pos(a0, K, K) * cs + nb12];
+                if (z0 && z1 && z2) val += slot[pos(K, K, K) * cs + nb012];
+                const int row = a0 + nx * a1 + nxy * a2;
+                const bool lo0 = z0 && hl0, lo1 = z1 && hl1, lo2 = z2 && hl2;
+                if ((z0 && dl0) || (z1 && dl1) || (z2 && dl2)) {
+                    const T xv = *at_byte(xt + row, lane_b);
+                    *at_byte(yt + row, lane_b) = xv;
+                    if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
+                    continue;
+                }
+                T* dst = at_byte(yt + row, lane_b);
+                if (lo0 || lo1 || lo2) {
+                    const int f = lo2 ? fz + a0 + nx * a1
+                                      : (lo1 ? fy + a0 + nx * nby * a2 : fx + nbx * (a1 + ny_free * a2));
+                    const int rank = (lo0 ? 1 : 0) + (lo0 ? 2 : 1) * ((lo1 ? 1 : 0) + (lo1 ? 2 : 1) * (lo2 ? 1 : 0));
+                    dst = part + ((unsigned)rank * nsh + (unsigned)f);
+                }
+                *dst = val;
+                if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)val;
+            }
+    }
+    return dsum;
+}
+
+template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT>
+__global__ void __launch_bounds__(2 * TX * TY * TZ) apply_half_kernel(ApplyArgs<T> a)
+{
+    static_assert(K == 3, "two z-planes per thread");
+    constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, NC = TX * TY * TZ, NTH = 2 * NC, CS = NC + 1;
+    __shared__ T slot[N3 * CS];
+    if (a.done && *a.done) return;
+    const MeshArgs& m = a.m;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
+    const int tid = threadIdx.x, c = tid >> 1, hz = tid & 1;
+    const int lx = c % TX, ly = (c / TX) % TY, lz = c / (TX * TY);
+    const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
+    const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+    for (int q = tid; q < N3; q += NTH) slot[q * CS + NC] = T(0);
+    // cell plane of local plane j
+    const int pl[2] = {hz ? K : 0, hz ? K - 1 : 1};
+    T v[2][N2];
+    if (active) {
+        const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+        const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+        const int faces = cell_dirichlet_faces(m, cx, cy, cz);
+        T cw[2][N2], u[2][N2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const unsigned lane_b =
+                (unsigned)(K * lx + nx * K * ly + nxy * (K * lz + pl[j])) * (unsigned)sizeof(T);
+#pragma unroll
+            for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+                for (int a0 = 0; a0 < N; ++a0) {
+                    cw[j][a0 + N * a1] = *at_byte(a.phi + tile0 + (a0 + nx * a1), lane_b);
+                    T xv = *at_byte(a.x + tile0 + (a0 + nx * a1), lane_b);
+                    if (faces && local_dirichlet<K>(faces, a0, a1, pl[j])) xv = T(0);
+                    u[j][a0 + N * a1] = xv;
+                }
+        }
+        // coefficient at the Gauss points of the two planes (frame plane j is
+        // Gauss plane j or k - j, with the same weight)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            sweep2<K, MS, false, 0>(cw[j]);
+            sweep2<K, MS, false, 1>(cw[j]);
+        }
+        zsweep_pair<K, MS, false>(cw);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < N2; ++q) cw[j][q] = coef_scaled<HV>(m, cw[j][q]) * T(wref<K>(q % N, q / N, j));
+        // operand at the Gauss points
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            sweep2<K, MS, false, 0>(u[j]);
+            sweep2<K, MS, false, 1>(u[j]);
+        }
+        zsweep_pair<K, MS, false>(u);
+        const T r1 = T(m.rd[1]), r2 = T(m.rd[2]);
+        // x and y derivative lines within the planes
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int i1 = 0; i1 < N; ++i1) {
+                T in[N], g[N], o[N];
+#pragma unroll
+                for (int b = 0; b < N; ++b) in[b] = u[j][b + N * i1];
+                line<K, MDC, false>(in, g);
+#pragma unroll
+                for (int b = 0; b < N; ++b) g[b] *= cw[j][b + N * i1];
+                line<K, MDC, true>(g, o);
+#pragma unroll
+                for (int b = 0; b < N; ++b) v[j][b + N * i1] = o[b];
+            }
+#pragma unroll
+            for (int i0 = 0; i0 < N; ++i0) {
+                T in[N], g[N], o[N];
+#pragma unroll
+                for (int b = 0; b < N; ++b) in[b] = u[j][i0 + N * b];
+                line<K, MDC, false>(in, g);
+#pragma unroll
+                for (int b = 0; b < N; ++b) g[b] *= cw[j][i0 + N * b] * r1;
+#pragma unroll
+                for (int b = 0; b < N; ++b) o[b] = v[j][i0 + N * b];
+                line_acc<K, MDC, true>(g, o);
+#pragma unroll
+                for (int b = 0; b < N; ++b) v[j][i0 + N * b] = o[b];
+            }
+        }
+        // z derivative lines across the pair
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            const T f[4] = {u[0][q], u[1][q], pair_swap(u[1][q]), pair_swap(u[0][q])};
+            T g[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                Acc<T> acc;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc.add(mat<K, MDC>(j, b), f[b]);
+                g[j] = acc.get() * (cw[j][q] * r2);
+            }
+            // the derivative is odd under the mirror: the partner's values
+            // change sign in this thread's frame
+            const T h[4] = {g[0], g[1], -pair_swap(g[1]), -pair_swap(g[0])};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                T s = v[j][q];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double cf = mat<K, MDC>(b, j);
+                    if (cf != 0.0) s = fma(T(cf), h[b], s);
+                }
+                v[j][q] = s;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // transposed value sweeps
+        zsweep_pair<K, MS, true>(v);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            sweep2<K, MS, true, 1>(v[j]);
+            sweep2<K, MS, true, 0>(v[j]);
+        }
+        // non-owned positions (some index K) go to the slot array
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < N2; ++q) {
+                const int a0 = q % N, a1 = q / N;
+                if (a0 == K || a1 == K || pl[j] == K) slot[(a0 + N * (a1 + N * pl[j])) * CS + c] = v[j][q];
+            }
+    }
+    __syncthreads();
+    double dsum = 0.0;
+    if (active)
+        dsum = flush_half_owned<K, T, TX, TY, TZ>(m, tc, slot, CS, v, pl, lx, ly, lz, cx, cy, cz, a.x, a.y, a.part,
+                                                  a.nshared, DOT);
+    dsum += upper_faces<K, T, TX, TY, TZ, NTH>(m, tc, slot, CS, a.x, a.y, a.part, a.nshared, DOT);
+    if constexpr (DOT) {
+        const double sum = block_sum<NTH>(dsum);
+        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = sum;
     }
 }
 
