@@ -101,6 +101,8 @@ typedef struct {
     int32_t tile[3];
     int32_t variant;           /* 0 = cell per thread, LDS atomic accumulation (k = 2);
                                   1 = plane per thread (k = 2, 3, 4);
+                                  2 = half a cell per thread, z-planes split over a
+                                      lane pair (k = 3);
                                   4 = cell per thread, LDS slot exchange (k = 2, 3) */
 } vpp_kernel_config;
 

@@ -10,6 +10,8 @@
 //              through an LDS slot array without atomics (k = 2);
 //   variant 0, cell per thread with the tile's node block accumulated by LDS
 //              atomic adds (k = 2);
+//   variant 2, half a cell per thread (k = 3): an even/odd lane pair holds a
+//              cell's z-planes, z sweeps by DPP lane swaps;
 //   variant 1, plane per thread: k+1 threads share a cell, each holding one
 //              x-plane of (k+1)^2 values; y/z sweeps are in registers and the
 //              x sweeps exchange planes through LDS (all k), or for k = 3,

@@ -25,7 +25,8 @@ struct ApplyArgs {
 
 // Per-problem launch configuration.
 struct LaunchCfg {
-    int variant;        // 0 cell per thread (LDS atomics), 1 plane per thread, 4 cell per thread (LDS slots)
+    int variant;        // 0 cell per thread (LDS atomics), 1 plane per thread, 2 half cell per thread (k = 3),
+                        // 4 cell per thread (LDS slots)
     int tile[3];
 };
 
