@@ -1020,15 +1020,14 @@ static vpp_status batch_tune(vpp_batch b, const char* cache_path)
             if (launch_fill<double>(xs[r], b->probs[i]->N, 1.0, b->stream) != hipSuccess)
                 st = fail(VPP_ERR_HIP, "fill");
         }
-    LaunchCfg cands[8];
+    LaunchCfg all[16], cands[16];
+    const int na = std::min(list_batch_configs(b->k, all, 16), 16);
     int nc = 0;
-    const int all[4][3] = {{8, 8, 4}, {16, 4, 4}, {8, 4, 4}, {4, 4, 4}};
-    for (int i = 0; i < 4; ++i) {
-        LaunchCfg t{4, {all[i][0], all[i][1], all[i][2]}};
-        if (batch_blocks_per_cu(t, b->k) > 0) cands[nc++] = t;
-    }
+    for (int i = 0; i < na; ++i)
+        if (batch_blocks_per_cu(all[i], b->k) > 0) cands[nc++] = all[i];
+    if (nc == 0) st = fail(VPP_ERR_UNSUPPORTED, "no batch kernel configuration for this degree");
     double best = 1e300;
-    LaunchCfg best_cfg = cands[0];
+    LaunchCfg best_cfg = nc ? cands[0] : LaunchCfg{4, {8, 8, 4}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         st = fail(VPP_ERR_HIP, "event");

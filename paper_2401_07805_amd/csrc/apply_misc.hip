@@ -236,9 +236,19 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
         const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
         const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
         const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
+        // gathers from a wave-uniform tile base plus the lane's cell offset
+        const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+        const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+        const unsigned lane_b = (unsigned)(K * lx + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(double);
         // the coefficient of the tile is computed once for all right-hand sides
         double cw[N3];
-        if (active) cell_coefficient<K, HV>(m, phi, cx, cy, cz, cw);
+        if (active) {
+            gather_cell_t<K>(phi + tile0, lane_b, nx, nxy, 0, cw);
+            sweep3<K, MS, false, 0>(cw);
+            sweep3<K, MS, false, 1>(cw);
+            sweep3<K, MS, false, 2>(cw);
+            coef_weights3<K, HV>(m, cw);
+        }
         const int faces = active ? cell_dirichlet_faces(m, cx, cy, cz) : 0;
         for (int r = 0; r < nrhs; ++r) {
             const double* x = a.x[rhs0 + r];
@@ -246,7 +256,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             double* part = a.part + a.probs[pi].part_begin + (int64_t)r * 8 * a.probs[pi].nshared;
             double u[N3];
             if (active) {
-                gather_cell<K>(m, x, cx, cy, cz, faces, u);
+                gather_cell_t<K>(x + tile0, lane_b, nx, nxy, faces, u);
                 cell_operator<K>(m, cw, u);
             }
             __syncthreads();   // the previous write-out has finished reading the slots
@@ -295,10 +305,11 @@ __global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a
 }
 
 #define VPP_BATCH_CONFIGS(X) \
+    X(2, 16, 8, 4)           \
+    X(2, 32, 4, 4)           \
     X(2, 8, 8, 4)            \
     X(2, 16, 4, 4)           \
-    X(2, 8, 4, 4)            \
-    X(2, 4, 4, 4)
+    X(2, 8, 4, 4)
 
 hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
                               hipStream_t s)
@@ -320,6 +331,19 @@ hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int
     VPP_BATCH_CONFIGS(VPP_BL)
 #undef VPP_BL
     return hipErrorInvalidValue;
+}
+
+int list_batch_configs(int k, LaunchCfg* out, int cap)
+{
+    int n = 0;
+#define VPP_BLIST(K, TX, TY, TZ)                                      \
+    if (k == K) {                                                     \
+        if (n < cap && out) out[n] = LaunchCfg{4, {TX, TY, TZ}};     \
+        ++n;                                                          \
+    }
+    VPP_BATCH_CONFIGS(VPP_BLIST)
+#undef VPP_BLIST
+    return n;
 }
 
 int batch_blocks_per_cu(const LaunchCfg& c, int k)

@@ -115,5 +115,7 @@ struct BatchArgs {
 hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
                               hipStream_t s);
 int batch_blocks_per_cu(const LaunchCfg& c, int k);
+// Instantiated batch configurations of degree k (writes up to cap, returns the count).
+int list_batch_configs(int k, LaunchCfg* out, int cap);
 
 }  // namespace vpp
