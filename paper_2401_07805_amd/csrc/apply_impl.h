@@ -454,15 +454,16 @@ __device__ __forceinline__ void contributors(int c, bool face, int ncell, int st
 
 // Writes the nodes of the tile block's upper face normal to direction FACE
 // (the two other coordinates strictly below their upper faces for the faces
-// written later, so every node is written once: z face first, then y, then x).
-// FULL: the tile holds TX x TY x TZ cells (compile-time extents).
-template <int K, typename T, int TX, int TY, int TZ, int FACE, bool FULL, int NTH = TX * TY * TZ>
+// written later, so every node is written once: z face first, then y, then x),
+// for a tile cut by the mesh's upper boundary (runtime extents); complete
+// tiles use upper_face_full.
+template <int K, typename T, int TX, int TY, int TZ, int FACE, int NTH = TX * TY * TZ>
 __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
 {
     constexpr int N = K + 1, NT = TX * TY * TZ;
-    const int E0 = FULL ? K * TX : f.tc.ext[0] - 1;
-    const int E1 = FULL ? K * TY : f.tc.ext[1] - 1;
-    const int E2 = FULL ? K * TZ : f.tc.ext[2] - 1;
+    const int E0 = f.tc.ext[0] - 1;
+    const int E1 = f.tc.ext[1] - 1;
+    const int E2 = f.tc.ext[2] - 1;
     // extents of the two free coordinates (a, b) of this face
     const int na = FACE == 0 ? E1 + 1 : E0;
     const int nb = FACE == 2 ? E1 : E2 + 1;
@@ -620,9 +621,9 @@ __device__ __forceinline__ double upper_faces(const MeshArgs& m, const TileCoord
         dsum += upper_face_full<K, T, TX, TY, TZ, 1, NTH>(fc, fb, dlo, dhi, dot);
         dsum += upper_face_full<K, T, TX, TY, TZ, 0, NTH>(fc, fb, dlo, dhi, dot);
     } else {
-        dsum += upper_face<K, T, TX, TY, TZ, 2, false, NTH>(fc, dot);
-        dsum += upper_face<K, T, TX, TY, TZ, 1, false, NTH>(fc, dot);
-        dsum += upper_face<K, T, TX, TY, TZ, 0, false, NTH>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 2, NTH>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 1, NTH>(fc, dot);
+        dsum += upper_face<K, T, TX, TY, TZ, 0, NTH>(fc, dot);
     }
     return dsum;
 }
