@@ -711,40 +711,6 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
 // eight cells of the tile that touch the node.  Column NT stays zero and stands
 // in for a neighbour cell below the tile.
 
-// Value of an owned node of cell `c` (local index a0, a1, a2) from the slot
-// array: the cell's own slot plus, for every direction with a_d = 0, the slot
-// of the cell below along d (local index K there), or the zero column ZERO when
-// that cell lies outside the tile.
-template <int K, typename T, int TX, int TY>
-struct SlotGet {
-    static constexpr int N = K + 1;
-    const T* slot;
-    int cs, c, nb0, nb1, nb2, nb01, nb02, nb12, nb012;
-    __device__ __forceinline__ SlotGet(const T* s, int cs_, int c_, int lx, int ly, int lz, int zero)
-        : slot(s), cs(cs_), c(c_)
-    {
-        nb0 = lx > 0 ? c - 1 : zero;
-        nb1 = ly > 0 ? c - TX : zero;
-        nb2 = lz > 0 ? c - TX * TY : zero;
-        nb01 = lx > 0 && ly > 0 ? c - 1 - TX : zero;
-        nb02 = lx > 0 && lz > 0 ? c - 1 - TX * TY : zero;
-        nb12 = ly > 0 && lz > 0 ? c - TX - TX * TY : zero;
-        nb012 = lx > 0 && ly > 0 && lz > 0 ? c - 1 - TX - TX * TY : zero;
-    }
-    __device__ __forceinline__ T operator()(int a0, int a1, int a2, const bool*) const
-    {
-        const bool s0 = a0 == 0, s1 = a1 == 0, s2 = a2 == 0;
-        T v = slot[(a0 + N * (a1 + N * a2)) * cs + c];
-        if (s0) v += slot[(K + N * (a1 + N * a2)) * cs + nb0];
-        if (s1) v += slot[(a0 + N * (K + N * a2)) * cs + nb1];
-        if (s2) v += slot[(a0 + N * (a1 + N * K)) * cs + nb2];
-        if (s0 && s1) v += slot[(K + N * (K + N * a2)) * cs + nb01];
-        if (s0 && s2) v += slot[(K + N * (a1 + N * K)) * cs + nb02];
-        if (s1 && s2) v += slot[(a0 + N * (K + N * K)) * cs + nb12];
-        if (s0 && s1 && s2) v += slot[(K + N * (K + N * K)) * cs + nb012];
-        return v;
-    }
-};
 
 template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT>
 __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a)
@@ -788,6 +754,79 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
 
 // ---------------------------------------------------------------------------
 // Variant 1: one x-plane of a cell per thread; x sweeps through LDS.
+
+// Pass 1 of the write-out for a plane-per-thread cell: the owned positions
+// (every index below K) of this thread's x-plane a0 = ip, from its registers
+// plus the slots of the cells below it in the tile, as flush_two_pass does for
+// a whole cell (the thread of plane ip = K owns none).
+template <int K, typename T, int TX, int TY, int TZ>
+__device__ __forceinline__ double flush_plane_owned(const MeshArgs& m, const TileCoord& tc, const T* slot, int cs,
+                                                    const T (&o)[(K + 1) * (K + 1)], int ip, int lx, int ly, int lz,
+                                                    int cx, int cy, int cz, const T* __restrict__ x,
+                                                    T* __restrict__ y, T* __restrict__ part, int64_t nshared,
+                                                    bool dot)
+{
+    constexpr int N = K + 1, NC = TX * TY * TZ;
+    if (ip >= K) return 0.0;
+    const int c = lx + TX * (ly + TY * lz), zero = NC;
+    const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
+    const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
+    const T* __restrict__ xt = x + tile0;
+    T* __restrict__ yt = y + tile0;
+    const int t0 = tc.t[0], t1 = tc.t[1], t2 = tc.t[2];
+    const int nbx = m.ntile[0] - 1, nby = m.ntile[1] - 1, nbz = m.ntile[2] - 1;
+    const int cz_n = nbz * nxy;
+    const int cy_n = nby * (m.nn[2] - nbz) * nx;
+    const int ny_free = m.nn[1] - nby;
+    const unsigned nsh = (unsigned)nshared;
+    const int nb0 = lx > 0 ? c - 1 : zero, nb1 = ly > 0 ? c - TX : zero, nb2 = lz > 0 ? c - TX * TY : zero;
+    const int nb01 = lx > 0 && ly > 0 ? c - 1 - TX : zero;
+    const int nb02 = lx > 0 && lz > 0 ? c - 1 - TX * TY : zero;
+    const int nb12 = ly > 0 && lz > 0 ? c - TX - TX * TY : zero;
+    const int nb012 = lx > 0 && ly > 0 && lz > 0 ? c - 1 - TX - TX * TY : zero;
+    const bool z0 = ip == 0;
+    const bool lo0 = z0 && lx == 0 && t0 > 0, hl1 = ly == 0 && t1 > 0, hl2 = lz == 0 && t2 > 0;
+    const int faces = cell_dirichlet_faces(m, cx, cy, cz);
+    const bool dir0 = z0 && (faces & 1), dl1 = faces & 4, dl2 = faces & 16;
+    const int i0 = K * cx + ip, j0 = K * cy, l0 = K * cz;
+    const unsigned lane_b = (unsigned)(K * lx + ip + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(T);
+    const int fz = i0 + nx * j0 + nxy * (t2 - 1);
+    const int fy = cz_n + i0 + nx * ((t1 - 1) + nby * (l0 - t2));
+    const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));
+    auto pos = [](int b0, int b1, int b2) { return b0 + N * (b1 + N * b2); };
+    double dsum = 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 < K; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 < K; ++a1) {
+            const bool z1 = a1 == 0, z2 = a2 == 0;
+            T val = o[a1 + N * a2];
+            if (z0) val += slot[pos(K, a1, a2) * cs + nb0];
+            if (z1) val += slot[pos(ip, K, a2) * cs + nb1];
+            if (z2) val += slot[pos(ip, a1, K) * cs + nb2];
+            if (z0 && z1) val += slot[pos(K, K, a2) * cs + nb01];
+            if (z0 && z2) val += slot[pos(K, a1, K) * cs + nb02];
+            if (z1 && z2) val += slot[pos(ip, K, K) * cs + nb12];
+            if (z0 && z1 && z2) val += slot[pos(K, K, K) * cs + nb012];
+            const int row = nx * a1 + nxy * a2;   // uniform
+            const bool lo1 = z1 && hl1, lo2 = z2 && hl2;
+            if (dir0 || (z1 && dl1) || (z2 && dl2)) {
+                const T xv = *at_byte(xt + row, lane_b);
+                *at_byte(yt + row, lane_b) = xv;
+                if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
+                continue;
+            }
+            T* dst = at_byte(yt + row, lane_b);
+            if (lo0 || lo1 || lo2) {
+                const int f = lo2 ? fz + nx * a1 : (lo1 ? fy + nx * nby * a2 : fx + nbx * (a1 + ny_free * a2));
+                const int rank = (lo0 ? 1 : 0) + (lo0 ? 2 : 1) * ((lo1 ? 1 : 0) + (lo1 ? 2 : 1) * (lo2 ? 1 : 0));
+                dst = part + ((unsigned)rank * nsh + (unsigned)f);
+            }
+            *dst = val;
+            if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)val;
+        }
+    return dsum;
+}
 
 // Value of lane L of this lane's quad (lanes 4q .. 4q+3), by a DPP quad
 // permutation: no LDS, no barrier.  Used where the k+1 = 4 threads of a cell
@@ -1023,11 +1062,10 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     }
     __syncthreads();
     double d = 0.0;
-    if (active) {
-        const SlotGet<K, T, TX, TY> get(slot, SS, cell, lx, ly, lz, NC);
-        d = flush_owned_get<K, T, TX, TY, TZ>(m, tc, get, lx, ly, lz, cx, cy, cz, ip, a.x, a.y, a.part, a.nshared,
-                                              DOT);
-    }
+    if (active)
+        d = flush_plane_owned<K, T, TX, TY, TZ>(m, tc, slot, SS, o, ip, lx, ly, lz, cx, cy, cz, a.x, a.y, a.part,
+                                                a.nshared, DOT);
+    d += upper_faces<K, T, TX, TY, TZ, NT>(m, tc, slot, SS, a.x, a.y, a.part, a.nshared, DOT);
     if constexpr (DOT) {
         const double s = block_sum<NT>(d);
         if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
