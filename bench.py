@@ -71,18 +71,20 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per apply from the committed counter summary, if it was taken on
-    the current kernel sources (else None)."""
+def measured_traffic(cfg):
+    """HBM bytes per apply of kernel configuration cfg (FP64) from the committed
+    counter summary, if it was taken on the current kernel sources and covers
+    that configuration (else None)."""
     try:
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     mh = re.search(r"kernel sources hash:\s*([0-9a-f]+)", text)
-    mb = re.search(r"HBM bytes per apply:\s*([0-9.eE+]+)", text)
-    if not mh or not mb or mh.group(1) != kernel_hash():
+    if not mh or mh.group(1) != kernel_hash():
         return None
-    return float(mb.group(1))
+    tile = ",".join(str(int(t)) for t in cfg["tile"])
+    mb = re.search(r"apply traffic: variant %d tile %s bytes ([0-9.eE+]+)" % (int(cfg["variant"]), tile), text)
+    return float(mb.group(1)) if mb else None
 
 
 def cpu_baseline():
@@ -303,7 +305,7 @@ def main():
     last = res[-1]
     err64 = float(torch.linalg.norm(last[3] - pstar) / torch.linalg.norm(pstar))
     errmx = float(torch.linalg.norm(last[6] - pstar) / torch.linalg.norm(pstar))
-    traffic = measured_traffic()
+    traffic = measured_traffic(cfg)
     out = {
         "metric": "operator MDoF/s + CG time to rtol 1e-8, FP64 vs FP32-mixed, Q2/Q3 hex",
         "value": value,
