@@ -236,7 +236,32 @@ def batch_figures(torch, vpp, W, dev, cache):
         _, r1 = rate(b1, xs[i:i + nr], ys[i:i + nr], wl.mesh.ndofs * nr)
         out["batch_per_mesh_mdofs"].append({"n": wl.mesh.ncells[0], "ratio": wl.extra["ratio"], "mdofs": r1})
         i += nr
+    out.update(batch_cg_figures(torch, bt, probs, xs))
     return out
+
+
+def batch_cg_figures(torch, bt, probs, bs):
+    """Batched FP64 PCG of the 32 systems of the batched workload (its vectors
+    as right-hand sides, rtol 1e-8), host call to return, against the same
+    systems solved one after another with the single-problem solver."""
+    owner = [p for p, nr in zip(probs, bt.nrhs) for _ in range(nr)]
+    # warm-up: workspaces and graphs of both paths
+    bt.cg_solve(bs, [torch.zeros_like(b) for b in bs], rtol=1e-8, max_iter=2, raise_on_failure=False)
+    for p in probs:
+        p.cg_solve(bs[owner.index(p)], rtol=1e-8, max_iter=2, raise_on_failure=False)
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = bt.cg_solve(bs, xs, rtol=1e-8)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    seq = [p.cg_solve(b, rtol=1e-8)[1] for p, b in zip(owner, bs)]
+    t_seq = time.perf_counter() - t0
+    return {"batch_cg_fp64_s": t_batch, "batch_cg_iters_max": max(i["iterations"] for i in infos),
+            "batch_cg_iters_sum": sum(i["iterations"] for i in infos),
+            "batch_cg_worst_true_rel_res": max(i["true_rel_residual"] for i in infos),
+            "batch_cg_sequential_fp64_s": t_seq,
+            "batch_cg_sequential_iters_sum": sum(i["iterations"] for i in seq)}
 
 
 def main():

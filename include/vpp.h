@@ -174,8 +174,22 @@ vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32
                             const char* tune_cache, vpp_batch* out);
 /* x, y: host arrays of sum(nrhs) device pointers, ordered problem-major. */
 vpp_status vpp_batch_apply(vpp_batch b, const double* const* x, double* const* y, void* stream);
-/* One PCG per (problem, rhs) pair (solved one after another with vpp_cg_solve);
- * info: sum(nrhs) entries. */
+/* One Jacobi-PCG per (problem, rhs) pair (Sec. "Numerical framework", Krylov
+ * solver with the diagonal preconditioner; stopping rule as vpp_cg_solve).
+ * rhs, x: host arrays of sum(nrhs) device pointers, ordered problem-major; x
+ * holds the initial guesses on entry and the solutions on return.
+ * VPP_FP64: the systems of meshes below 2^20 unknowns iterate in lockstep,
+ * one iteration being one persistent batched apply and two batched vector
+ * launches over every such system that has not stopped (systems that have
+ * stopped are skipped), recorded in a hipGraph of check_every iterations; each
+ * system's reductions are summed in the order of a single solve on the batch's
+ * tiles.  Systems of larger meshes fill the GPU on their own and are solved
+ * one after another with vpp_cg_solve (and the problem's tuned kernels), after
+ * the lockstep group.  VPP_MIXED: every system is solved with vpp_cg_solve, one
+ * after another.  Synchronizes.
+ * info: sum(nrhs) entries (may be NULL).  Returns the first non-OK status of
+ * the systems (VPP_ERR_NOT_CONVERGED, VPP_ERR_BREAKDOWN) after all of them
+ * have been solved; every x then holds its last iterate. */
 vpp_status vpp_batch_cg_solve(vpp_batch b, const double* const* rhs, double* const* x,
                               const vpp_cg_opts* opts, vpp_cg_info* info, void* stream);
 vpp_status vpp_batch_get_config(vpp_batch b, vpp_kernel_config* cfg);

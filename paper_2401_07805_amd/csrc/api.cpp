@@ -142,6 +142,28 @@ struct vpp_batch_s {
     hipGraphExec_t graph = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
+    std::vector<BatchProblem> tab;     // host copy of d_probs
+    // batched FP64 PCG workspace (set up by the first batched solve): one system
+    // per (problem, rhs), its vectors at offsets cg_off in cg_x/r/p/q
+    std::vector<int> cg_prob;          // problems whose systems advance in lockstep
+    std::vector<int> cg_index;         // system (problem-major) -> lockstep system, -1 if solved alone
+    BatchProblem* cg_probs = nullptr;  // device table of the lockstep problems
+    int cg_nitems = 0, cg_nblocks = 0, cg_nsys = 0;
+    std::vector<int64_t> cg_off;
+    double *cg_x = nullptr, *cg_r = nullptr, *cg_p = nullptr, *cg_q = nullptr;
+    double** cg_tx = nullptr;          // device pointer tables of x, p, q per system
+    double** cg_tp = nullptr;
+    double** cg_tq = nullptr;
+    CgState* cg_st = nullptr;          // device, one per system
+    CgState* cg_hst = nullptr;         // pinned mirror
+    double* cg_red = nullptr;          // kRedDoubles per system
+    double* cg_dot = nullptr;          // per-tile partials of p.Ap of every system
+    double* cg_rr = nullptr;           // device, one residual norm per system
+    double* cg_hrr = nullptr;          // pinned mirror
+    CgSystem<double>* cg_sys = nullptr;
+    int cg_blocks = 0;                 // workgroups of the batched vector launches
+    hipGraphExec_t cg_graph = nullptr;
+    int cg_graph_iters = 0;
 };
 
 static void set_tiles(MeshArgs& m, const LaunchCfg& c)
@@ -291,8 +313,9 @@ static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
             if (err == hipSuccess)
                 err = launch_cg_assemble_update<double>(w.st, par, w.red, p->dot_part, tile_count(p->m), p->m,
                                                         shared_enum(p->m, p->k, p->cfg.tile), p->part, stride,
-                                                        w.x, w.r, w.p, w.q, p->inv64, p->N, s);
-            if (err == hipSuccess) err = launch_cg_pupdate<double>(w.st, par, w.red, w.r, w.p, p->inv64, p->N, s);
+                                                        w.r, w.q, p->inv64, p->N, s);
+            if (err == hipSuccess)
+                err = launch_cg_pupdate<double>(w.st, par, w.red, w.x, w.r, w.p, p->inv64, p->N, s);
         } else {
             const int64_t stride = shared_stride(p->m32);
             const float* part = reinterpret_cast<float*>(p->part);
@@ -302,9 +325,9 @@ static vpp_status build_cg_graph(vpp_problem p, int iters, hipGraphExec_t* out)
             if (err == hipSuccess)
                 err = launch_cg_assemble_update<float>(w.st32, par, w.red, p->dot_part, tile_count(p->m32), p->m32,
                                                        shared_enum(p->m32, p->k, p->cfg32.tile), part, stride,
-                                                       w.x32, w.r32, w.p32, w.q32, p->inv32, p->N, s);
+                                                       w.r32, w.q32, p->inv32, p->N, s);
             if (err == hipSuccess)
-                err = launch_cg_pupdate<float>(w.st32, par, w.red, w.r32, w.p32, p->inv32, p->N, s);
+                err = launch_cg_pupdate<float>(w.st32, par, w.red, w.x32, w.r32, w.p32, p->inv32, p->N, s);
         }
     }
     hipError_t e2 = hipStreamEndCapture(s, &g);
@@ -933,7 +956,7 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream)
 static vpp_status batch_build_table(vpp_batch b)
 {
     std::vector<BatchProblem> tab(b->probs.size());
-    int item = 0, rhs = 0;
+    int item = 0, rhs = 0, dot = 0;
     int64_t part = 0;
     for (size_t i = 0; i < b->probs.size(); ++i) {
         MeshArgs m = b->probs[i]->m;
@@ -946,6 +969,9 @@ static vpp_status batch_build_table(vpp_batch b)
         tab[i].part_begin = part;
         tab[i].nshared = shared_stride(m);
         tab[i].se = shared_enum(m, b->k, b->cfg.tile);
+        tab[i].ntiles = tile_count(m);
+        tab[i].dot_begin = dot;
+        dot += tab[i].ntiles * b->nrhs[i];
         item += tile_count(m);
         rhs += b->nrhs[i];
         part += 8 * std::max<int64_t>(1, tab[i].nshared) * b->nrhs[i];
@@ -959,6 +985,7 @@ static vpp_status batch_build_table(vpp_batch b)
         b->part_n = (size_t)part;
     }
     VPP_HIP(hipMemcpy(b->d_probs, tab.data(), tab.size() * sizeof(BatchProblem), hipMemcpyHostToDevice));
+    b->tab = tab;
     int per_cu = batch_blocks_per_cu(b->cfg, b->k);
     if (per_cu < 1) per_cu = 1;
     hipDeviceProp_t prop;
@@ -974,8 +1001,8 @@ static vpp_status batch_build_graph(vpp_batch b)
     hipGraph_t g = nullptr;
     VPP_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     BatchArgs ba{b->d_probs, (int)b->probs.size(), b->nitems, b->d_x, b->d_y, b->d_part, b->d_queue,
-                 b->probs[0]->desc.heaviside};
-    hipError_t err = launch_batch_apply(b->cfg, b->k, ba, b->nblocks, b->total_rhs, b->stream);
+                 b->probs[0]->desc.heaviside, nullptr, 0, nullptr};
+    hipError_t err = launch_batch_apply(b->cfg, b->k, ba, b->nblocks, b->total_rhs, false, b->stream);
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (err != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -1068,6 +1095,264 @@ static vpp_status batch_tune(vpp_batch b, const char* cache_path)
     return batch_build_table(b);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched FP64 PCG.  A system (one (problem, rhs) pair) whose mesh has at
+// least kLockstepMaxDofs unknowns fills the GPU on its own and is solved with
+// the single-problem solver and its tuned kernels.  All other systems advance
+// in lockstep, one iteration being the persistent batched apply (tile kernel
+// with per-tile p.Ap partials) and the batched update and search-direction
+// update; a system that has stopped is skipped by all three.  Each lockstep
+// system's reductions have the workgroup count and summation order of a single
+// solve on the batch's tiles.
+constexpr int64_t kLockstepMaxDofs = int64_t(1) << 20;
+
+static void batch_cg_free(vpp_batch b)
+{
+    if (b->cg_graph) (void)hipGraphExecDestroy(b->cg_graph);
+    b->cg_graph = nullptr;
+    b->cg_graph_iters = 0;
+    dev_free(b->cg_probs);
+    dev_free(b->cg_x); dev_free(b->cg_r); dev_free(b->cg_p); dev_free(b->cg_q);
+    dev_free(b->cg_tx); dev_free(b->cg_tp); dev_free(b->cg_tq);
+    dev_free(b->cg_st); dev_free(b->cg_red); dev_free(b->cg_dot); dev_free(b->cg_rr); dev_free(b->cg_sys);
+    if (b->cg_hst) (void)hipHostFree(b->cg_hst);
+    if (b->cg_hrr) (void)hipHostFree(b->cg_hrr);
+    b->cg_hst = nullptr;
+    b->cg_hrr = nullptr;
+    b->cg_prob.clear();
+    b->cg_index.clear();
+    b->cg_nsys = 0;
+}
+
+static vpp_status batch_cg_setup(vpp_batch b)
+{
+    if (!b->cg_index.empty()) return VPP_OK;
+    // the lockstep problems, renumbered: items, rhs and dot partials of the subset
+    std::vector<BatchProblem> tab;
+    int item = 0, rhs = 0, ndot = 0;
+    b->cg_index.assign(b->total_rhs, -1);
+    for (size_t i = 0, k = 0; i < b->probs.size(); k += b->nrhs[i], ++i) {
+        if (b->probs[i]->N >= kLockstepMaxDofs) continue;
+        BatchProblem P = b->tab[i];
+        P.tile_begin = item;
+        P.rhs_begin = rhs;
+        P.dot_begin = ndot;
+        for (int j = 0; j < b->nrhs[i]; ++j) b->cg_index[k + j] = rhs + j;
+        item += P.ntiles;
+        rhs += P.nrhs;
+        ndot += P.ntiles * P.nrhs;
+        tab.push_back(P);
+        b->cg_prob.push_back((int)i);
+    }
+    const int S = rhs;
+    b->cg_nsys = S;
+    b->cg_nitems = item;
+    if (S == 0) return VPP_OK;
+    int per_cu = batch_blocks_per_cu(b->cfg, b->k);
+    b->cg_nblocks = std::max(1, std::min(device_cu_count() * std::max(1, per_cu), item));
+    b->cg_off.assign(S + 1, 0);
+    for (size_t t = 0, sidx = 0; t < tab.size(); ++t)
+        for (int j = 0; j < tab[t].nrhs; ++j, ++sidx)   // 512-byte aligned system vectors
+            b->cg_off[sidx + 1] = b->cg_off[sidx] + ((b->probs[b->cg_prob[t]]->N + 63) & ~int64_t(63));
+    const size_t nv = (size_t)b->cg_off[S];
+    vpp_status st;
+    if ((st = dev_alloc(&b->cg_probs, tab.size(), "batch cg table")) ||
+        (st = dev_alloc(&b->cg_x, nv, "batch cg x")) || (st = dev_alloc(&b->cg_r, nv, "batch cg r")) ||
+        (st = dev_alloc(&b->cg_p, nv, "batch cg p")) || (st = dev_alloc(&b->cg_q, nv, "batch cg q")) ||
+        (st = dev_alloc(&b->cg_tx, S, "batch cg table")) || (st = dev_alloc(&b->cg_tp, S, "batch cg table")) ||
+        (st = dev_alloc(&b->cg_tq, S, "batch cg table")) || (st = dev_alloc(&b->cg_st, S, "batch cg states")) ||
+        (st = dev_alloc(&b->cg_red, (size_t)S * kRedDoubles, "batch cg partials")) ||
+        (st = dev_alloc(&b->cg_dot, (size_t)std::max(1, ndot), "batch cg dot partials")) ||
+        (st = dev_alloc(&b->cg_rr, S, "batch cg norms")) || (st = dev_alloc(&b->cg_sys, S, "batch cg table"))) {
+        batch_cg_free(b);
+        return st;
+    }
+    if (hipHostMalloc((void**)&b->cg_hst, S * sizeof(CgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->cg_hrr, S * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        batch_cg_free(b);
+        return fail(VPP_ERR_OUT_OF_MEMORY, "batch cg host mirrors");
+    }
+    std::vector<double*> tx(S), tp(S), tq(S);
+    std::vector<CgSystem<double>> sys(S);
+    int blk = 0;
+    for (size_t t = 0, sidx = 0; t < tab.size(); ++t)
+        for (int j = 0; j < tab[t].nrhs; ++j, ++sidx) {
+            const BatchProblem& P = tab[t];
+            const vpp_problem prob = b->probs[b->cg_prob[t]];
+            const int64_t off = b->cg_off[sidx];
+            tx[sidx] = b->cg_x + off;
+            tp[sidx] = b->cg_p + off;
+            tq[sidx] = b->cg_q + off;
+            CgSystem<double>& y = sys[sidx];
+            y.st = b->cg_st + sidx;
+            y.red = b->cg_red + sidx * kRedDoubles;
+            y.e = P.se;
+            y.bcmask = P.m.bcmask;
+            y.part = b->d_part + P.part_begin + (int64_t)j * 8 * P.nshared;
+            y.stride = P.nshared;
+            y.dot_part = b->cg_dot + P.dot_begin + j * P.ntiles;
+            y.ndot = P.ntiles;
+            y.x = tx[sidx];
+            y.r = b->cg_r + off;
+            y.p = tp[sidx];
+            y.q = tq[sidx];
+            y.invd = prob->inv64;
+            y.n = prob->N;
+            y.blk_begin = blk;
+            y.nblk = cg_update_blocks(y.n);
+            blk += y.nblk;
+        }
+    b->cg_blocks = blk;
+    if (hipMemcpy(b->cg_probs, tab.data(), tab.size() * sizeof(BatchProblem), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->cg_tx, tx.data(), S * sizeof(double*), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->cg_tp, tp.data(), S * sizeof(double*), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->cg_tq, tq.data(), S * sizeof(double*), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->cg_sys, sys.data(), S * sizeof(CgSystem<double>), hipMemcpyHostToDevice) != hipSuccess) {
+        batch_cg_free(b);
+        return fail(VPP_ERR_HIP, "batch cg tables");
+    }
+    return VPP_OK;
+}
+
+// Record `iters` (even) lockstep PCG iterations into a graph.
+static vpp_status batch_cg_graph(vpp_batch b, int iters)
+{
+    if (b->cg_graph && b->cg_graph_iters == iters) return VPP_OK;
+    if (b->cg_graph) (void)hipGraphExecDestroy(b->cg_graph);
+    b->cg_graph = nullptr;
+    hipGraph_t g = nullptr;
+    VPP_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int it = 0; it < iters && err == hipSuccess; ++it) {
+        const int par = it & 1;
+        BatchArgs ba{b->cg_probs, (int)b->cg_prob.size(), b->cg_nitems, b->cg_tp, b->cg_tq, b->d_part, b->d_queue,
+                     b->probs[0]->desc.heaviside, b->cg_st, par, b->cg_dot};
+        err = launch_batch_apply(b->cfg, b->k, ba, b->cg_nblocks, b->cg_nsys, true, b->stream);
+        if (err == hipSuccess)
+            err = launch_cg_batch_step(b->cg_sys, b->cg_nsys, b->cg_blocks, par, b->d_queue, b->stream);
+    }
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(VPP_ERR_HIP, std::string("batch cg graph capture: ") + hipGetErrorString(err));
+    }
+    VPP_HIP(e2);
+    hipError_t e3 = hipGraphInstantiate(&b->cg_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    VPP_HIP(e3);
+    b->cg_graph_iters = iters;
+    return VPP_OK;
+}
+
+// q = A x of every lockstep system (plain batched apply, assembly included).
+static vpp_status batch_cg_apply_x(vpp_batch b)
+{
+    BatchArgs ba{b->cg_probs, (int)b->cg_prob.size(), b->cg_nitems, b->cg_tx, b->cg_tq, b->d_part, b->d_queue,
+                 b->probs[0]->desc.heaviside, nullptr, 0, nullptr};
+    VPP_HIP(launch_batch_apply(b->cfg, b->k, ba, b->cg_nblocks, b->cg_nsys, false, b->stream));
+    return VPP_OK;
+}
+
+// Lockstep PCG of the systems k with cg_index[k] >= 0; rhs, x, info indexed by k.
+static vpp_status batch_pcg64_lockstep(vpp_batch b, const double* const* rhs, double* const* x, const vpp_cg_opts& o,
+                                       int chunk, std::vector<vpp_cg_info>& info)
+{
+    vpp_status st;
+    const int S = b->cg_nsys;
+    if (S == 0) return VPP_OK;
+    if ((st = batch_cg_graph(b, chunk))) return st;
+    hipStream_t s = b->stream;
+    std::vector<int> sys_k(S);           // lockstep system -> caller's system index
+    std::vector<int64_t> n(S);
+    std::vector<const double*> inv(S);
+    for (size_t i = 0, k = 0; i < b->probs.size(); ++i)
+        for (int j = 0; j < b->nrhs[i]; ++j, ++k) {
+            const int l = b->cg_index[k];
+            if (l < 0) continue;
+            sys_k[l] = (int)k;
+            n[l] = b->probs[i]->N;
+            inv[l] = b->probs[i]->inv64;
+        }
+    for (int l = 0; l < S; ++l)
+        VPP_HIP(hipMemcpyAsync(b->cg_x + b->cg_off[l], x[sys_k[l]], n[l] * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if ((st = batch_cg_apply_x(b))) return st;
+    CgState* hs = b->cg_hst;
+    std::memset(hs, 0, S * sizeof(CgState));
+    VPP_HIP(hipMemcpyAsync(b->cg_st, hs, S * sizeof(CgState), hipMemcpyHostToDevice, s));
+    for (int l = 0; l < S; ++l) {
+        const int64_t off = b->cg_off[l];
+        VPP_HIP(launch_cg_init<double>(b->cg_st + l, b->cg_red + (size_t)l * kRedDoubles, rhs[sys_k[l]],
+                                       b->cg_q + off, b->cg_r + off, b->cg_p + off, inv[l], n[l], s));
+    }
+    VPP_HIP(hipMemcpyAsync(hs, b->cg_st, S * sizeof(CgState), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    std::vector<double> r0(S), tol2(S);
+    std::vector<bool> decided(S, true);
+    for (int l = 0; l < S; ++l) {
+        vpp_cg_info& inf = info[sys_k[l]];
+        const double rr0 = hs[l].rr_last, rz0 = hs[l].rz[0];
+        r0[l] = std::sqrt(rr0);
+        const double thr = std::max(o.rtol * r0[l], o.atol);
+        tol2[l] = thr * thr;
+        inf = vpp_cg_info{};
+        inf.rel_residual = r0[l] > 0 ? 1.0 : 0.0;
+        CgState init{};
+        init.rz[0] = rz0;
+        init.tol2 = tol2[l];
+        init.max_iter = o.max_iter;
+        if (!std::isfinite(rr0) || !std::isfinite(rz0)) {
+            inf.status = VPP_ERR_BREAKDOWN;
+            init.breakdown = 1;
+            init.halt[0] = 1;
+        } else if (r0[l] == 0.0 || r0[l] < o.atol) {
+            inf.status = VPP_OK;
+            init.halt[0] = 1;   // converged before any iteration
+        } else if (o.max_iter == 0) {
+            inf.status = VPP_ERR_NOT_CONVERGED;
+            init.halt[0] = 1;
+        } else {
+            decided[l] = false;
+        }
+        hs[l] = init;
+    }
+    VPP_HIP(hipMemcpyAsync(b->cg_st, hs, S * sizeof(CgState), hipMemcpyHostToDevice, s));
+    const int max_launch = o.max_iter / chunk + 2;
+    for (int launch = 0; launch < max_launch; ++launch) {
+        bool all = true;
+        for (int l = 0; l < S && all; ++l) all = hs[l].halt[0] || hs[l].halt[1];
+        if (all) break;
+        VPP_HIP(hipGraphLaunch(b->cg_graph, s));
+        VPP_HIP(hipMemcpyAsync(hs, b->cg_st, S * sizeof(CgState), hipMemcpyDeviceToHost, s));
+        VPP_HIP(hipStreamSynchronize(s));
+    }
+    for (int l = 0; l < S; ++l) {
+        if (decided[l]) continue;
+        vpp_cg_info& inf = info[sys_k[l]];
+        inf.iterations = hs[l].iters;
+        inf.rel_residual = std::sqrt(hs[l].rr_last) / r0[l];
+        if (hs[l].breakdown) inf.status = VPP_ERR_BREAKDOWN;
+        else if (hs[l].rr_last < tol2[l]) inf.status = VPP_OK;
+        else inf.status = VPP_ERR_NOT_CONVERGED;
+    }
+    // true residuals ||b - A x|| in FP64, then the solutions back to the caller
+    if ((st = batch_cg_apply_x(b))) return st;
+    for (int l = 0; l < S; ++l) {
+        const int64_t off = b->cg_off[l];
+        VPP_HIP(launch_residual(rhs[sys_k[l]], b->cg_q + off, nullptr, n[l], b->cg_red + (size_t)l * kRedDoubles,
+                                b->cg_rr + l, s));
+        VPP_HIP(hipMemcpyAsync(x[sys_k[l]], b->cg_x + off, n[l] * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    VPP_HIP(hipMemcpyAsync(b->cg_hrr, b->cg_rr, S * sizeof(double), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l < S; ++l)
+        info[sys_k[l]].true_rel_residual = r0[l] > 0 ? std::sqrt(b->cg_hrr[l]) / r0[l] : 0.0;
+    return VPP_OK;
+}
+
+extern "C" {
+
 vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32_t nprob, const char* tune_cache,
                             vpp_batch* out)
 {
@@ -1143,16 +1428,39 @@ vpp_status vpp_batch_cg_solve(vpp_batch b, const double* const* rhs, double* con
                               vpp_cg_info* info, void* stream)
 {
     if (!b || !rhs || !x || !opts) return fail(VPP_ERR_INVALID_ARG, "null argument");
-    vpp_status worst = VPP_OK;
-    int r = 0;
-    for (size_t i = 0; i < b->probs.size(); ++i)
+    if (!(opts->rtol >= 0.0) || !(opts->atol >= 0.0) || opts->max_iter < 0)
+        return fail(VPP_ERR_INVALID_ARG, "tolerances must be >= 0 and max_iter >= 0");
+    if (opts->precision != VPP_FP64 && opts->precision != VPP_MIXED)
+        return fail(VPP_ERR_INVALID_ARG, "precision must be VPP_FP64 or VPP_MIXED");
+    for (int i = 0; i < b->total_rhs; ++i)
+        if (!rhs[i] || !x[i]) return fail(VPP_ERR_INVALID_ARG, "null vector in batch");
+    for (auto* p : b->probs)
+        if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called for every problem");
+    DeviceGuard dg(b->device);
+    std::vector<vpp_cg_info> inf(b->total_rhs);
+    const bool fp64 = opts->precision == VPP_FP64;
+    if (fp64) {
+        int chunk = opts->check_every > 0 ? opts->check_every : 32;
+        chunk = std::max(2, std::min(chunk, 512));
+        chunk += chunk & 1;
+        vpp_status st;
+        if ((st = batch_cg_setup(b))) return st;
+        VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+        if ((st = batch_pcg64_lockstep(b, rhs, x, *opts, chunk, inf))) return st;
+    }
+    // systems solved one at a time: the large ones (FP64) or all (mixed
+    // precision, each system with its own FP64 phases)
+    for (size_t i = 0, r = 0; i < b->probs.size(); ++i)
         for (int j = 0; j < b->nrhs[i]; ++j, ++r) {
-            vpp_cg_info inf{};
-            vpp_status st = vpp_cg_solve(b->probs[i], rhs[r], x[r], opts, &inf, stream);
-            if (info) info[r] = inf;
+            if (fp64 && b->cg_index[r] >= 0) continue;
+            vpp_status st = vpp_cg_solve(b->probs[i], rhs[r], x[r], opts, &inf[r], stream);
             if (st == VPP_ERR_HIP || st == VPP_ERR_OUT_OF_MEMORY || st == VPP_ERR_INVALID_ARG) return st;
-            if (st != VPP_OK && worst == VPP_OK) worst = st;
         }
+    vpp_status worst = VPP_OK;
+    for (int r = 0; r < b->total_rhs; ++r) {
+        if (info) info[r] = inf[r];
+        if (inf[r].status != VPP_OK && worst == VPP_OK) worst = (vpp_status)inf[r].status;
+    }
     if (worst != VPP_OK) return fail(worst, "at least one solve of the batch did not converge");
     return VPP_OK;
 }
@@ -1171,6 +1479,7 @@ vpp_status vpp_batch_destroy(vpp_batch b)
     DeviceGuard dg(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    batch_cg_free(b);
     dev_free(b->d_probs); dev_free(b->d_x); dev_free(b->d_y); dev_free(b->d_part); dev_free(b->d_queue);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;

@@ -240,9 +240,15 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
         const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
         const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
         const unsigned lane_b = (unsigned)(K * lx + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(double);
+        // systems of a batched PCG that have stopped are skipped
+        bool any = true;
+        if (a.st) {
+            any = false;
+            for (int r = 0; r < nrhs; ++r) any = any || !a.st[rhs0 + r].halt[a.par];
+        }
         // the coefficient of the tile is computed once for all right-hand sides
         double cw[N3];
-        if (active) {
+        if (active && any) {
             gather_cell_t<K>(phi + tile0, lane_b, nx, nxy, 0, cw);
             sweep3<K, MS, false, 0>(cw);
             sweep3<K, MS, false, 1>(cw);
@@ -251,6 +257,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
         }
         const int faces = active ? cell_dirichlet_faces(m, cx, cy, cz) : 0;
         for (int r = 0; r < nrhs; ++r) {
+            if (a.st && a.st[rhs0 + r].halt[a.par]) continue;   // uniform over the workgroup
             const double* x = a.x[rhs0 + r];
             double* y = a.y[rhs0 + r];
             double* part = a.part + a.probs[pi].part_begin + (int64_t)r * 8 * a.probs[pi].nshared;
@@ -266,8 +273,12 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
                     if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) slot[q * CS + tid] = u[q];
             }
             __syncthreads();
-            flush_two_pass<K, double, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy, cz, x, y, part,
-                                                  a.probs[pi].nshared, false);
+            const double d = flush_two_pass<K, double, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy,
+                                                                   cz, x, y, part, a.probs[pi].nshared, a.st != nullptr);
+            if (a.st) {
+                const double sum = block_sum<NT>(d);
+                if (tid == 0) a.dot_part[a.probs[pi].dot_begin + r * a.probs[pi].ntiles + tile] = sum;
+            }
         }
     }
 }
@@ -312,7 +323,7 @@ __global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a
     X(2, 8, 4, 4)
 
 hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
-                              hipStream_t s)
+                              bool tiles_only, hipStream_t s)
 {
 #define VPP_BL(K, TX, TY, TZ)                                                                       \
     if (k == K && c.variant == 4 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {       \
@@ -323,7 +334,7 @@ hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int
             hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, 1>), dim3(nblocks),                \
                                dim3(TX * TY * TZ), 0, s, a);                                        \
         hipError_t e = hipGetLastError();                                                           \
-        if (e != hipSuccess) return e;                                                              \
+        if (e != hipSuccess || tiles_only) return e;                                                \
         BatchAssembleArgs b{a.probs, a.nprob, a.y, a.part, a.queue};                                \
         hipLaunchKernelGGL(batch_assemble_kernel, dim3(512, (unsigned)total_rhs), dim3(256), 0, s, b);  \
         return hipGetLastError();                                                                   \

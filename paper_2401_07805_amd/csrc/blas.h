@@ -10,7 +10,7 @@ namespace vpp {
 // Device-resident scalars of one PCG (FP64 for every precision).
 struct CgState {
     double rz[2];     // r.D^-1 r at the start of the iteration of parity 0 / 1
-    double pAp;       // p.Ap, written by the apply of the current iteration
+    double pAp;       // p.Ap of the current iteration, written by the update
     double rr[2];     // r.r of the new residual (by iteration parity)
     double rznew[2];  // r.D^-1 r of the new residual (by iteration parity)
     double tol2;      // convergence threshold on r.r
@@ -31,15 +31,45 @@ hipError_t launch_cg_init(CgState* st, double* red, const T* b, const T* q, T* r
                           hipStream_t s);
 // CG update after a tiles-only apply q = A p: p.Ap from the ndot per-workgroup
 // partials dot_part; the values of q on shared nodes assembled from the partial
-// array part (stride `stride`, enumeration e); alpha = rz / pAp, x += alpha p,
+// array part (stride `stride`, enumeration e); alpha = rz / pAp,
 // r -= alpha q, and per-workgroup partials of r.r and r.(D^-1 r).
 template <typename T>
 hipError_t launch_cg_assemble_update(CgState* st, int par, double* red, const double* dot_part, int ndot,
-                                     const MeshArgs& m, const SharedEnum& e, const T* part, int64_t stride, T* x,
-                                     T* r, const T* p, const T* q, const T* invd, int64_t n, hipStream_t s);
+                                     const MeshArgs& m, const SharedEnum& e, const T* part, int64_t stride, T* r,
+                                     const T* q, const T* invd, int64_t n, hipStream_t s);
+// Stop decision, x += alpha p (alpha as in the update) and p = D^-1 r + beta p.
 template <typename T>
-hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, const T* r, T* p, const T* invd, int64_t n,
-                             hipStream_t s);
+hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, T* x, const T* r, T* p, const T* invd,
+                             int64_t n, hipStream_t s);
+
+// One system of a batched PCG (entry of a device table; one per (mesh, rhs)).
+template <typename T>
+struct CgSystem {
+    CgState* st;
+    double* red;              // kRedDoubles partials of this system's reductions
+    SharedEnum e;             // shared-node enumeration of the batched apply's tiles
+    int bcmask;
+    const T* part;            // the batched apply's shared-node partials of this system
+    int64_t stride;
+    const double* dot_part;   // the batched apply's per-tile partials of p.Ap (ndot)
+    int ndot;
+    T* x;
+    T* r;
+    T* p;
+    const T* q;
+    const T* invd;
+    int64_t n;
+    int blk_begin;            // first workgroup of this system in the batched launches
+    int nblk;                 // its workgroup count, cg_update_blocks(n)
+};
+
+// Workgroups of the single-system update and search-direction update.
+int cg_update_blocks(int64_t n);
+// The update and the search-direction update of every system of sys[0..nsys)
+// (device table) as two launches of total_blocks workgroups; the first also
+// resets the batched apply's work counter *queue (if not null).
+hipError_t launch_cg_batch_step(const CgSystem<double>* sys, int nsys, int total_blocks, int par, int* queue,
+                                hipStream_t s);
 
 // r = b - q in FP64 (r may be null) and *rr = r.r.
 hipError_t launch_residual(const double* b, const double* q, double* r, int64_t n, double* red, double* rr,

@@ -7,11 +7,14 @@
 //   apply:    the tile kernel of q = A p with per-workgroup partials of p.q
 //             (apply kernels; the shared-node assembly is left to update)
 //   update:   pAp from those partials; alpha = rz/pAp; q on shared nodes from
-//             the apply's partials; x += alpha p; r -= alpha q;
+//             the apply's partials; r -= alpha q;
 //             per-workgroup partial sums of r.r and r.(D^-1 r)
 //   pupdate:  every workgroup sums the partials in the same fixed order,
-//             beta = rz_new/rz; p = D^-1 r + beta p; workgroup 0 records the
-//             iteration and the stop decision.
+//             beta = rz_new/rz; x += alpha p and p = D^-1 r + beta p in one
+//             pass over p; workgroup 0 records the iteration and the stop
+//             decision.
+// The solution update sits in pupdate because that kernel reads p anyway:
+// the iteration then moves 80 instead of 88 bytes per FP64 unknown.
 // Reductions use no atomics: a producer writes one partial per workgroup and
 // the consumer sums them in a fixed order, so every run gives the same bits.
 //
@@ -73,12 +76,16 @@ __device__ __forceinline__ void sum_partials(const double* red, int ng, double& 
     block_sum2<BT>(a, b);
 }
 
-__device__ __forceinline__ void write_partials(double* red, double a, double b)
+__device__ __forceinline__ void write_partials(double* red, double a, double b, int bid)
 {
     if (threadIdx.x == 0) {
-        red[blockIdx.x] = a;
-        red[kMaxRedBlocks + blockIdx.x] = b;
+        red[bid] = a;
+        red[kMaxRedBlocks + bid] = b;
     }
+}
+__device__ __forceinline__ void write_partials(double* red, double a, double b)
+{
+    write_partials(red, a, b, blockIdx.x);
 }
 
 // Number of workgroups of the streaming kernels (about 4 packets per thread).
@@ -158,29 +165,28 @@ __device__ __forceinline__ T node_value(const SharedParts<T>& sp, const T* __res
     return v;
 }
 
+// Body of the update for workgroup bid of nblk (one system); the workgroup
+// returns at once when the system has stopped.
 template <typename T>
-__global__ void __launch_bounds__(BT) cg_assemble_update_kernel(CgState* st, int par, double* red, SharedParts<T> sp,
-                                                                T* __restrict__ x, T* __restrict__ r,
-                                                                const T* __restrict__ p, const T* __restrict__ q,
-                                                                const T* __restrict__ invd, int64_t n)
+__device__ __forceinline__ void assemble_update_body(int bid, int nblk, CgState* st, int par, double* red,
+                                                     const SharedParts<T>& sp, T* __restrict__ r,
+                                                     const T* __restrict__ q, const T* __restrict__ invd, int64_t n)
 {
     if (st->halt[par]) return;
     double pAp = 0.0, unused = 0.0;
     for (int i = threadIdx.x; i < sp.ndot; i += BT) pAp += sp.dot_part[i];
     block_sum2<BT>(pAp, unused);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->pAp = pAp;
+    if (bid == 0 && threadIdx.x == 0) st->pAp = pAp;
     if (!(pAp > 0.0) || !isfinite(pAp)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->breakdown = 1;
+        if (bid == 0 && threadIdx.x == 0) st->breakdown = 1;
         return;
     }
     const T alpha = T(st->rz[par] / pAp);
     double rr = 0.0, rz = 0.0;
     using P = Pack<T>;
     const int64_t np = n / P::W;
-    for (int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x; c < np; c += (int64_t)gridDim.x * BT) {
-        P xv = reinterpret_cast<const P*>(x)[c];
+    for (int64_t c = (int64_t)bid * BT + threadIdx.x; c < np; c += (int64_t)nblk * BT) {
         P rv = reinterpret_cast<const P*>(r)[c];
-        const P pv = reinterpret_cast<const P*>(p)[c];
         const P dv = reinterpret_cast<const P*>(invd)[c];
         P qv = reinterpret_cast<const P*>(q)[c];
         // shared nodes of the packet: all partial loads issued before any use;
@@ -209,41 +215,47 @@ __global__ void __launch_bounds__(BT) cg_assemble_update_kernel(CgState* st, int
             }
 #pragma unroll
         for (int j = 0; j < P::W; ++j) {
-            const T qj = qv.v[j];
-            xv.v[j] = fma(alpha, pv.v[j], xv.v[j]);
-            const T ri = fma(-alpha, qj, rv.v[j]);
+            const T ri = fma(-alpha, qv.v[j], rv.v[j]);
             rv.v[j] = ri;
             rr += (double)ri * (double)ri;
             rz += (double)ri * (double)(ri * dv.v[j]);
         }
-        reinterpret_cast<P*>(x)[c] = xv;
         reinterpret_cast<P*>(r)[c] = rv;
     }
-    if (blockIdx.x == 0)
+    if (bid == 0)
         for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) {
-            x[i] = fma(alpha, p[i], x[i]);
             const T ri = fma(-alpha, node_value(sp, q, i), r[i]);
             r[i] = ri;
             rr += (double)ri * (double)ri;
             rz += (double)ri * (double)(ri * invd[i]);
         }
     block_sum2<BT>(rr, rz);
-    write_partials(red, rr, rz);
+    write_partials(red, rr, rz, bid);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BT) cg_pupdate_kernel(CgState* st, int par, const double* red, int ng,
-                                                        const T* __restrict__ r, T* __restrict__ p,
-                                                        const T* __restrict__ invd, int64_t n)
+__global__ void __launch_bounds__(BT) cg_assemble_update_kernel(CgState* st, int par, double* red, SharedParts<T> sp,
+                                                                T* __restrict__ r, const T* __restrict__ q,
+                                                                const T* __restrict__ invd, int64_t n)
+{
+    assemble_update_body<T>(blockIdx.x, gridDim.x, st, par, red, sp, r, q, invd, n);
+}
+
+// Body of the search-direction update for workgroup bid of nblk (one system;
+// ng partials of the update to sum).
+template <typename T>
+__device__ __forceinline__ void pupdate_body(int bid, int nblk, CgState* st, int par, const double* red, int ng,
+                                             T* __restrict__ x, const T* __restrict__ r, T* __restrict__ p,
+                                             const T* __restrict__ invd, int64_t n)
 {
     if (st->halt[par] || st->breakdown) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->halt[1 - par] = 1;
+        if (bid == 0 && threadIdx.x == 0) st->halt[1 - par] = 1;
         return;
     }
     double rr, rzn;
     sum_partials(red, ng, rr, rzn);
     const double beta_d = rzn / st->rz[par];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         const int it = st->iters + 1;
         st->iters = it;
         st->rr_last = rr;
@@ -257,19 +269,69 @@ __global__ void __launch_bounds__(BT) cg_pupdate_kernel(CgState* st, int par, co
             st->halt[1 - par] = 1;
         }
     }
+    // the same alpha as the update's (same operands, same rounding)
+    const T alpha = T(st->rz[par] / st->pAp);
     const T beta = T(beta_d);
     using P = Pack<T>;
     const int64_t np = n / P::W;
-    for (int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x; c < np; c += (int64_t)gridDim.x * BT) {
+    for (int64_t c = (int64_t)bid * BT + threadIdx.x; c < np; c += (int64_t)nblk * BT) {
         const P rv = reinterpret_cast<const P*>(r)[c];
         const P dv = reinterpret_cast<const P*>(invd)[c];
         P pv = reinterpret_cast<const P*>(p)[c];
+        P xv = reinterpret_cast<const P*>(x)[c];
 #pragma unroll
-        for (int j = 0; j < P::W; ++j) pv.v[j] = fma(beta, pv.v[j], rv.v[j] * dv.v[j]);
+        for (int j = 0; j < P::W; ++j) {
+            xv.v[j] = fma(alpha, pv.v[j], xv.v[j]);
+            pv.v[j] = fma(beta, pv.v[j], rv.v[j] * dv.v[j]);
+        }
+        reinterpret_cast<P*>(x)[c] = xv;
         reinterpret_cast<P*>(p)[c] = pv;
     }
-    if (blockIdx.x == 0)
-        for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) p[i] = fma(beta, p[i], r[i] * invd[i]);
+    if (bid == 0)
+        for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) {
+            x[i] = fma(alpha, p[i], x[i]);
+            p[i] = fma(beta, p[i], r[i] * invd[i]);
+        }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BT) cg_pupdate_kernel(CgState* st, int par, const double* red, int ng,
+                                                        T* __restrict__ x, const T* __restrict__ r,
+                                                        T* __restrict__ p, const T* __restrict__ invd, int64_t n)
+{
+    pupdate_body<T>(blockIdx.x, gridDim.x, st, par, red, ng, x, r, p, invd, n);
+}
+
+// ---------------------------------------------------------------------------
+// Batched PCG: the update and the search-direction update of every system of a
+// batch in one launch each.  System i owns workgroups [blk_begin, blk_begin +
+// nblk) of the grid, nblk being what the single-system launch would use, so
+// each system's reductions are summed in the same order as in a single solve.
+
+template <typename T>
+__device__ __forceinline__ int system_of_block(const CgSystem<T>* sys, int nsys)
+{
+    int s = 0;
+    for (int i = 1; i < nsys; ++i)
+        if (sys[i].blk_begin <= (int)blockIdx.x) s = i;
+    return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BT) cg_batch_update_kernel(const CgSystem<T>* sys, int nsys, int par, int* queue)
+{
+    // the batched apply that precedes this launch pulls work items from queue
+    if (queue && blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;
+    const CgSystem<T>& y = sys[system_of_block(sys, nsys)];
+    const SharedParts<T> sp{y.e, y.bcmask, y.part, y.stride, y.dot_part, y.ndot};
+    assemble_update_body<T>((int)blockIdx.x - y.blk_begin, y.nblk, y.st, par, y.red, sp, y.r, y.q, y.invd, y.n);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BT) cg_batch_pupdate_kernel(const CgSystem<T>* sys, int nsys, int par)
+{
+    const CgSystem<T>& y = sys[system_of_block(sys, nsys)];
+    pupdate_body<T>((int)blockIdx.x - y.blk_begin, y.nblk, y.st, par, y.red, y.nblk, y.x, y.r, y.p, y.invd, y.n);
 }
 
 // r = b - q in FP64 and partials of r.r (outer residual of the mixed solver and
@@ -353,32 +415,44 @@ hipError_t launch_cg_init(CgState* st, double* red, const T* b, const T* q, T* r
 
 template <typename T>
 hipError_t launch_cg_assemble_update(CgState* st, int par, double* red, const double* dot_part, int ndot,
-                                     const MeshArgs& m, const SharedEnum& e, const T* part, int64_t stride, T* x,
-                                     T* r, const T* p, const T* q, const T* invd, int64_t n, hipStream_t s)
+                                     const MeshArgs& m, const SharedEnum& e, const T* part, int64_t stride, T* r,
+                                     const T* q, const T* invd, int64_t n, hipStream_t s)
 {
     SharedParts<T> sp{e, m.bcmask, part, stride, dot_part, ndot};
-    hipLaunchKernelGGL(cg_assemble_update_kernel<T>, dim3(grid_update<T>(n)), dim3(BT), 0, s, st, par, red, sp, x,
-                       r, p, q, invd, n);
+    hipLaunchKernelGGL(cg_assemble_update_kernel<T>, dim3(grid_update<T>(n)), dim3(BT), 0, s, st, par, red, sp, r,
+                       q, invd, n);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, const T* r, T* p, const T* invd, int64_t n,
-                             hipStream_t s)
+hipError_t launch_cg_pupdate(CgState* st, int par, const double* red, T* x, const T* r, T* p, const T* invd,
+                             int64_t n, hipStream_t s)
 {
     const int g = grid_update<T>(n);   // also the number of partials the update wrote
-    hipLaunchKernelGGL(cg_pupdate_kernel<T>, dim3(g), dim3(BT), 0, s, st, par, red, g, r, p, invd, n);
+    hipLaunchKernelGGL(cg_pupdate_kernel<T>, dim3(g), dim3(BT), 0, s, st, par, red, g, x, r, p, invd, n);
+    return hipGetLastError();
+}
+
+int cg_update_blocks(int64_t n) { return grid_update<double>(n); }
+
+hipError_t launch_cg_batch_step(const CgSystem<double>* sys, int nsys, int total_blocks, int par, int* queue,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(cg_batch_update_kernel<double>, dim3(total_blocks), dim3(BT), 0, s, sys, nsys, par, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cg_batch_pupdate_kernel<double>, dim3(total_blocks), dim3(BT), 0, s, sys, nsys, par);
     return hipGetLastError();
 }
 
 #define VPP_INST(T)                                                                                          \
     template hipError_t launch_cg_init<T>(CgState*, double*, const T*, const T*, T*, T*, const T*, int64_t,  \
                                           hipStream_t);                                                      \
-    template hipError_t launch_cg_pupdate<T>(CgState*, int, const double*, const T*, T*, const T*, int64_t, \
-                                             hipStream_t);                                                   \
+    template hipError_t launch_cg_pupdate<T>(CgState*, int, const double*, T*, const T*, T*, const T*, int64_t, \
+                                             hipStream_t);                                                       \
     template hipError_t launch_cg_assemble_update<T>(CgState*, int, double*, const double*, int, const MeshArgs&, \
-                                                     const SharedEnum&, const T*, int64_t, T*, T*, const T*,      \
-                                                     const T*, const T*, int64_t, hipStream_t);
+                                                     const SharedEnum&, const T*, int64_t, T*, const T*,          \
+                                                     const T*, int64_t, hipStream_t);
 VPP_INST(double)
 VPP_INST(float)
 #undef VPP_INST

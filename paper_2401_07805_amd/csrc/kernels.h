@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "common.h"
+#include "blas.h"
 #include "shared_nodes.h"
 
 namespace vpp {
@@ -97,6 +98,8 @@ struct BatchProblem {
     int64_t part_begin;  // first partial entry of this problem's first right-hand side
     int64_t nshared;     // stride of this problem's rank arrays (8 * nshared partial entries per rhs)
     SharedEnum se;       // their enumeration
+    int ntiles;          // tiles of this problem
+    int dot_begin;       // first p.Ap partial of this problem's first rhs (ntiles per rhs)
 };
 
 struct BatchArgs {
@@ -108,12 +111,19 @@ struct BatchArgs {
     double* part;        // partial slots of every (problem, rhs)
     int* queue;          // work counter, zero at launch (reset by the assembly kernel)
     int heaviside;       // shared by every problem of the batch
+    // batched PCG (st null: plain apply): the (problem, rhs) vectors whose state
+    // st[rhs].halt[par] is set are skipped, and every tile writes its partial of
+    // x.y to dot_part[dot_begin + rhs_in_problem * ntiles + tile]
+    const CgState* st;
+    int par;
+    double* dot_part;
 };
 
-// Persistent tile kernel over all work items, then one assembly launch over all
-// (problem, rhs) vectors.
+// Persistent tile kernel over all work items, then (unless tiles_only) one
+// assembly launch over all (problem, rhs) vectors, which also resets the work
+// counter; with tiles_only the caller assembles and resets it.
 hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
-                              hipStream_t s);
+                              bool tiles_only, hipStream_t s);
 int batch_blocks_per_cu(const LaunchCfg& c, int k);
 // Instantiated batch configurations of degree k (writes up to cap, returns the count).
 int list_batch_configs(int k, LaunchCfg* out, int cap);

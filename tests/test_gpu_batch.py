@@ -1,8 +1,11 @@
-"""Batched persistent apply == unbatched applies; tuning candidates agree."""
+"""Batched persistent apply == unbatched applies; tuning candidates agree;
+batched PCG reaches the oracle's solutions."""
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 import torch
 
+import oracle
 import workloads as W
 from gpu_util import dev, host, rel, say
 
@@ -61,3 +64,127 @@ def test_tune_and_candidate_invariance(tmp_path):
     c1 = prob.tune(cache)
     c2 = prob.tune(cache)
     assert c1 == c2
+
+
+def _batch_systems(nrhs=2):
+    """Four single-sphere meshes (density ratios 1e4, 1e2, 1e4, 1e4) with the
+    manufactured sine load of the mesh's own sphere and the phi-free sine load."""
+    wls = W.batch_meshes(sizes=(4, 6, 9, 5), nrhs=nrhs)
+    probs, systems = [], []
+    for wl in wls:
+        m = wl.mesh
+        p = vpp.Problem.from_mesh(m)
+        p.set_phi(dev(wl.phi))
+        probs.append(p)
+        op = oracle.Operator(m, phi=wl.phi)
+        loads = (oracle.manufactured_sine_rhs(m, wl.extra["radius"], m.eps), oracle.sine_load(m))
+        for r in range(nrhs):
+            systems.append((p, op, loads[r % 2]))
+    return probs, systems
+
+
+def test_batch_cg_fp64_matches_oracle():
+    """All (mesh, rhs) systems in lockstep: each reaches the oracle's direct
+    solution, its true residual (oracle CSR) is below rtol, and the iteration
+    counts (14 to 32 here, so systems stop at different chunks) agree with the
+    oracle's PCG and with a single solve of the same system."""
+    probs, systems = _batch_systems()
+    say("batch cg create")
+    bt = vpp.Batch(probs, [2] * len(probs))
+    bs = [dev(b) for _, _, b in systems]
+    xs = [torch.zeros_like(b) for b in bs]
+    say("batch cg fp64", bt.config)
+    infos = bt.cg_solve(bs, xs, rtol=1e-10, check_every=4)
+    for i, ((prob, op, b), inf) in enumerate(zip(systems, infos)):
+        x = host(xs[i])
+        pref = spla.spsolve(op.to_scipy().tocsc(), b)
+        res = np.linalg.norm(b - op.matvec(x)) / np.linalg.norm(b)
+        _, oinf = op.pcg(b, rtol=1e-10)
+        _, sinf = prob.cg_solve(bs[i], rtol=1e-10)
+        print(i, inf, "true res", res, "err", rel(x, pref), "oracle it", oinf["iterations"],
+              "single it", sinf["iterations"])
+        assert inf["status"] == 0
+        assert res < 1e-10 * 1.01
+        assert abs(inf["true_rel_residual"] - res) < 1e-3 * res + 1e-14
+        assert rel(x, pref) < 1e-8
+        assert abs(inf["iterations"] - oinf["iterations"]) <= 2
+        assert abs(inf["iterations"] - sinf["iterations"]) <= 2
+    # the chunk length of the graph does not change the arithmetic
+    xs2 = [torch.zeros_like(b) for b in bs]
+    infos2 = bt.cg_solve(bs, xs2, rtol=1e-10)
+    for a, b_, ia, ib in zip(xs, xs2, infos, infos2):
+        assert torch.equal(a, b_)
+        assert ia["iterations"] == ib["iterations"]
+
+
+def test_batch_cg_edge_cases():
+    """Zero and NaN right-hand sides, iteration limits and warm starts inside
+    one batch: each system ends with its own status, the others are unaffected."""
+    probs, systems = _batch_systems()
+    bt = vpp.Batch(probs, [2] * len(probs))
+    bs = [dev(b) for _, _, b in systems]
+    bs[1] = torch.zeros_like(bs[1])                 # converged before any iteration
+    bs[4] = bs[4].clone()
+    bs[4][len(bs[4]) // 2] = float("nan")            # breakdown
+    xs = [torch.zeros_like(b) for b in bs]
+    say("batch cg edge cases")
+    infos = bt.cg_solve(bs, xs, rtol=1e-10, raise_on_failure=False)
+    for i, inf in enumerate(infos):
+        if i == 1:
+            assert inf["status"] == 0 and inf["iterations"] == 0
+            assert float(xs[i].abs().max()) == 0.0
+        elif i == 4:
+            assert inf["status"] == 6
+        else:
+            _, op, b = systems[i]
+            res = np.linalg.norm(b - op.matvec(host(xs[i]))) / np.linalg.norm(b)
+            assert inf["status"] == 0 and res < 1e-10 * 1.01
+    with pytest.raises(vpp.VppError) as e:
+        bt.cg_solve(bs, [torch.zeros_like(b) for b in bs], rtol=1e-10)
+    assert e.value.status == 6
+    # iteration limit: every live system stops after exactly max_iter iterations
+    good = [dev(b) for _, _, b in systems]
+    infos = bt.cg_solve(good, [torch.zeros_like(b) for b in good], rtol=1e-14, max_iter=3,
+                        raise_on_failure=False)
+    assert all(inf["status"] == 5 and inf["iterations"] == 3 for inf in infos)
+    # warm start from the solutions: the rule is relative to the new initial
+    # residual, so the systems iterate again and converge
+    xs = [torch.zeros_like(b) for b in good]
+    bt.cg_solve(good, xs, rtol=1e-6)
+    infos = bt.cg_solve(good, xs, rtol=1e-6)
+    assert all(inf["status"] == 0 and inf["iterations"] >= 1 for inf in infos)
+    # mixed precision runs the systems one after another and reaches the FP64 criterion
+    xm = [torch.zeros_like(b) for b in good]
+    infos = bt.cg_solve(good, xm, rtol=1e-8, precision="mixed")
+    for (_, op, b), x, inf in zip(systems, xm, infos):
+        res = np.linalg.norm(b - op.matvec(host(x))) / np.linalg.norm(b)
+        assert inf["status"] == 0 and res < 1e-8 * 1.01
+
+
+def test_batch_cg_mesh_above_lockstep_size():
+    """A system of a mesh with at least 2^20 unknowns is solved on its own with
+    the single-problem solver (bit-identical to vpp_cg_solve), next to lockstep
+    systems of a small mesh that still reach the oracle's solution."""
+    small = W.batch_meshes(sizes=(6,), nrhs=2)[0]
+    big = W.small_droplet(n=52, k=2, seed=5)
+    assert big.mesh.ndofs >= 1 << 20
+    probs = []
+    for wl in (small, big):
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(dev(wl.phi))
+        probs.append(p)
+    op = oracle.Operator(small.mesh, phi=small.phi)
+    b_small = oracle.sine_load(small.mesh)
+    b_big = dev(big.vectors[0])
+    bs = [dev(b_small), dev(b_small * -2.0), b_big]
+    bt = vpp.Batch(probs, [2, 1])
+    xs = [torch.zeros_like(b) for b in bs]
+    say("batch cg with a large mesh", big.mesh.ndofs)
+    infos = bt.cg_solve(bs, xs, rtol=1e-8)
+    x1, inf1 = probs[1].cg_solve(b_big, rtol=1e-8)
+    assert infos[2]["status"] == 0 and infos[2]["iterations"] == inf1["iterations"]
+    assert torch.equal(xs[2], x1)
+    pref = spla.spsolve(op.to_scipy().tocsc(), b_small)
+    for x, scale, inf in zip(xs[:2], (1.0, -2.0), infos[:2]):
+        assert inf["status"] == 0
+        assert rel(host(x), scale * pref) < 1e-6
