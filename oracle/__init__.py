@@ -35,7 +35,7 @@ class _Desc(C.Structure):
     _fields_ = [("ncells", C.c_int32 * 3), ("origin", C.c_double * 3),
                 ("extent", C.c_double * 3), ("degree", C.c_int32), ("bc", C.c_int32 * 6),
                 ("rho_l", C.c_double), ("rho_g", C.c_double), ("heaviside", C.c_int32),
-                ("eps", C.c_double)]
+                ("eps", C.c_double), ("mass", C.c_double)]
 
 
 _lib = None
@@ -109,6 +109,7 @@ def desc_of(mesh) -> _Desc:
     d.rho_g = mesh.rho_g
     d.heaviside = mesh.heaviside
     d.eps = mesh.eps if mesh.eps > 0 else 1.0
+    d.mass = float(getattr(mesh, "mass", 0.0))
     return d
 
 

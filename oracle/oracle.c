@@ -372,9 +372,11 @@ static orc_csr* assemble_from_cq(const orc_desc* d, const double* cq, int constr
                         basis_at_qp(&L, q0, q1, q2, N, G0, G1, G2);
                         const double W = L.gw[q0] * L.gw[q1] * L.gw[q2] * L.W3;
                         const double cw = cq[c * nb + q] * W;
+                        const double mw = d->mass * W;
                         for (int a = 0; a < nb; ++a)
                             for (int b = 0; b < nb; ++b)
-                                K[a * nb + b] += cw * (G0[a] * G0[b] + G1[a] * G1[b] + G2[a] * G2[b]);
+                                K[a * nb + b] += cw * (G0[a] * G0[b] + G1[a] * G1[b] + G2[a] * G2[b]) +
+                                                 mw * N[a] * N[b];
                     }
             for (int a = 0; a < nb; ++a)
                 for (int b = 0; b < nb; ++b)
@@ -752,9 +754,11 @@ void orc_apply_rows(const orc_desc* d, const double* phi, const double* x, const
                                 for (int a = 0; a < nb; ++a) ph += N[a] * phi[gg[a]];
                                 const double W = L.gw[q0] * L.gw[q1] * L.gw[q2] * L.W3;
                                 const double cw = orc_coefficient(d, ph) * W;
+                                const double mw = d->mass * W;
                                 for (int b = 0; b < nb; ++b) {
                                     if (is_dirichlet(d, &L, gg[b])) continue;
-                                    s += cw * (G0[arow] * G0[b] + G1[arow] * G1[b] + G2[arow] * G2[b]) * x[gg[b]];
+                                    s += (cw * (G0[arow] * G0[b] + G1[arow] * G1[b] + G2[arow] * G2[b]) +
+                                          mw * N[arow] * N[b]) * x[gg[b]];
                                 }
                             }
                 }

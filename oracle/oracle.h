@@ -7,6 +7,9 @@
  *
  * What it computes (definitions, not an optimised method):
  *   a(p,q) = sum_cells sum_Gauss W_q c(x_q) grad p . grad q     (weak pressure terms, App. F)
+ *          + mu sum_cells sum_Gauss W_q p q                      (mass shift; mu = 1 and a
+ *            constant c = eta h^2 give the filters of Eqs. normal_vector_regularized and
+ *            curvature_regularized in weak form)
  *   c = 1/rho(phi) = H(phi)/rho_l + (1-H(phi))/rho_g            (Eq. rhoEff)
  *   H linear (phi+1)/2, or the sine ramp of Eq. heaviside in d(phi) (Eq. distance)
  *   (k+1)^3 Gauss points per cell (Sec. "Numerical framework")
@@ -33,6 +36,7 @@ typedef struct {
     double rho_l, rho_g;
     int32_t heaviside;   /* 0 linear, 1 sine ramp */
     double eps;          /* interface thickness (used by the sine ramp's d(phi)) */
+    double mass;         /* mass shift mu: the operator is mu M + K_c (0: pressure operator) */
 } orc_desc;
 
 typedef struct orc_csr orc_csr;

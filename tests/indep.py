@@ -80,9 +80,10 @@ def global_1d(k: int, n: int, h: float):
     return M, K
 
 
-def dense_operator(mesh, coef_at, constrained=True):
+def dense_operator(mesh, coef_at, constrained=True, mass=0.0):
     """Brute-force dense matrix: sum over cells and Gauss points of c W grad N_a . grad N_b
-    for every basis pair (a,b) of the cell (outer product of the gradient table).
+    + mass W N_a N_b for every basis pair (a,b) of the cell (outer products of the
+    gradient and value tables).
 
     coef_at(cell_index, q_tuple, x_q) -> coefficient value at that Gauss point."""
     k = mesh.degree
@@ -114,6 +115,8 @@ def dense_operator(mesh, coef_at, constrained=True):
                             W = gw[q0] * gw[q1] * gw[q2] * h[0] * h[1] * h[2]
                             c = coef_at(cell, (q0, q1, q2), xq)
                             grads = []
+                            vals = np.array([L[a0](gx[q0]) * L[a1](gx[q1]) * L[a2](gx[q2])
+                                             for (g, a0, a1, a2) in loc])
                             for (g, a0, a1, a2) in loc:
                                 grads.append(np.array([
                                     dL[a0](gx[q0]) * L[a1](gx[q1]) * L[a2](gx[q2]) / h[0],
@@ -121,7 +124,7 @@ def dense_operator(mesh, coef_at, constrained=True):
                                     L[a0](gx[q0]) * L[a1](gx[q1]) * dL[a2](gx[q2]) / h[2]]))
                             G = np.array(grads)                  # (k+1)^3 x 3
                             idx = np.array([g for (g, *_) in loc])
-                            A[np.ix_(idx, idx)] += c * W * (G @ G.T)
+                            A[np.ix_(idx, idx)] += c * W * (G @ G.T) + mass * W * np.outer(vals, vals)
     if constrained:
         mask = mesh.boundary_mask()
         A[mask, :] = 0.0

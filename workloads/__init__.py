@@ -55,6 +55,7 @@ class Mesh:
     rho_g: float = 1.0
     heaviside: int = H_LINEAR
     eps: float = 0.0          # interface thickness; only the field generators use it
+    mass: float = 0.0         # mass shift mu of the operator mu M + K_c (0: pressure operator)
 
     @property
     def nnodes(self) -> Tuple[int, int, int]:
