@@ -120,6 +120,21 @@ int64_t vpp_num_qpoints(vpp_problem p);     /* prod_d n_d * (k+1)^3, -1 on null 
  * Must precede apply / solve / gradient calls. */
 vpp_status vpp_set_phi(vpp_problem p, const double* phi, void* stream);
 
+/* Mass shift: the operator becomes mu M + K_c (Dirichlet rows stay identity
+ * rows), M the Q_k mass matrix with the same (k+1)^3 Gauss rule.  With mu = 1,
+ * rho_l = rho_g = 1/(eta h^2) and Neumann faces it is the weak form of the
+ * level-set filters n - eta h^2 Lap n = n_bar and kappa - eta h^2 Lap kappa =
+ * kappa_bar (Eqs. normal_vector_regularized, curvature_regularized; solved
+ * with CG and the diagonal preconditioner, Table tab:solver_settings); the
+ * right-hand sides (n_bar, v) are inputs like every b here.  mu >= 0, finite;
+ * mu = 0 restores the pressure operator.  Degrees 2 and 3 only
+ * (VPP_ERR_UNSUPPORTED for k = 4 with mu != 0): with mu != 0 the problem runs
+ * the variant-4 configurations listed for it (vpp_set_config rejects others;
+ * the current ones are switched if needed).  Rebuilds the diagonal if phi is
+ * set; synchronizes `stream` and the problem's stream.  Batches copy their
+ * problems' operators when created, so set mu before vpp_batch_create. */
+vpp_status vpp_set_mass(vpp_problem p, double mu, void* stream);
+
 /* y = A_D x.  prec VPP_FP64: x, y are double*; VPP_FP32: float* (the
  * coefficient and tables are then FP32 too).  x and y must not alias. */
 vpp_status vpp_apply(vpp_problem p, int32_t prec, const void* x, void* y, void* stream);

@@ -54,6 +54,7 @@ def load() -> C.CDLL:
         "vpp_num_dofs": (C.c_int64, [vp]),
         "vpp_num_qpoints": (C.c_int64, [vp]),
         "vpp_set_phi": (C.c_int, [vp, vp, vp]),
+        "vpp_set_mass": (C.c_int, [vp, C.c_double, vp]),
         "vpp_apply": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "vpp_diagonal": (C.c_int, [vp, vp, vp]),
         "vpp_cg_solve": (C.c_int, [vp, vp, vp, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),

@@ -103,6 +103,10 @@ class Problem:
                                     _stream(self.device)))
         self._phi_version += 1
 
+    def set_mass(self, mu: float):
+        """Operator mu M + K_c (vpp_set_mass); mu = 0 is the pressure operator."""
+        _check(L.load().vpp_set_mass(self._h, float(mu), _stream(self.device)))
+
     def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         prec = L.VPP_FP64 if x.dtype == torch.float64 else L.VPP_FP32
         if x.dtype not in (torch.float64, torch.float32):

@@ -233,6 +233,29 @@ static vpp_status ensure_apply_scratch(vpp_problem p)
 }
 
 // y = A x on `s`; with `dot`, also x . y (written by the assembly kernel).
+// Diagonal of A_D for the current phi and mass shift, and its inverses.
+static vpp_status build_diagonal(vpp_problem p, hipStream_t s)
+{
+    VPP_HIP(launch_fill<double>(p->diag, p->N, 0.0, s));
+    VPP_HIP(launch_diag(p->k, p->m, p->phi64, p->diag, s));
+    VPP_HIP(launch_fix_diagonal(p->m, p->diag, p->inv64, p->inv32, s));
+    return VPP_OK;
+}
+
+static void put_config(vpp_problem p, int prec, const LaunchCfg& c);
+
+// Configurations a problem may run: those instantiated with the mass shift
+// when it has one, else every configuration of its degree.
+static bool config_ok(vpp_problem p, const LaunchCfg& c)
+{
+    return p->m.mass != 0.0 ? mass_config_supported(c, p->k) : apply_config_supported(c, p->k);
+}
+
+static int config_list(vpp_problem p, LaunchCfg* out, int cap)
+{
+    return p->m.mass != 0.0 ? list_mass_configs(p->k, out, cap) : list_apply_configs(p->k, out, cap);
+}
+
 static vpp_status do_apply64(vpp_problem p, const double* x, double* y, double* dot, const int* done, hipStream_t s)
 {
     ApplyArgs<double> a{p->m, x, y, p->phi64, p->part, shared_stride(p->m), dot ? p->dot_part : nullptr, dot,
@@ -722,10 +745,33 @@ vpp_status vpp_set_phi(vpp_problem p, const double* phi, void* stream)
     hipStream_t s = (hipStream_t)stream;
     VPP_HIP(hipMemcpyAsync(p->phi64, phi, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
     VPP_HIP(launch_convert(p->phi64, p->phi32, p->N, s));
-    VPP_HIP(launch_fill<double>(p->diag, p->N, 0.0, s));
-    VPP_HIP(launch_diag(p->k, p->m, p->phi64, p->diag, s));
-    VPP_HIP(launch_fix_diagonal(p->m, p->diag, p->inv64, p->inv32, s));
+    vpp_status st = build_diagonal(p, s);
+    if (st) return st;
     p->phi_set = true;
+    return VPP_OK;
+}
+
+vpp_status vpp_set_mass(vpp_problem p, double mu, void* stream)
+{
+    if (!p) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(VPP_ERR_INVALID_ARG, "the mass shift must be finite and >= 0");
+    LaunchCfg mc[16];
+    if (mu != 0.0 && list_mass_configs(p->k, mc, 16) < 1)
+        return fail(VPP_ERR_UNSUPPORTED, "the mass shift is available for degrees 2 and 3");
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    if (p->stream) VPP_HIP(hipStreamSynchronize(p->stream));
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) vol *= p->desc.extent[d] / p->desc.ncells[d];
+    p->m.mass = p->m32.mass = mu * vol;
+    if (mu != 0.0) {
+        if (!mass_config_supported(p->cfg, p->k)) put_config(p, VPP_FP64, mc[0]);
+        if (!mass_config_supported(p->cfg32, p->k)) put_config(p, VPP_FP32, mc[0]);
+    }
+    free_graphs(p->w);   // they hold the operator's arguments by value
+    vpp_status st = ensure_apply_scratch(p);
+    if (st) return st;
+    if (p->phi_set && (st = build_diagonal(p, (hipStream_t)stream))) return st;
     return VPP_OK;
 }
 
@@ -835,7 +881,9 @@ vpp_status vpp_set_config_for(vpp_problem p, int32_t precision, const vpp_kernel
     if (precision != VPP_FP64 && precision != VPP_FP32)
         return fail(VPP_ERR_INVALID_ARG, "precision must be VPP_FP64 or VPP_FP32");
     LaunchCfg c{cfg->variant, {cfg->tile[0], cfg->tile[1], cfg->tile[2]}};
-    if (!apply_config_supported(c, p->k)) return fail(VPP_ERR_UNSUPPORTED, "kernel configuration not available");
+    if (!config_ok(p, c))
+        return fail(VPP_ERR_UNSUPPORTED, p->m.mass != 0.0 ? "kernel configuration not available with the mass shift"
+                                                          : "kernel configuration not available");
     DeviceGuard dg(p->desc.device);
     if (p->stream) VPP_HIP(hipStreamSynchronize(p->stream));
     put_config(p, precision, c);
@@ -869,9 +917,12 @@ int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t ca
 // back to back.
 static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path, double* flush, int64_t nflush)
 {
-    const std::string key = size_bucket_key(prec == VPP_FP32 ? "apply32/hbm" : "apply/hbm", p->k, p->N);
+    const bool mass = p->m.mass != 0.0;
+    const std::string key = size_bucket_key(prec == VPP_FP32 ? (mass ? "apply32m/hbm" : "apply32/hbm")
+                                                             : (mass ? "applym/hbm" : "apply/hbm"),
+                                            p->k, p->N);
     LaunchCfg c;
-    if (cache_lookup(cache_path, key, &c) && apply_config_supported(c, p->k)) {
+    if (cache_lookup(cache_path, key, &c) && config_ok(p, c)) {
         put_config(p, prec, c);
         return ensure_apply_scratch(p);
     }
@@ -882,7 +933,7 @@ static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path
     if (prec == VPP_FP32) VPP_HIP(launch_fill<float>(w.p32, p->N, 1.0f, s));
     else VPP_HIP(launch_fill<double>(w.x, p->N, 1.0, s));
     LaunchCfg cands[64];
-    const int n = list_apply_configs(p->k, cands, 64);
+    const int n = std::min(config_list(p, cands, 64), 64);
     constexpr int reps = 6;
     hipEvent_t ev[2 * reps] = {};
     for (int r = 0; r < 2 * reps && !st; ++r)

@@ -28,21 +28,30 @@ namespace vpp {
     X(4, 1, 2, 2, 2)          \
     X(4, 1, 4, 4, 1)
 
-template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT>
+// Configurations also instantiated with the mass shift mu M of the level-set
+// filter operators (variant 4 only: the mass term sits in cell_operator).
+#define VPP_MASS_CONFIGS(X) \
+    X(2, 4, 16, 8, 4)       \
+    X(2, 4, 32, 4, 4)       \
+    X(2, 4, 8, 4, 4)        \
+    X(3, 4, 8, 4, 4)
+
+template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT, bool MASS>
 inline auto kernel_ptr()
 {
+    static_assert(!MASS || V == 4, "the mass shift is instantiated for variant 4 only");
     if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV, DOT>;
     else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV, DOT>;
     else if constexpr (V == 2) return &apply_half_kernel<K, T, TX, TY, TZ, HV, DOT>;
-    else return &apply_slot_kernel<K, T, TX, TY, TZ, HV, DOT>;
+    else return &apply_slot_kernel<K, T, TX, TY, TZ, HV, DOT, MASS>;
 }
 
-template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT>
+template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT, bool MASS>
 inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
 {
     const int nblocks = a.m.ntile[0] * a.m.ntile[1] * a.m.ntile[2];
     constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : (V == 2 ? 2 : 1) * TX * TY * TZ;
-    hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV, DOT>()), dim3(nblocks), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV, DOT, MASS>()), dim3(nblocks), dim3(threads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.tiles_only) return e;
     const int tile[3] = {TX, TY, TZ};
@@ -50,21 +59,29 @@ inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
     return launch_assemble<T>(b, s);
 }
 
-template <int K, typename T, int V, int TX, int TY, int TZ>
+template <int K, typename T, int V, int TX, int TY, int TZ, bool MASS = false>
 inline hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s)
 {
     // the x . (A x) partials are a separate instantiation, used inside CG only
     if (a.dot_part) {
-        if (a.m.heaviside == 0) return launch_hv<K, T, V, TX, TY, TZ, 0, true>(a, s);
-        return launch_hv<K, T, V, TX, TY, TZ, 1, true>(a, s);
+        if (a.m.heaviside == 0) return launch_hv<K, T, V, TX, TY, TZ, 0, true, MASS>(a, s);
+        return launch_hv<K, T, V, TX, TY, TZ, 1, true, MASS>(a, s);
     }
-    if (a.m.heaviside == 0) return launch_hv<K, T, V, TX, TY, TZ, 0, false>(a, s);
-    return launch_hv<K, T, V, TX, TY, TZ, 1, false>(a, s);
+    if (a.m.heaviside == 0) return launch_hv<K, T, V, TX, TY, TZ, 0, false, MASS>(a, s);
+    return launch_hv<K, T, V, TX, TY, TZ, 1, false, MASS>(a, s);
 }
 
 template <typename T>
 inline hipError_t launch_apply_t(const LaunchCfg& c, int k, const ApplyArgs<T>& a, hipStream_t s)
 {
+    if (a.m.mass != 0.0) {
+#define VPP_LAUNCH_MASS(K, V, TX, TY, TZ)                                                    \
+    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) \
+        return launch_one<K, T, V, TX, TY, TZ, true>(a, s);
+        VPP_MASS_CONFIGS(VPP_LAUNCH_MASS)
+#undef VPP_LAUNCH_MASS
+        return hipErrorInvalidValue;
+    }
 #define VPP_LAUNCH(K, V, TX, TY, TZ)                                                         \
     if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) \
         return launch_one<K, T, V, TX, TY, TZ>(a, s);

@@ -30,4 +30,26 @@ int list_apply_configs(int k, LaunchCfg* out, int cap)
     return n;
 }
 
+bool mass_config_supported(const LaunchCfg& c, int k)
+{
+#define VPP_MSUP(K, V, TX, TY, TZ) \
+    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) return true;
+    VPP_MASS_CONFIGS(VPP_MSUP)
+#undef VPP_MSUP
+    return false;
+}
+
+int list_mass_configs(int k, LaunchCfg* out, int cap)
+{
+    int n = 0;
+#define VPP_MLIST(K, V, TX, TY, TZ)                              \
+    if (k == K) {                                                \
+        if (n < cap && out) out[n] = LaunchCfg{V, {TX, TY, TZ}}; \
+        ++n;                                                     \
+    }
+    VPP_MASS_CONFIGS(VPP_MLIST)
+#undef VPP_MLIST
+    return n;
+}
+
 }  // namespace vpp

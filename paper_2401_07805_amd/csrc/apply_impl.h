@@ -137,8 +137,11 @@ __device__ __forceinline__ void cell_coefficient(const MeshArgs& m, const T* __r
 // replaced by A_e u.
 //   forward:  u_q = (S x S x S) u,  g_d = Dc along d of u_q   (collocation derivative)
 //   Gauss point: f_d = cw rd[d] g_d
-//   backward: v = sum_d Dc_d^T f_d,  A_e u = (S^T x S^T x S^T) v
-template <int K, typename T>
+//   backward: v = sum_d Dc_d^T f_d (+ mu hx hy hz wref_q u_q with MASS),
+//             A_e u = (S^T x S^T x S^T) v
+// The mass term is added where the last derivative pass still holds u_q, so it
+// keeps no value alive for longer.
+template <int K, typename T, bool MASS = false>
 __device__ __forceinline__ void cell_operator(const MeshArgs& m, const T (&cw)[(K + 1) * (K + 1) * (K + 1)],
                                               T (&u)[(K + 1) * (K + 1) * (K + 1)])
 {
@@ -192,6 +195,11 @@ __device__ __forceinline__ void cell_operator(const MeshArgs& m, const T (&cw)[(
 #pragma unroll
             for (int a = 0; a < N; ++a) o[a] = v[i0 + N * (i1 + N * a)];
             line_acc<K, MDC, true>(g, o);
+            if constexpr (MASS) {
+                const T ms = T(m.mass);
+#pragma unroll
+                for (int a = 0; a < N; ++a) o[a] = fma(ms * T(wref<K>(i0, i1, a)), in[a], o[a]);
+            }
 #pragma unroll
             for (int a = 0; a < N; ++a) v[i0 + N * (i1 + N * a)] = o[a];
         }
@@ -712,7 +720,7 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
 // in for a neighbour cell below the tile.
 
 
-template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT>
+template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT, bool MASS = false>
 __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a)
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ, CS = NT + 1;
@@ -738,7 +746,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
         sweep3<K, MS, false, 2>(cw);
         coef_weights3<K, HV>(m, cw);
         gather_cell_t<K>(a.x + tile0, lane_b, nx, nxy, cell_dirichlet_faces(m, cx, cy, cz), u);
-        cell_operator<K>(m, cw, u);
+        cell_operator<K, T, MASS>(m, cw, u);
 #pragma unroll
         for (int q = 0; q < N3; ++q)
             if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) slot[q * CS + tid] = u[q];

@@ -5,8 +5,9 @@
 namespace vpp {
 
 // ---------------------------------------------------------------------------
-// Diagonal: diag_a = sum_q cw_q sum_d rd[d] (dN_a/dxi_d (x_q))^2, from squared
-// 1D tables (each term is a product of three 1D factors).  Runs once per phi.
+// Diagonal: diag_a = sum_q cw_q sum_d rd[d] (dN_a/dxi_d (x_q))^2 (+ the mass
+// shift's mu hx hy hz sum_q wref_q N_a(x_q)^2), from squared 1D tables (each
+// term is a product of three 1D factors).  Runs once per phi.
 
 template <int K, int HV>
 __global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __restrict__ phi,
@@ -40,6 +41,16 @@ __global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __re
     sweep3<K, MS2, true, 0>(A);
 #pragma unroll
     for (int q = 0; q < N3; ++q) out[q] = fma(m.rd[2], A[q], out[q]);
+    if (m.mass != 0.0) {
+        // mass shift: mu hx hy hz sum_q wref_q N_a(x_q)^2
+#pragma unroll
+        for (int q = 0; q < N3; ++q) A[q] = m.mass * wref<K>(q % N, (q / N) % N, q / (N * N));
+        sweep3<K, MS2, true, 2>(A);
+        sweep3<K, MS2, true, 1>(A);
+        sweep3<K, MS2, true, 0>(A);
+#pragma unroll
+        for (int q = 0; q < N3; ++q) out[q] += A[q];
+    }
     const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
     const int64_t base = node_index(m, (int64_t)K * cx, (int64_t)K * cy, (int64_t)K * cz);
 #pragma unroll
@@ -264,7 +275,8 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             double u[N3];
             if (active) {
                 gather_cell_t<K>(x + tile0, lane_b, nx, nxy, faces, u);
-                cell_operator<K>(m, cw, u);
+                if (m.mass != 0.0) cell_operator<K, double, true>(m, cw, u);   // uniform per problem
+                else cell_operator<K>(m, cw, u);
             }
             __syncthreads();   // the previous write-out has finished reading the slots
             if (active) {

@@ -30,6 +30,7 @@ struct MeshArgs {
     double rd[3];
     double dcdphi;    // r0-free (1/rho_l - 1/rho_g), used by the adjoint
     double r0;
+    double mass;      // mass shift mu scaled as the Gauss-point factors: mu hx hy hz (0: no mass term)
 };
 
 __host__ __device__ inline int64_t node_index(const MeshArgs& m, int64_t i, int64_t j, int64_t l)

@@ -55,6 +55,9 @@ hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& 
 hipError_t launch_apply_f32(const LaunchCfg& c, int k, const ApplyArgs<float>& a, hipStream_t s);
 bool apply_config_supported(const LaunchCfg& c, int k);
 int list_apply_configs(int k, LaunchCfg* out, int cap);
+// Configurations instantiated with the mass shift (a problem with mu != 0 runs these only).
+bool mass_config_supported(const LaunchCfg& c, int k);
+int list_mass_configs(int k, LaunchCfg* out, int cap);
 
 // Assembly of shared-face nodes from the tile partials (and of x . y).
 template <typename T>

@@ -1,0 +1,136 @@
+"""GPU parity of the mass-shifted operator mu M + K_c (the level-set filter
+systems of Eqs. normal_vector_regularized and curvature_regularized in weak
+form) against the FP64 oracle: apply and diagonal within 1e-12, FP32 apply
+within the FP32 bound of the pressure operator, and the filtered interface
+normal (three right-hand sides, pure Neumann, constant eta h^2) solved by
+Jacobi PCG, single and batched, against the oracle's direct solutions."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import dev, host, rel, rel_max, say
+
+pytestmark = pytest.mark.gpu
+
+vpp = pytest.importorskip("paper_2401_07805_amd")
+
+NEU = (1,) * 6
+
+
+def _mass_configs(prob, k):
+    """Every configuration the problem accepts with the mass shift set."""
+    ok = []
+    for cfg in vpp.config_candidates(k):
+        try:
+            prob.set_config(cfg["variant"], cfg["tile"])
+        except vpp.VppError as e:
+            assert e.status == 2     # VPP_ERR_UNSUPPORTED
+            continue
+        ok.append(cfg)
+    return ok
+
+
+CASES = [
+    # (ncells, k, bc, heaviside, extent, mu)
+    ((5, 4, 3), 2, NEU, W.H_LINEAR, (1.0, 1.0, 1.0), 1.0),
+    ((17, 9, 6), 2, (0, 1, 1, 0, 0, 1), W.H_PAPER, (1.0, 0.6, 0.9), 2.5),
+    ((33, 5, 9), 2, NEU, W.H_LINEAR, (1.1, 0.5, 0.8), 1.0),
+    ((1, 1, 1), 2, NEU, W.H_LINEAR, (1.0, 1.0, 1.0), 0.3),
+    ((9, 5, 6), 3, NEU, W.H_LINEAR, (1.0, 1.0, 1.0), 1.0),
+    ((3, 4, 2), 3, (1, 0, 1, 1, 0, 1), W.H_PAPER, (0.5, 1.0, 0.7), 4.0),
+]
+
+
+@pytest.mark.parametrize("ncells,k,bc,hv,ext,mu", CASES)
+def test_mass_apply_and_diagonal(ncells, k, bc, hv, ext, mu):
+    m = W.Mesh(ncells=ncells, degree=k, bc=bc, heaviside=hv, extent=ext, rho_l=1000.0, rho_g=1.0, mass=mu)
+    m.eps = 0.1
+    phi = W.droplet_phi(m, 0.3, m.eps, centre=(0.45, 0.5, 0.55))
+    x = W.uniform_vectors(12, 1, m.ndofs)[0]
+    op = oracle.Operator(m, phi=phi)
+    yref = op.matvec(x)
+    prob = vpp.Problem.from_mesh(m)
+    prob.set_phi(dev(phi))
+    prob.set_mass(mu)
+    cfgs = _mass_configs(prob, k)
+    assert cfgs and all(c["variant"] == 4 for c in cfgs)
+    for cfg in cfgs:
+        say("mass apply", ncells, k, bc, mu, cfg)
+        prob.set_config(cfg["variant"], cfg["tile"])
+        y = host(prob.apply(dev(x)))
+        assert rel(y, yref) < 1e-12, (cfg, rel(y, yref))
+        assert rel_max(y, yref) < 1e-12, (cfg, rel_max(y, yref))
+    d = host(prob.diagonal())
+    assert rel(d, op.diagonal()) < 1e-12
+    y32 = host(prob.apply(dev(x, torch.float32)))
+    assert rel(y32, yref) < 2e-6
+
+
+def test_mass_zero_restores_pressure_operator_and_errors():
+    wl = W.small_droplet(n=6, k=2, seed=2)
+    prob = vpp.Problem.from_mesh(wl.mesh)
+    prob.set_phi(dev(wl.phi))
+    x = dev(wl.vectors[0])
+    y0 = host(prob.apply(x))
+    prob.set_mass(1.5)
+    y1 = host(prob.apply(x))
+    assert rel(y1, y0) > 1e-5          # the shift is applied (7e-4 here)
+    prob.set_mass(0.0)
+    assert rel(host(prob.apply(x)), y0) < 1e-15
+    with pytest.raises(vpp.VppError) as e:
+        prob.set_mass(-1.0)
+    assert e.value.status == 1
+    with pytest.raises(vpp.VppError) as e:
+        prob.set_mass(float("nan"))
+    assert e.value.status == 1
+    m4 = W.unit_cube(2, 4, 1.0, 1.0)
+    p4 = vpp.Problem.from_mesh(m4)
+    with pytest.raises(vpp.VppError) as e:
+        p4.set_mass(1.0)
+    assert e.value.status == 2
+    # with the shift set, configurations without it are refused
+    prob.set_mass(1.0)
+    with pytest.raises(vpp.VppError) as e:
+        prob.set_config(0, (16, 4, 4))
+    assert e.value.status == 2
+
+
+def _normal_rhs(m, centre):
+    """(n_bar, v) for the three components of the droplet's interface normal
+    n_bar = grad phi / |grad phi| = (c0 - x) / |x - c0| (analytic, at the Gauss points)."""
+    x, y, z, _ = oracle.qp_coords(m)
+    dx, dy, dz = x - centre[0], y - centre[1], z - centre[2]
+    r = np.maximum(np.sqrt(dx * dx + dy * dy + dz * dz), 1e-12)
+    return [oracle.rhs_qp(m, -dx / r), oracle.rhs_qp(m, -dy / r), oracle.rhs_qp(m, -dz / r)]
+
+
+@pytest.mark.parametrize("k,n", [(2, 10), (3, 6)])
+def test_filtered_normal_solve(k, n):
+    """n - eta h^2 Lap n = n_bar with eta = 2 (the paper's default), pure Neumann:
+    single solves and one batch with the three components as right-hand sides."""
+    h = 1.0 / n
+    filt = 2.0 * h * h
+    m = W.Mesh(ncells=(n, n, n), degree=k, bc=NEU, rho_l=1.0 / filt, rho_g=1.0 / filt, mass=1.0)
+    op = oracle.Operator(m, phi=np.zeros(m.ndofs))
+    A = op.to_scipy().tocsc()
+    bs = _normal_rhs(m, (0.5, 0.5, 0.5))
+    refs = [spla.spsolve(A, b) for b in bs]
+    prob = vpp.Problem.from_mesh(m)
+    prob.set_phi(dev(np.zeros(m.ndofs)))
+    prob.set_mass(1.0)
+    say("filter solve", k, n)
+    for b, ref in zip(bs, refs):
+        x, info = prob.cg_solve(dev(b), rtol=1e-12, atol=1e-20)
+        res = np.linalg.norm(b - op.matvec(host(x))) / np.linalg.norm(b)
+        assert info["status"] == 0 and res < 1e-12 * 1.01
+        assert rel(host(x), ref) < 1e-9
+    if k == 2:
+        bt = vpp.Batch([prob], [3])
+        xs = [torch.zeros(m.ndofs, dtype=torch.float64, device="cuda") for _ in bs]
+        infos = bt.cg_solve([dev(b) for b in bs], xs, rtol=1e-12, atol=1e-20)
+        for x, ref, inf in zip(xs, refs, infos):
+            assert inf["status"] == 0
+            assert rel(host(x), ref) < 1e-9
