@@ -157,6 +157,7 @@ def extras(torch, vpp, W, dev, cache):
                 out[f"q3_cg_{prec}_s"] = time.perf_counter() - t0
                 out[f"q3_cg_{prec}_iters"] = info["iterations"]
     out.update(batch_figures(torch, vpp, W, dev, cache))
+    out.update(filter_figures(torch, vpp, W, dev, cache))
     out.update(c2_figures(torch, vpp, W, dev, cache))
     wl = W.droplet_at_scale(k=2, nvec=0, bubble=True)
     p = vpp.Problem.from_mesh(wl.mesh)
@@ -172,6 +173,45 @@ def extras(torch, vpp, W, dev, cache):
         out[f"bubble_q2_cg_{prec}_s"] = time.perf_counter() - t0
         out[f"bubble_q2_cg_{prec}_iters"] = info["iterations"]
     return out
+
+
+def filter_figures(torch, vpp, W, dev, cache):
+    """Level-set filter system at 64^3 Q2: (M + eta h^2 K) n = b with eta = 2 and
+    pure Neumann faces (Eq. normal_vector_regularized in weak form); hot FP64
+    apply of the mass-shifted operator, and Jacobi PCG to the tolerances of
+    Table tab:solver_settings (rtol 1e-12, atol 1e-20) for the three components
+    of a droplet's interface normal, each with b = A n (so n is the exact
+    discrete solution)."""
+    n = 64
+    filt = 2.0 / (n * n)
+    m = W.Mesh(ncells=(n, n, n), degree=2, bc=(1,) * 6, rho_l=1.0 / filt, rho_g=1.0 / filt, mass=1.0)
+    p = vpp.Problem.from_mesh(m)
+    p.set_phi(torch.zeros(m.ndofs, dtype=torch.float64, device=dev))
+    p.set_mass(1.0)
+    p.tune(cache)
+    comps = [torch.from_numpy(c).to(dev) for c in W.normal_field(m)]
+    yy = torch.empty_like(comps[0])
+    for _ in range(3):
+        p.apply(comps[0], out=yy)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        p.apply(comps[0], out=yy)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / 50
+    bs = [p.apply(c) for c in comps]
+    p.cg_solve(bs[0], rtol=1e-12, atol=1e-20, max_iter=2, raise_on_failure=False)   # graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sols = [p.cg_solve(b, rtol=1e-12, atol=1e-20) for b in bs]
+    t = time.perf_counter() - t0
+    err = max(float(torch.linalg.norm(x - c) / torch.linalg.norm(c)) for (x, _), c in zip(sols, comps))
+    return {"filter_q2_config": p.config, "filter_q2_f64_hot_apply_us": us,
+            "filter_q2_f64_hot_mdofs": m.ndofs / us, "filter_normal_cg_s": t,
+            "filter_normal_cg_iters": [i["iterations"] for _, i in sols], "filter_normal_cg_max_rel_err": err}
 
 
 def c2_figures(torch, vpp, W, dev, cache):

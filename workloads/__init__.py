@@ -145,6 +145,16 @@ def sine_field(mesh: Mesh) -> np.ndarray:
     return (np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)).ravel()
 
 
+def normal_field(mesh: Mesh, centre=(0.5, 0.5, 0.5)) -> List[np.ndarray]:
+    """The three components of the unit vector (c0 - x)/|x - c0| at the nodes
+    (the interface normal of a droplet field centred at c0; 0 at the centre)."""
+    X, Y, Z = mesh.node_grid()
+    D = [X - centre[0], Y - centre[1], Z - centre[2]]
+    r = np.sqrt(D[0] ** 2 + D[1] ** 2 + D[2] ** 2)
+    inv = np.where(r > 0, 1.0 / np.where(r > 0, r, 1.0), 0.0)
+    return [(-d * inv).ravel() for d in D]
+
+
 def uniform_vectors(seed: int, count: int, n: int) -> np.ndarray:
     """`count` vectors with entries uniform in [-1,1] (rows of the returned array)."""
     rng = np.random.default_rng(seed)
