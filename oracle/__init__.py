@@ -330,3 +330,6 @@ def discrete_manufactured_rhs(op, mesh, p_nodal) -> np.ndarray:
     p = np.array(p_nodal, dtype=np.float64)
     p[mesh.boundary_mask()] = 0.0
     return op.matvec(p)
+
+
+from .closest_point import band_nodes, closest_points, node_coords  # noqa: E402  (closest-point projection)
