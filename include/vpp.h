@@ -96,6 +96,15 @@ typedef struct {
     double true_rel_residual;  /* ||b - A x|| / ||b - A x0|| recomputed in FP64 at the end */
 } vpp_cg_info;
 
+/* Options of the closest-point projection (vpp_closest_points). */
+typedef struct {
+    double eps;                /* interface thickness of Eq. distance, > 0 */
+    double phi_lim;            /* narrow band |phi| < phi_lim of the node mode, in (0, 1] */
+    double tol;                /* stop once |y^(k+1) - y^(k)| < tol, > 0 */
+    int32_t max_iter;          /* outer steps, 1..10000 */
+    int32_t normal_steps;      /* normal corrections per outer step, 0..100 */
+} vpp_cp_opts;
+
 /* Kernel configuration: cells of one workgroup tile (tx, ty, tz). */
 typedef struct {
     int32_t tile[3];
@@ -158,6 +167,25 @@ vpp_status vpp_cg_solve(vpp_problem p, const double* b, double* x, const vpp_cg_
 vpp_status vpp_grad_coef(vpp_problem p, const double* pv, const double* lam, double* g_q,
                          void* stream);
 vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* stream);
+
+/* Closest points on the zero isosurface {phi_h = 0} of the FE level set
+ * (appendix "Extension of solution quantities from a level-set isosurface
+ * using closest point projection", Eq. cpp), one GPU thread per point.  From
+ * y = x each outer step takes opts->normal_steps corrections
+ * y <- y - d(y) n(y) (d of Eq. distance from phi_h(y), n = grad phi_h/|grad phi_h|)
+ * and one tangential correction y <- y - sum_j ((y - x).t_j) t_j (unit
+ * tangents t_0 from v = e_x, or e_y when |n_x| > 0.9, and t_1 = n x t_0), until
+ * |y^(k+1) - y^(k)| < tol; y is clipped to the domain box after every
+ * correction.  pts: n points, xyz interleaved (device, FP64); or NULL for the
+ * narrow band of the mesh's support points: then n is ignored, the outputs
+ * have vpp_num_dofs entries and node g is projected iff |phi_g| < phi_lim.
+ * y: 3 entries per point (xyz); info: outer steps to convergence, 0 when
+ * max_iter steps did not converge (y is the last iterate; the C0 normal field
+ * jumps across cell faces, so points projecting onto a face can cycle), -1
+ * for a node outside the band (y = x).  Needs vpp_set_phi.  Asynchronous on
+ * `stream`. */
+vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* opts,
+                              double* y, int32_t* info, void* stream);
 
 /* Kernel configuration of a problem (what the autotuner chooses), held per
  * precision: the FP64 and the FP32 apply may use different kernels and tiles.

@@ -35,6 +35,11 @@ class KernelConfig(C.Structure):
     _fields_ = [("tile", C.c_int32 * 3), ("variant", C.c_int32)]
 
 
+class CpOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("phi_lim", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("normal_steps", C.c_int32)]
+
+
 _lib = None
 vp = C.c_void_p
 PP = C.POINTER(C.c_void_p)
@@ -55,6 +60,7 @@ def load() -> C.CDLL:
         "vpp_num_qpoints": (C.c_int64, [vp]),
         "vpp_set_phi": (C.c_int, [vp, vp, vp]),
         "vpp_set_mass": (C.c_int, [vp, C.c_double, vp]),
+        "vpp_closest_points": (C.c_int, [vp, vp, C.c_int64, C.POINTER(CpOpts), vp, vp, vp]),
         "vpp_apply": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "vpp_diagonal": (C.c_int, [vp, vp, vp]),
         "vpp_cg_solve": (C.c_int, [vp, vp, vp, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),

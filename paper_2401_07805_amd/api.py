@@ -103,6 +103,29 @@ class Problem:
                                     _stream(self.device)))
         self._phi_version += 1
 
+    def closest_points(self, eps: float, pts: Optional[torch.Tensor] = None, phi_lim: float = 0.9,
+                       tol: float = 1e-11, max_iter: int = 50, normal_steps: int = 3):
+        """Closest points on {phi_h = 0} (vpp_closest_points).  pts: (P, 3) float64
+        on the device, or None for the narrow band |phi| < phi_lim of the mesh
+        nodes.  Returns (y (P, 3), info (P,) int32: outer steps to convergence,
+        0 not converged, -1 outside the band)."""
+        o = L.CpOpts(float(eps), float(phi_lim), float(tol), int(max_iter), int(normal_steps))
+        if pts is None:
+            n, ptr = self.n, None
+        else:
+            if pts.dtype != torch.float64 or pts.device != self.device or pts.dim() != 2 or pts.shape[1] != 3:
+                raise ValueError("pts must be a (P, 3) float64 tensor on the problem's device")
+            pts = pts.contiguous()
+            n, ptr = pts.shape[0], C.c_void_p(pts.data_ptr())
+            if n == 0:
+                return (torch.empty((0, 3), dtype=torch.float64, device=self.device),
+                        torch.empty(0, dtype=torch.int32, device=self.device))
+        y = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        info = torch.empty(n, dtype=torch.int32, device=self.device)
+        _check(L.load().vpp_closest_points(self._h, ptr, n, C.byref(o), C.c_void_p(y.data_ptr()),
+                                           C.c_void_p(info.data_ptr()), _stream(self.device)))
+        return y, info
+
     def set_mass(self, mu: float):
         """Operator mu M + K_c (vpp_set_mass); mu = 0 is the pressure operator."""
         _check(L.load().vpp_set_mass(self._h, float(mu), _stream(self.device)))

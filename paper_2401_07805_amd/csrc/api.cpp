@@ -853,6 +853,38 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
     return VPP_OK;
 }
 
+vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* o, double* y,
+                              int32_t* info, void* stream)
+{
+    if (!p || !o || !y || !info) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (pts && n < 0) return fail(VPP_ERR_INVALID_ARG, "n must be >= 0");
+    if (!(o->eps > 0.0) || !std::isfinite(o->eps) || !(o->tol > 0.0) || !std::isfinite(o->tol) ||
+        !(o->phi_lim > 0.0 && o->phi_lim <= 1.0) || o->max_iter < 1 || o->max_iter > 10000 ||
+        o->normal_steps < 0 || o->normal_steps > 100)
+        return fail(VPP_ERR_INVALID_ARG, "closest-point options out of range");
+    if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    DeviceGuard dg(p->desc.device);
+    CpArgs a{};
+    a.m = p->m;
+    for (int d = 0; d < 3; ++d) {
+        a.lo[d] = p->desc.origin[d];
+        a.hi[d] = p->desc.origin[d] + p->desc.extent[d];
+        a.h[d] = p->desc.extent[d] / p->desc.ncells[d];
+    }
+    a.phi = p->phi64;
+    a.pts = pts;
+    a.n = pts ? n : p->N;
+    a.phi_lim = o->phi_lim;
+    a.eps = o->eps;
+    a.tol = o->tol;
+    a.max_iter = o->max_iter;
+    a.normal_steps = o->normal_steps;
+    a.y = y;
+    a.info = info;
+    VPP_HIP(launch_closest_points(p->k, a, (hipStream_t)stream));
+    return VPP_OK;
+}
+
 static void put_config(vpp_problem p, int prec, const LaunchCfg& c)
 {
     if (prec == VPP_FP32) {

@@ -91,6 +91,21 @@ hipError_t launch_grad_coef(int k, const MeshArgs& m, const double* p, const dou
 hipError_t launch_grad_phi(int k, const MeshArgs& m, const double* phi, const double* g, double* out,
                            hipStream_t s);
 
+// Closest-point projection onto {phi_h = 0} (one thread per point).
+struct CpArgs {
+    MeshArgs m;
+    double lo[3], hi[3], h[3];   // domain box and cell size
+    const double* phi;           // nodal phi (N)
+    const double* pts;           // n points, xyz interleaved; null: the N mesh nodes
+    int64_t n;
+    double phi_lim;              // band of the node mode: |phi_g| < phi_lim
+    double eps, tol;
+    int max_iter, normal_steps;
+    double* y;                   // 3 n
+    int* info;                   // n: outer steps to convergence, 0 not converged, -1 outside the band
+};
+hipError_t launch_closest_points(int k, const CpArgs& a, hipStream_t s);
+
 // Batched persistent apply (FP64).
 struct BatchProblem {
     MeshArgs m;

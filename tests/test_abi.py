@@ -48,6 +48,7 @@ int main(void){
   printf("%zu %zu %zu\n", sizeof(vpp_cg_opts), offsetof(vpp_cg_opts, inner_rtol), offsetof(vpp_cg_opts, check_every));
   printf("%zu %zu\n", sizeof(vpp_cg_info), offsetof(vpp_cg_info, rel_residual));
   printf("%zu %zu\n", sizeof(vpp_kernel_config), offsetof(vpp_kernel_config, variant));
+  printf("%zu %zu %zu\n", sizeof(vpp_cp_opts), offsetof(vpp_cp_opts, max_iter), offsetof(vpp_cp_opts, normal_steps));
   return 0;}
 ''')
     exe = tmp_path / "l"
@@ -59,6 +60,8 @@ int main(void){
     assert out[1].split() == [str(v) for v in (ctypes.sizeof(O), O.inner_rtol.offset, O.check_every.offset)]
     assert out[2].split() == [str(v) for v in (ctypes.sizeof(I), I.rel_residual.offset)]
     assert out[3].split() == [str(v) for v in (ctypes.sizeof(K), K.variant.offset)]
+    P = _lib.CpOpts
+    assert out[4].split() == [str(v) for v in (ctypes.sizeof(P), P.max_iter.offset, P.normal_steps.offset)]
 
 
 def test_candidates_listed_without_gpu():

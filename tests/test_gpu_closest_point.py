@@ -1,0 +1,93 @@
+"""GPU closest-point projection (vpp_closest_points) against the oracle's
+(oracle/closest_point.py, the appendix's normal and tangential corrections).
+
+Bar: the band selection is identical (integer); points that converge on both
+sides agree within 1e-9 (both stop once a step is below tol = 1e-11, and the
+iteration contracts); their step counts differ by at most one (the stopping
+test on a difference of rounded iterates).  Points that do not converge on
+one side (their closest point lies on a cell face, where the C0 normal jumps,
+and the iterates cycle) are checked for validity instead: still within the
+cycle's amplitude of the oracle's iterate and close to the interface."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.closest_point import evaluate
+import workloads as W
+from gpu_util import dev, say
+
+pytestmark = pytest.mark.gpu
+
+vpp = pytest.importorskip("paper_2401_07805_amd")
+
+
+def _problem(m, phi):
+    p = vpp.Problem.from_mesh(m)
+    p.set_phi(dev(phi))
+    return p
+
+
+@pytest.mark.parametrize("n,k", [(12, 2), (7, 3), (5, 4)])
+def test_band_of_a_sphere_matches_oracle(n, k):
+    eps = 0.05
+    m = W.unit_cube(n, k, 1000.0, 1.0, bc=(1,) * 6)
+    phi = W.droplet_phi(m, 0.3, eps, centre=(0.48, 0.51, 0.5))
+    prob = _problem(m, phi)
+    say("closest points band", n, k)
+    y, info = prob.closest_points(eps, phi_lim=0.6, tol=1e-11, max_iter=50)
+    y, info = y.cpu().numpy(), info.cpu().numpy()
+    idx = oracle.band_nodes(m, phi, 0.6)
+    out = np.setdiff1d(np.arange(m.ndofs), idx)
+    assert (info[out] == -1).all() and (info[idx] >= 0).all()
+    # outside the band y is the support point itself (GLL coordinates to rounding)
+    np.testing.assert_allclose(y[out], oracle.node_coords(m, out), rtol=0, atol=1e-15)
+    x = oracle.node_coords(m, idx)
+    yo, so, do = oracle.closest_points(m, phi, x, eps, max_iter=50, tol=1e-11)
+    yg, ig = y[idx], info[idx]
+    both = do & (ig > 0)
+    print(n, k, len(idx), "converged oracle", do.mean(), "gpu", (ig > 0).mean(), "both", both.mean())
+    assert both.mean() > 0.75
+    d = np.linalg.norm(yg[both] - yo[both], axis=1)
+    assert d.max() < 1e-9, d.max()
+    assert np.abs(ig[both] - so[both]).max() <= 1
+    rest = ~both
+    if rest.any():
+        dr = np.linalg.norm(yg[rest] - yo[rest], axis=1)
+        val, _ = evaluate(m, phi, yg[rest])
+        print("not converged on one side:", rest.sum(), "max distance", dr.max(), "max |phi_h|", np.abs(val).max())
+        assert dr.max() < 5e-3
+        assert np.abs(val).max() < 0.05
+
+
+def test_points_mode_and_plane_interface():
+    eps = 0.1
+    m = W.unit_cube(8, 2, 1000.0, 1.0, bc=(1,) * 6)
+    phi = W.slab_phi(m, 0.5, eps)              # interface on the node plane x = 1/2
+    prob = _problem(m, phi)
+    rng = np.random.default_rng(9)
+    pts = rng.uniform([0.3, 0.0, 0.0], [0.7, 1.0, 1.0], size=(500, 3))
+    say("closest points plane")
+    y, info = prob.closest_points(eps, pts=dev(pts), tol=1e-13)
+    y, info = y.cpu().numpy(), info.cpu().numpy()
+    assert (info > 0).all() and info.max() <= 6
+    ref = pts.copy()
+    ref[:, 0] = 0.5
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12)
+    # an empty point set is a no-op
+    y0, i0 = prob.closest_points(eps, pts=torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
+    assert y0.shape == (0, 3) and i0.shape == (0,)
+
+
+def test_closest_points_argument_errors():
+    m = W.unit_cube(4, 2, 1000.0, 1.0)
+    prob = vpp.Problem.from_mesh(m)
+    with pytest.raises(vpp.VppError) as e:
+        prob.closest_points(0.1)                # phi not set
+    assert e.value.status == 7
+    prob.set_phi(dev(W.droplet_phi(m, 0.3, 0.1)))
+    for kw in ({"eps": 0.0}, {"eps": 0.1, "tol": 0.0}, {"eps": 0.1, "phi_lim": 1.5},
+               {"eps": 0.1, "max_iter": 0}, {"eps": 0.1, "normal_steps": -1}):
+        with pytest.raises(vpp.VppError) as e:
+            prob.closest_points(**kw)
+        assert e.value.status == 1
