@@ -158,6 +158,7 @@ def extras(torch, vpp, W, dev, cache):
                 out[f"q3_cg_{prec}_iters"] = info["iterations"]
     out.update(batch_figures(torch, vpp, W, dev, cache))
     out.update(filter_figures(torch, vpp, W, dev, cache))
+    out.update(closest_point_figures(torch, vpp, W, dev))
     out.update(c2_figures(torch, vpp, W, dev, cache))
     wl = W.droplet_at_scale(k=2, nvec=0, bubble=True)
     p = vpp.Problem.from_mesh(wl.mesh)
@@ -212,6 +213,32 @@ def filter_figures(torch, vpp, W, dev, cache):
     return {"filter_q2_config": p.config, "filter_q2_f64_hot_apply_us": us,
             "filter_q2_f64_hot_mdofs": m.ndofs / us, "filter_normal_cg_s": t,
             "filter_normal_cg_iters": [i["iterations"] for _, i in sols], "filter_normal_cg_max_rel_err": err}
+
+
+def closest_point_figures(torch, vpp, W, dev):
+    """Closest-point projection of the narrow band |phi| < 0.9 of the 64^3 Q2
+    droplet (r 0.25, eps = 2h) onto {phi_h = 0}: 3 normal corrections per outer
+    step, tol 1e-11, at most 50 outer steps; one launch over all support points."""
+    wl = W.droplet_at_scale(k=2, nvec=0)
+    p = vpp.Problem.from_mesh(wl.mesh)
+    p.set_phi(torch.from_numpy(wl.phi).to(dev))
+    eps = wl.mesh.eps
+    y, info = p.closest_points(eps)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 5
+    for _ in range(reps):
+        y, info = p.closest_points(eps)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    band = info >= 0
+    nb = int(band.sum())
+    return {"cp_band_points": nb, "cp_us": us, "cp_mpoints_per_s": nb / us,
+            "cp_converged_fraction": float((info > 0).sum()) / max(nb, 1),
+            "cp_mean_outer_steps": float(info[info > 0].double().mean())}
 
 
 def c2_figures(torch, vpp, W, dev, cache):
