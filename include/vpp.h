@@ -187,6 +187,15 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
 vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* opts,
                               double* y, int32_t* info, void* stream);
 
+/* Extension of a nodal Q_k field f of the mesh from the interface over the
+ * narrow band (same appendix: values at the closest points extended to the
+ * band): out[g] = f_h(y_g), the FE interpolant at node g's closest point, for
+ * every node with info[g] >= 0, and out[g] = f[g] for info[g] = -1.  y, info:
+ * the node-mode output of vpp_closest_points (3 N and N entries); f, out: N
+ * entries, FP64 device pointers, not aliased.  Asynchronous on `stream`. */
+vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const double* f, double* out,
+                      void* stream);
+
 /* Kernel configuration of a problem (what the autotuner chooses), held per
  * precision: the FP64 and the FP32 apply may use different kernels and tiles.
  * Setting an unsupported one returns VPP_ERR_UNSUPPORTED.  vpp_get_config /

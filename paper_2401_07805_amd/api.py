@@ -126,6 +126,17 @@ class Problem:
                                            C.c_void_p(info.data_ptr()), _stream(self.device)))
         return y, info
 
+    def extend(self, y: torch.Tensor, info: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
+        """f extended from the closest points (vpp_extend): f_h(y_g) on the band, f elsewhere."""
+        if y.shape != (self.n, 3) or info.shape != (self.n,) or info.dtype != torch.int32:
+            raise ValueError("y, info must be the node-mode output of closest_points")
+        out = torch.empty_like(f)
+        _check(L.load().vpp_extend(self._h, C.c_void_p(y.contiguous().data_ptr()),
+                                   C.c_void_p(info.contiguous().data_ptr()),
+                                   _vec(f, self.n, torch.float64, self.device, "f"),
+                                   _vec(out, self.n, torch.float64, self.device, "out"), _stream(self.device)))
+        return out
+
     def set_mass(self, mu: float):
         """Operator mu M + K_c (vpp_set_mass); mu = 0 is the pressure operator."""
         _check(L.load().vpp_set_mass(self._h, float(mu), _stream(self.device)))

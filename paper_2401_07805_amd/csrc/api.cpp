@@ -885,6 +885,26 @@ vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const
     return VPP_OK;
 }
 
+vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const double* f, double* out,
+                      void* stream)
+{
+    if (!p || !y || !info || !f || !out) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (f == out) return fail(VPP_ERR_INVALID_ARG, "f and out must not alias");
+    DeviceGuard dg(p->desc.device);
+    CpArgs a{};
+    a.m = p->m;
+    for (int d = 0; d < 3; ++d) {
+        a.lo[d] = p->desc.origin[d];
+        a.hi[d] = p->desc.origin[d] + p->desc.extent[d];
+        a.h[d] = p->desc.extent[d] / p->desc.ncells[d];
+    }
+    a.n = p->N;
+    a.y = const_cast<double*>(y);
+    a.info = const_cast<int32_t*>(info);
+    VPP_HIP(launch_extend(p->k, a, f, out, (hipStream_t)stream));
+    return VPP_OK;
+}
+
 static void put_config(vpp_problem p, int prec, const LaunchCfg& c)
 {
     if (prec == VPP_FP32) {

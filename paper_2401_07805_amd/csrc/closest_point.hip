@@ -45,8 +45,10 @@ __device__ __forceinline__ void lagrange_at(double t, double (&V)[K + 1], double
     }
 }
 
+// Value and gradient at y of the nodal field f (phi or any Q_k field of the mesh).
 template <int K>
-__device__ __forceinline__ void eval_phi(const CpArgs& a, const double (&y)[3], double& val, double (&g)[3])
+__device__ __forceinline__ void eval_field(const CpArgs& a, const double* __restrict__ f, const double (&y)[3],
+                                           double& val, double (&g)[3])
 {
     constexpr int N = K + 1;
     double V[3][N], D[3][N];
@@ -64,7 +66,7 @@ __device__ __forceinline__ void eval_phi(const CpArgs& a, const double (&y)[3], 
         for (int i = 0; i < N; ++i) D[d][i] /= a.h[d];
     }
     const int64_t nx = a.m.nn[0], nxy = (int64_t)a.m.nn[0] * a.m.nn[1];
-    const double* p = a.phi + node_index(a.m, (int64_t)K * c[0], (int64_t)K * c[1], (int64_t)K * c[2]);
+    const double* p = f + node_index(a.m, (int64_t)K * c[0], (int64_t)K * c[1], (int64_t)K * c[2]);
     val = 0.0;
     g[0] = g[1] = g[2] = 0.0;
 #pragma unroll
@@ -73,11 +75,11 @@ __device__ __forceinline__ void eval_phi(const CpArgs& a, const double (&y)[3], 
         for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
             for (int a0 = 0; a0 < N; ++a0) {
-                const double f = p[a0 + nx * a1 + nxy * a2];
-                val += V[0][a0] * V[1][a1] * V[2][a2] * f;
-                g[0] += D[0][a0] * V[1][a1] * V[2][a2] * f;
-                g[1] += V[0][a0] * D[1][a1] * V[2][a2] * f;
-                g[2] += V[0][a0] * V[1][a1] * D[2][a2] * f;
+                const double fv = p[a0 + nx * a1 + nxy * a2];
+                val += V[0][a0] * V[1][a1] * V[2][a2] * fv;
+                g[0] += D[0][a0] * V[1][a1] * V[2][a2] * fv;
+                g[1] += V[0][a0] * D[1][a1] * V[2][a2] * fv;
+                g[2] += V[0][a0] * V[1][a1] * D[2][a2] * fv;
             }
 }
 
@@ -123,7 +125,7 @@ __global__ void __launch_bounds__(256) closest_point_kernel(CpArgs a)
         const double prev[3] = {y[0], y[1], y[2]};
         double val, g[3];
         for (int s = 0; s < a.normal_steps; ++s) {
-            eval_phi<K>(a, y, val, g);
+            eval_field<K>(a, a.phi, y, val, g);
             const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
             if (gn > 0.0) {
                 const double pc = fmin(fmax(val, -kPhiClip), kPhiClip);
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(256) closest_point_kernel(CpArgs a)
                 clip_box(a, y);
             }
         }
-        eval_phi<K>(a, y, val, g);
+        eval_field<K>(a, a.phi, y, val, g);
         const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
         if (gn > 0.0) {
             const double n[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
@@ -164,7 +166,39 @@ __global__ void __launch_bounds__(256) closest_point_kernel(CpArgs a)
     a.info[i] = info;
 }
 
+// Extension from the closest points: out[g] = f_h(y_g) for a node in the band
+// (info[g] >= 0), f[g] elsewhere.
+template <int K>
+__global__ void __launch_bounds__(256) extend_kernel(CpArgs a, const double* __restrict__ f,
+                                                     double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.info[i] < 0) {
+        out[i] = f[i];
+        return;
+    }
+    const double y[3] = {a.y[3 * i], a.y[3 * i + 1], a.y[3 * i + 2]};
+    double val, g[3];
+    eval_field<K>(a, f, y, val, g);
+    out[i] = val;
+}
+
 }  // namespace
+
+hipError_t launch_extend(int k, const CpArgs& a, const double* f, double* out, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const int64_t blocks = (a.n + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    switch (k) {
+    case 2: hipLaunchKernelGGL(extend_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, a, f, out); break;
+    case 3: hipLaunchKernelGGL(extend_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, a, f, out); break;
+    case 4: hipLaunchKernelGGL(extend_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s, a, f, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_closest_points(int k, const CpArgs& a, hipStream_t s)
 {

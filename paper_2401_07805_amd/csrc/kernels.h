@@ -105,6 +105,8 @@ struct CpArgs {
     int* info;                   // n: outer steps to convergence, 0 not converged, -1 outside the band
 };
 hipError_t launch_closest_points(int k, const CpArgs& a, hipStream_t s);
+// out[g] = f_h(a.y[g]) where a.info[g] >= 0, else f[g] (a.n = N mesh nodes).
+hipError_t launch_extend(int k, const CpArgs& a, const double* f, double* out, hipStream_t s);
 
 // Batched persistent apply (FP64).
 struct BatchProblem {

@@ -91,3 +91,28 @@ def test_closest_points_argument_errors():
         with pytest.raises(vpp.VppError) as e:
             prob.closest_points(**kw)
         assert e.value.status == 1
+
+
+def test_extension_from_closest_points():
+    """Values at the closest points extended over the band: a field that is
+    constant along the normals of the sphere is unchanged (up to its
+    interpolation error), and every band value equals the oracle's FE
+    evaluation of the field at the GPU's closest point."""
+    eps = 0.05
+    m = W.unit_cube(10, 2, 1000.0, 1.0, bc=(1,) * 6)
+    phi = W.droplet_phi(m, 0.3, eps)
+    prob = _problem(m, phi)
+    X, Y, Z = m.node_grid()
+    f = (np.cos(2 * X) * (1 + Y) + Z ** 2).ravel()
+    y, info = prob.closest_points(eps, phi_lim=0.6)
+    out = prob.extend(y, info, dev(f))
+    y, info, out = y.cpu().numpy(), info.cpu().numpy(), out.cpu().numpy()
+    band = info >= 0
+    np.testing.assert_array_equal(out[~band], f[~band])
+    ref, _ = evaluate(m, f, y[band])
+    np.testing.assert_allclose(out[band], ref, rtol=0, atol=1e-13)
+    # a field constant along the radial lines is reproduced at the band nodes
+    R = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2).ravel()
+    g = np.where(R > 0, (X.ravel() - 0.5) / np.where(R > 0, R, 1.0), 0.0)   # x-component of the radial unit vector
+    ext = prob.extend(dev(y), dev(info, torch.int32), dev(g)).cpu().numpy()
+    assert np.abs(ext[band & (info > 0)] - g[band & (info > 0)]).max() < 0.05
