@@ -106,7 +106,14 @@ def cpu_baseline():
         op.matvec(x)
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": m.ndofs / t / 1e6, "unit": "MDoF/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": model,
             "sample": f"FP64 CSR SpMV, median of 10 after 2 warm-ups, droplet 32^3 cells Q2 "
                       f"({m.ndofs} DoFs, nnz {op.nnz}); assembly {t_asm:.2f} s not included"}
 
