@@ -120,6 +120,8 @@ struct vpp_problem_s {
     bool phi_set = false;
     hipStream_t stream = nullptr;   // library stream for solves and graph capture
     CgWork w;
+    int* cp_list = nullptr;         // band nodes of the closest-point projection (N)
+    int* cp_ctr = nullptr;          // its band count and queue head (2)
 };
 
 struct vpp_batch_s {
@@ -730,6 +732,7 @@ vpp_status vpp_destroy(vpp_problem p)
     free_work(p->w);
     dev_free(p->phi64); dev_free(p->phi32); dev_free(p->diag); dev_free(p->inv64); dev_free(p->inv32);
     dev_free(p->part); dev_free(p->dot_part);
+    dev_free(p->cp_list); dev_free(p->cp_ctr);
     if (p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
     return VPP_OK;
@@ -881,7 +884,10 @@ vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const
     a.normal_steps = o->normal_steps;
     a.y = y;
     a.info = info;
-    VPP_HIP(launch_closest_points(p->k, a, (hipStream_t)stream));
+    vpp_status st;
+    if (!p->cp_ctr && (st = dev_alloc(&p->cp_ctr, 2, "closest-point counters"))) return st;
+    if (!pts && !p->cp_list && (st = dev_alloc(&p->cp_list, (size_t)p->N, "closest-point band list"))) return st;
+    VPP_HIP(launch_closest_points(p->k, a, p->cp_list, p->cp_ctr, closest_point_blocks(p->k), (hipStream_t)stream));
     return VPP_OK;
 }
 

@@ -62,8 +62,9 @@ __device__ __forceinline__ void eval_field(const CpArgs& a, const double* __rest
         if (cd > a.m.nc[d] - 1) cd = a.m.nc[d] - 1;
         c[d] = cd;
         lagrange_at<K>(s - cd, V[d], D[d]);
+        const double ih = 1.0 / a.h[d];
 #pragma unroll
-        for (int i = 0; i < N; ++i) D[d][i] /= a.h[d];
+        for (int i = 0; i < N; ++i) D[d][i] *= ih;
     }
     const int64_t nx = a.m.nn[0], nxy = (int64_t)a.m.nn[0] * a.m.nn[1];
     const double* p = f + node_index(a.m, (int64_t)K * c[0], (int64_t)K * c[1], (int64_t)K * c[2]);
@@ -89,81 +90,153 @@ __device__ __forceinline__ void clip_box(const CpArgs& a, double (&y)[3])
     for (int d = 0; d < 3; ++d) y[d] = fmin(fmax(y[d], a.lo[d]), a.hi[d]);
 }
 
+// Coordinates of support point i of the mesh.
 template <int K>
-__global__ void __launch_bounds__(256) closest_point_kernel(CpArgs a)
+__device__ __forceinline__ void node_coords(const CpArgs& a, int64_t i, double (&x)[3])
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= a.n) return;
-    double x[3];
-    if (a.pts) {
+    const int64_t ij[3] = {i % a.m.nn[0], (i / a.m.nn[0]) % a.m.nn[1], i / ((int64_t)a.m.nn[0] * a.m.nn[1])};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) x[d] = a.pts[3 * i + d];
-    } else {
-        // support point i of the mesh: in the band only if |phi_i| < phi_lim
-        const int64_t ij[3] = {i % a.m.nn[0], (i / a.m.nn[0]) % a.m.nn[1], i / ((int64_t)a.m.nn[0] * a.m.nn[1])};
+    for (int d = 0; d < 3; ++d) {
+        int cd = (int)(ij[d] / K);
+        if (cd > a.m.nc[d] - 1) cd = a.m.nc[d] - 1;
+        const int al = (int)(ij[d] - (int64_t)K * cd);
+        double xi = 0.0;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            int cd = (int)(ij[d] / K);
-            if (cd > a.m.nc[d] - 1) cd = a.m.nc[d] - 1;
-            const int al = (int)(ij[d] - (int64_t)K * cd);
-            double xi = 0.0;
-#pragma unroll
-            for (int q = 0; q <= K; ++q)
-                if (q == al) xi = Tab<K>::t.gll[q];   // compile-time table entries only
-            x[d] = a.lo[d] + (cd + xi) * a.h[d];
-        }
-        if (!(fabs(a.phi[i]) < a.phi_lim)) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) a.y[3 * i + d] = x[d];
-            a.info[i] = -1;
-            return;
-        }
+        for (int q = 0; q <= K; ++q)
+            if (q == al) xi = Tab<K>::t.gll[q];   // compile-time table entries only
+        x[d] = a.lo[d] + (cd + xi) * a.h[d];
     }
-    double y[3] = {x[0], x[1], x[2]};
-    int info = 0;
-    for (int it = 1; it <= a.max_iter; ++it) {
-        const double prev[3] = {y[0], y[1], y[2]};
-        double val, g[3];
-        for (int s = 0; s < a.normal_steps; ++s) {
-            eval_field<K>(a, a.phi, y, val, g);
-            const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-            if (gn > 0.0) {
-                const double pc = fmin(fmax(val, -kPhiClip), kPhiClip);
-                const double dist = a.eps * log((1.0 + pc) / (1.0 - pc));
-#pragma unroll
-                for (int d = 0; d < 3; ++d) y[d] -= dist * (g[d] / gn);
-                clip_box(a, y);
-            }
-        }
+}
+
+// One outer step from y towards the closest point of x; true once the step
+// moved y by less than tol.
+template <int K>
+__device__ __forceinline__ bool outer_step(const CpArgs& a, const double (&x)[3], double (&y)[3])
+{
+    const double prev[3] = {y[0], y[1], y[2]};
+    double val, g[3];
+    for (int s = 0; s < a.normal_steps; ++s) {
         eval_field<K>(a, a.phi, y, val, g);
         const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
         if (gn > 0.0) {
-            const double n[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
-            const bool use_y = fabs(n[0]) > 0.9;
-            const double v[3] = {use_y ? 0.0 : 1.0, use_y ? 1.0 : 0.0, 0.0};
-            const double vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
-            double t0[3] = {v[0] - vn * n[0], v[1] - vn * n[1], v[2] - vn * n[2]};
-            const double tl = sqrt(t0[0] * t0[0] + t0[1] * t0[1] + t0[2] * t0[2]);
+            const double pc = fmin(fmax(val, -kPhiClip), kPhiClip);
+            const double dist = a.eps * log((1.0 + pc) / (1.0 - pc));
 #pragma unroll
-            for (int d = 0; d < 3; ++d) t0[d] /= tl;
-            const double t1[3] = {n[1] * t0[2] - n[2] * t0[1], n[2] * t0[0] - n[0] * t0[2],
-                                  n[0] * t0[1] - n[1] * t0[0]};
-            const double r[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
-            const double r0 = r[0] * t0[0] + r[1] * t0[1] + r[2] * t0[2];
-            const double r1 = r[0] * t1[0] + r[1] * t1[1] + r[2] * t1[2];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) y[d] -= r0 * t0[d] + r1 * t1[d];
+            for (int d = 0; d < 3; ++d) y[d] -= dist * (g[d] / gn);
             clip_box(a, y);
         }
-        const double dy[3] = {y[0] - prev[0], y[1] - prev[1], y[2] - prev[2]};
-        if (sqrt(dy[0] * dy[0] + dy[1] * dy[1] + dy[2] * dy[2]) < a.tol) {
-            info = it;
-            break;
+    }
+    eval_field<K>(a, a.phi, y, val, g);
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (gn > 0.0) {
+        const double n[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+        const bool use_y = fabs(n[0]) > 0.9;
+        const double v[3] = {use_y ? 0.0 : 1.0, use_y ? 1.0 : 0.0, 0.0};
+        const double vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+        double t0[3] = {v[0] - vn * n[0], v[1] - vn * n[1], v[2] - vn * n[2]};
+        const double tl = sqrt(t0[0] * t0[0] + t0[1] * t0[1] + t0[2] * t0[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) t0[d] /= tl;
+        const double t1[3] = {n[1] * t0[2] - n[2] * t0[1], n[2] * t0[0] - n[0] * t0[2],
+                              n[0] * t0[1] - n[1] * t0[0]};
+        const double r[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+        const double r0 = r[0] * t0[0] + r[1] * t0[1] + r[2] * t0[2];
+        const double r1 = r[0] * t1[0] + r[1] * t1[1] + r[2] * t1[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) y[d] -= r0 * t0[d] + r1 * t1[d];
+        clip_box(a, y);
+    }
+    const double dy[3] = {y[0] - prev[0], y[1] - prev[1], y[2] - prev[2]};
+    return sqrt(dy[0] * dy[0] + dy[1] * dy[1] + dy[2] * dy[2]) < a.tol;
+}
+
+__device__ __forceinline__ unsigned long long lanes_below()
+{
+    const int lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Node mode, first pass: the band nodes |phi_g| < phi_lim are appended to list
+// (one atomic per wave; their order does not matter, each point's result is
+// written to its own node); every other node gets y = x and info = -1.
+template <int K>
+__global__ void __launch_bounds__(256) band_list_kernel(CpArgs a, int* __restrict__ list, int* __restrict__ count)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool in_mesh = i < a.n;
+    const bool band = in_mesh && fabs(a.phi[i]) < a.phi_lim;
+    const unsigned long long mask = __ballot(band);
+    if (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (__lane_id() == leader) base = atomicAdd(count, __popcll(mask));
+        base = __shfl(base, leader);
+        if (band) list[base + __popcll(mask & lanes_below())] = (int)i;
+    }
+    if (in_mesh && !band) {
+        double x[3];
+        node_coords<K>(a, i, x);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.y[3 * i + d] = x[d];
+        a.info[i] = -1;
+    }
+}
+
+// Persistent projection over a queue of points (the band list, or the caller's
+// points 0..n-1): a lane whose point has converged or used max_iter outer steps
+// writes it and takes the next one (one atomic per wave and refill), so a
+// point that needs many steps does not hold its wave's other lanes idle.
+// Every lane leaves once the queue is empty and its point is done; each point
+// takes at most max_iter steps, so every wave finishes.
+template <int K>
+__global__ void __launch_bounds__(256) closest_point_queue_kernel(CpArgs a, const int* __restrict__ list,
+                                                                  const int* __restrict__ count,
+                                                                  int* __restrict__ next)
+{
+    const int64_t total = a.pts ? a.n : (int64_t)*count;
+    bool have = false, live = true;
+    int64_t g = 0;
+    int it = 0;
+    double x[3] = {0.0, 0.0, 0.0}, y[3] = {0.0, 0.0, 0.0};
+    for (;;) {
+        const unsigned long long need = __ballot(live && !have);
+        if (need) {
+            const int leader = __ffsll((long long)need) - 1;
+            int base = 0;
+            if (__lane_id() == leader) base = atomicAdd(next, __popcll(need));
+            base = __shfl(base, leader);
+            if (live && !have) {
+                const int64_t q = (int64_t)base + __popcll(need & lanes_below());
+                if (q < total) {
+                    if (a.pts) {
+                        g = q;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) x[d] = a.pts[3 * q + d];
+                    } else {
+                        g = list[q];
+                        node_coords<K>(a, g, x);
+                    }
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) y[d] = x[d];
+                    it = 0;
+                    have = true;
+                } else {
+                    live = false;
+                }
+            }
+        }
+        if (!__ballot(have)) break;   // queue empty and every point written
+        if (have) {
+            ++it;
+            const bool conv = outer_step<K>(a, x, y);
+            if (conv || it >= a.max_iter) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) a.y[3 * g + d] = y[d];
+                a.info[g] = conv ? it : 0;
+                have = false;
+            }
         }
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) a.y[3 * i + d] = y[d];
-    a.info[i] = info;
 }
 
 // Extension from the closest points: out[g] = f_h(y_g) for a node in the band
@@ -200,18 +273,44 @@ hipError_t launch_extend(int k, const CpArgs& a, const double* f, double* out, h
     return hipGetLastError();
 }
 
-hipError_t launch_closest_points(int k, const CpArgs& a, hipStream_t s)
+hipError_t launch_closest_points(int k, const CpArgs& a, int* list, int* ctr, int nblocks, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
+    hipError_t e = launch_fill<int>(ctr, 2, 0, s);   // ctr[0]: band count, ctr[1]: queue head
+    if (e != hipSuccess) return e;
     const int64_t blocks = (a.n + 255) / 256;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
+#define VPP_CP(K)                                                                                          \
+    if (!a.pts) hipLaunchKernelGGL(band_list_kernel<K>, dim3((unsigned)blocks), dim3(256), 0, s, a, list, ctr); \
+    hipLaunchKernelGGL(closest_point_queue_kernel<K>, dim3(nblocks), dim3(256), 0, s, a, list, ctr, ctr + 1);
     switch (k) {
-    case 2: hipLaunchKernelGGL(closest_point_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(closest_point_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(closest_point_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    case 2: VPP_CP(2) break;
+    case 3: VPP_CP(3) break;
+    case 4: VPP_CP(4) break;
     default: return hipErrorInvalidValue;
     }
+#undef VPP_CP
     return hipGetLastError();
+}
+
+// Persistent workgroups of the projection: two per CU (two waves per SIMD), so
+// that the lanes are fewer than the points of a typical band and refill from
+// the queue, while the loads of one wave still overlap the other's arithmetic.
+constexpr int kCpBlocksPerCu = 2;
+
+int closest_point_blocks(int k)
+{
+    int per_cu = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (k) {
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, closest_point_queue_kernel<2>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, closest_point_queue_kernel<3>, 256, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, closest_point_queue_kernel<4>, 256, 0); break;
+    default: break;
+    }
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (per_cu > kCpBlocksPerCu) per_cu = kCpBlocksPerCu;
+    return per_cu * device_cu_count();
 }
 
 }  // namespace vpp

@@ -104,7 +104,10 @@ struct CpArgs {
     double* y;                   // 3 n
     int* info;                   // n: outer steps to convergence, 0 not converged, -1 outside the band
 };
-hipError_t launch_closest_points(int k, const CpArgs& a, hipStream_t s);
+// list: N ints (band nodes of the node mode), ctr: 2 ints (reset here by a fill
+// kernel); nblocks: persistent workgroups (closest_point_blocks).
+hipError_t launch_closest_points(int k, const CpArgs& a, int* list, int* ctr, int nblocks, hipStream_t s);
+int closest_point_blocks(int k);
 // out[g] = f_h(a.y[g]) where a.info[g] >= 0, else f[g] (a.n = N mesh nodes).
 hipError_t launch_extend(int k, const CpArgs& a, const double* f, double* out, hipStream_t s);
 
