@@ -187,6 +187,21 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
 vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* opts,
                               double* y, int32_t* info, void* stream);
 
+/* Right-hand sides of the level-set filter systems (vpp_set_mass), assembled
+ * on every row of the problem's mesh with its (k+1)^3 Gauss rule, no
+ * constraint applied:
+ *   vpp_normal_rhs:    b_d = (n_bar_d, v), n_bar = grad phi_h / |grad phi_h|
+ *                      (Eq. normal_vector; 0 where the gradient vanishes) for
+ *                      the nodal level set phi given here (N entries);
+ *   vpp_curvature_rhs: b = (kappa_bar, v), kappa_bar = -div n_h (Eq. curvature)
+ *                      for the nodal normal components n0, n1, n2 (N each),
+ *                      typically the solutions of the normal filter.
+ * FP64 device pointers, outputs not aliased with inputs.  The phi of the
+ * problem (vpp_set_phi) is not used.  Asynchronous on `stream`. */
+vpp_status vpp_normal_rhs(vpp_problem p, const double* phi, double* b0, double* b1, double* b2, void* stream);
+vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, const double* n2, double* b,
+                             void* stream);
+
 /* Extension of a nodal Q_k field f of the mesh from the interface over the
  * narrow band (same appendix: values at the closest points extended to the
  * band): out[g] = f_h(y_g), the FE interpolant at node g's closest point, for

@@ -62,6 +62,8 @@ def load() -> C.CDLL:
         "vpp_set_mass": (C.c_int, [vp, C.c_double, vp]),
         "vpp_closest_points": (C.c_int, [vp, vp, C.c_int64, C.POINTER(CpOpts), vp, vp, vp]),
         "vpp_extend": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "vpp_normal_rhs": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "vpp_curvature_rhs": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vpp_apply": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "vpp_diagonal": (C.c_int, [vp, vp, vp]),
         "vpp_cg_solve": (C.c_int, [vp, vp, vp, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),

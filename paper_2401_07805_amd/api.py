@@ -137,6 +137,22 @@ class Problem:
                                    _vec(out, self.n, torch.float64, self.device, "out"), _stream(self.device)))
         return out
 
+    def normal_rhs(self, phi: torch.Tensor):
+        """(n_bar_d, v) for d = x, y, z with n_bar = grad phi_h / |grad phi_h| (vpp_normal_rhs)."""
+        bs = [torch.empty(self.n, dtype=torch.float64, device=self.device) for _ in range(3)]
+        _check(L.load().vpp_normal_rhs(self._h, _vec(phi, self.n, torch.float64, self.device, "phi"),
+                                       *[_vec(b, self.n, torch.float64, self.device, "b") for b in bs],
+                                       _stream(self.device)))
+        return bs
+
+    def curvature_rhs(self, n0: torch.Tensor, n1: torch.Tensor, n2: torch.Tensor) -> torch.Tensor:
+        """(-div n_h, v) for the nodal normal components (vpp_curvature_rhs)."""
+        b = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(L.load().vpp_curvature_rhs(self._h, *[_vec(v, self.n, torch.float64, self.device, "n")
+                                                     for v in (n0, n1, n2)],
+                                          _vec(b, self.n, torch.float64, self.device, "b"), _stream(self.device)))
+        return b
+
     def set_mass(self, mu: float):
         """Operator mu M + K_c (vpp_set_mass); mu = 0 is the pressure operator."""
         _check(L.load().vpp_set_mass(self._h, float(mu), _stream(self.device)))

@@ -911,6 +911,41 @@ vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const
     return VPP_OK;
 }
 
+static RhsGeo rhs_geometry(vpp_problem p)
+{
+    RhsGeo g{};
+    g.m = p->m;
+    g.vol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        const double h = p->desc.extent[d] / p->desc.ncells[d];
+        g.ih[d] = 1.0 / h;
+        g.vol *= h;
+    }
+    return g;
+}
+
+vpp_status vpp_normal_rhs(vpp_problem p, const double* phi, double* b0, double* b1, double* b2, void* stream)
+{
+    if (!p || !phi || !b0 || !b1 || !b2) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (b0 == b1 || b0 == b2 || b1 == b2 || (const void*)phi == b0 || (const void*)phi == b1 ||
+        (const void*)phi == b2)
+        return fail(VPP_ERR_INVALID_ARG, "phi and the outputs must not alias");
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(launch_normal_rhs(p->k, rhs_geometry(p), phi, b0, b1, b2, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, const double* n2, double* b,
+                             void* stream)
+{
+    if (!p || !n0 || !n1 || !n2 || !b) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if ((const void*)b == n0 || (const void*)b == n1 || (const void*)b == n2)
+        return fail(VPP_ERR_INVALID_ARG, "the output must not alias an input");
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(launch_curvature_rhs(p->k, rhs_geometry(p), n0, n1, n2, b, (hipStream_t)stream));
+    return VPP_OK;
+}
+
 static void put_config(vpp_problem p, int prec, const LaunchCfg& c)
 {
     if (prec == VPP_FP32) {

@@ -111,6 +111,19 @@ int closest_point_blocks(int k);
 // out[g] = f_h(a.y[g]) where a.info[g] >= 0, else f[g] (a.n = N mesh nodes).
 hipError_t launch_extend(int k, const CpArgs& a, const double* f, double* out, hipStream_t s);
 
+// Right-hand sides of the level-set filter systems (all rows assembled).
+struct RhsGeo {
+    MeshArgs m;
+    double ih[3];   // 1 / h_d
+    double vol;     // hx hy hz
+};
+// b_d = (grad phi_h / |grad phi_h|, v)_d for d = 0, 1, 2.
+hipError_t launch_normal_rhs(int k, const RhsGeo& g, const double* phi, double* b0, double* b1, double* b2,
+                             hipStream_t s);
+// b = (-div n_h, v) for the nodal components n0, n1, n2.
+hipError_t launch_curvature_rhs(int k, const RhsGeo& g, const double* n0, const double* n1, const double* n2,
+                                double* b, hipStream_t s);
+
 // Batched persistent apply (FP64).
 struct BatchProblem {
     MeshArgs m;
