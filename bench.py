@@ -217,9 +217,31 @@ def filter_figures(torch, vpp, W, dev, cache):
     sols = [p.cg_solve(b, rtol=1e-12, atol=1e-20) for b in bs]
     t = time.perf_counter() - t0
     err = max(float(torch.linalg.norm(x - c) / torch.linalg.norm(c)) for (x, _), c in zip(sols, comps))
+    # the chain on a droplet (r 0.25, eps = 2h): phi -> (n_bar, v) -> normal filters
+    # -> (-div n, v) -> curvature filter, each right-hand side formed on the GPU
+    phi = torch.from_numpy(W.droplet_phi(m, 0.25, 2.0 / n)).to(dev)
+    p.normal_rhs(phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bn = p.normal_rhs(phi)
+    torch.cuda.synchronize()
+    t_nrhs = time.perf_counter() - t0
+    ns = [p.cg_solve(b, rtol=1e-12, atol=1e-20)[0] for b in bn]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bk = p.curvature_rhs(*ns)
+    torch.cuda.synchronize()
+    t_krhs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    kap, kinfo = p.cg_solve(bk, rtol=1e-12, atol=1e-20)
+    t_k = time.perf_counter() - t0
+    band = phi.abs() < 0.5
     return {"filter_q2_config": p.config, "filter_q2_f64_hot_apply_us": us,
             "filter_q2_f64_hot_mdofs": m.ndofs / us, "filter_normal_cg_s": t,
-            "filter_normal_cg_iters": [i["iterations"] for _, i in sols], "filter_normal_cg_max_rel_err": err}
+            "filter_normal_cg_iters": [i["iterations"] for _, i in sols], "filter_normal_cg_max_rel_err": err,
+            "filter_normal_rhs_us": t_nrhs * 1e6, "filter_curvature_rhs_us": t_krhs * 1e6,
+            "filter_curvature_cg_s": t_k, "filter_curvature_cg_iters": kinfo["iterations"],
+            "filter_curvature_band_mean_over_2_by_r": float(kap[band].mean()) / (2.0 / 0.25)}
 
 
 def closest_point_figures(torch, vpp, W, dev):
