@@ -116,3 +116,22 @@ def test_extension_from_closest_points():
     g = np.where(R > 0, (X.ravel() - 0.5) / np.where(R > 0, R, 1.0), 0.0)   # x-component of the radial unit vector
     ext = prob.extend(dev(y), dev(info, torch.int32), dev(g)).cpu().numpy()
     assert np.abs(ext[band & (info > 0)] - g[band & (info > 0)]).max() < 0.05
+
+
+def test_full_size_band_sample():
+    """The 64^3 Q2 droplet's narrow band (the bench workload): a sample of 2000
+    band nodes against the oracle, converged points within 1e-9."""
+    wl = W.droplet_at_scale(k=2, nvec=0)
+    m = wl.mesh
+    prob = _problem(m, wl.phi)
+    say("full size band")
+    y, info = prob.closest_points(m.eps)
+    y, info = y.cpu().numpy(), info.cpu().numpy()
+    idx = oracle.band_nodes(m, wl.phi, 0.9)
+    assert (info[idx] >= 0).all() and (info >= 0).sum() == len(idx)
+    rng = np.random.default_rng(17)
+    s = np.sort(rng.choice(idx, 2000, replace=False))
+    yo, so, do = oracle.closest_points(m, wl.phi, oracle.node_coords(m, s), m.eps, max_iter=50, tol=1e-11)
+    both = do & (info[s] > 0)
+    assert both.mean() > 0.9
+    assert np.linalg.norm(y[s][both] - yo[both], axis=1).max() < 1e-9
