@@ -157,22 +157,35 @@ __device__ __forceinline__ unsigned long long lanes_below()
 }
 
 // Node mode, first pass: the band nodes |phi_g| < phi_lim are appended to list
-// (one atomic per wave; their order does not matter, each point's result is
-// written to its own node); every other node gets y = x and info = -1.
+// with one atomic per 1024-thread workgroup (the waves' counts are summed in
+// LDS; same-address atomics serialise, so one per wave took 130 us at 64^3);
+// their order does not matter, each point's result is written to its own node.
+// Every other node gets y = x and info = -1.
+constexpr int kListThreads = 1024;
+
 template <int K>
-__global__ void __launch_bounds__(256) band_list_kernel(CpArgs a, int* __restrict__ list, int* __restrict__ count)
+__global__ void __launch_bounds__(kListThreads) band_list_kernel(CpArgs a, int* __restrict__ list,
+                                                                  int* __restrict__ count)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    constexpr int NW = kListThreads / 64;
+    __shared__ int wcount[NW], wbase[NW], bbase;
+    const int64_t i = (int64_t)blockIdx.x * kListThreads + threadIdx.x;
+    const int wave = threadIdx.x / 64;
     const bool in_mesh = i < a.n;
     const bool band = in_mesh && fabs(a.phi[i]) < a.phi_lim;
     const unsigned long long mask = __ballot(band);
-    if (mask) {
-        const int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (__lane_id() == leader) base = atomicAdd(count, __popcll(mask));
-        base = __shfl(base, leader);
-        if (band) list[base + __popcll(mask & lanes_below())] = (int)i;
+    if (__lane_id() == 0) wcount[wave] = __popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < NW; ++w) {
+            wbase[w] = t;
+            t += wcount[w];
+        }
+        bbase = t ? atomicAdd(count, t) : 0;
     }
+    __syncthreads();
+    if (band) list[bbase + wbase[wave] + __popcll(mask & lanes_below())] = (int)i;
     if (in_mesh && !band) {
         double x[3];
         node_coords<K>(a, i, x);
@@ -278,10 +291,11 @@ hipError_t launch_closest_points(int k, const CpArgs& a, int* list, int* ctr, in
     if (a.n <= 0) return hipSuccess;
     hipError_t e = launch_fill<int>(ctr, 2, 0, s);   // ctr[0]: band count, ctr[1]: queue head
     if (e != hipSuccess) return e;
-    const int64_t blocks = (a.n + 255) / 256;
+    const int64_t blocks = (a.n + kListThreads - 1) / kListThreads;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
 #define VPP_CP(K)                                                                                          \
-    if (!a.pts) hipLaunchKernelGGL(band_list_kernel<K>, dim3((unsigned)blocks), dim3(256), 0, s, a, list, ctr); \
+    if (!a.pts)                                                                                             \
+        hipLaunchKernelGGL(band_list_kernel<K>, dim3((unsigned)blocks), dim3(kListThreads), 0, s, a, list, ctr); \
     hipLaunchKernelGGL(closest_point_queue_kernel<K>, dim3(nblocks), dim3(256), 0, s, a, list, ctr, ctr + 1);
     switch (k) {
     case 2: VPP_CP(2) break;
