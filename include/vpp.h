@@ -182,8 +182,8 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
  * y: 3 entries per point (xyz); info: outer steps to convergence, 0 when
  * max_iter steps did not converge (y is the last iterate; the C0 normal field
  * jumps across cell faces, so points projecting onto a face can cycle), -1
- * for a node outside the band (y = x).  Needs vpp_set_phi.  Asynchronous on
- * `stream`. */
+ * for a node outside the band (y = x).  Needs vpp_set_phi; VPP_ERR_UNSUPPORTED
+ * for more than 2^31 - 2^24 points.  Asynchronous on `stream`. */
 vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* opts,
                               double* y, int32_t* info, void* stream);
 

@@ -866,6 +866,9 @@ vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const
         o->normal_steps < 0 || o->normal_steps > 100)
         return fail(VPP_ERR_INVALID_ARG, "closest-point options out of range");
     if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    // the queue head counts past the last point by at most one fetch per resident lane
+    if ((pts ? n : p->N) > (int64_t)INT32_MAX - (int64_t(1) << 24))
+        return fail(VPP_ERR_UNSUPPORTED, "too many points for the 32-bit work queue");
     DeviceGuard dg(p->desc.device);
     CpArgs a{};
     a.m = p->m;
