@@ -1,6 +1,9 @@
 // Closest-point projection onto the zero isosurface of the FE level set phi_h
 // (appendix "Extension of solution quantities from a level-set isosurface
-// using closest point projection", Eq. cpp), one thread per point.
+// using closest point projection", Eq. cpp), one lane per point at a time:
+// a persistent grid works through a queue of points (the compacted narrow
+// band of the mesh nodes, or the caller's points), and the extension of nodal
+// fields from the closest points.
 //
 // From y = x, every outer step takes `normal_steps` corrections along the
 // normal, y <- y - d(y) n(y) with the signed distance d = eps log((1+phi)/(1-phi))
