@@ -333,3 +333,4 @@ def discrete_manufactured_rhs(op, mesh, p_nodal) -> np.ndarray:
 
 
 from .closest_point import band_nodes, closest_points, node_coords  # noqa: E402  (closest-point projection)
+from .reinit import reinit_matrix, reinit_rhs  # noqa: E402  (reinitialization step)
