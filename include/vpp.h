@@ -105,6 +105,14 @@ typedef struct {
     int32_t normal_steps;      /* normal corrections per outer step, 0..100 */
 } vpp_cp_opts;
 
+/* Options of the reinitialization step (vpp_reinit_step). */
+typedef struct {
+    double eps;                /* interface thickness, > 0 */
+    double dtau;               /* pseudo-time step, > 0 (the paper takes min(eps, dt)) */
+    double rtol, atol;         /* CG stopping rule (Table tab:solver_settings: 1e-12, 1e-20) */
+    int32_t max_iter;          /* 0..1e7 */
+} vpp_reinit_opts;
+
 /* Kernel configuration: cells of one workgroup tile (tx, ty, tz). */
 typedef struct {
     int32_t tile[3];
@@ -201,6 +209,22 @@ vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const
 vpp_status vpp_normal_rhs(vpp_problem p, const double* phi, double* b0, double* b1, double* b2, void* stream);
 vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, const double* n2, double* b,
                              void* stream);
+
+/* One step of the level-set reinitialization (Eq. reinitialization): the
+ * semi-implicit Euler step in pseudo-time with the compressive flux explicit,
+ *   (psi', v)/dtau + eps ((grad psi' . n)(grad v . n))
+ *       = (psi, v)/dtau + ((1 - psi^2)/2 n, grad v),
+ * solved by Jacobi-preconditioned CG (Table tab:solver_settings) from psi'
+ * = psi.  n: the nodal (filtered) normal components n0, n1, n2, interpolated at
+ * the Gauss points as they are; the boundary terms of both integrations by
+ * parts are dropped (natural conditions on every face, whatever the problem's
+ * faces).  The operator, its diagonal and the right-hand side are evaluated
+ * per cell (sum factorization, atomic scatter).  psi, n0..n2, psi_out: N
+ * entries, FP64 device pointers; psi_out may alias psi.  The problem's phi and
+ * mass shift are not used.  Synchronizes; info as for vpp_cg_solve. */
+vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, const double* n1,
+                           const double* n2, const vpp_reinit_opts* opts, double* psi_out,
+                           vpp_cg_info* info, void* stream);
 
 /* Extension of a nodal Q_k field f of the mesh from the interface over the
  * narrow band (same appendix: values at the closest points extended to the

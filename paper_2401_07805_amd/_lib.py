@@ -35,6 +35,11 @@ class KernelConfig(C.Structure):
     _fields_ = [("tile", C.c_int32 * 3), ("variant", C.c_int32)]
 
 
+class ReinitOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("dtau", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
+                ("max_iter", C.c_int32)]
+
+
 class CpOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("phi_lim", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("normal_steps", C.c_int32)]
@@ -63,6 +68,7 @@ def load() -> C.CDLL:
         "vpp_closest_points": (C.c_int, [vp, vp, C.c_int64, C.POINTER(CpOpts), vp, vp, vp]),
         "vpp_extend": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vpp_normal_rhs": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "vpp_reinit_step": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, C.POINTER(CgInfo), vp]),
         "vpp_curvature_rhs": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vpp_apply": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "vpp_diagonal": (C.c_int, [vp, vp, vp]),

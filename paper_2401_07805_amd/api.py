@@ -153,6 +153,21 @@ class Problem:
                                           _vec(b, self.n, torch.float64, self.device, "b"), _stream(self.device)))
         return b
 
+    def reinit_step(self, psi: torch.Tensor, normal, eps: float, dtau: float, rtol: float = 1e-12,
+                    atol: float = 1e-20, max_iter: int = 100000, raise_on_failure: bool = True):
+        """One semi-implicit reinitialization step (vpp_reinit_step); normal: the three
+        nodal components.  Returns (psi', info)."""
+        out = torch.empty_like(psi)
+        o = L.ReinitOpts(float(eps), float(dtau), float(rtol), float(atol), int(max_iter))
+        ci = L.CgInfo()
+        st = L.load().vpp_reinit_step(self._h, _vec(psi, self.n, torch.float64, self.device, "psi"),
+                                      *[_vec(c, self.n, torch.float64, self.device, "normal") for c in normal],
+                                      C.byref(o), _vec(out, self.n, torch.float64, self.device, "psi_out"),
+                                      C.byref(ci), _stream(self.device))
+        if st != L.VPP_OK and (raise_on_failure or st not in (5, 6)):
+            _check(st)
+        return out, _info(ci)
+
     def set_mass(self, mu: float):
         """Operator mu M + K_c (vpp_set_mass); mu = 0 is the pressure operator."""
         _check(L.load().vpp_set_mass(self._h, float(mu), _stream(self.device)))

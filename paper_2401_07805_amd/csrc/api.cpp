@@ -100,6 +100,15 @@ struct CgWork {
     LaunchCfg graph_cfg32{-1, {0, 0, 0}};
 };
 
+// Workspace of the reinitialization step (allocated on first use).
+struct ReinitWork {
+    double *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *x = nullptr;
+    double *diag = nullptr, *invd = nullptr, *red = nullptr, *dot = nullptr, *rr = nullptr, *hrr = nullptr;
+    float* inv32 = nullptr;
+    CgState* st = nullptr;
+    CgState* hst = nullptr;
+};
+
 struct vpp_problem_s {
     vpp_desc desc;
     int k = 2;
@@ -122,7 +131,19 @@ struct vpp_problem_s {
     CgWork w;
     int* cp_list = nullptr;         // band nodes of the closest-point projection (N)
     int* cp_ctr = nullptr;          // its band count and queue head (2)
+    ReinitWork* rw = nullptr;       // reinitialization step
 };
+
+static void free_reinit(ReinitWork* w)
+{
+    if (!w) return;
+    dev_free(w->b); dev_free(w->r); dev_free(w->p); dev_free(w->q); dev_free(w->x);
+    dev_free(w->diag); dev_free(w->invd); dev_free(w->red); dev_free(w->dot); dev_free(w->rr);
+    dev_free(w->inv32); dev_free(w->st);
+    if (w->hst) (void)hipHostFree(w->hst);
+    if (w->hrr) (void)hipHostFree(w->hrr);
+    delete w;
+}
 
 struct vpp_batch_s {
     std::vector<vpp_problem> probs;
@@ -733,6 +754,7 @@ vpp_status vpp_destroy(vpp_problem p)
     dev_free(p->phi64); dev_free(p->phi32); dev_free(p->diag); dev_free(p->inv64); dev_free(p->inv32);
     dev_free(p->part); dev_free(p->dot_part);
     dev_free(p->cp_list); dev_free(p->cp_ctr);
+    free_reinit(p->rw);
     if (p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
     return VPP_OK;
@@ -946,6 +968,119 @@ vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, 
         return fail(VPP_ERR_INVALID_ARG, "the output must not alias an input");
     DeviceGuard dg(p->desc.device);
     VPP_HIP(launch_curvature_rhs(p->k, rhs_geometry(p), n0, n1, n2, b, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+static vpp_status ensure_reinit_work(vpp_problem p)
+{
+    if (p->rw) return VPP_OK;
+    ReinitWork* w = new ReinitWork();
+    const size_t n = (size_t)p->N;
+    vpp_status st;
+    if ((st = dev_alloc(&w->b, n, "reinit b")) || (st = dev_alloc(&w->r, n, "reinit r")) ||
+        (st = dev_alloc(&w->p, n, "reinit p")) || (st = dev_alloc(&w->q, n, "reinit q")) ||
+        (st = dev_alloc(&w->x, n, "reinit x")) || (st = dev_alloc(&w->diag, n, "reinit diag")) ||
+        (st = dev_alloc(&w->invd, n, "reinit inverse diag")) || (st = dev_alloc(&w->inv32, n, "reinit inverse diag")) ||
+        (st = dev_alloc(&w->red, kRedDoubles, "reinit partials")) ||
+        (st = dev_alloc(&w->dot, kMaxRedBlocks, "reinit dot partials")) || (st = dev_alloc(&w->rr, 1, "norm")) ||
+        (st = dev_alloc(&w->st, 1, "reinit state"))) {
+        free_reinit(w);
+        return st;
+    }
+    if (hipHostMalloc((void**)&w->hst, sizeof(CgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&w->hrr, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        free_reinit(w);
+        return fail(VPP_ERR_OUT_OF_MEMORY, "reinit host mirrors");
+    }
+    p->rw = w;
+    return VPP_OK;
+}
+
+vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, const double* n1, const double* n2,
+                           const vpp_reinit_opts* o, double* psi_out, vpp_cg_info* info, void* stream)
+{
+    if (!p || !psi || !n0 || !n1 || !n2 || !o || !psi_out) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    if (!(o->eps > 0.0) || !std::isfinite(o->eps) || !(o->dtau > 0.0) || !std::isfinite(o->dtau) ||
+        !(o->rtol >= 0.0) || !(o->atol >= 0.0) || o->max_iter < 0 || o->max_iter > 10000000)
+        return fail(VPP_ERR_INVALID_ARG, "reinitialization options out of range");
+    DeviceGuard dg(p->desc.device);
+    vpp_status st;
+    if ((st = ensure_reinit_work(p))) return st;
+    VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    hipStream_t s = p->stream;
+    ReinitWork& w = *p->rw;
+    const int64_t n = p->N;
+    ReinitArgs ra{rhs_geometry(p), o->eps, 1.0 / o->dtau, n0, n1, n2};
+    // natural conditions on every face: no identity rows, whatever the problem's faces
+    ra.g.m.bcmask = 0;
+    MeshArgs m1 = ra.g.m;
+    m1.ntile[0] = m1.ntile[1] = m1.ntile[2] = 1;
+    const int one[3] = {1, 1, 1};
+    const SharedEnum none = shared_enum(m1, p->k, one);   // no shared nodes: q is used as it is
+    const int gdot = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxRedBlocks, (n + 1023) / 1024));
+    VPP_HIP(launch_reinit_rhs(p->k, ra, psi, w.b, s));
+    VPP_HIP(launch_reinit_diag(p->k, ra, w.diag, s));
+    VPP_HIP(launch_fix_diagonal(ra.g.m, w.diag, w.invd, w.inv32, s));
+    VPP_HIP(hipMemcpyAsync(w.x, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    VPP_HIP(launch_reinit_apply(p->k, ra, w.x, w.q, s));
+    CgState* hs = w.hst;
+    std::memset(hs, 0, sizeof(CgState));
+    VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
+    VPP_HIP(launch_cg_init<double>(w.st, w.red, w.b, w.q, w.r, w.p, w.invd, n, s));
+    VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    vpp_cg_info inf{};
+    const double r0 = std::sqrt(hs->rr_last), rz0 = hs->rz[0];
+    const double thr = std::max(o->rtol * r0, o->atol);
+    inf.rel_residual = r0 > 0 ? 1.0 : 0.0;
+    bool iterate = true;
+    if (!std::isfinite(r0) || !std::isfinite(rz0)) {
+        inf.status = VPP_ERR_BREAKDOWN;
+        iterate = false;
+    } else if (r0 == 0.0 || r0 < o->atol) {
+        inf.status = VPP_OK;
+        iterate = false;
+    } else if (o->max_iter == 0) {
+        inf.status = VPP_ERR_NOT_CONVERGED;
+        iterate = false;
+    }
+    if (iterate) {
+        CgState init{};
+        init.rz[0] = rz0;
+        init.tol2 = thr * thr;
+        init.max_iter = o->max_iter;
+        *hs = init;
+        VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
+        constexpr int chunk = 16;
+        for (int done = 0; done < o->max_iter + chunk;) {
+            for (int it = 0; it < chunk; ++it, ++done) {
+                const int par = done & 1;
+                VPP_HIP(launch_reinit_apply(p->k, ra, w.p, w.q, s));
+                VPP_HIP(launch_dot_partials(w.p, w.q, n, w.dot, gdot, s));
+                VPP_HIP(launch_cg_assemble_update<double>(w.st, par, w.red, w.dot, gdot, ra.g.m, none, nullptr, 0,
+                                                          w.r, w.q, w.invd, n, s));
+                VPP_HIP(launch_cg_pupdate<double>(w.st, par, w.red, w.x, w.r, w.p, w.invd, n, s));
+            }
+            VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            VPP_HIP(hipStreamSynchronize(s));
+            if (hs->halt[0] || hs->halt[1]) break;
+        }
+        inf.iterations = hs->iters;
+        inf.rel_residual = std::sqrt(hs->rr_last) / r0;
+        if (hs->breakdown) inf.status = VPP_ERR_BREAKDOWN;
+        else if (hs->rr_last < init.tol2) inf.status = VPP_OK;
+        else inf.status = VPP_ERR_NOT_CONVERGED;
+    }
+    // true residual, then the new level set
+    VPP_HIP(launch_reinit_apply(p->k, ra, w.x, w.q, s));
+    VPP_HIP(launch_residual(w.b, w.q, nullptr, n, w.red, w.rr, s));
+    VPP_HIP(hipMemcpyAsync(w.hrr, w.rr, sizeof(double), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipMemcpyAsync(psi_out, w.x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    inf.true_rel_residual = r0 > 0 ? std::sqrt(*w.hrr) / r0 : 0.0;
+    if (info) *info = inf;
+    if (inf.status == VPP_ERR_NOT_CONVERGED) return fail(VPP_ERR_NOT_CONVERGED, "reinitialization CG did not converge");
+    if (inf.status == VPP_ERR_BREAKDOWN) return fail(VPP_ERR_BREAKDOWN, "reinitialization CG breakdown");
     return VPP_OK;
 }
 

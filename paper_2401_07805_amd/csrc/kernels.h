@@ -124,6 +124,23 @@ hipError_t launch_normal_rhs(int k, const RhsGeo& g, const double* phi, double* 
 hipError_t launch_curvature_rhs(int k, const RhsGeo& g, const double* n0, const double* n1, const double* n2,
                                 double* b, hipStream_t s);
 
+// One semi-implicit step of the level-set reinitialization:
+//   A psi' = b,  A = M/dtau + eps K_n,  K_n = ((grad u . n)(grad v . n)),
+//   b = (psi, v)/dtau + ((1 - psi^2)/2 n, grad v).
+struct ReinitArgs {
+    RhsGeo g;
+    double eps, idtau;
+    const double* n0;   // nodal normal components (N each)
+    const double* n1;
+    const double* n2;
+};
+hipError_t launch_reinit_apply(int k, const ReinitArgs& r, const double* x, double* y, hipStream_t s);
+hipError_t launch_reinit_diag(int k, const ReinitArgs& r, double* diag, hipStream_t s);
+hipError_t launch_reinit_rhs(int k, const ReinitArgs& r, const double* psi, double* b, hipStream_t s);
+// part[b] = partial of x . y over the elements workgroup b visits (nblocks <= 1024).
+hipError_t launch_dot_partials(const double* x, const double* y, int64_t n, double* part, int nblocks,
+                               hipStream_t s);
+
 // Batched persistent apply (FP64).
 struct BatchProblem {
     MeshArgs m;

@@ -49,6 +49,7 @@ int main(void){
   printf("%zu %zu\n", sizeof(vpp_cg_info), offsetof(vpp_cg_info, rel_residual));
   printf("%zu %zu\n", sizeof(vpp_kernel_config), offsetof(vpp_kernel_config, variant));
   printf("%zu %zu %zu\n", sizeof(vpp_cp_opts), offsetof(vpp_cp_opts, max_iter), offsetof(vpp_cp_opts, normal_steps));
+  printf("%zu %zu\n", sizeof(vpp_reinit_opts), offsetof(vpp_reinit_opts, max_iter));
   return 0;}
 ''')
     exe = tmp_path / "l"
@@ -62,6 +63,8 @@ int main(void){
     assert out[3].split() == [str(v) for v in (ctypes.sizeof(K), K.variant.offset)]
     P = _lib.CpOpts
     assert out[4].split() == [str(v) for v in (ctypes.sizeof(P), P.max_iter.offset, P.normal_steps.offset)]
+    R = _lib.ReinitOpts
+    assert out[5].split() == [str(v) for v in (ctypes.sizeof(R), R.max_iter.offset)]
 
 
 def test_candidates_listed_without_gpu():
