@@ -144,10 +144,10 @@ vpp_status vpp_set_phi(vpp_problem p, const double* phi, void* stream);
  * kappa_bar (Eqs. normal_vector_regularized, curvature_regularized; solved
  * with CG and the diagonal preconditioner, Table tab:solver_settings); the
  * right-hand sides (n_bar, v) are inputs like every b here.  mu >= 0, finite;
- * mu = 0 restores the pressure operator.  Degrees 2 and 3 only
- * (VPP_ERR_UNSUPPORTED for k = 4 with mu != 0): with mu != 0 the problem runs
- * the variant-4 configurations listed for it (vpp_set_config rejects others;
- * the current ones are switched if needed).  Rebuilds the diagonal if phi is
+ * mu = 0 restores the pressure operator.  With mu != 0 the problem runs the
+ * configurations instantiated with the shift (variant 4 for k = 2, 3, variant
+ * 1 for k = 4; vpp_set_config rejects others, the current ones are switched
+ * if needed).  Rebuilds the diagonal if phi is
  * set; synchronizes `stream` and the problem's stream.  Batches copy their
  * problems' operators when created, so set mu before vpp_batch_create. */
 vpp_status vpp_set_mass(vpp_problem p, double mu, void* stream);

@@ -782,7 +782,7 @@ vpp_status vpp_set_mass(vpp_problem p, double mu, void* stream)
     if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(VPP_ERR_INVALID_ARG, "the mass shift must be finite and >= 0");
     LaunchCfg mc[16];
     if (mu != 0.0 && list_mass_configs(p->k, mc, 16) < 1)
-        return fail(VPP_ERR_UNSUPPORTED, "the mass shift is available for degrees 2 and 3");
+        return fail(VPP_ERR_UNSUPPORTED, "no kernel configuration with the mass shift for this degree");
     DeviceGuard dg(p->desc.device);
     VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
     if (p->stream) VPP_HIP(hipStreamSynchronize(p->stream));

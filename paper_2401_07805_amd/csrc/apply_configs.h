@@ -29,19 +29,22 @@ namespace vpp {
     X(4, 1, 4, 4, 1)
 
 // Configurations also instantiated with the mass shift mu M of the level-set
-// filter operators (variant 4 only: the mass term sits in cell_operator).
+// filter operators (variant 4: the mass term sits in cell_operator; variant 1:
+// in the plane kernel's Gauss-point step).
 #define VPP_MASS_CONFIGS(X) \
     X(2, 4, 16, 8, 4)       \
     X(2, 4, 32, 4, 4)       \
     X(2, 4, 8, 4, 4)        \
-    X(3, 4, 8, 4, 4)
+    X(3, 4, 8, 4, 4)        \
+    X(4, 1, 4, 2, 2)        \
+    X(4, 1, 2, 2, 2)
 
 template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT, bool MASS>
 inline auto kernel_ptr()
 {
-    static_assert(!MASS || V == 4, "the mass shift is instantiated for variant 4 only");
+    static_assert(!MASS || V == 4 || V == 1, "the mass shift is instantiated for variants 1 and 4");
     if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV, DOT>;
-    else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV, DOT>;
+    else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV, DOT, MASS>;
     else if constexpr (V == 2) return &apply_half_kernel<K, T, TX, TY, TZ, HV, DOT>;
     else return &apply_slot_kernel<K, T, TX, TY, TZ, HV, DOT, MASS>;
 }

@@ -876,7 +876,7 @@ __device__ __forceinline__ double pick(int r, int i)
     return v;
 }
 
-template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT>
+template <int K, typename T, int TX, int TY, int TZ, int HV, bool DOT, bool MASS = false>
 __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(ApplyArgs<T> a)
 {
     constexpr int N = K + 1, N2 = N * N, NC = TX * TY * TZ, NT = N * NC;
@@ -1011,6 +1011,14 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     if constexpr (QUAD) __syncthreads();   // bounds the scheduling region (register pressure)
     if (active) {
         T gy[N2];
+        // mass shift: mu hx hy hz wref u at this thread's Gauss points, added to
+        // the values that the transposed interpolation in x receives
+        T mv[MASS ? N2 : 1];
+        if constexpr (MASS) {
+            const T ms = T(m.mass) * wx;
+#pragma unroll
+            for (int q = 0; q < N2; ++q) mv[q] = ms * T(Tab<K>::t.w[q % N] * Tab<K>::t.w[q / N]) * uq[q];
+        }
 #pragma unroll
         for (int q = 0; q < N2; ++q) gy[q] = uq[q];
         sweep2<K, MDC, false, 0>(gy);
@@ -1024,6 +1032,10 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
         }
         sweep2<K, MDC, true, 0>(gy);
         sweep2<K, MDC, true, 1>(uq);
+        if constexpr (MASS) {
+#pragma unroll
+            for (int q = 0; q < N2; ++q) gy[q] += mv[q];
+        }
         if constexpr (QUAD) {
 #pragma unroll
             for (int q = 0; q < N2; ++q) {
