@@ -165,6 +165,7 @@ def extras(torch, vpp, W, dev, cache):
                 out[f"q3_cg_{prec}_iters"] = info["iterations"]
     out.update(batch_figures(torch, vpp, W, dev, cache))
     out.update(filter_figures(torch, vpp, W, dev, cache))
+    out.update(adjoint_figures(torch, vpp, W, dev, cache))
     out.update(closest_point_figures(torch, vpp, W, dev))
     out.update(c2_figures(torch, vpp, W, dev, cache))
     wl = W.droplet_at_scale(k=2, nvec=0, bubble=True)
@@ -252,6 +253,38 @@ def filter_figures(torch, vpp, W, dev, cache):
             "filter_normal_rhs_us": t_nrhs * 1e6, "filter_curvature_rhs_us": t_krhs * 1e6,
             "filter_curvature_cg_s": t_k, "filter_curvature_cg_iters": kinfo["iterations"],
             "filter_curvature_band_mean_over_2_by_r": float(kap[band].mean()) / (2.0 / 0.25)}
+
+
+def adjoint_figures(torch, vpp, W, dev, cache):
+    """The adjoint workload: 48^3 Q2 droplet r 0.3 against the target r 0.28,
+    J = 1/2 |p - p_t|^2; forward PCG, then the backward pass of the autograd
+    Function (adjoint PCG, dJ/dc at every Gauss point, dJ/dphi at the nodes),
+    both to rtol 1e-10.  b = A_D(phi_t) p* for the manufactured sine p*,
+    formed once and then held fixed (an input independent of phi)."""
+    m, phi, phit = W.adjoint_case(n=48, k=2)
+    prob = vpp.Problem.from_mesh(m)
+    prob.set_phi(torch.from_numpy(phit).to(dev))
+    prob.tune(cache)
+    ps = torch.from_numpy(W.sine_field(m)).to(dev)
+    ps[torch.from_numpy(m.boundary_mask()).to(dev)] = 0.0
+    b = prob.apply(ps)
+    pt, _ = prob.cg_solve(b, rtol=1e-10)
+    times = {}
+    for rep in range(2):                       # the first pass builds the graphs
+        phi_t = torch.from_numpy(phi).to(dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = vpp.poisson_solve(phi_t, b, prob, rtol=1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J = 0.5 * ((p - pt) ** 2).sum()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times = {"forward": t1 - t0, "backward": t2 - t1}
+    return {"adjoint_c4_ndofs": m.ndofs, "adjoint_c4_forward_s": times["forward"],
+            "adjoint_c4_backward_s": times["backward"],
+            "adjoint_c4_grad_norm": float(torch.linalg.norm(phi_t.grad))}
 
 
 def closest_point_figures(torch, vpp, W, dev):
