@@ -308,9 +308,29 @@ def closest_point_figures(torch, vpp, W, dev):
     us = e0.elapsed_time(e1) * 1e3 / reps
     band = info >= 0
     nb = int(band.sum())
-    return {"cp_band_points": nb, "cp_us": us, "cp_mpoints_per_s": nb / us,
-            "cp_converged_fraction": float((info > 0).sum()) / max(nb, 1),
-            "cp_mean_outer_steps": float(info[info > 0].double().mean())}
+    out = {"cp_band_points": nb, "cp_us": us, "cp_mpoints_per_s": nb / us,
+           "cp_converged_fraction": float((info > 0).sum()) / max(nb, 1),
+           "cp_mean_outer_steps": float(info[info > 0].double().mean())}
+    # the same band with the filtered normal (eta = 2) as the normal of the corrections
+    n = wl.mesh.ncells[0]
+    filt = 2.0 / n ** 2
+    mf = W.Mesh(ncells=wl.mesh.ncells, degree=2, bc=(1,) * 6, rho_l=1 / filt, rho_g=1 / filt)
+    pf = vpp.Problem.from_mesh(mf)
+    pf.set_phi(torch.zeros(mf.ndofs, dtype=torch.float64, device=dev))
+    pf.set_mass(1.0)
+    comps = [pf.cg_solve(b, rtol=1e-12, atol=1e-20)[0] for b in pf.normal_rhs(torch.from_numpy(wl.phi).to(dev))]
+    y, info = p.closest_points(eps, normal=comps)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y, info = p.closest_points(eps, normal=comps)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    out.update({"cp_filtered_normal_us": us,
+                "cp_filtered_normal_converged_fraction": float((info > 0).sum()) / max(nb, 1),
+                "cp_filtered_normal_mean_outer_steps": float(info[info > 0].double().mean())})
+    return out
 
 
 def c2_figures(torch, vpp, W, dev, cache):

@@ -195,6 +195,18 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
 vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* opts,
                               double* y, int32_t* info, void* stream);
 
+/* The same projection with the interface normal n_Gamma of Eq. cpp taken as
+ * the paper defines it, the filtered normal of Eq. normal_vector_regularized:
+ * n(y) = n_h(y)/|n_h(y)| for the nodal field (n0, n1, n2) (N entries each,
+ * FP64 device pointers; typically the three solutions of the normal filter
+ * system, vpp_set_mass and vpp_normal_rhs).  n_h is continuous across cell
+ * faces, so far fewer points cycle than with the gradient of phi_h.  phi_h
+ * still gives the distance of Eq. distance.  Errors and outputs as for
+ * vpp_closest_points; VPP_ERR_INVALID_ARG if a component is NULL. */
+vpp_status vpp_closest_points_normal(vpp_problem p, const double* pts, int64_t n, const double* n0,
+                                     const double* n1, const double* n2, const vpp_cp_opts* opts,
+                                     double* y, int32_t* info, void* stream);
+
 /* Right-hand sides of the level-set filter systems (vpp_set_mass), assembled
  * on every row of the problem's mesh with its (k+1)^3 Gauss rule, no
  * constraint applied:

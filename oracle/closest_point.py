@@ -20,7 +20,12 @@ gradient at an arbitrary point come from the Q_k Lagrange basis on the GLL
 support points of the cell holding the point (product formula).  Readings
 where the appendix is silent: y is clipped to the domain box after every
 correction; phi_h is clipped to +-(1 - 1e-12) inside the logarithm; a step
-whose gradient vanishes leaves y unchanged.
+whose normal vanishes leaves y unchanged.
+
+The normal n_Gamma of Eq. cpp is the filtered interface normal of Eq.
+normal_vector_regularized.  With a nodal normal field given (`normal`, three
+arrays), n(y) = n_h(y)/|n_h(y)| with n_h its Q_k interpolant; without it n is
+the normalised gradient of phi_h (the unfiltered normal of Eq. normal_vector).
 """
 from __future__ import annotations
 
@@ -86,11 +91,25 @@ def evaluate(mesh, phi: np.ndarray, pts: np.ndarray):
     return val, grad
 
 
+def _unit_normal(mesh, phi, normal, y):
+    """phi_h(y), the unit normal at y (P, 3) and where it is defined (P,)."""
+    val, grad = evaluate(mesh, phi, y)
+    if normal is not None:
+        grad = np.stack([evaluate(mesh, normal[d], y)[0] for d in range(3)], axis=1)
+    gn = np.linalg.norm(grad, axis=1)
+    ok = gn > 0
+    n = np.where(ok[:, None], grad / np.where(ok, gn, 1.0)[:, None], 0.0)
+    return val, n, ok
+
+
 def closest_points(mesh, phi, pts, eps: float, max_iter: int = 20, normal_steps: int = 3,
-                   tol: float = 1e-12):
+                   tol: float = 1e-12, normal=None):
     """Closest points y (P, 3) of pts on {phi_h = 0}, the outer steps taken (P,)
-    and whether |y^(k+1) - y^(k)| < tol was reached (P,)."""
+    and whether |y^(k+1) - y^(k)| < tol was reached (P,).  normal: None (the
+    gradient of phi_h) or three nodal fields of the filtered normal."""
     phi = np.asarray(phi, dtype=np.float64)
+    if normal is not None:
+        normal = [np.asarray(c, dtype=np.float64) for c in normal]
     x = np.array(pts, dtype=np.float64).reshape(-1, 3)
     lo = np.asarray(mesh.origin, dtype=np.float64)
     hi = lo + np.asarray(mesh.extent, dtype=np.float64)
@@ -104,17 +123,11 @@ def closest_points(mesh, phi, pts, eps: float, max_iter: int = 20, normal_steps:
         ya = y[act]
         prev = ya.copy()
         for _ in range(normal_steps):
-            val, grad = evaluate(mesh, phi, ya)
-            gn = np.linalg.norm(grad, axis=1)
-            ok = gn > 0
-            n = np.where(ok[:, None], grad / np.where(ok, gn, 1.0)[:, None], 0.0)
+            val, n, ok = _unit_normal(mesh, phi, normal, ya)
             pc = np.clip(val, -_PHI_CLIP, _PHI_CLIP)
             dist = eps * np.log((1.0 + pc) / (1.0 - pc))
             ya = np.clip(ya - np.where(ok, dist, 0.0)[:, None] * n, lo, hi)
-        _, grad = evaluate(mesh, phi, ya)
-        gn = np.linalg.norm(grad, axis=1)
-        ok = gn > 0
-        n = np.where(ok[:, None], grad / np.where(ok, gn, 1.0)[:, None], 0.0)
+        _, n, ok = _unit_normal(mesh, phi, normal, ya)
         v = np.zeros_like(n)
         use_y = np.abs(n[:, 0]) > 0.9
         v[~use_y, 0] = 1.0

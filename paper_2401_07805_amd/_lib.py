@@ -66,6 +66,7 @@ def load() -> C.CDLL:
         "vpp_set_phi": (C.c_int, [vp, vp, vp]),
         "vpp_set_mass": (C.c_int, [vp, C.c_double, vp]),
         "vpp_closest_points": (C.c_int, [vp, vp, C.c_int64, C.POINTER(CpOpts), vp, vp, vp]),
+        "vpp_closest_points_normal": (C.c_int, [vp, vp, C.c_int64, vp, vp, vp, C.POINTER(CpOpts), vp, vp, vp]),
         "vpp_extend": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vpp_normal_rhs": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vpp_reinit_step": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, C.POINTER(CgInfo), vp]),

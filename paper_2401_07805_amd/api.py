@@ -104,12 +104,19 @@ class Problem:
         self._phi_version += 1
 
     def closest_points(self, eps: float, pts: Optional[torch.Tensor] = None, phi_lim: float = 0.9,
-                       tol: float = 1e-11, max_iter: int = 50, normal_steps: int = 3):
+                       tol: float = 1e-11, max_iter: int = 50, normal_steps: int = 3,
+                       normal: Optional[Sequence[torch.Tensor]] = None):
         """Closest points on {phi_h = 0} (vpp_closest_points).  pts: (P, 3) float64
         on the device, or None for the narrow band |phi| < phi_lim of the mesh
-        nodes.  Returns (y (P, 3), info (P,) int32: outer steps to convergence,
+        nodes.  normal: three nodal fields (the filtered normal) to take the
+        normal from (vpp_closest_points_normal), or None for the gradient of
+        phi_h.  Returns (y (P, 3), info (P,) int32: outer steps to convergence,
         0 not converged, -1 outside the band)."""
         o = L.CpOpts(float(eps), float(phi_lim), float(tol), int(max_iter), int(normal_steps))
+        if normal is not None:
+            if len(normal) != 3:
+                raise ValueError("normal must hold three nodal fields")
+            nptr = [_vec(c, self.n, torch.float64, self.device, "normal") for c in normal]
         if pts is None:
             n, ptr = self.n, None
         else:
@@ -122,8 +129,13 @@ class Problem:
                         torch.empty(0, dtype=torch.int32, device=self.device))
         y = torch.empty((n, 3), dtype=torch.float64, device=self.device)
         info = torch.empty(n, dtype=torch.int32, device=self.device)
-        _check(L.load().vpp_closest_points(self._h, ptr, n, C.byref(o), C.c_void_p(y.data_ptr()),
-                                           C.c_void_p(info.data_ptr()), _stream(self.device)))
+        if normal is None:
+            _check(L.load().vpp_closest_points(self._h, ptr, n, C.byref(o), C.c_void_p(y.data_ptr()),
+                                               C.c_void_p(info.data_ptr()), _stream(self.device)))
+        else:
+            _check(L.load().vpp_closest_points_normal(self._h, ptr, n, *nptr, C.byref(o),
+                                                      C.c_void_p(y.data_ptr()), C.c_void_p(info.data_ptr()),
+                                                      _stream(self.device)))
         return y, info
 
     def extend(self, y: torch.Tensor, info: torch.Tensor, f: torch.Tensor) -> torch.Tensor:

@@ -878,8 +878,8 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
     return VPP_OK;
 }
 
-vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* o, double* y,
-                              int32_t* info, void* stream)
+static vpp_status closest_points(vpp_problem p, const double* pts, int64_t n, const double* const nrm[3],
+                                 const vpp_cp_opts* o, double* y, int32_t* info, void* stream)
 {
     if (!p || !o || !y || !info) return fail(VPP_ERR_INVALID_ARG, "null argument");
     if (pts && n < 0) return fail(VPP_ERR_INVALID_ARG, "n must be >= 0");
@@ -900,6 +900,7 @@ vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const
         a.h[d] = p->desc.extent[d] / p->desc.ncells[d];
     }
     a.phi = p->phi64;
+    for (int d = 0; d < 3; ++d) a.nrm[d] = nrm ? nrm[d] : nullptr;
     a.pts = pts;
     a.n = pts ? n : p->N;
     a.phi_lim = o->phi_lim;
@@ -914,6 +915,21 @@ vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const
     if (!pts && !p->cp_list && (st = dev_alloc(&p->cp_list, (size_t)p->N, "closest-point band list"))) return st;
     VPP_HIP(launch_closest_points(p->k, a, p->cp_list, p->cp_ctr, closest_point_blocks(p->k), (hipStream_t)stream));
     return VPP_OK;
+}
+
+vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* o, double* y,
+                              int32_t* info, void* stream)
+{
+    return closest_points(p, pts, n, nullptr, o, y, info, stream);
+}
+
+vpp_status vpp_closest_points_normal(vpp_problem p, const double* pts, int64_t n, const double* n0,
+                                     const double* n1, const double* n2, const vpp_cp_opts* o, double* y,
+                                     int32_t* info, void* stream)
+{
+    if (!n0 || !n1 || !n2) return fail(VPP_ERR_INVALID_ARG, "null normal component");
+    const double* const nrm[3] = {n0, n1, n2};
+    return closest_points(p, pts, n, nrm, o, y, info, stream);
 }
 
 vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const double* f, double* out,

@@ -12,12 +12,17 @@
 // t_0 = (v - (v.n) n)/|.| and t_1 = n x t_0 (v = e_x, or e_y when |n_x| > 0.9),
 // until |y^(k+1) - y^(k)| < tol or max_iter outer steps.  y is clipped to the
 // domain box after every correction, phi_h to +-(1 - 1e-12) inside the
-// logarithm, and a step whose gradient vanishes leaves y unchanged.
+// logarithm, and a step whose normal vanishes leaves y unchanged.  With a
+// nodal normal field given (the filtered interface normal of Eq.
+// normal_vector_regularized, which is the n of Eq. cpp), n = n_h(y)/|n_h(y)|
+// replaces the normalised gradient: n_h is continuous across cell faces,
+// where the gradient of phi_h jumps.
 //
-// phi_h and its gradient at y come from the Q_k Lagrange basis on the GLL
+// phi_h, its gradient and n_h at y come from the Q_k Lagrange basis on the GLL
 // support points of the cell holding y (values and derivatives by the product
-// formula at the point's reference coordinates; (k+1)^3 nodal loads).  Every
-// cell index is clamped into the mesh (NaN-safe), so no load leaves phi.
+// formula at the point's reference coordinates; (k+1)^3 nodal loads per
+// field).  Every cell index is clamped into the mesh (NaN-safe), so no load
+// leaves the nodal arrays.
 #include "common.h"
 #include "kernels.h"
 
@@ -48,13 +53,13 @@ __device__ __forceinline__ void lagrange_at(double t, double (&V)[K + 1], double
     }
 }
 
-// Value and gradient at y of the nodal field f (phi or any Q_k field of the mesh).
+// Cell of y (clamped into the mesh), Lagrange values V and physical
+// derivatives D at y's reference coordinates; returns the cell's first node.
 template <int K>
-__device__ __forceinline__ void eval_field(const CpArgs& a, const double* __restrict__ f, const double (&y)[3],
-                                           double& val, double (&g)[3])
+__device__ __forceinline__ int64_t locate(const CpArgs& a, const double (&y)[3], double (&V)[3][K + 1],
+                                          double (&D)[3][K + 1])
 {
     constexpr int N = K + 1;
-    double V[3][N], D[3][N];
     int c[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -69,8 +74,18 @@ __device__ __forceinline__ void eval_field(const CpArgs& a, const double* __rest
 #pragma unroll
         for (int i = 0; i < N; ++i) D[d][i] *= ih;
     }
+    return node_index(a.m, (int64_t)K * c[0], (int64_t)K * c[1], (int64_t)K * c[2]);
+}
+
+// Value and gradient at y of the nodal field f (phi or any Q_k field of the mesh).
+template <int K>
+__device__ __forceinline__ void eval_field(const CpArgs& a, const double* __restrict__ f, const double (&y)[3],
+                                           double& val, double (&g)[3])
+{
+    constexpr int N = K + 1;
+    double V[3][N], D[3][N];
     const int64_t nx = a.m.nn[0], nxy = (int64_t)a.m.nn[0] * a.m.nn[1];
-    const double* p = f + node_index(a.m, (int64_t)K * c[0], (int64_t)K * c[1], (int64_t)K * c[2]);
+    const double* p = f + locate<K>(a, y, V, D);
     val = 0.0;
     g[0] = g[1] = g[2] = 0.0;
 #pragma unroll
@@ -85,6 +100,47 @@ __device__ __forceinline__ void eval_field(const CpArgs& a, const double* __rest
                 g[1] += V[0][a0] * D[1][a1] * V[2][a2] * fv;
                 g[2] += V[0][a0] * V[1][a1] * D[2][a2] * fv;
             }
+}
+
+// Values at y of phi_h and of the nodal normal field's three components.
+template <int K>
+__device__ __forceinline__ void eval_phi_normal(const CpArgs& a, const double (&y)[3], double& val,
+                                                double (&nv)[3])
+{
+    constexpr int N = K + 1;
+    double V[3][N], D[3][N];
+    const int64_t nx = a.m.nn[0], nxy = (int64_t)a.m.nn[0] * a.m.nn[1];
+    const int64_t base = locate<K>(a, y, V, D);
+    val = 0.0;
+    nv[0] = nv[1] = nv[2] = 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 < N; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0) {
+                const int64_t i = base + a0 + nx * a1 + nxy * a2;
+                const double w = V[0][a0] * V[1][a1] * V[2][a2];
+                val += w * a.phi[i];
+                nv[0] += w * a.nrm[0][i];
+                nv[1] += w * a.nrm[1][i];
+                nv[2] += w * a.nrm[2][i];
+            }
+}
+
+// phi_h(y) and the unit normal at y (the normalised gradient of phi_h, or of
+// the nodal normal field when one is given); false where that vector vanishes.
+template <int K>
+__device__ __forceinline__ bool normal_at(const CpArgs& a, const double (&y)[3], double& val, double (&n)[3])
+{
+    double g[3];
+    if (a.nrm[0]) eval_phi_normal<K>(a, y, val, g);
+    else eval_field<K>(a, a.phi, y, val, g);
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (!(gn > 0.0)) return false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) n[d] = g[d] / gn;
+    return true;
 }
 
 __device__ __forceinline__ void clip_box(const CpArgs& a, double (&y)[3])
@@ -117,22 +173,17 @@ template <int K>
 __device__ __forceinline__ bool outer_step(const CpArgs& a, const double (&x)[3], double (&y)[3])
 {
     const double prev[3] = {y[0], y[1], y[2]};
-    double val, g[3];
+    double val, n[3];
     for (int s = 0; s < a.normal_steps; ++s) {
-        eval_field<K>(a, a.phi, y, val, g);
-        const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-        if (gn > 0.0) {
+        if (normal_at<K>(a, y, val, n)) {
             const double pc = fmin(fmax(val, -kPhiClip), kPhiClip);
             const double dist = a.eps * log((1.0 + pc) / (1.0 - pc));
 #pragma unroll
-            for (int d = 0; d < 3; ++d) y[d] -= dist * (g[d] / gn);
+            for (int d = 0; d < 3; ++d) y[d] -= dist * n[d];
             clip_box(a, y);
         }
     }
-    eval_field<K>(a, a.phi, y, val, g);
-    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-    if (gn > 0.0) {
-        const double n[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+    if (normal_at<K>(a, y, val, n)) {
         const bool use_y = fabs(n[0]) > 0.9;
         const double v[3] = {use_y ? 0.0 : 1.0, use_y ? 1.0 : 0.0, 0.0};
         const double vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];

@@ -96,6 +96,7 @@ struct CpArgs {
     MeshArgs m;
     double lo[3], hi[3], h[3];   // domain box and cell size
     const double* phi;           // nodal phi (N)
+    const double* nrm[3];        // nodal normal field (N each), or null: the gradient of phi_h
     const double* pts;           // n points, xyz interleaved; null: the N mesh nodes
     int64_t n;
     double phi_lim;              // band of the node mode: |phi_g| < phi_lim

@@ -135,3 +135,95 @@ def test_full_size_band_sample():
     both = do & (info[s] > 0)
     assert both.mean() > 0.9
     assert np.linalg.norm(y[s][both] - yo[both], axis=1).max() < 1e-9
+
+
+def _oracle_filtered_normal(m, phi, eta=2.0):
+    """Inputs for both sides: the three solutions of the oracle's normal filter
+    (M + eta h^2 K) n = (grad phi_h/|grad phi_h|, v), pure Neumann."""
+    filt = eta / m.ncells[0] ** 2
+    mf = W.Mesh(ncells=m.ncells, degree=m.degree, bc=(1,) * 6, rho_l=1 / filt, rho_g=1 / filt, mass=1.0)
+    op = oracle.Operator(mf, phi=np.zeros(mf.ndofs), constrained=False)
+    xq, yq, zq, _ = oracle.qp_coords(m)
+    _, g = evaluate(m, phi, np.stack([xq, yq, zq], 1))
+    nb = g / np.linalg.norm(g, axis=1)[:, None]
+    return [op.pcg(oracle.rhs_qp(m, nb[:, d]), rtol=1e-12)[0] for d in range(3)]
+
+
+@pytest.mark.parametrize("n,k", [(12, 2), (7, 3), (5, 4)])
+def test_band_with_the_filtered_normal_matches_oracle(n, k):
+    """vpp_closest_points_normal against the oracle with the same nodal normal
+    field; with the continuous normal nearly every point converges on both sides."""
+    eps = 0.05
+    m = W.unit_cube(n, k, 1000.0, 1.0, bc=(1,) * 6)
+    phi = W.droplet_phi(m, 0.3, eps, centre=(0.48, 0.51, 0.5))
+    nf = _oracle_filtered_normal(m, phi)
+    prob = _problem(m, phi)
+    say("closest points band, filtered normal", n, k)
+    y, info = prob.closest_points(eps, phi_lim=0.6, tol=1e-11, max_iter=50, normal=[dev(c) for c in nf])
+    y, info = y.cpu().numpy(), info.cpu().numpy()
+    idx = oracle.band_nodes(m, phi, 0.6)
+    out = np.setdiff1d(np.arange(m.ndofs), idx)
+    assert (info[out] == -1).all() and (info[idx] >= 0).all()
+    x = oracle.node_coords(m, idx)
+    yo, so, do = oracle.closest_points(m, phi, x, eps, max_iter=50, tol=1e-11, normal=nf)
+    yg, ig = y[idx], info[idx]
+    both = do & (ig > 0)
+    print(n, k, len(idx), "converged oracle", do.mean(), "gpu", (ig > 0).mean(), "both", both.mean())
+    assert both.mean() > 0.95
+    assert np.linalg.norm(yg[both] - yo[both], axis=1).max() < 1e-9
+    assert np.abs(ig[both] - so[both]).max() <= 1
+    rest = ~both
+    if rest.any():
+        assert np.linalg.norm(yg[rest] - yo[rest], axis=1).max() < 5e-3
+
+
+def test_points_mode_with_a_normal_field_and_errors():
+    """Caller's points with a constant normal field on a planar interface
+    (closest point (x0, y, z)), and the argument checks of the normal entry point."""
+    import ctypes
+    from paper_2401_07805_amd import _lib as L
+    m = W.unit_cube(6, 2, 1000.0, 1.0, bc=(1,) * 6)
+    eps = 0.1
+    phi = W.slab_phi(m, 0.5, eps)
+    prob = _problem(m, phi)
+    rng = np.random.default_rng(3)
+    pts = rng.uniform([0.3, 0.0, 0.0], [0.7, 1.0, 1.0], size=(500, 3))
+    nf = [dev(np.full(m.ndofs, -1.0)), dev(np.zeros(m.ndofs)), dev(np.zeros(m.ndofs))]
+    y, info = prob.closest_points(eps, pts=dev(pts), tol=1e-13, normal=nf)
+    y, info = y.cpu().numpy(), info.cpu().numpy()
+    ref = pts.copy()
+    ref[:, 0] = 0.5
+    assert (info > 0).all()
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12)
+    with pytest.raises(ValueError):
+        prob.closest_points(eps, normal=nf[:2])
+    o = L.CpOpts(eps, 0.9, 1e-11, 50, 3)
+    yb = torch.empty((m.ndofs, 3), dtype=torch.float64, device="cuda")
+    ib = torch.empty(m.ndofs, dtype=torch.int32, device="cuda")
+    st = L.load().vpp_closest_points_normal(prob._h, None, 0, ctypes.c_void_p(nf[0].data_ptr()), None,
+                                            ctypes.c_void_p(nf[2].data_ptr()), ctypes.byref(o),
+                                            ctypes.c_void_p(yb.data_ptr()), ctypes.c_void_p(ib.data_ptr()), None)
+    assert st == 1 and b"normal" in L.load().vpp_last_error()
+
+
+def test_full_size_band_with_a_continuous_normal():
+    """The 64^3 Q2 droplet's band with the droplet's exact (continuous) normal
+    field as the nodal normal: a sample of 2000 band nodes against the oracle."""
+    wl = W.droplet_at_scale(k=2, nvec=0)
+    m = wl.mesh
+    nf = W.normal_field(m)
+    prob = _problem(m, wl.phi)
+    say("full size band, continuous normal")
+    y, info = prob.closest_points(m.eps, normal=[dev(c) for c in nf])
+    y, info = y.cpu().numpy(), info.cpu().numpy()
+    idx = oracle.band_nodes(m, wl.phi, 0.9)
+    assert (info[idx] >= 0).all() and (info >= 0).sum() == len(idx)
+    print("converged", (info[idx] > 0).mean())
+    assert (info[idx] > 0).mean() > 0.99
+    rng = np.random.default_rng(18)
+    s = np.sort(rng.choice(idx, 2000, replace=False))
+    yo, so, do = oracle.closest_points(m, wl.phi, oracle.node_coords(m, s), m.eps, max_iter=50, tol=1e-11,
+                                       normal=nf)
+    both = do & (info[s] > 0)
+    assert both.mean() > 0.98
+    assert np.linalg.norm(y[s][both] - yo[both], axis=1).max() < 1e-9

@@ -88,3 +88,62 @@ def test_converged_points_satisfy_the_definition():
     d = x[done] - y[done]
     cross = np.linalg.norm(np.cross(d, nrm), axis=1)
     assert (cross < 1e-9 + 1e-9 * np.linalg.norm(d, axis=1)).all()
+
+
+# ---------------------------------------------------------------------------
+# The normal taken from a nodal normal field (n_Gamma of Eq. cpp is the
+# filtered normal of Eq. normal_vector_regularized).
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_plane_with_a_constant_normal_field(k):
+    """phi(x) only, normal field a positive multiple of grad phi's direction
+    (-e_x): the closest point of (x, y, z) is (x0, y, z), whatever the scale."""
+    m = W.unit_cube(8, k, 1000.0, 1.0, bc=(1,) * 6)
+    eps = 0.1
+    phi = W.slab_phi(m, 0.5, eps)
+    idx = oracle.band_nodes(m, phi, 0.95)
+    x = oracle.node_coords(m, idx)
+    nf = [np.full(m.ndofs, -2.5), np.zeros(m.ndofs), np.zeros(m.ndofs)]
+    y, steps, done = oracle.closest_points(m, phi, x, eps, tol=1e-13, normal=nf)
+    assert done.all() and steps.max() <= 3
+    ref = x.copy()
+    ref[:, 0] = 0.5
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12)
+
+
+def _filtered_normal(m, phi, eta=2.0):
+    """The three solutions of (M + eta h^2 K) n = (grad phi_h/|grad phi_h|, v),
+    pure Neumann, by the oracle's assembly and PCG."""
+    n = m.ncells[0]
+    filt = eta / n ** 2
+    mf = W.Mesh(ncells=m.ncells, degree=m.degree, bc=(1,) * 6, rho_l=1 / filt, rho_g=1 / filt, mass=1.0)
+    op = oracle.Operator(mf, phi=np.zeros(mf.ndofs), constrained=False)
+    xq, yq, zq, _ = oracle.qp_coords(m)
+    _, g = evaluate(m, phi, np.stack([xq, yq, zq], 1))
+    nb = g / np.linalg.norm(g, axis=1)[:, None]
+    return [op.pcg(oracle.rhs_qp(m, nb[:, d]), rtol=1e-12)[0] for d in range(3)]
+
+
+def test_sphere_with_the_filtered_normal():
+    """Droplet at 12^3 Q2: with the continuous filtered normal more points
+    converge than with the C0 gradient, and every converged point satisfies
+    the definition with that normal: phi_h(y) = 0 and x - y parallel to n_h(y)."""
+    eps = 0.05
+    m = W.unit_cube(12, 2, 1000.0, 1.0, bc=(1,) * 6)
+    phi = W.droplet_phi(m, 0.3, eps)
+    nf = _filtered_normal(m, phi)
+    idx = oracle.band_nodes(m, phi, 0.6)
+    x = oracle.node_coords(m, idx)
+    y, steps, done = oracle.closest_points(m, phi, x, eps, max_iter=50, tol=1e-11, normal=nf)
+    _, _, done_g = oracle.closest_points(m, phi, x, eps, max_iter=50, tol=1e-11)
+    assert done.mean() > done_g.mean() and done.mean() > 0.95, (done.mean(), done_g.mean())
+    val, _ = evaluate(m, phi, y[done])
+    assert np.abs(val).max() < 1e-10
+    nv = np.stack([evaluate(m, nf[d], y[done])[0] for d in range(3)], 1)
+    nv /= np.linalg.norm(nv, axis=1)[:, None]
+    d = x[done] - y[done]
+    cross = np.linalg.norm(np.cross(d, nv), axis=1)
+    assert (cross < 1e-9 + 1e-9 * np.linalg.norm(d, axis=1)).all()
+    # and the points lie on the sphere to the interpolation error of phi_h
+    r = np.linalg.norm(y[done] - 0.5, axis=1)
+    assert np.abs(r - 0.3).max() < 2e-3
