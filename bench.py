@@ -34,6 +34,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 BYTES_PER_DOF_F64 = 24.0      # x read, phi read, y written once per DoF
+# Vector bytes per DoF of one FP64 PCG iteration as the three launches move
+# them: the apply (p, phi read; q written: 24), the assembly + update (q, r,
+# 1/diag read; r written: 32) and the x / p update (r, 1/diag, p, x read; p, x
+# written: 48); the shared-node partials and the scalar reductions not counted.
+CG_BYTES_PER_DOF_ITER_F64 = 104.0
 # FP64 operations of the Q2 cell kernel per cell (coefficient: 3 value sweeps
 # and the material law; operator: 3 value sweeps, 3 collocation-derivative
 # line pairs with the Gauss-point scaling, 3 transposed value sweeps), counted
@@ -106,16 +111,26 @@ def cpu_baseline():
         op.matvec(x)
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    ts1 = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        op.matvec(x)
+        ts1.append(time.perf_counter() - t0)
+    oracle.set_num_threads(threads)
+    t1 = float(np.median(ts1))
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": m.ndofs / t / 1e6, "unit": "MDoF/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "cpu_model": model,
+    return {"value": m.ndofs / t / 1e6, "unit": "MDoF/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": m.ndofs / t1 / 1e6, "cpu_model": model,
             "sample": f"FP64 CSR SpMV, median of 10 after 2 warm-ups, droplet 32^3 cells Q2 "
-                      f"({m.ndofs} DoFs, nnz {op.nnz}); assembly {t_asm:.2f} s not included"}
+                      f"({m.ndofs} DoFs, nnz {op.nnz}); assembly {t_asm:.2f} s not included; "
+                      f"value_1_thread: median of 3 on one thread"}
 
 
 def timed_applies(torch, probs, xs, ys, napp, stream, prec_tensor=None):
@@ -522,6 +537,12 @@ def main():
     }
     if traffic is not None:
         out["roofline"]["traffic_bytes_per_apply"] = traffic
+    it64 = max(out["cg_fp64_iters"], 1)
+    t_it = out["cg_fp64_s"] / it64
+    out["cg_fp64_us_per_iter"] = t_it * 1e6
+    out["cg_fp64_bytes_per_dof_iter"] = CG_BYTES_PER_DOF_ITER_F64
+    out["cg_fp64_effective_gbs"] = CG_BYTES_PER_DOF_ITER_F64 * N / t_it / 1e9
+    out["cg_mixed_us_per_fp32_iter"] = out["cg_mixed_s"] / max(out["cg_mixed_fp32_iters"], 1) * 1e6
     ncells = m.ncells[0] * m.ncells[1] * m.ncells[2]
     tflops = FLOPS_PER_CELL_Q2 * ncells / per_apply / 1e12
     out["valu"] = {"achieved": tflops, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",

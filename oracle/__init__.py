@@ -78,6 +78,7 @@ def _load():
         "orc_grad_coef": (None, [P, _D, _D, _D]),
         "orc_grad_phi": (None, [P, _D, _D, _D]),
         "orc_num_threads": (C.c_int, []),
+        "orc_set_num_threads": (None, [C.c_int]),
         "orc_apply_rows": (None, [P, _D, _D, C.POINTER(C.c_int64), C.c_int64, _D]),
     }
     for name, (res, args) in sig.items():
@@ -115,6 +116,11 @@ def desc_of(mesh) -> _Desc:
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (n > 0)."""
+    _load().orc_set_num_threads(int(n))
 
 
 # -- 1D tables ----------------------------------------------------------------

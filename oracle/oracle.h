@@ -98,6 +98,7 @@ void orc_apply_rows(const orc_desc* d, const double* phi, const double* x, const
                     int64_t nrows, double* out);
 
 int orc_num_threads(void);
+void orc_set_num_threads(int n);                               /* n > 0; later calls only */
 
 #ifdef __cplusplus
 }
