@@ -155,6 +155,17 @@ __device__ __forceinline__ void normal_at_gauss(const ReinitArgs& r, int cx, int
     }
 }
 
+// One nodal normal component at the Gauss points of a cell.
+template <int K, int D>
+__device__ __forceinline__ void normal_comp_at_gauss(const ReinitArgs& r, int cx, int cy, int cz,
+                                                     double (&nd)[(K + 1) * (K + 1) * (K + 1)])
+{
+    load_nodes<K>(r.g.m, D == 0 ? r.n0 : (D == 1 ? r.n1 : r.n2), cx, cy, cz, nd);
+    sweep3<K, MS, false, 0>(nd);
+    sweep3<K, MS, false, 1>(nd);
+    sweep3<K, MS, false, 2>(nd);
+}
+
 template <int K, int D>
 __device__ __forceinline__ void add_directional(const double (&u)[(K + 1) * (K + 1) * (K + 1)],
                                                 const double (&n)[(K + 1) * (K + 1) * (K + 1)], double ih,
@@ -195,26 +206,33 @@ __global__ void __launch_bounds__(64) reinit_apply_kernel(ReinitArgs r, const do
     if (cell >= ncell) return;
     const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
               cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
-    double nq[3][N3], u[N3], s[N3], out[N3];
-    normal_at_gauss<K>(r, cx, cy, cz, nq);
+    // One normal component is live at a time (interpolated again for the
+    // flux pass): holding all three at the Gauss points left one wave per SIMD.
+    double u[N3], s[N3], out[N3], nd[N3];
     load_nodes<K>(m, x, cx, cy, cz, u);
     sweep3<K, MS, false, 0>(u);
     sweep3<K, MS, false, 1>(u);
     sweep3<K, MS, false, 2>(u);
 #pragma unroll
     for (int q = 0; q < N3; ++q) s[q] = 0.0;
-    add_directional<K, 0>(u, nq[0], r.g.ih[0], s);
-    add_directional<K, 1>(u, nq[1], r.g.ih[1], s);
-    add_directional<K, 2>(u, nq[2], r.g.ih[2], s);
+    normal_comp_at_gauss<K, 0>(r, cx, cy, cz, nd);
+    add_directional<K, 0>(u, nd, r.g.ih[0], s);
+    normal_comp_at_gauss<K, 1>(r, cx, cy, cz, nd);
+    add_directional<K, 1>(u, nd, r.g.ih[1], s);
+    normal_comp_at_gauss<K, 2>(r, cx, cy, cz, nd);
+    add_directional<K, 2>(u, nd, r.g.ih[2], s);
 #pragma unroll
     for (int q = 0; q < N3; ++q) {
         const double w = r.g.vol * wref<K>(q % N, (q / N) % N, q / (N * N));
         out[q] = r.idtau * w * u[q];
         s[q] *= r.eps * w;
     }
-    add_flux<K, 0>(s, nq[0], r.g.ih[0], out);
-    add_flux<K, 1>(s, nq[1], r.g.ih[1], out);
-    add_flux<K, 2>(s, nq[2], r.g.ih[2], out);
+    normal_comp_at_gauss<K, 0>(r, cx, cy, cz, nd);
+    add_flux<K, 0>(s, nd, r.g.ih[0], out);
+    normal_comp_at_gauss<K, 1>(r, cx, cy, cz, nd);
+    add_flux<K, 1>(s, nd, r.g.ih[1], out);
+    normal_comp_at_gauss<K, 2>(r, cx, cy, cz, nd);
+    add_flux<K, 2>(s, nd, r.g.ih[2], out);
     transpose_interp<K>(out);
     scatter_add<K>(m, cx, cy, cz, out, y);
 }
