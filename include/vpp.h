@@ -188,8 +188,9 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
  * narrow band of the mesh's support points: then n is ignored, the outputs
  * have vpp_num_dofs entries and node g is projected iff |phi_g| < phi_lim.
  * y: 3 entries per point (xyz); info: outer steps to convergence, 0 when
- * max_iter steps did not converge (y is the last iterate; the C0 normal field
- * jumps across cell faces, so points projecting onto a face can cycle), -1
+ * max_iter steps did not converge (y is the last iterate; the gradient of
+ * phi_h jumps across cell faces, so points projecting onto a face can cycle;
+ * vpp_closest_points_normal, with a continuous normal, avoids this), -1
  * for a node outside the band (y = x).  Needs vpp_set_phi; VPP_ERR_UNSUPPORTED
  * for more than 2^31 - 2^24 points.  Asynchronous on `stream`. */
 vpp_status vpp_closest_points(vpp_problem p, const double* pts, int64_t n, const vpp_cp_opts* opts,
