@@ -1,5 +1,8 @@
-"""GPU closest-point projection (vpp_closest_points) against the oracle's
-(oracle/closest_point.py, the appendix's normal and tangential corrections).
+"""GPU closest-point projection (vpp_closest_points, and
+vpp_closest_points_normal with a nodal normal field) against the oracle's
+(oracle/closest_point.py, the appendix's normal and tangential corrections),
+on unit cubes for k = 2-4, an anisotropic box away from the origin, a planar
+interface and the full 64^3 band.
 
 Bar: the band selection is identical (integer); points that converge on both
 sides agree within 1e-9 (both stop once a step is below tol = 1e-11, and the
@@ -227,3 +230,38 @@ def test_full_size_band_with_a_continuous_normal():
     both = do & (info[s] > 0)
     assert both.mean() > 0.98
     assert np.linalg.norm(y[s][both] - yo[both], axis=1).max() < 1e-9
+
+
+@pytest.mark.parametrize("use_normal", [False, True])
+def test_anisotropic_offset_box_matches_oracle(use_normal):
+    """Cells of different widths per direction and a box not at the origin
+    (the 1/h_d of the gradient, the cell search from the origin, the clip to
+    the box), with the gradient of phi_h and with a filtered normal field."""
+    import dataclasses
+    eps = 0.05
+    m = W.Mesh(ncells=(10, 7, 9), degree=2, origin=(-0.1, 0.05, 0.0), extent=(1.2, 0.9, 1.0), bc=(1,) * 6)
+    phi = W.droplet_phi(m, 0.3, eps, centre=(0.5, 0.5, 0.5))
+    nf = None
+    if use_normal:
+        filt = 2.0 * max(m.h) ** 2
+        mf = dataclasses.replace(m, rho_l=1 / filt, rho_g=1 / filt, mass=1.0)
+        op = oracle.Operator(mf, phi=np.zeros(mf.ndofs), constrained=False)
+        xq, yq, zq, _ = oracle.qp_coords(m)
+        _, g = evaluate(m, phi, np.stack([xq, yq, zq], 1))
+        nb = g / np.linalg.norm(g, axis=1)[:, None]
+        nf = [op.pcg(oracle.rhs_qp(m, nb[:, d]), rtol=1e-12)[0] for d in range(3)]
+    prob = _problem(m, phi)
+    say("closest points anisotropic box, normal field" if use_normal else "closest points anisotropic box")
+    y, info = prob.closest_points(eps, phi_lim=0.6, tol=1e-11, max_iter=50,
+                                  normal=None if nf is None else [dev(c) for c in nf])
+    y, info = y.cpu().numpy(), info.cpu().numpy()
+    idx = oracle.band_nodes(m, phi, 0.6)
+    assert (info[idx] >= 0).all() and (info >= 0).sum() == len(idx)
+    x = oracle.node_coords(m, idx)
+    yo, so, do = oracle.closest_points(m, phi, x, eps, max_iter=50, tol=1e-11, normal=nf)
+    yg, ig = y[idx], info[idx]
+    both = do & (ig > 0)
+    print("converged oracle", do.mean(), "gpu", (ig > 0).mean(), "both", both.mean())
+    assert both.mean() > (0.95 if use_normal else 0.75)
+    assert np.linalg.norm(yg[both] - yo[both], axis=1).max() < 1e-9
+    assert np.abs(ig[both] - so[both]).max() <= 1
