@@ -18,7 +18,9 @@
  * Conventions for every entry point:
  *  - Vectors are device pointers on the problem's device, length N =
  *    prod_d (k n_d + 1), lexicographic node order with x fastest,
- *    g = i + Nx (j + Ny l).  The caller owns them.
+ *    g = i + Nx (j + Ny l).  The caller owns them.  Each must be aligned to
+ *    its element size (8 bytes for FP64, 4 for FP32 and int32), else
+ *    VPP_ERR_INVALID_ARG.
  *  - Dirichlet rows/columns: the operator is A_D = [A_II 0; 0 I] (identity on
  *    nodes of Dirichlet faces; their entries of x never reach free rows).
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls

@@ -6,9 +6,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <initializer_list>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -28,6 +30,20 @@ vpp_status fail(vpp_status s, const std::string& msg)
     g_err = msg;
     return s;
 }
+
+// True if a non-null caller vector is not aligned to its element size (a
+// caller's error: the kernels take whole elements).
+bool misaligned(size_t elem, std::initializer_list<const void*> ptrs)
+{
+    for (const void* q : ptrs)
+        if (q && reinterpret_cast<uintptr_t>(q) % elem != 0) return true;
+    return false;
+}
+#define VPP_ALIGNED(elem, ...)                                                                  \
+    do {                                                                                        \
+        if (misaligned((elem), {__VA_ARGS__}))                                                  \
+            return fail(VPP_ERR_INVALID_ARG, "vector not aligned to its element size");         \
+    } while (0)
 
 #define VPP_HIP(expr)                                                                           \
     do {                                                                                        \
@@ -766,6 +782,7 @@ int64_t vpp_num_qpoints(vpp_problem p) { return p ? p->NQ : -1; }
 vpp_status vpp_set_phi(vpp_problem p, const double* phi, void* stream)
 {
     if (!p || !phi) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, phi);
     DeviceGuard dg(p->desc.device);
     hipStream_t s = (hipStream_t)stream;
     VPP_HIP(hipMemcpyAsync(p->phi64, phi, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -805,6 +822,7 @@ vpp_status vpp_apply(vpp_problem p, int32_t prec, const void* x, void* y, void* 
     if (!p || !x || !y) return fail(VPP_ERR_INVALID_ARG, "null argument");
     if (x == y) return fail(VPP_ERR_INVALID_ARG, "x and y must not alias");
     if (prec != VPP_FP64 && prec != VPP_FP32) return fail(VPP_ERR_INVALID_ARG, "precision must be FP64 or FP32");
+    VPP_ALIGNED(prec == VPP_FP32 ? 4 : 8, x, y);
     if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
     DeviceGuard dg(p->desc.device);
     hipStream_t s = (hipStream_t)stream;
@@ -815,6 +833,7 @@ vpp_status vpp_apply(vpp_problem p, int32_t prec, const void* x, void* y, void* 
 vpp_status vpp_diagonal(vpp_problem p, double* diag, void* stream)
 {
     if (!p || !diag) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, diag);
     if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
     DeviceGuard dg(p->desc.device);
     VPP_HIP(hipMemcpyAsync(diag, p->diag, p->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
@@ -825,6 +844,7 @@ vpp_status vpp_cg_solve(vpp_problem p, const double* b, double* x, const vpp_cg_
                         void* stream)
 {
     if (!p || !b || !x || !opts) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, b, x);
     if (!(opts->rtol >= 0.0) || !(opts->atol >= 0.0) || opts->max_iter < 0)
         return fail(VPP_ERR_INVALID_ARG, "tolerances must be >= 0 and max_iter >= 0");
     if (opts->precision != VPP_FP64 && opts->precision != VPP_MIXED)
@@ -862,6 +882,7 @@ vpp_status vpp_cg_solve(vpp_problem p, const double* b, double* x, const vpp_cg_
 vpp_status vpp_grad_coef(vpp_problem p, const double* pv, const double* lam, double* g_q, void* stream)
 {
     if (!p || !pv || !lam || !g_q) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, pv, lam, g_q);
     DeviceGuard dg(p->desc.device);
     VPP_HIP(launch_grad_coef(p->k, p->m, pv, lam, g_q, (hipStream_t)stream));
     return VPP_OK;
@@ -870,6 +891,7 @@ vpp_status vpp_grad_coef(vpp_problem p, const double* pv, const double* lam, dou
 vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* stream)
 {
     if (!p || !g_q || !g_phi) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, g_q, g_phi);
     if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
     DeviceGuard dg(p->desc.device);
     hipStream_t s = (hipStream_t)stream;
@@ -882,6 +904,8 @@ static vpp_status closest_points(vpp_problem p, const double* pts, int64_t n, co
                                  const vpp_cp_opts* o, double* y, int32_t* info, void* stream)
 {
     if (!p || !o || !y || !info) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, pts, y, nrm ? nrm[0] : nullptr, nrm ? nrm[1] : nullptr, nrm ? nrm[2] : nullptr);
+    VPP_ALIGNED(4, info);
     if (pts && n < 0) return fail(VPP_ERR_INVALID_ARG, "n must be >= 0");
     if (!(o->eps > 0.0) || !std::isfinite(o->eps) || !(o->tol > 0.0) || !std::isfinite(o->tol) ||
         !(o->phi_lim > 0.0 && o->phi_lim <= 1.0) || o->max_iter < 1 || o->max_iter > 10000 ||
@@ -936,6 +960,8 @@ vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const
                       void* stream)
 {
     if (!p || !y || !info || !f || !out) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, y, f, out);
+    VPP_ALIGNED(4, info);
     if (f == out) return fail(VPP_ERR_INVALID_ARG, "f and out must not alias");
     DeviceGuard dg(p->desc.device);
     CpArgs a{};
@@ -968,6 +994,7 @@ static RhsGeo rhs_geometry(vpp_problem p)
 vpp_status vpp_normal_rhs(vpp_problem p, const double* phi, double* b0, double* b1, double* b2, void* stream)
 {
     if (!p || !phi || !b0 || !b1 || !b2) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, phi, b0, b1, b2);
     if (b0 == b1 || b0 == b2 || b1 == b2 || (const void*)phi == b0 || (const void*)phi == b1 ||
         (const void*)phi == b2)
         return fail(VPP_ERR_INVALID_ARG, "phi and the outputs must not alias");
@@ -980,6 +1007,7 @@ vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, 
                              void* stream)
 {
     if (!p || !n0 || !n1 || !n2 || !b) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, n0, n1, n2, b);
     if ((const void*)b == n0 || (const void*)b == n1 || (const void*)b == n2)
         return fail(VPP_ERR_INVALID_ARG, "the output must not alias an input");
     DeviceGuard dg(p->desc.device);
@@ -1016,6 +1044,7 @@ vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, c
                            const vpp_reinit_opts* o, double* psi_out, vpp_cg_info* info, void* stream)
 {
     if (!p || !psi || !n0 || !n1 || !n2 || !o || !psi_out) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, psi, n0, n1, n2, psi_out);
     if (!(o->eps > 0.0) || !std::isfinite(o->eps) || !(o->dtau > 0.0) || !std::isfinite(o->dtau) ||
         !(o->rtol >= 0.0) || !(o->atol >= 0.0) || o->max_iter < 0 || o->max_iter > 10000000)
         return fail(VPP_ERR_INVALID_ARG, "reinitialization options out of range");
@@ -1705,6 +1734,7 @@ vpp_status vpp_batch_apply(vpp_batch b, const double* const* x, double* const* y
     if (!b || !x || !y) return fail(VPP_ERR_INVALID_ARG, "null argument");
     for (int i = 0; i < b->total_rhs; ++i) {
         if (!x[i] || !y[i]) return fail(VPP_ERR_INVALID_ARG, "null vector in batch");
+        VPP_ALIGNED(8, x[i], y[i]);
         for (int j = 0; j < b->total_rhs; ++j)
             if ((const void*)x[i] == (const void*)y[j]) return fail(VPP_ERR_INVALID_ARG, "x and y must not alias");
     }
@@ -1732,6 +1762,7 @@ vpp_status vpp_batch_cg_solve(vpp_batch b, const double* const* rhs, double* con
         return fail(VPP_ERR_INVALID_ARG, "precision must be VPP_FP64 or VPP_MIXED");
     for (int i = 0; i < b->total_rhs; ++i)
         if (!rhs[i] || !x[i]) return fail(VPP_ERR_INVALID_ARG, "null vector in batch");
+    for (int i = 0; i < b->total_rhs; ++i) VPP_ALIGNED(8, rhs[i], x[i]);
     for (auto* p : b->probs)
         if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called for every problem");
     DeviceGuard dg(b->device);

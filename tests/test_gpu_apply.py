@@ -147,3 +147,48 @@ def test_full_size_sampled_rows_q3_q4(k):
     yr = oracle.apply_rows(m, wl.phi, x, rows)
     assert rel(y[rows], yr) < 1e-12
 
+
+
+def test_misaligned_vectors_are_rejected_before_any_launch():
+    """Caller vectors not aligned to their element size return
+    VPP_ERR_INVALID_ARG from the C ABI.  Every buffer holds one spare element,
+    so even a launch on the shifted pointer would stay inside it; an aligned
+    call afterwards still gives the same result as before."""
+    import ctypes
+    import torch
+    import paper_2401_07805_amd as vpp
+    from paper_2401_07805_amd import _lib as L
+    lib = L.load()
+    m = W.unit_cube(4, 2, 1000.0, 1.0)
+    m.eps = 0.5
+    n = m.ndofs
+    prob = vpp.Problem.from_mesh(m)
+    phi = W.droplet_phi(m, 0.3, m.eps)
+    prob.set_phi(dev(phi))
+    x = dev(W.uniform_vectors(0, 1, n)[0])
+    y_ref = host(prob.apply(x))
+    buf = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    out = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    b32 = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    o32 = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    y3 = torch.zeros(3 * n + 1, dtype=torch.float64, device="cuda")
+    inf = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+    P = lambda t, off=0: ctypes.c_void_p(t.data_ptr() + off)
+    say("misaligned pointers")
+    h = prob._h
+    assert lib.vpp_apply(h, 0, P(buf, 4), P(out), None) == 1
+    assert b"aligned" in lib.vpp_last_error()
+    assert lib.vpp_apply(h, 0, P(buf), P(out, 4), None) == 1
+    assert lib.vpp_apply(h, 1, P(b32, 2), P(o32), None) == 1
+    assert lib.vpp_set_phi(h, P(buf, 4), None) == 1
+    assert lib.vpp_diagonal(h, P(out, 4), None) == 1
+    o = L.CgOpts(1e-8, 0.0, 10, 0, 1e-3, 100, 8)
+    ci = L.CgInfo()
+    assert lib.vpp_cg_solve(h, P(buf, 4), P(out), ctypes.byref(o), ctypes.byref(ci), None) == 1
+    co = L.CpOpts(m.eps, 0.9, 1e-11, 50, 3)
+    assert lib.vpp_closest_points(h, None, 0, ctypes.byref(co), P(y3, 4), P(inf), None) == 1
+    assert lib.vpp_closest_points(h, None, 0, ctypes.byref(co), P(y3), P(inf, 2), None) == 1
+    assert lib.vpp_extend(h, P(y3), P(inf, 2), P(buf), P(out), None) == 1
+    torch.cuda.synchronize()
+    # nothing above ran: the problem still applies as before
+    assert rel(host(prob.apply(x)), y_ref) < 1e-14
