@@ -11,7 +11,9 @@ solve and one FP32/FP64 mixed-precision solve to rtol 1e-8 with the
 manufactured right-hand side b = A_D p*, p* = sin(pi x) sin(pi y) sin(pi z).
 
 value = operator MDoF/s of the applies (N * applies / apply time), timed with
-HIP events on the stream the kernels run on.  One apply is two launches: the
+HIP events on the stream the kernels run on.  After the timed steps the same
+applies are also captured in one HIP graph and replayed (`apply_us_graph`,
+each replay checked against the eager outputs); `value` stays the eager rate.  One apply is two launches: the
 tile kernel and the shared-node assembly; `roofline` prices the pair against
 24 algorithmic bytes per DoF (x and phi read, y written once).
 """
@@ -143,6 +145,43 @@ def timed_applies(torch, probs, xs, ys, napp, stream, prec_tensor=None):
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3
+
+
+def graph_applies(torch, probs, xs, ys, napp, dev, reps=5):
+    """The same applies captured in one HIP graph (torch's stream capture of the
+    library's launches) and replayed `reps` times, outside the timed steps.
+    Before every replay the outputs are cleared by eager work; after it they
+    are compared with the eager applies' outputs.  Returns the median seconds
+    per apply and the largest relative difference of any replay."""
+    npool = len(probs)
+    ref = ys.clone()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        for i in range(napp):
+            probs[i % npool].apply(xs[i], out=ys[i])
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for i in range(napp):
+            probs[i % npool].apply(xs[i], out=ys[i])
+    torch.cuda.synchronize()
+    scale = float(ref.abs().max())
+    ts, diff = [], 0.0
+    for _ in range(reps):
+        ys.zero_()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3 / napp)
+        diff = max(diff, float((ys - ref).abs().max()) / scale)
+    del g
+    return float(np.median(ts)), diff
 
 
 def extras(torch, vpp, W, dev, cache):
@@ -507,6 +546,7 @@ def main():
     last = res[-1]
     err64 = float(torch.linalg.norm(last[3] - pstar) / torch.linalg.norm(pstar))
     errmx = float(torch.linalg.norm(last[6] - pstar) / torch.linalg.norm(pstar))
+    t_graph, graph_diff = graph_applies(torch, probs, xs, ys, napp, dev)
     traffic = measured_traffic(cfg)
     out = {
         "metric": "operator MDoF/s + CG time to rtol 1e-8, FP64 vs FP32-mixed, Q2/Q3 hex",
@@ -540,6 +580,9 @@ def main():
     }
     if traffic is not None:
         out["roofline"]["traffic_bytes_per_apply"] = traffic
+    out["apply_us_graph"] = t_graph * 1e6
+    out["mdofs_graph"] = N / t_graph / 1e6
+    out["graph_max_rel_diff_vs_eager"] = graph_diff
     it64 = max(out["cg_fp64_iters"], 1)
     t_it = out["cg_fp64_s"] / it64
     out["cg_fp64_us_per_iter"] = t_it * 1e6
