@@ -55,7 +55,16 @@ typedef enum {
 } vpp_status;
 
 enum { VPP_BC_DIRICHLET = 0, VPP_BC_NEUMANN = 1 };       /* faces x-,x+,y-,y+,z-,z+ */
-enum { VPP_H_LINEAR = 0, VPP_H_PAPER = 1 };              /* (phi+1)/2 | Eq. heaviside */
+/* Material law.  VPP_H_LINEAR / VPP_H_PAPER: the reciprocal density of
+ * Eq. rhoEff with H = (phi+1)/2 or the sine ramp of Eq. heaviside.
+ * VPP_H_LINEAR_ARITH / VPP_H_PAPER_ARITH: the same H with the arithmetic
+ * density mean, c = 1/(H rho_l + (1 - H) rho_g), the law App. D contrasts with
+ * Eq. rhoEff (its 1D phase-change flow keeps the diffuse pressure jump only
+ * with the reciprocal mean).  The arithmetic laws run one kernel configuration
+ * per degree (the autotuner has a single candidate), apply / diagonal / CG /
+ * vpp_grad_coef; vpp_grad_phi, the mass shift and batches return
+ * VPP_ERR_UNSUPPORTED for them. */
+enum { VPP_H_LINEAR = 0, VPP_H_PAPER = 1, VPP_H_LINEAR_ARITH = 2, VPP_H_PAPER_ARITH = 3 };
 enum { VPP_FP64 = 0, VPP_FP32 = 1, VPP_MIXED = 2 };
 
 /* Mesh, element degree and material law of one problem. */
@@ -66,7 +75,7 @@ typedef struct {
     int32_t degree;         /* k in {2,3,4} */
     int32_t bc[6];          /* VPP_BC_* per face */
     double rho_l, rho_g;    /* liquid (phi>0) and gas densities, > 0 */
-    int32_t heaviside;      /* VPP_H_* */
+    int32_t heaviside;      /* VPP_H_* (material law) */
     int32_t device;         /* HIP device ordinal */
 } vpp_desc;
 
@@ -240,6 +249,24 @@ vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, 
 vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, const double* n1,
                            const double* n2, const vpp_reinit_opts* opts, double* psi_out,
                            vpp_cg_info* info, void* stream);
+
+/* The three pieces of that step on their own, each formed exactly as
+ * vpp_reinit_step forms it (same kernels, natural conditions on every face):
+ *   vpp_reinit_apply:    y = A x,  A = M/dtau + eps K_n, K_n the matrix of
+ *                        ((grad u . n)(grad v . n)) (Eq. reinitialization,
+ *                        diffusion implicit);
+ *   vpp_reinit_diagonal: diag = diag(A) (the step's Jacobi preconditioner);
+ *   vpp_reinit_rhs:      b = (psi, v)/dtau + ((1 - psi_h^2)/2 n, grad v)
+ *                        (the explicit compressive flux).
+ * Only opts->eps and opts->dtau are read (> 0, finite).  n0..n2, x, psi: N
+ * entries; y, diag, b: N entries written (need no initialisation), not
+ * aliased with an input.  FP64 device pointers; asynchronous on `stream`. */
+vpp_status vpp_reinit_apply(vpp_problem p, const double* n0, const double* n1, const double* n2,
+                            const vpp_reinit_opts* opts, const double* x, double* y, void* stream);
+vpp_status vpp_reinit_diagonal(vpp_problem p, const double* n0, const double* n1, const double* n2,
+                               const vpp_reinit_opts* opts, double* diag, void* stream);
+vpp_status vpp_reinit_rhs(vpp_problem p, const double* psi, const double* n0, const double* n1,
+                          const double* n2, const vpp_reinit_opts* opts, double* b, void* stream);
 
 /* Extension of a nodal Q_k field f of the mesh from the interface over the
  * narrow band (same appendix: values at the closest points extended to the

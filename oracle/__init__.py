@@ -163,6 +163,21 @@ def coef_qp(mesh, phi) -> np.ndarray:
     return out
 
 
+def coef_qp_arith(mesh, phi, paper: bool = False) -> np.ndarray:
+    """The arithmetic density mean App. D contrasts with Eq. rhoEff, at every
+    Gauss point (cell-major, like coef_qp): phi_h(x_q) interpolated from the
+    nodal phi, clamped to [-1, 1] (reading R3), H linear (phi+1)/2 or the sine
+    ramp of Eq. heaviside (paper=True), rho = H rho_l + (1 - H) rho_g, c = 1/rho."""
+    ph = np.clip(eval_qp(mesh, phi), -1.0, 1.0)
+    if paper:
+        d = desc_of(mesh)
+        d.heaviside = 1
+        H = np.array([_load().orc_heaviside(C.byref(d), float(v)) for v in ph])
+    else:
+        H = 0.5 * (ph + 1.0)
+    return 1.0 / (H * mesh.rho_l + (1.0 - H) * mesh.rho_g)
+
+
 # -- assembled operator -------------------------------------------------------
 
 class Operator:
@@ -322,6 +337,43 @@ def manufactured_sine_rhs(mesh, radius: float, eps: float, centre=(0.5, 0.5, 0.5
     return b
 
 
+def manufactured_sine_rhs_spheres(mesh, centres, radii, eps: float) -> np.ndarray:
+    """Load vector of f = -div(c grad p*) for p* = sin(pi x) sin(pi y) sin(pi z) on a
+    union of liquid spheres: d = max_i (r_i - |x - c_i|) with ties to the lowest
+    i, phi = tanh(d/(2 eps)), and grad d = -(x - c_i)/|x - c_i| of the sphere
+    that attains the maximum; c is the analytic coefficient of Eq. rhoEff for
+    that phi, so f = 3 pi^2 c p* - grad c . grad p* as for one sphere.
+    Homogeneous Dirichlet values (p* vanishes on the cube faces)."""
+    x, y, z, _ = qp_coords(mesh)
+    centres = np.asarray(centres, dtype=np.float64)
+    radii = np.asarray(radii, dtype=np.float64)
+    dist = np.stack([r - np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+                     for c, r in zip(centres, radii)])
+    owner = np.argmax(dist, axis=0)                   # first maximum: lowest sphere index
+    d = dist[owner, np.arange(x.size)]
+    cx, cy, cz = centres[owner, 0], centres[owner, 1], centres[owner, 2]
+    dx, dy, dz = x - cx, y - cy, z - cz
+    r = np.sqrt(dx * dx + dy * dy + dz * dz)
+    rs = np.where(r > 0, r, 1.0)
+    phi = np.tanh(d / (2 * eps))
+    Hd = np.array([heaviside(mesh, v, deriv=True) for v in phi]) if mesh.heaviside else 0.5
+    Hv = np.array([heaviside(mesh, v) for v in phi]) if mesh.heaviside else 0.5 * (phi + 1)
+    dcdphi = (1.0 / mesh.rho_l - 1.0 / mesh.rho_g) * Hd
+    c = Hv / mesh.rho_l + (1 - Hv) / mesh.rho_g
+    dphi = (1 - phi * phi) / (2 * eps)
+    gd = np.where(r > 0, -1.0, 0.0)
+    gx, gy, gz = (gd * dd / rs * dphi * dcdphi for dd in (dx, dy, dz))
+    pi = np.pi
+    s = np.sin(pi * x) * np.sin(pi * y) * np.sin(pi * z)
+    px = pi * np.cos(pi * x) * np.sin(pi * y) * np.sin(pi * z)
+    py = pi * np.sin(pi * x) * np.cos(pi * y) * np.sin(pi * z)
+    pz = pi * np.sin(pi * x) * np.sin(pi * y) * np.cos(pi * z)
+    f = 3 * pi * pi * c * s - (gx * px + gy * py + gz * pz)
+    b = rhs_qp(mesh, f)
+    b[mesh.boundary_mask()] = 0.0
+    return b
+
+
 def sine_load(mesh) -> np.ndarray:
     """Load vector of f0 = 3 pi^2 sin sin sin (phi-independent), zero on Dirichlet rows."""
     x, y, z, _ = qp_coords(mesh)
@@ -339,4 +391,4 @@ def discrete_manufactured_rhs(op, mesh, p_nodal) -> np.ndarray:
 
 
 from .closest_point import band_nodes, closest_points, node_coords  # noqa: E402  (closest-point projection)
-from .reinit import reinit_matrix, reinit_rhs  # noqa: E402  (reinitialization step)
+from .reinit import reinit_matrix, reinit_rhs, reinit_rows  # noqa: E402  (reinitialization step)

@@ -96,3 +96,43 @@ def reinit_rhs(mesh, psi, normal, dtau: float) -> np.ndarray:
         be = val.T @ (W * pq / dtau) + np.einsum("dqa,dq->a", grad, flux * W)
         np.add.at(b, g, be)
     return b
+
+
+def _cells_around(mesh, g):
+    """Base nodes of the (at most 8) cells containing node g."""
+    k = mesh.degree
+    Nx, Ny, _ = mesh.nnodes
+    idx = (g % Nx, (g // Nx) % Ny, g // (Nx * Ny))
+    ranges = []
+    for d in range(3):
+        i = idx[d]
+        lo = i // k - 1 if i % k == 0 else i // k
+        hi = i // k
+        ranges.append(range(max(lo, 0), min(hi, mesh.ncells[d] - 1) + 1))
+    for cz in ranges[2]:
+        for cy in ranges[1]:
+            for cx in ranges[0]:
+                yield k * cx + Nx * (k * cy + Ny * k * cz)
+
+
+def reinit_rows(mesh, normal, eps: float, dtau: float, x, psi, rows):
+    """Rows `rows` of A x, of diag(A) and of the right-hand side of the step (the
+    same cell integrals as reinit_matrix / reinit_rhs, summed over the cells
+    around each row's node only).  Returns (Ax, diag, b), each of len(rows)."""
+    val, grad, W, off = _cell_tables(mesh)
+    x = np.asarray(x, dtype=np.float64)
+    psi = np.asarray(psi, dtype=np.float64)
+    ax, dg, rb = (np.zeros(len(rows)) for _ in range(3))
+    for r, g in enumerate(np.asarray(rows, dtype=np.int64)):
+        for base in _cells_around(mesh, int(g)):
+            gl = base + off
+            a = int(np.nonzero(gl == g)[0][0])
+            nqv = np.stack([val @ np.asarray(normal[d])[gl] for d in range(3)])
+            dn = np.einsum("dq,dqa->qa", nqv, grad)
+            Ke_row = (val[:, a] * (W / dtau)) @ val + eps * (dn[:, a] * W) @ dn
+            ax[r] += Ke_row @ x[gl]
+            dg[r] += Ke_row[a]
+            pq = val @ psi[gl]
+            flux = 0.5 * (1.0 - pq * pq) * nqv
+            rb[r] += val[:, a] @ (W * pq / dtau) + np.einsum("dq,dq->", grad[:, :, a], flux * W)
+    return ax, dg, rb

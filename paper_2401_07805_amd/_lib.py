@@ -71,6 +71,9 @@ def load() -> C.CDLL:
         "vpp_normal_rhs": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vpp_reinit_step": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, C.POINTER(CgInfo), vp]),
         "vpp_curvature_rhs": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "vpp_reinit_apply": (C.c_int, [vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, vp, vp]),
+        "vpp_reinit_diagonal": (C.c_int, [vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, vp]),
+        "vpp_reinit_rhs": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, vp]),
         "vpp_apply": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "vpp_diagonal": (C.c_int, [vp, vp, vp]),
         "vpp_cg_solve": (C.c_int, [vp, vp, vp, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),

@@ -180,6 +180,39 @@ class Problem:
             _check(st)
         return out, _info(ci)
 
+    def _reinit_opts(self, eps: float, dtau: float):
+        return L.ReinitOpts(float(eps), float(dtau), 0.0, 0.0, 0)
+
+    def reinit_apply(self, x: torch.Tensor, normal, eps: float, dtau: float) -> torch.Tensor:
+        """y = (M/dtau + eps K_n) x, the reinitialization step's operator (vpp_reinit_apply)."""
+        y = torch.empty_like(x)
+        o = self._reinit_opts(eps, dtau)
+        _check(L.load().vpp_reinit_apply(self._h, *[_vec(c, self.n, torch.float64, self.device, "normal")
+                                                    for c in normal], C.byref(o),
+                                         _vec(x, self.n, torch.float64, self.device, "x"),
+                                         _vec(y, self.n, torch.float64, self.device, "y"), _stream(self.device)))
+        return y
+
+    def reinit_diagonal(self, normal, eps: float, dtau: float) -> torch.Tensor:
+        """diag(M/dtau + eps K_n) (vpp_reinit_diagonal)."""
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        o = self._reinit_opts(eps, dtau)
+        _check(L.load().vpp_reinit_diagonal(self._h, *[_vec(c, self.n, torch.float64, self.device, "normal")
+                                                       for c in normal], C.byref(o),
+                                            _vec(d, self.n, torch.float64, self.device, "diag"),
+                                            _stream(self.device)))
+        return d
+
+    def reinit_rhs(self, psi: torch.Tensor, normal, eps: float, dtau: float) -> torch.Tensor:
+        """(psi, v)/dtau + ((1 - psi_h^2)/2 n, grad v) (vpp_reinit_rhs)."""
+        b = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        o = self._reinit_opts(eps, dtau)
+        _check(L.load().vpp_reinit_rhs(self._h, _vec(psi, self.n, torch.float64, self.device, "psi"),
+                                       *[_vec(c, self.n, torch.float64, self.device, "normal") for c in normal],
+                                       C.byref(o), _vec(b, self.n, torch.float64, self.device, "b"),
+                                       _stream(self.device)))
+        return b
+
     def set_mass(self, mu: float):
         """Operator mu M + K_c (vpp_set_mass); mu = 0 is the pressure operator."""
         _check(L.load().vpp_set_mass(self._h, float(mu), _stream(self.device)))

@@ -238,7 +238,14 @@ static MeshArgs make_mesh_args(const vpp_desc& d)
     // sine ramp:  c = ig + (il - ig) H
     m.cg = m.r0 * ig;
     m.cd = m.r0 * (il - ig);
+    // arithmetic density mean: rho = rho_g + (rho_l - rho_g) H, c' = r0 / rho
+    m.qa = (d.rho_g + 0.5 * (d.rho_l - d.rho_g)) / m.r0;
+    m.qb = 0.5 * (d.rho_l - d.rho_g) / m.r0;
+    m.qs = d.rho_g / m.r0;
+    m.qd = (d.rho_l - d.rho_g) / m.r0;
     m.dcdphi = il - ig;
+    m.rho_l = d.rho_l;
+    m.rho_g = d.rho_g;
     return m;
 }
 
@@ -283,15 +290,20 @@ static vpp_status build_diagonal(vpp_problem p, hipStream_t s)
 
 static void put_config(vpp_problem p, int prec, const LaunchCfg& c);
 
-// Configurations a problem may run: those instantiated with the mass shift
-// when it has one, else every configuration of its degree.
+static bool arith_law(const vpp_desc& d) { return d.heaviside >= VPP_H_LINEAR_ARITH; }
+
+// Configurations a problem may run: those instantiated with the arithmetic
+// density mean or with the mass shift when it has one, else every
+// configuration of its degree.
 static bool config_ok(vpp_problem p, const LaunchCfg& c)
 {
+    if (arith_law(p->desc)) return arith_config_supported(c, p->k);
     return p->m.mass != 0.0 ? mass_config_supported(c, p->k) : apply_config_supported(c, p->k);
 }
 
 static int config_list(vpp_problem p, LaunchCfg* out, int cap)
 {
+    if (arith_law(p->desc)) return list_arith_configs(p->k, out, cap);
     return p->m.mass != 0.0 ? list_mass_configs(p->k, out, cap) : list_apply_configs(p->k, out, cap);
 }
 
@@ -714,7 +726,8 @@ vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
     for (int f = 0; f < 6; ++f)
         if (d->bc[f] != VPP_BC_DIRICHLET && d->bc[f] != VPP_BC_NEUMANN)
             return fail(VPP_ERR_INVALID_ARG, "bc must be VPP_BC_DIRICHLET or VPP_BC_NEUMANN");
-    if (d->heaviside != VPP_H_LINEAR && d->heaviside != VPP_H_PAPER)
+    if (d->heaviside != VPP_H_LINEAR && d->heaviside != VPP_H_PAPER && d->heaviside != VPP_H_LINEAR_ARITH &&
+        d->heaviside != VPP_H_PAPER_ARITH)
         return fail(VPP_ERR_INVALID_ARG, "unknown heaviside");
     const int64_t k = d->degree;
     const int64_t N = (k * d->ncells[0] + 1) * (k * d->ncells[1] + 1) * (k * d->ncells[2] + 1);
@@ -739,6 +752,14 @@ vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
     p->NQ = ncell * (k + 1) * (k + 1) * (k + 1);
     p->m = make_mesh_args(*d);
     p->cfg = default_config(p->k);
+    if (arith_law(*d)) {
+        LaunchCfg ac[4];
+        if (list_arith_configs(p->k, ac, 4) < 1) {
+            delete p;
+            return fail(VPP_ERR_UNSUPPORTED, "no kernel configuration with the arithmetic density mean");
+        }
+        p->cfg = ac[0];
+    }
     set_tiles(p->m, p->cfg);
     p->m32 = p->m;
     p->cfg32 = p->cfg;
@@ -797,6 +818,8 @@ vpp_status vpp_set_mass(vpp_problem p, double mu, void* stream)
 {
     if (!p) return fail(VPP_ERR_INVALID_ARG, "null argument");
     if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(VPP_ERR_INVALID_ARG, "the mass shift must be finite and >= 0");
+    if (mu != 0.0 && arith_law(p->desc))
+        return fail(VPP_ERR_UNSUPPORTED, "the mass shift is not available with the arithmetic density mean");
     LaunchCfg mc[16];
     if (mu != 0.0 && list_mass_configs(p->k, mc, 16) < 1)
         return fail(VPP_ERR_UNSUPPORTED, "no kernel configuration with the mass shift for this degree");
@@ -893,6 +916,8 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
     if (!p || !g_q || !g_phi) return fail(VPP_ERR_INVALID_ARG, "null argument");
     VPP_ALIGNED(8, g_q, g_phi);
     if (!p->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called");
+    if (arith_law(p->desc))
+        return fail(VPP_ERR_UNSUPPORTED, "dJ/dphi is available for the reciprocal density mean (Eq. rhoEff) only");
     DeviceGuard dg(p->desc.device);
     hipStream_t s = (hipStream_t)stream;
     VPP_HIP(launch_fill<double>(g_phi, p->N, 0.0, s));
@@ -1126,6 +1151,65 @@ vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, c
     if (info) *info = inf;
     if (inf.status == VPP_ERR_NOT_CONVERGED) return fail(VPP_ERR_NOT_CONVERGED, "reinitialization CG did not converge");
     if (inf.status == VPP_ERR_BREAKDOWN) return fail(VPP_ERR_BREAKDOWN, "reinitialization CG breakdown");
+    return VPP_OK;
+}
+
+// The reinitialization step's operator, diagonal and right-hand side on their
+// own (the same launches vpp_reinit_step makes).
+static vpp_status reinit_args(vpp_problem p, const double* n0, const double* n1, const double* n2,
+                              const vpp_reinit_opts* o, ReinitArgs* ra)
+{
+    if (!o || !n0 || !n1 || !n2) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, n0, n1, n2);
+    if (!(o->eps > 0.0) || !std::isfinite(o->eps) || !(o->dtau > 0.0) || !std::isfinite(o->dtau))
+        return fail(VPP_ERR_INVALID_ARG, "reinitialization eps and dtau must be positive and finite");
+    *ra = ReinitArgs{rhs_geometry(p), o->eps, 1.0 / o->dtau, n0, n1, n2};
+    ra->g.m.bcmask = 0;
+    return VPP_OK;
+}
+
+vpp_status vpp_reinit_apply(vpp_problem p, const double* n0, const double* n1, const double* n2,
+                            const vpp_reinit_opts* o, const double* x, double* y, void* stream)
+{
+    if (!p || !x || !y) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, x, y);
+    if ((const void*)x == y || (const void*)y == n0 || (const void*)y == n1 || (const void*)y == n2)
+        return fail(VPP_ERR_INVALID_ARG, "y must not alias an input");
+    ReinitArgs ra;
+    vpp_status st;
+    if ((st = reinit_args(p, n0, n1, n2, o, &ra))) return st;
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(launch_reinit_apply(p->k, ra, x, y, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+vpp_status vpp_reinit_diagonal(vpp_problem p, const double* n0, const double* n1, const double* n2,
+                               const vpp_reinit_opts* o, double* diag, void* stream)
+{
+    if (!p || !diag) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, diag);
+    if ((const void*)diag == n0 || (const void*)diag == n1 || (const void*)diag == n2)
+        return fail(VPP_ERR_INVALID_ARG, "diag must not alias an input");
+    ReinitArgs ra;
+    vpp_status st;
+    if ((st = reinit_args(p, n0, n1, n2, o, &ra))) return st;
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(launch_reinit_diag(p->k, ra, diag, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+vpp_status vpp_reinit_rhs(vpp_problem p, const double* psi, const double* n0, const double* n1, const double* n2,
+                          const vpp_reinit_opts* o, double* b, void* stream)
+{
+    if (!p || !psi || !b) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, psi, b);
+    if ((const void*)b == psi || (const void*)b == n0 || (const void*)b == n1 || (const void*)b == n2)
+        return fail(VPP_ERR_INVALID_ARG, "b must not alias an input");
+    ReinitArgs ra;
+    vpp_status st;
+    if ((st = reinit_args(p, n0, n1, n2, o, &ra))) return st;
+    DeviceGuard dg(p->desc.device);
+    VPP_HIP(launch_reinit_rhs(p->k, ra, psi, b, (hipStream_t)stream));
     return VPP_OK;
 }
 
@@ -1693,6 +1777,8 @@ vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32
         if (probs[i]->desc.device != dev) return fail(VPP_ERR_UNSUPPORTED, "all problems must be on one device");
         if (probs[i]->desc.heaviside != probs[0]->desc.heaviside)
             return fail(VPP_ERR_UNSUPPORTED, "all problems of a batch must share the Heaviside law");
+        if (arith_law(probs[i]->desc))
+            return fail(VPP_ERR_UNSUPPORTED, "batches run the reciprocal density mean (Eq. rhoEff) only");
         if (!probs[i]->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called for every problem");
         if (nrhs[i] < 1) return fail(VPP_ERR_INVALID_ARG, "nrhs must be >= 1");
     }

@@ -39,6 +39,14 @@ namespace vpp {
     X(4, 1, 4, 2, 2)        \
     X(4, 1, 2, 2, 2)
 
+// Configurations also instantiated with the arithmetic density mean (laws 2
+// and 3 of coef_scaled; the contrast of App. D): one per degree, the default
+// configuration of a new problem.
+#define VPP_ARITH_CONFIGS(X) \
+    X(2, 4, 8, 8, 4)         \
+    X(3, 1, 4, 4, 2)         \
+    X(4, 1, 4, 2, 2)
+
 template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT, bool MASS>
 inline auto kernel_ptr()
 {
@@ -74,9 +82,29 @@ inline hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s)
     return launch_hv<K, T, V, TX, TY, TZ, 1, false, MASS>(a, s);
 }
 
+template <int K, typename T, int V, int TX, int TY, int TZ>
+inline hipError_t launch_one_arith(const ApplyArgs<T>& a, hipStream_t s)
+{
+    if (a.dot_part) {
+        if (a.m.heaviside == 2) return launch_hv<K, T, V, TX, TY, TZ, 2, true, false>(a, s);
+        return launch_hv<K, T, V, TX, TY, TZ, 3, true, false>(a, s);
+    }
+    if (a.m.heaviside == 2) return launch_hv<K, T, V, TX, TY, TZ, 2, false, false>(a, s);
+    return launch_hv<K, T, V, TX, TY, TZ, 3, false, false>(a, s);
+}
+
 template <typename T>
 inline hipError_t launch_apply_t(const LaunchCfg& c, int k, const ApplyArgs<T>& a, hipStream_t s)
 {
+    if (a.m.heaviside >= 2) {
+        if (a.m.mass != 0.0) return hipErrorInvalidValue;
+#define VPP_LAUNCH_ARITH(K, V, TX, TY, TZ)                                                   \
+    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) \
+        return launch_one_arith<K, T, V, TX, TY, TZ>(a, s);
+        VPP_ARITH_CONFIGS(VPP_LAUNCH_ARITH)
+#undef VPP_LAUNCH_ARITH
+        return hipErrorInvalidValue;
+    }
     if (a.m.mass != 0.0) {
 #define VPP_LAUNCH_MASS(K, V, TX, TY, TZ)                                                    \
     if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) \

@@ -30,6 +30,28 @@ int list_apply_configs(int k, LaunchCfg* out, int cap)
     return n;
 }
 
+bool arith_config_supported(const LaunchCfg& c, int k)
+{
+#define VPP_ASUP(K, V, TX, TY, TZ) \
+    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) return true;
+    VPP_ARITH_CONFIGS(VPP_ASUP)
+#undef VPP_ASUP
+    return false;
+}
+
+int list_arith_configs(int k, LaunchCfg* out, int cap)
+{
+    int n = 0;
+#define VPP_ALIST(K, V, TX, TY, TZ)                              \
+    if (k == K) {                                                \
+        if (n < cap && out) out[n] = LaunchCfg{V, {TX, TY, TZ}}; \
+        ++n;                                                     \
+    }
+    VPP_ARITH_CONFIGS(VPP_ALIST)
+#undef VPP_ALIST
+    return n;
+}
+
 bool mass_config_supported(const LaunchCfg& c, int k)
 {
 #define VPP_MSUP(K, V, TX, TY, TZ) \

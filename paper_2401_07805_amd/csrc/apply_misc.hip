@@ -106,9 +106,11 @@ hipError_t launch_diag(int k, const MeshArgs& m, const double* phi, double* diag
 {
     const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
     const int blocks = (int)((ncell + 63) / 64);
-#define VPP_DIAG(K)                                                                              \
-    if (m.heaviside == 0) hipLaunchKernelGGL((diag_kernel<K, 0>), dim3(blocks), dim3(64), 0, s, m, phi, diag); \
-    else hipLaunchKernelGGL((diag_kernel<K, 1>), dim3(blocks), dim3(64), 0, s, m, phi, diag);
+#define VPP_DIAG(K)                                                                                  \
+    if (m.heaviside == 0) hipLaunchKernelGGL((diag_kernel<K, 0>), dim3(blocks), dim3(64), 0, s, m, phi, diag);      \
+    else if (m.heaviside == 1) hipLaunchKernelGGL((diag_kernel<K, 1>), dim3(blocks), dim3(64), 0, s, m, phi, diag); \
+    else if (m.heaviside == 2) hipLaunchKernelGGL((diag_kernel<K, 2>), dim3(blocks), dim3(64), 0, s, m, phi, diag); \
+    else hipLaunchKernelGGL((diag_kernel<K, 3>), dim3(blocks), dim3(64), 0, s, m, phi, diag);
     switch (k) {
     case 2: VPP_DIAG(2) break;
     case 3: VPP_DIAG(3) break;

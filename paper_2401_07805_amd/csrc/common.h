@@ -19,16 +19,23 @@ namespace vpp {
 // c(phi) = 1/rho_g + H(clamp(phi)) (1/rho_l - 1/rho_g)        (Eq. rhoEff)
 //   linear H:  c' = ca + cb * phi
 //   sine ramp: c' = cg + cd * H(phi), H from Eq. heaviside written in phi.
+// The arithmetic density mean rho = H rho_l + (1 - H) rho_g, the law App. D
+// contrasts with Eq. rhoEff, gives c = 1/rho:
+//   linear H:  c' = 1 / (qa + qb * phi)
+//   sine ramp: c' = 1 / (qs + qd * H(phi))   (all scaled by 1/r0)
 struct MeshArgs {
     int nc[3];        // cells per direction
     int nn[3];        // nodes per direction (k nc + 1)
     int ntile[3];     // workgroup tiles per direction
     int bcmask;       // bit f set: face f (x-,x+,y-,y+,z-,z+) is Dirichlet
-    int heaviside;    // 0 linear, 1 sine ramp
+    int heaviside;    // 0 linear, 1 sine ramp; 2, 3 the same with the arithmetic density mean
     double ca, cb;    // linear law (scaled by r0)
     double cg, cd;    // sine-ramp law (scaled by r0)
+    double qa, qb;    // arithmetic mean, linear H (density scaled by 1/r0)
+    double qs, qd;    // arithmetic mean, sine ramp
     double rd[3];
     double dcdphi;    // r0-free (1/rho_l - 1/rho_g), used by the adjoint
+    double rho_l, rho_g;
     double r0;
     double mass;      // mass shift mu scaled as the Gauss-point factors: mu hx hy hz (0: no mass term)
 };
@@ -187,13 +194,17 @@ __device__ __forceinline__ constexpr double wref(int q0, int q1, int q2)
     return Tab<K>::t.w[q0] * Tab<K>::t.w[q1] * Tab<K>::t.w[q2];
 }
 
-// Scaled coefficient c'(phi) at one Gauss point; HV selects the Heaviside
-// (0 linear, 1 sine ramp) at compile time so that each kernel carries one law.
+// Scaled coefficient c'(phi) at one Gauss point; HV selects the law at
+// compile time so that each kernel carries one: the reciprocal mean of
+// Eq. rhoEff with H linear (0) or the sine ramp (1), or the arithmetic density
+// mean with H linear (2) or the sine ramp (3).
 template <int HV, typename T>
 __device__ __forceinline__ T coef_scaled(const MeshArgs& m, T phi)
 {
     if constexpr (HV == 0) return fma(T(m.cb), clamp1(phi), T(m.ca));
-    else return fma(T(m.cd), sine_ramp(clamp1(phi)), T(m.cg));
+    else if constexpr (HV == 1) return fma(T(m.cd), sine_ramp(clamp1(phi)), T(m.cg));
+    else if constexpr (HV == 2) return T(1) / fma(T(m.qb), clamp1(phi), T(m.qa));
+    else return T(1) / fma(T(m.qd), sine_ramp(clamp1(phi)), T(m.qs));
 }
 
 // Scaled coefficient c'(phi) * wref at every Gauss point of a cell, in place

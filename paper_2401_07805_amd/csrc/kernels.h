@@ -58,6 +58,10 @@ int list_apply_configs(int k, LaunchCfg* out, int cap);
 // Configurations instantiated with the mass shift (a problem with mu != 0 runs these only).
 bool mass_config_supported(const LaunchCfg& c, int k);
 int list_mass_configs(int k, LaunchCfg* out, int cap);
+// Configurations instantiated with the arithmetic density mean (laws 2, 3: the
+// only ones such a problem runs).
+bool arith_config_supported(const LaunchCfg& c, int k);
+int list_arith_configs(int k, LaunchCfg* out, int cap);
 
 // Assembly of shared-face nodes from the tile partials (and of x . y).
 template <typename T>

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import workloads as W
-from gpu_util import dev, host, rel, say
+from gpu_util import dev, host, rel, rel_max, say
 
 pytestmark = pytest.mark.gpu
 
@@ -188,3 +188,45 @@ def test_batch_cg_mesh_above_lockstep_size():
     for x, scale, inf in zip(xs[:2], (1.0, -2.0), infos[:2]):
         assert inf["status"] == 0
         assert rel(host(x), scale * pref) < 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_c3_batch_apply_against_oracle():
+    """The batched workload at its real sizes (8 meshes of 16..64 cells per side,
+    Q2, one seeded sphere each, ratios from {1e2, 1e3, 1e4}, 4 seeded right-hand
+    sides per mesh): every output of one persistent batched apply against the
+    oracle, at 1e-12 relative - all rows on the 16^3 and 24^3 meshes (CSR SpMV),
+    1500 seeded rows plus every 997th row on the larger ones (row by row)."""
+    wls = W.batch_meshes()
+    probs, xs = [], []
+    for wl in wls:
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(dev(wl.phi))
+        probs.append(p)
+        xs += [dev(v) for v in wl.vectors]
+    ys = [torch.empty_like(x) for x in xs]
+    say("c3 batch create")
+    bt = vpp.Batch(probs, [len(wl.vectors) for wl in wls])
+    say("c3 batch apply", bt.config)
+    bt.apply(xs, ys)
+    torch.cuda.synchronize()
+    i = 0
+    rng = np.random.default_rng(77)
+    for wl in wls:
+        m = wl.mesh
+        full = m.ncells[0] <= 24
+        op = oracle.Operator(m, phi=wl.phi) if full else None
+        rows = None if full else np.unique(np.concatenate([rng.choice(m.ndofs, 1500, replace=False),
+                                                            np.arange(0, m.ndofs, 997)]))
+        for r in range(len(wl.vectors)):
+            y = host(ys[i])
+            x = wl.vectors[r]
+            if full:
+                yref = op.matvec(x)
+                err, errm = rel(y, yref), rel_max(y, yref)
+            else:
+                yr = oracle.apply_rows(m, wl.phi, x, rows)
+                err, errm = rel(y[rows], yr), rel_max(y[rows], yr)
+            say("c3 mesh", m.ncells[0], "ratio", wl.extra["ratio"], "rhs", r, f"err {err:.2e} max {errm:.2e}")
+            assert err < 1e-12 and errm < 1e-12
+            i += 1

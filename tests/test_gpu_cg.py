@@ -65,24 +65,81 @@ def test_solve_variants(k, n, precision):
     assert rel(p, pref) < 1e-8
 
 
-def test_mixed_spheres_small_levels():
-    """Union of 20 spheres, density ratio 1e4 (7430/0.743), eps = 1.5h, Q3: the
-    mixed solver reaches the FP64 solution at each small refinement level."""
-    for n in (6, 12):
-        wl = W.spheres_mixed(n=n, k=3)
-        m = wl.mesh
-        op = oracle.Operator(m, phi=wl.phi)
-        pstar = W.sine_field(m)
-        b = oracle.discrete_manufactured_rhs(op, m, pstar)
-        pref = spla.spsolve(op.to_scipy().tocsc(), b)
-        prob = _setup(m, wl.phi)
-        say("mixed spheres", n)
-        p, info = prob.cg_solve(dev(b), rtol=1e-8, precision="mixed")
+def _c2_level(n):
+    """C2 at refinement level n: Q3, union of 20 spheres, ratio 1e4 (7430/0.743),
+    eps = 1.5h; b assembled by the oracle from the analytic f (R7, R8);
+    reference = oracle PCG to rtol 1e-13."""
+    wl = W.spheres_mixed(n=n, k=3)
+    m = wl.mesh
+    say("c2 oracle assembly", n, m.ndofs)
+    op = oracle.Operator(m, phi=wl.phi)
+    b = oracle.manufactured_sine_rhs_spheres(m, wl.extra["centres"], wl.extra["radii"], m.eps)
+    say("c2 oracle pcg", n)
+    pref, oinfo = op.pcg(b, rtol=1e-13)
+    assert oinfo["status"] == 0
+    return wl, m, op, b, pref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("n", [12, 24, 48])
+def test_c2_levels_against_oracle(n):
+    """Per refinement level, FP64 and mixed PCG (i) at the timing tolerance
+    rtol 1e-8 reach a true FP64 residual <= 1e-8 ||b|| recomputed with the
+    oracle's CSR, and (ii) with rtol tightened to 1e-12 for parity (R11) lie
+    within 1e-8 of the oracle's solution.  Errors are reported per level."""
+    wl, m, op, b, pref = _c2_level(n)
+    prob = _setup(m, wl.phi)
+    bd = dev(b)
+    nb = np.linalg.norm(b)
+    for prec in ("fp64", "mixed"):
+        say("c2 level", n, prec, "rtol 1e-8")
+        p, info = prob.cg_solve(bd, rtol=1e-8, precision=prec)
         p = host(p)
-        res = np.linalg.norm(b - op.matvec(p)) / np.linalg.norm(b)
-        print("spheres", n, info, "res", res, "err vs ref", rel(p, pref))
+        res = np.linalg.norm(b - op.matvec(p)) / nb
+        e8 = rel(p, pref)
+        say("c2 level", n, prec, "rtol 1e-12")
+        pt, tinfo = prob.cg_solve(bd, rtol=1e-12, precision=prec)
+        pt = host(pt)
+        e12 = rel(pt, pref)
+        res12 = np.linalg.norm(b - op.matvec(pt)) / nb
+        print(f"c2 level {n} {prec}: rtol 1e-8 it {info['iterations']} true res {res:.3e} err {e8:.3e}; "
+              f"rtol 1e-12 it {tinfo['iterations']} true res {res12:.3e} err vs oracle {e12:.3e}")
         assert info["status"] == 0 and res < 1e-8 * 1.01
-        assert rel(p, pref) < 1e-5
+        assert e8 < 1e-8
+        # at 1e-12 the FP64 recurrence residual and the true residual part by
+        # rounding (reported); the parity bar is the distance to the oracle
+        assert tinfo["status"] == 0 and e12 < 1e-8
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("bubble", [False, True])
+def test_c1_solve_oracle_rhs_and_residual(bubble):
+    """64^3 Q2 (2.15M DoFs), droplet or bubble r 0.25, eps = 2h, ratio 1000: b is
+    the oracle's load of the analytic f (R7).  FP64 and mixed PCG to rtol 1e-8
+    reach a true residual <= 1e-8 ||b|| recomputed with the oracle's CSR, and
+    at rtol 1e-12 lie within 1e-8 of the oracle's PCG solution (rtol 1e-13)."""
+    wl = W.droplet_at_scale(k=2, nvec=0, bubble=bubble)
+    m = wl.mesh
+    say("c1 oracle assembly", wl.name)
+    op = oracle.Operator(m, phi=wl.phi)
+    b = oracle.manufactured_sine_rhs(m, 0.25, m.eps, sign=-1.0 if bubble else 1.0)
+    pref, oinfo = op.pcg(b, rtol=1e-13)
+    assert oinfo["status"] == 0
+    prob = _setup(m, wl.phi)
+    bd = dev(b)
+    nb = np.linalg.norm(b)
+    for prec in ("fp64", "mixed"):
+        say("c1 solve", wl.name, prec)
+        p, info = prob.cg_solve(bd, rtol=1e-8, precision=prec)
+        p = host(p)
+        res = np.linalg.norm(b - op.matvec(p)) / nb
+        pt, tinfo = prob.cg_solve(bd, rtol=1e-12, precision=prec)
+        e12 = rel(host(pt), pref)
+        print(f"{wl.name} {prec}: rtol 1e-8 it {info['iterations']} true res {res:.3e}; "
+              f"rtol 1e-12 it {tinfo['iterations']} err vs oracle {e12:.3e}")
+        assert info["status"] == 0 and res < 1e-8 * 1.01
+        assert abs(info["true_rel_residual"] - res) < 1e-3 * res
+        assert tinfo["status"] == 0 and e12 < 1e-8
 
 
 def test_warm_start_and_failures():
@@ -153,27 +210,6 @@ def test_mixed_recovers_from_fp32_breakdown():
         res = np.linalg.norm(b - op.matvec(host(p))) / np.linalg.norm(b)
         print("inner", inner, info, "res", res)
         assert info["status"] == 0 and res < 1e-8 * 1.01
-
-
-def test_c2_mixed_levels_against_fp64():
-    """C2 at levels 24 and 48 (Q3, 20 spheres, ratio 1e4): mixed reaches the FP64
-    residual criterion and the tight FP64 GPU solve (itself oracle-pinned at the
-    small levels above) to within the error the rtol allows."""
-    for n in (24, 48):
-        wl = W.spheres_mixed(n=n, k=3)
-        m = wl.mesh
-        prob = _setup(m, wl.phi)
-        pstar = dev(W.sine_field(m))
-        pstar[dev(m.boundary_mask().astype(np.float64)) > 0] = 0.0
-        b = prob.apply(pstar)
-        say("c2 level", n)
-        pref, iref = prob.cg_solve(b, rtol=1e-12)
-        pm, im = prob.cg_solve(b, rtol=1e-8, precision="mixed")
-        p64, i64 = prob.cg_solve(b, rtol=1e-8)
-        em, e64 = rel(host(pm), host(pref)), rel(host(p64), host(pref))
-        print("c2", n, "mixed", im, "err", em, "fp64", i64, "err", e64)
-        assert im["status"] == 0 and im["true_rel_residual"] < 1e-8 * 1.01
-        assert em < 1e-5 and e64 < 1e-5
 
 
 def test_per_precision_configs():

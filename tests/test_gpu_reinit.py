@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import workloads as W
-from gpu_util import dev, host, rel, say
+from gpu_util import dev, host, rel, rel_max, say
 
 pytestmark = pytest.mark.gpu
 
@@ -54,3 +54,51 @@ def test_planar_profile_stays_steady_and_argument_errors():
     with pytest.raises(vpp.VppError) as e:
         prob.reinit_step(x, [dev(ones), dev(zeros), dev(zeros)], 0.0, eps)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("k,ncells", [(2, (6, 5, 4)), (3, (3, 4, 3)), (4, (2, 2, 3))])
+def test_reinit_pieces_match_oracle(k, ncells):
+    """The step's operator, diagonal and right-hand side, each on its own through
+    the C ABI, against the oracle's assembled matrix and load vector: 1e-12
+    relative (2-norm and max-norm) for A x and b, 1e-13 max-norm for diag(A)."""
+    m = W.Mesh(ncells=ncells, degree=k, bc=(0, 1, 1, 0, 1, 1))
+    eps, dtau = 0.08, 0.05
+    centre = (0.47, 0.52, 0.5)
+    psi = W.droplet_phi(m, 0.3, 0.6 * eps, centre=centre)
+    normal = W.normal_field(m, centre)
+    x = W.uniform_vectors(9, 1, m.ndofs)[0]
+    A = oracle.reinit_matrix(m, normal, eps, dtau)
+    b = oracle.reinit_rhs(m, psi, normal, dtau)
+    prob = vpp.Problem.from_mesh(m)
+    nd = [dev(c) for c in normal]
+    say("reinit pieces", k, ncells)
+    y = host(prob.reinit_apply(dev(x), nd, eps, dtau))
+    assert rel(y, A @ x) < 1e-12 and rel_max(y, A @ x) < 1e-12
+    d = host(prob.reinit_diagonal(nd, eps, dtau))
+    assert rel_max(d, A.diagonal()) < 1e-13
+    bb = host(prob.reinit_rhs(dev(psi), nd, eps, dtau))
+    assert rel(bb, b) < 1e-12 and rel_max(bb, b) < 1e-12
+
+
+@pytest.mark.timeout(600)
+def test_reinit_pieces_64cube_sampled_rows():
+    """64^3 Q2 (the timed size): droplet r 0.25 with an eps/2-sharp profile, the
+    unit radial normal, dtau = eps = 2h; 2000 seeded rows of A x, diag(A) and b
+    against the oracle's row-by-row evaluation, 1e-12 relative."""
+    m = W.unit_cube(64, 2, 1.0, 1.0, bc=(1,) * 6)
+    eps = 2.0 / 64
+    psi = W.droplet_phi(m, 0.25, 0.5 * eps)
+    normal = W.normal_field(m)
+    x = W.uniform_vectors(12, 1, m.ndofs)[0]
+    rows = np.random.default_rng(64).choice(m.ndofs, 2000, replace=False)
+    say("reinit 64^3 oracle rows")
+    ax, dg, rb = oracle.reinit_rows(m, normal, eps, eps, x, psi, rows)
+    prob = vpp.Problem.from_mesh(m)
+    nd = [dev(c) for c in normal]
+    say("reinit 64^3 gpu")
+    y = host(prob.reinit_apply(dev(x), nd, eps, eps))[rows]
+    d = host(prob.reinit_diagonal(nd, eps, eps))[rows]
+    bb = host(prob.reinit_rhs(dev(psi), nd, eps, eps))[rows]
+    assert rel(y, ax) < 1e-12 and rel_max(y, ax) < 1e-12
+    assert rel_max(d, dg) < 1e-13
+    assert rel(bb, rb) < 1e-12 and rel_max(bb, rb) < 1e-12

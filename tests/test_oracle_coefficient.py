@@ -86,3 +86,31 @@ def test_distance_inverse_of_profile():
         phi = math.tanh(d / (2 * eps))
         direct = 0.5 + d / (6 * eps) + math.sin(math.pi * d / (3 * eps)) / (2 * math.pi)
         assert abs(oracle.heaviside(m, phi) - direct) < 1e-12
+
+
+@pytest.mark.parametrize("paper", [False, True])
+def test_arithmetic_mean_coefficient(paper):
+    """coef_qp_arith: 1/(H rho_l + (1-H) rho_g) at the Gauss points.  By Jensen's
+    inequality (1/x convex) it lies below the reciprocal mean of Eq. rhoEff
+    wherever 0 < H < 1 and equals it where H is 0 or 1; at H = 1/2 it is
+    2/(rho_l + rho_g); c rho = 1 with rho the arithmetic mean of the same H; and
+    interpolated values beyond +-1 take the pure-phase value (clamp, R3)."""
+    rl, rg = 1000.0, 2.0
+    m = W.Mesh(ncells=(3, 2, 2), degree=2, rho_l=rl, rho_g=rg, heaviside=W.H_PAPER if paper else W.H_LINEAR)
+    m.eps = 0.08
+    phi = W.droplet_phi(m, 0.3, m.eps, centre=(0.45, 0.5, 0.55))
+    ca = oracle.coef_qp_arith(m, phi, paper=paper)
+    cr = oracle.coef_qp(m, phi)
+    ph = np.clip(oracle.eval_qp(m, phi), -1, 1)
+    H = heaviside_closed(ph, linear=not paper)
+    inner = (H > 1e-12) & (H < 1 - 1e-12)
+    assert inner.any() and (~inner).any() if paper else inner.all()
+    assert np.all(ca[inner] < cr[inner])
+    np.testing.assert_allclose(ca[~inner], cr[~inner], rtol=1e-14)
+    # (the sine ramp's H here is the eps-free arctanh form, the oracle's the
+    # logarithm of Eq. distance: equal up to the rounding of the two formulas)
+    np.testing.assert_allclose(ca * (H * rl + (1 - H) * rg), 1.0, rtol=1e-12 if paper else 1e-14)
+    # the value at H = 1/2 (phi_h = 0) and the clamp, through a constant nodal field
+    for val, Hv in ((0.0, 0.5), (1.4, 1.0), (-2.0, 0.0)):
+        c = oracle.coef_qp_arith(m, np.full(m.ndofs, val), paper=paper)
+        np.testing.assert_allclose(c, 1.0 / (Hv * rl + (1 - Hv) * rg), rtol=1e-14)

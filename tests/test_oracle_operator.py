@@ -162,3 +162,24 @@ def test_apply_rows_match_matrix(k, n, bc):
     y = op.matvec(x)
     rows = np.arange(m.ndofs)
     np.testing.assert_allclose(oracle.apply_rows(m, phi, x, rows), y, rtol=0, atol=1e-13 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("ncells,k,bc,hv,mass", [
+    ((2, 2, 2), 2, (0,) * 6, W.H_LINEAR, 0.0),
+    ((2, 1, 2), 2, (0, 1, 1, 0, 0, 1), W.H_PAPER, 0.0),
+    ((2, 1, 1), 3, (1,) * 6, W.H_LINEAR, 2.5),
+    ((1, 2, 1), 4, (1, 1, 0, 0, 1, 1), W.H_LINEAR, 0.0),
+])
+def test_diagonal_brute_force(ncells, k, bc, hv, mass):
+    """orc_diag returns the diagonal of the brute-force dense matrix (identity
+    entries on Dirichlet rows), with and without the mass shift."""
+    m, phi = droplet_mesh(ncells, k, bc, heaviside=hv)
+    m.mass = mass
+    cq = oracle.coef_qp(m, phi)
+    nq = (k + 1) ** 3
+    A_dense = dense_operator(m, lambda cell, q, x: cq[cell * nq + q[0] + (k + 1) * (q[1] + (k + 1) * q[2])],
+                             mass=mass)
+    d = oracle.Operator(m, phi=phi).diagonal()
+    ref = np.diag(A_dense)
+    np.testing.assert_allclose(d, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+    assert np.all(d[m.boundary_mask()] == 1.0)

@@ -60,3 +60,54 @@ def test_planar_profile_is_steady(k):
         new = spla.spsolve(A.tocsc(), b)
         errs.append(np.abs(new - psi).max())
     assert errs[1] < errs[0] / 2 ** (k - 0.5), errs
+
+
+def test_rhs_exact_for_linear_profile_q2():
+    """k = 2, psi = a + b x (a Q2 function) and n = e_x: the integrands of the
+    right-hand side have degree <= 5, which the 3-point Gauss rule integrates
+    exactly, so b = M psi / dtau + (f_x, v) equals the 1D closed forms (numpy
+    polynomial integrals of (1 - psi^2)/2 against the basis derivatives, the 1D
+    mass matrix) times the node integrals in y and z."""
+    from numpy.polynomial import Polynomial as Poly
+    from indep import gll_closed_form, global_1d, lagrange_polys
+    ncells, ext = (3, 1, 2), (0.6, 0.25, 2.0)
+    m = W.Mesh(ncells=ncells, degree=2, extent=ext, bc=NEU)
+    a0, b0, dtau = -0.3, 0.9, 0.07
+    X, _, _ = m.node_grid()
+    psi = a0 + b0 * X.ravel()
+    ones, zeros = np.ones(m.ndofs), np.zeros(m.ndofs)
+    b = oracle.reinit_rhs(m, psi, [ones, zeros, zeros], dtau)
+    h = m.h
+    Mx, _ = global_1d(2, ncells[0], h[0])
+    My, _ = global_1d(2, ncells[1], h[1])
+    Mz, _ = global_1d(2, ncells[2], h[2])
+    xs = np.linspace(0.0, ext[0], 2 * ncells[0] + 1)
+    L = lagrange_polys(gll_closed_form(2))
+    fx = np.zeros(xs.size)
+    for c in range(ncells[0]):
+        x0 = c * h[0]
+        xpoly = Poly([x0, h[0]])                       # x(xi) on the cell
+        f = (1.0 - (a0 + b0 * xpoly) ** 2) / 2.0
+        for a in range(3):
+            fx[2 * c + a] += (f * L[a].deriv()).integ()(1.0)   # dx = h dxi, d/dx = d/dxi / h
+    my, mz = My.sum(axis=1), Mz.sum(axis=1)
+    ref = np.kron(mz, np.kron(my, Mx @ (a0 + b0 * xs))) / dtau + np.kron(mz, np.kron(my, fx))
+    np.testing.assert_allclose(b, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_rows_match_full_assembly(k):
+    """reinit_rows (cells around each node only) gives the rows of A x, diag(A)
+    and b of the full assembly, on every node of a small mesh."""
+    m = W.Mesh(ncells=(3, 2, 2), degree=k, bc=NEU)
+    comps = W.normal_field(m, (0.4, 0.55, 0.5))
+    eps, dtau = 0.1, 0.05
+    psi = W.droplet_phi(m, 0.3, 0.05, centre=(0.4, 0.55, 0.5))
+    x = W.uniform_vectors(5, 1, m.ndofs)[0]
+    A = oracle.reinit_matrix(m, comps, eps, dtau)
+    b = oracle.reinit_rhs(m, psi, comps, dtau)
+    rows = np.arange(m.ndofs)
+    ax, dg, rb = oracle.reinit_rows(m, comps, eps, dtau, x, psi, rows)
+    np.testing.assert_allclose(ax, A @ x, rtol=0, atol=1e-13 * np.abs(A @ x).max())
+    np.testing.assert_allclose(dg, A.diagonal(), rtol=0, atol=1e-13 * np.abs(A.diagonal()).max())
+    np.testing.assert_allclose(rb, b, rtol=0, atol=1e-13 * np.abs(b).max())

@@ -214,3 +214,21 @@ def test_app_d_rejects_arithmetic_density():
     b = oracle.constrain_rhs(op_full, m, ell, g_bnd=pex)
     pa = spla.spsolve(op_a.to_scipy().tocsc(), b)
     assert np.linalg.norm(pa - pex) / np.linalg.norm(pex) > 0.05
+
+
+def test_spheres_rhs_reduces_to_one_sphere():
+    """The union-of-spheres load vector (R8: d = max_i (r_i - |x - c_i|), the
+    gradient of the sphere attaining the maximum, ties to the lowest index)
+    equals the single-sphere manufactured load, itself pinned by the
+    convergence test above: for one sphere, for a sphere listed twice, and when
+    a second sphere lies inside the first and never attains the maximum."""
+    m = W.unit_cube(5, 2, 1000.0, 1.0)
+    m.eps = 0.08
+    c0, r0 = (0.45, 0.5, 0.55), 0.3
+    ref = oracle.manufactured_sine_rhs(m, r0, m.eps, centre=c0)
+    for cs, rs in (([c0], [r0]), ([c0, c0], [r0, r0]), ([c0, (0.5, 0.5, 0.5)], [r0, 0.1])):
+        b = oracle.manufactured_sine_rhs_spheres(m, cs, rs, m.eps)
+        np.testing.assert_allclose(b, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+    # a second, separate sphere changes the load where it attains the maximum
+    b2 = oracle.manufactured_sine_rhs_spheres(m, [c0, (0.8, 0.2, 0.2)], [r0, 0.15], m.eps)
+    assert np.abs(b2 - ref).max() > 1e-3 * np.abs(ref).max()
