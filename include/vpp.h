@@ -167,6 +167,21 @@ vpp_status vpp_set_mass(vpp_problem p, double mu, void* stream);
  * coefficient and tables are then FP32 too).  x and y must not alias. */
 vpp_status vpp_apply(vpp_problem p, int32_t prec, const void* x, void* y, void* stream);
 
+/* y = A_D x without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The problem is described by desc and the nodal phi
+ * (FP64 device pointers: phi, x, y, N entries each, y not aliased) instead of
+ * a vpp_problem; FP64 only, with a fixed kernel configuration per degree (no
+ * autotuning).  The shared-face partials go to a static device array of the
+ * library (48 MiB per device, held from the library's load on that device to
+ * the end of the process; its address is looked up on the first call on each
+ * device): meshes whose partials do not fit (above about 64^3 Q2, 43^3 Q3 or
+ * 32^3 Q4 cells) return VPP_ERR_UNSUPPORTED before any launch.  Calls that
+ * overlap in time on one device race on that array (serialise them, e.g. on
+ * one stream).  Argument checks as vpp_create and vpp_apply; asynchronous on
+ * `stream`; no hipMalloc, hipFree or other allocating call. */
+vpp_status vpp_apply_noalloc(const vpp_desc* desc, const double* phi, const double* x, double* y, void* stream);
+
 /* diag(A_D) in FP64 (1 on Dirichlet rows). */
 vpp_status vpp_diagonal(vpp_problem p, double* diag, void* stream);
 

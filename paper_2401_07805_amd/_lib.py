@@ -75,6 +75,7 @@ def load() -> C.CDLL:
         "vpp_reinit_diagonal": (C.c_int, [vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, vp]),
         "vpp_reinit_rhs": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(ReinitOpts), vp, vp]),
         "vpp_apply": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+        "vpp_apply_noalloc": (C.c_int, [C.POINTER(Desc), vp, vp, vp, vp]),
         "vpp_diagonal": (C.c_int, [vp, vp, vp]),
         "vpp_cg_solve": (C.c_int, [vp, vp, vp, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),
         "vpp_grad_coef": (C.c_int, [vp, vp, vp, vp, vp]),

@@ -18,6 +18,7 @@
 #include "../../include/vpp.h"
 #include "blas.h"
 #include "kernels.h"
+#include "noalloc.h"
 
 using namespace vpp;
 
@@ -705,15 +706,9 @@ static void cache_store(const char* path, const std::string& key, const LaunchCf
 // ---------------------------------------------------------------------------
 // C ABI
 
-extern "C" {
-
-const char* vpp_last_error(void) { return g_err.c_str(); }
-int32_t vpp_abi_version(void) { return VPP_ABI_VERSION; }
-
-vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
+// Argument checks of a problem description (vpp_create, vpp_apply_noalloc).
+static vpp_status validate_desc(const vpp_desc* d)
 {
-    if (!d || !out) return fail(VPP_ERR_INVALID_ARG, "null argument");
-    *out = nullptr;
     if (d->degree < 2 || d->degree > 4) return fail(VPP_ERR_INVALID_ARG, "degree must be 2, 3 or 4");
     for (int i = 0; i < 3; ++i) {
         if (d->ncells[i] < 1) return fail(VPP_ERR_INVALID_ARG, "ncells must be >= 1");
@@ -743,6 +738,23 @@ vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
         return fail(VPP_ERR_HIP, "no HIP device available");
     }
     if (d->device < 0 || d->device >= ndev) return fail(VPP_ERR_INVALID_ARG, "device ordinal out of range");
+    return VPP_OK;
+}
+
+extern "C" {
+
+const char* vpp_last_error(void) { return g_err.c_str(); }
+int32_t vpp_abi_version(void) { return VPP_ABI_VERSION; }
+
+vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
+{
+    if (!d || !out) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    vpp_status vs = validate_desc(d);
+    if (vs) return vs;
+    const int64_t k = d->degree;
+    const int64_t N = (k * d->ncells[0] + 1) * (k * d->ncells[1] + 1) * (k * d->ncells[2] + 1);
+    const int64_t ncell = (int64_t)d->ncells[0] * d->ncells[1] * d->ncells[2];
     DeviceGuard dg(d->device);
     vpp_problem p = new vpp_problem_s();
     p->desc = *d;
@@ -851,6 +863,43 @@ vpp_status vpp_apply(vpp_problem p, int32_t prec, const void* x, void* y, void* 
     hipStream_t s = (hipStream_t)stream;
     if (prec == VPP_FP64) return do_apply64(p, (const double*)x, (double*)y, nullptr, nullptr, s);
     return do_apply32(p, (const float*)x, (float*)y, nullptr, nullptr, s);
+}
+
+// Configuration of the allocation-free apply: fixed per degree and law (no
+// autotuning, which needs a cache-flush buffer).
+static LaunchCfg noalloc_config(const vpp_desc& d)
+{
+    if (arith_law(d)) {
+        LaunchCfg c[4];
+        list_arith_configs(d.degree, c, 4);
+        return c[0];
+    }
+    if (d.degree == 2) return LaunchCfg{4, {16, 8, 4}};
+    if (d.degree == 3) return LaunchCfg{2, {8, 4, 4}};
+    return LaunchCfg{1, {4, 2, 2}};
+}
+
+vpp_status vpp_apply_noalloc(const vpp_desc* d, const double* phi, const double* x, double* y, void* stream)
+{
+    if (!d || !phi || !x || !y) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, phi, x, y);
+    if ((const void*)x == y || (const void*)phi == y) return fail(VPP_ERR_INVALID_ARG, "y must not alias x or phi");
+    vpp_status vs = validate_desc(d);
+    if (vs) return vs;
+    const LaunchCfg cfg = noalloc_config(*d);
+    MeshArgs m = make_mesh_args(*d);
+    set_tiles(m, cfg);
+    const int64_t ns = shared_stride(m);
+    if (8 * ns > (int64_t)kNoallocScratchDoubles)
+        return fail(VPP_ERR_UNSUPPORTED, "mesh too large for the static scratch of vpp_apply_noalloc (its shared-face "
+                                         "partials need " + std::to_string(8 * ns * 8) + " bytes, the scratch holds " +
+                                         std::to_string(kNoallocScratchDoubles * 8) + ")");
+    DeviceGuard dg(d->device);
+    double* scratch = nullptr;
+    VPP_HIP(noalloc_scratch(d->device, &scratch));
+    ApplyArgs<double> a{m, x, y, phi, scratch, ns, nullptr, nullptr, nullptr, false};
+    VPP_HIP(launch_apply_f64(cfg, d->degree, a, (hipStream_t)stream));
+    return VPP_OK;
 }
 
 vpp_status vpp_diagonal(vpp_problem p, double* diag, void* stream)
