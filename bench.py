@@ -11,7 +11,11 @@ solve and one FP32/FP64 mixed-precision solve to rtol 1e-8 with the
 manufactured right-hand side b = A_D p*, p* = sin(pi x) sin(pi y) sin(pi z).
 
 value = operator MDoF/s of the applies (N * applies / apply time), timed with
-HIP events on the stream the kernels run on.  After the timed steps the same
+HIP events on the stream the kernels run on.  After the timed steps the line
+also carries the rest of the metric: the cold FP32 Q2 apply, the Q3 (43^3)
+FP64 and FP32 applies under the same protocol and its FP64-vs-mixed PCG to
+rtol 1e-8, the same solves on the 64^3 Q2 bubble, and the adjoint kernels
+against their algorithmic bytes.  After the timed steps the same
 applies are also captured in one HIP graph and replayed (`apply_us_graph`,
 each replay checked against the eager outputs); `value` stays the eager rate.  One apply is two launches: the
 tile kernel and the shared-node assembly; `roofline` prices the pair against
@@ -36,6 +40,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 BYTES_PER_DOF_F64 = 24.0      # x read, phi read, y written once per DoF
+BYTES_PER_DOF_F32 = 12.0      # the same vectors in FP32
 # Vector bytes per DoF of one FP64 PCG iteration as the three launches move
 # them: the apply (p, phi read; q written: 24), the assembly + update (q, r,
 # 1/diag read; r written: 32) and the x / p update (r, 1/diag, p, x read; p, x
@@ -94,9 +99,29 @@ def measured_traffic(cfg):
     return float(mb.group(1)) if mb else None
 
 
+def lscpu_facts():
+    """Model, sockets, cores and threads of the host from `lscpu` (empty if unavailable)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return {}
+    keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+            "Thread(s) per core": "threads_per_core", "CPU(s)": "cpus"}
+    facts = {}
+    for line in out.splitlines():
+        if ":" not in line:
+            continue
+        k, v = (t.strip() for t in line.split(":", 1))
+        if k in keys:
+            facts[keys[k]] = int(v) if v.isdigit() else v
+    return facts
+
+
 def cpu_baseline():
-    """The FP64 oracle (CSR assembled by full quadrature, CSR SpMV) on the host
-    cores, on a bounded sample: 32^3 cells Q2 of the same droplet workload."""
+    """The FP64 oracle (CSR assembled by full quadrature; CSR SpMV; textbook
+    Jacobi PCG) on the host cores, on a bounded sample of the same workload:
+    32^3 cells Q2 of the droplet (r 0.25, eps = 2h, ratio 1000)."""
     import oracle
     import workloads as W
     wl = W.droplet_at_scale(k=2, n=32, nvec=1, seed=1)
@@ -113,6 +138,10 @@ def cpu_baseline():
         op.matvec(x)
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
+    b = oracle.manufactured_sine_rhs(m, 0.25, m.eps)
+    t0 = time.perf_counter()
+    _, pinfo = op.pcg(b, rtol=1e-8)
+    t_pcg = time.perf_counter() - t0
     threads = oracle.num_threads()
     oracle.set_num_threads(1)
     ts1 = []
@@ -122,17 +151,14 @@ def cpu_baseline():
         ts1.append(time.perf_counter() - t0)
     oracle.set_num_threads(threads)
     t1 = float(np.median(ts1))
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
-    except OSError:
-        pass
     return {"value": m.ndofs / t / 1e6, "unit": "MDoF/s", "cores": threads, "kind": "oracle",
-            "value_1_thread": m.ndofs / t1 / 1e6, "cpu_model": model,
+            "value_1_thread": m.ndofs / t1 / 1e6, "lscpu": lscpu_facts(),
+            "pcg_rtol_1e-8_s": t_pcg, "pcg_iterations": pinfo["iterations"],
+            "pcg_us_per_iter": t_pcg / max(pinfo["iterations"], 1) * 1e6,
             "sample": f"FP64 CSR SpMV, median of 10 after 2 warm-ups, droplet 32^3 cells Q2 "
                       f"({m.ndofs} DoFs, nnz {op.nnz}); assembly {t_asm:.2f} s not included; "
-                      f"value_1_thread: median of 3 on one thread"}
+                      f"value_1_thread: median of 3 on one thread; pcg: Jacobi PCG from 0 to rtol 1e-8 with "
+                      f"the manufactured right-hand side, wall time on `cores` threads"}
 
 
 def timed_applies(torch, probs, xs, ys, napp, stream, prec_tensor=None):
@@ -182,6 +208,124 @@ def graph_applies(torch, probs, xs, ys, napp, dev, reps=5):
         diff = max(diff, float((ys - ref).abs().max()) / scale)
     del g
     return float(np.median(ts)), diff
+
+
+def cold_rate(torch, probs, X, Y, napp, reps=3):
+    """Median seconds per apply of napp applies rotating over a pool of problems
+    (each with its own phi copy) and over napp distinct x / y vectors."""
+    npool = len(probs)
+    for i in range(napp):
+        probs[i % npool].apply(X[i], out=Y[i])
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(napp):
+            probs[i % npool].apply(X[i], out=Y[i])
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3 / napp)
+    return float(np.median(ts))
+
+
+def solve_pair(p, b, rtol=1e-8):
+    """Host wall time of FP64 and mixed PCG from 0 to rtol (the same FP64 true
+    residual criterion), each after one untimed solve that builds its graphs."""
+    out = {}
+    for prec in ("fp64", "mixed"):
+        p.cg_solve(b, rtol=rtol, precision=prec)
+        t0 = time.perf_counter()
+        _, info = p.cg_solve(b, rtol=rtol, precision=prec)
+        out[f"cg_{prec}_s"] = time.perf_counter() - t0
+        out[f"cg_{prec}_iters"] = info["iterations"]
+        out[f"cg_{prec}_true_rel_res"] = info["true_rel_residual"]
+    return out
+
+
+def secondary(torch, vpp, W, dev, cache, xs, ys, probs_q2):
+    """Figures of the metric beyond the headline apply, outside the timed steps:
+    the cold FP32 Q2 apply; the Q3 43^3 FP64 and FP32 applies (cold, same
+    protocol) and its FP64-vs-mixed PCG to rtol 1e-8; the same solves on the 64^3
+    Q2 bubble; dJ/dc (grad_coef) and dJ/dphi (grad_phi) at 64^3 Q2 against
+    their algorithmic bytes."""
+    out = {}
+    napp = xs.shape[0]
+    N2 = probs_q2[0].n
+    x32, y32 = xs.float(), torch.empty(xs.shape, dtype=torch.float32, device=dev)
+    t = cold_rate(torch, probs_q2, x32, y32, napp)
+    out["q2_f32"] = {"apply_us": t * 1e6, "mdofs": N2 / t / 1e6,
+                     "roofline_frac": BYTES_PER_DOF_F32 * N2 / t / 1e9 / HBM_PEAK_GBS,
+                     "kernel": probs_q2[0].config_for("fp32")}
+    del x32, y32
+    # Q3, 43^3 cells (2,197,000 DoFs), same droplet and protocol
+    wl = W.droplet_at_scale(k=3, nvec=0)
+    m3 = wl.mesh
+    N3 = m3.ndofs
+    phi3 = torch.from_numpy(wl.phi).to(dev)
+    npool = max(1, min(napp, math.ceil(600e6 / (BYTES_PER_DOF_F64 * N3))))
+    p3 = []
+    for i in range(npool):
+        p = vpp.Problem.from_mesh(m3)
+        p.set_phi(phi3)
+        p3.append(p)
+    c3 = p3[0].tune(cache)
+    c332 = p3[0].config_for("fp32")
+    for p in p3[1:]:
+        p.set_config(c3["variant"], c3["tile"], "fp64")
+        p.set_config(c332["variant"], c332["tile"], "fp32")
+    X3 = torch.from_numpy(W.uniform_vectors(1, napp, N3)).to(dev)
+    Y3 = torch.empty_like(X3)
+    t64 = cold_rate(torch, p3, X3, Y3, napp)
+    X3f = X3.float()
+    del X3, Y3
+    Y3f = torch.empty_like(X3f)
+    t32 = cold_rate(torch, p3, X3f, Y3f, napp)
+    del X3f, Y3f
+    q3 = {"ndofs": N3, "f64_apply_us": t64 * 1e6, "f64_mdofs": N3 / t64 / 1e6,
+          "f64_roofline_frac": BYTES_PER_DOF_F64 * N3 / t64 / 1e9 / HBM_PEAK_GBS,
+          "f32_apply_us": t32 * 1e6, "f32_mdofs": N3 / t32 / 1e6,
+          "f32_roofline_frac": BYTES_PER_DOF_F32 * N3 / t32 / 1e9 / HBM_PEAK_GBS,
+          "kernel_fp64": c3, "kernel_fp32": c332}
+    ps = torch.from_numpy(W.sine_field(m3)).to(dev)
+    ps[torch.from_numpy(m3.boundary_mask()).to(dev)] = 0.0
+    q3.update(solve_pair(p3[0], p3[0].apply(ps)))
+    out["q3"] = q3
+    del p3
+    # bubble 64^3 Q2: the same solves
+    wb = W.droplet_at_scale(k=2, nvec=0, bubble=True)
+    pb = vpp.Problem.from_mesh(wb.mesh)
+    pb.set_phi(torch.from_numpy(wb.phi).to(dev))
+    pb.tune(cache)
+    ps = torch.from_numpy(W.sine_field(wb.mesh)).to(dev)
+    ps[torch.from_numpy(wb.mesh.boundary_mask()).to(dev)] = 0.0
+    out["bubble_q2"] = solve_pair(pb, pb.apply(ps))
+    del pb
+    # adjoint kernels at 64^3 Q2 (hot: p, lam, g_q from the previous call)
+    p0 = probs_q2[0]
+    pv, lam = xs[0], xs[1]
+    g = p0.grad_coef(pv, lam)
+    gphi = p0.grad_phi(g)
+    nq = p0.nq
+    res = {}
+    for name, fn, nbytes in (("grad_coef", lambda: p0.grad_coef(pv, lam), 16.0 * N2 + 8.0 * nq),
+                             ("grad_phi", lambda: p0.grad_phi(g), 16.0 * N2 + 8.0 * nq)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            fn()
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        res[name] = {"us": us, "algorithmic_bytes": nbytes, "achieved_gbs": nbytes / us / 1e3,
+                     "roofline_frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
+    del gphi
+    out["adjoint_q2"] = res
+    return out
 
 
 def extras(torch, vpp, W, dev, cache):
@@ -548,6 +692,8 @@ def main():
     errmx = float(torch.linalg.norm(last[6] - pstar) / torch.linalg.norm(pstar))
     t_graph, graph_diff = graph_applies(torch, probs, xs, ys, napp, dev)
     traffic = measured_traffic(cfg)
+    log("secondary figures")
+    sec = secondary(torch, vpp, W, dev, cache, xs, ys, probs)
     out = {
         "metric": "operator MDoF/s + CG time to rtol 1e-8, FP64 vs FP32-mixed, Q2/Q3 hex",
         "value": value,
@@ -593,6 +739,7 @@ def main():
     tflops = FLOPS_PER_CELL_Q2 * ncells / per_apply / 1e12
     out["valu"] = {"achieved": tflops, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                    "frac": tflops / FP64_VALU_PEAK_TFLOPS, "flops_per_apply": FLOPS_PER_CELL_Q2 * ncells}
+    out.update(sec)
     if args.copy_probe:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         c = torch.empty_like(a)
