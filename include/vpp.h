@@ -292,6 +292,43 @@ vpp_status vpp_reinit_rhs(vpp_problem p, const double* psi, const double* n0, co
 vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const double* f, double* out,
                       void* stream);
 
+/* Once-refined meshes with hanging nodes (adaptive refinement around the
+ * interface, Sec. "Numerical framework", restricted to one level): the box of
+ * `coarse` with the coarse cells marked in `refined` (host array, one byte per
+ * coarse cell, cx fastest; nonzero = split into 2 x 2 x 2) refined once.
+ * Unknowns sit in one vector of vpp_amr_num_dofs entries: the coarse lattice
+ * (k n_d + 1 nodes per direction, lexicographic, x fastest) and then the fine
+ * lattice over the whole box (2 k n_d + 1 per direction).  Free unknowns are
+ * the coarse nodes of unrefined cells and the fine nodes of refined cells that
+ * lie on no unrefined cell; a fine node on the closure of an unrefined cell is
+ * constrained to that cell's Q_k interpolant (a hanging node, or a copy where
+ * it coincides with a coarse node), so the space stays continuous.  The
+ * operator is A = C^T A_cells C (C the constraints, A_cells the element
+ * matrices of the active cells with the coefficient of Eq. rhoEff from the
+ * nodal phi of the cell's own lattice), with identity rows and columns on
+ * every entry that is not a free unknown and on free unknowns of Dirichlet
+ * faces (as A_D).  One cell per thread with atomic scatter (summation order
+ * not fixed: results vary at the rounding level); FP64 only.
+ *   vpp_amr_create:   host call; VPP_ERR_INVALID_ARG as vpp_create, or for a
+ *                     NULL mask, more than 2^27 coarse cells or 2^31 entries.
+ *   vpp_amr_set_phi:  nodal phi on both lattices (vpp_amr_num_dofs entries);
+ *                     builds the Jacobi diagonal.
+ *   vpp_amr_apply:    y = A x (all entries written); x, y not aliased.
+ *   vpp_amr_diagonal: diag(A), 1 on identity rows.
+ *   vpp_amr_cg_solve: Jacobi PCG as vpp_cg_solve (opts->precision VPP_FP64,
+ *                     else VPP_ERR_UNSUPPORTED); synchronizes.
+ * vpp_amr_num_free: the number of free unknowns not on Dirichlet faces. */
+typedef struct vpp_amr_s* vpp_amr;
+vpp_status vpp_amr_create(const vpp_desc* coarse, const uint8_t* refined, vpp_amr* out);
+vpp_status vpp_amr_destroy(vpp_amr a);
+int64_t vpp_amr_num_dofs(vpp_amr a);
+int64_t vpp_amr_num_free(vpp_amr a);
+vpp_status vpp_amr_set_phi(vpp_amr a, const double* phi, void* stream);
+vpp_status vpp_amr_apply(vpp_amr a, const double* x, double* y, void* stream);
+vpp_status vpp_amr_diagonal(vpp_amr a, double* diag, void* stream);
+vpp_status vpp_amr_cg_solve(vpp_amr a, const double* b, double* x, const vpp_cg_opts* opts, vpp_cg_info* info,
+                            void* stream);
+
 /* Kernel configuration of a problem (what the autotuner chooses), held per
  * precision: the FP64 and the FP32 apply may use different kernels and tiles.
  * Setting an unsupported one returns VPP_ERR_UNSUPPORTED.  vpp_get_config /

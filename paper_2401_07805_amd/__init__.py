@@ -8,7 +8,7 @@ compute path is the HIP library libvpp.so (C ABI in include/vpp.h); this package
 only marshals arguments to it.
 """
 from ._lib import LIB_PATH, declared_functions, load  # noqa: F401
-from .api import Batch, PoissonSolve, Problem, VppError, config_candidates, poisson_solve  # noqa: F401
+from .api import AmrProblem, Batch, PoissonSolve, Problem, VppError, config_candidates, poisson_solve  # noqa: F401
 
-__all__ = ["Problem", "Batch", "PoissonSolve", "poisson_solve", "VppError", "config_candidates", "load",
+__all__ = ["Problem", "AmrProblem", "Batch", "PoissonSolve", "poisson_solve", "VppError", "config_candidates", "load",
            "LIB_PATH", "declared_functions"]

@@ -91,6 +91,14 @@ def load() -> C.CDLL:
         "vpp_batch_cg_solve": (C.c_int, [vp, PP, PP, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),
         "vpp_batch_get_config": (C.c_int, [vp, C.POINTER(KernelConfig)]),
         "vpp_batch_destroy": (C.c_int, [vp]),
+        "vpp_amr_create": (C.c_int, [C.POINTER(Desc), C.c_void_p, PP]),
+        "vpp_amr_destroy": (C.c_int, [vp]),
+        "vpp_amr_num_dofs": (C.c_int64, [vp]),
+        "vpp_amr_num_free": (C.c_int64, [vp]),
+        "vpp_amr_set_phi": (C.c_int, [vp, vp, vp]),
+        "vpp_amr_apply": (C.c_int, [vp, vp, vp, vp]),
+        "vpp_amr_diagonal": (C.c_int, [vp, vp, vp]),
+        "vpp_amr_cg_solve": (C.c_int, [vp, vp, vp, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),
         "vpp_last_error": (C.c_char_p, []),
         "vpp_abi_version": (C.c_int32, []),
     }

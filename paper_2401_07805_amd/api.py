@@ -361,6 +361,76 @@ class Batch:
         return {"variant": c.variant, "tile": tuple(c.tile)}
 
 
+class AmrProblem:
+    """A box whose marked coarse cells are refined once, with hanging-node
+    constraints (vpp_amr_create).  Vectors hold the coarse lattice and then the
+    fine lattice (num_dofs entries)."""
+
+    def __init__(self, ncells: Sequence[int], degree: int, refined, origin=(0.0, 0.0, 0.0),
+                 extent=(1.0, 1.0, 1.0), bc=(0, 0, 0, 0, 0, 0), rho_l: float = 1000.0, rho_g: float = 1.0,
+                 heaviside: int = 0, device: int = 0):
+        import numpy as np
+        lib = L.load()
+        d = L.Desc()
+        d.ncells[:] = [int(v) for v in ncells]
+        d.origin[:] = [float(v) for v in origin]
+        d.extent[:] = [float(v) for v in extent]
+        d.degree = int(degree)
+        d.bc[:] = [int(v) for v in bc]
+        d.rho_l = float(rho_l)
+        d.rho_g = float(rho_g)
+        d.heaviside = int(heaviside)
+        d.device = int(device)
+        mask = np.ascontiguousarray(np.asarray(refined, dtype=np.uint8).ravel())
+        if mask.size != int(np.prod(ncells)):
+            raise ValueError("refined must hold one entry per coarse cell")
+        self._h = C.c_void_p()
+        _check(lib.vpp_amr_create(C.byref(d), mask.ctypes.data_as(C.c_void_p), C.byref(self._h)))
+        self.device = torch.device("cuda", int(device))
+        self.n = lib.vpp_amr_num_dofs(self._h)
+        self.nfree = lib.vpp_amr_num_free(self._h)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and h.value and L._lib is not None:
+            L._lib.vpp_amr_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_phi(self, phi: torch.Tensor):
+        _check(L.load().vpp_amr_set_phi(self._h, _vec(phi, self.n, torch.float64, self.device, "phi"),
+                                        _stream(self.device)))
+
+    def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        y = torch.empty_like(x) if out is None else out
+        _check(L.load().vpp_amr_apply(self._h, _vec(x, self.n, torch.float64, self.device, "x"),
+                                      _vec(y, self.n, torch.float64, self.device, "y"), _stream(self.device)))
+        return y
+
+    def diagonal(self) -> torch.Tensor:
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(L.load().vpp_amr_diagonal(self._h, _vec(d, self.n, torch.float64, self.device, "diag"),
+                                         _stream(self.device)))
+        return d
+
+    def cg_solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, rtol: float = 1e-8, atol: float = 0.0,
+                 max_iter: int = 100000, check_every: int = 0, raise_on_failure: bool = True):
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        o = L.CgOpts(rtol, atol, int(max_iter), L.VPP_FP64, 0.0, 0, int(check_every))
+        ci = L.CgInfo()
+        st = L.load().vpp_amr_cg_solve(self._h, _vec(b, self.n, torch.float64, self.device, "b"),
+                                       _vec(x, self.n, torch.float64, self.device, "x"), C.byref(o), C.byref(ci),
+                                       _stream(self.device))
+        if st != L.VPP_OK and (raise_on_failure or st not in (5, 6)):
+            _check(st)
+        return x, _info(ci)
+
+
 class PoissonSolve(torch.autograd.Function):
     """p = A_D(phi)^{-1} b with a hand-written adjoint.
 

@@ -11,7 +11,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvpp.so")
 SOURCES = ["apply_f64.hip", "apply_f32.hip", "apply_misc.hip", "blas.hip", "adjoint.hip", "closest_point.hip",
-           "levelset.hip", "noalloc.hip", "api.cpp"]
+           "levelset.hip", "noalloc.hip", "amr.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

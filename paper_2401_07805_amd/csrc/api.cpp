@@ -17,6 +17,7 @@
 
 #include "../../include/vpp.h"
 #include "blas.h"
+#include "amr.h"
 #include "kernels.h"
 #include "noalloc.h"
 
@@ -1261,6 +1262,349 @@ vpp_status vpp_reinit_rhs(vpp_problem p, const double* psi, const double* n0, co
     VPP_HIP(launch_reinit_rhs(p->k, ra, psi, b, (hipStream_t)stream));
     return VPP_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Once-refined meshes with hanging nodes.
+
+struct vpp_amr_s {
+    vpp_desc desc{};
+    int k = 2;
+    int64_t nc = 0, nf = 0, n = 0, nfree = 0;
+    AmrArgs args{};
+    int *d_cells = nullptr, *d_fkind = nullptr, *d_cptr = nullptr, *d_ccol = nullptr;
+    double* d_cw = nullptr;
+    unsigned char* d_ident = nullptr;
+    double *phi = nullptr, *diag = nullptr, *inv64 = nullptr;
+    float* inv32 = nullptr;
+    bool phi_set = false;
+    hipStream_t stream = nullptr;
+    ReinitWork* w = nullptr;   // CG vectors (allocated by the first solve)
+};
+
+static double gll_point(int k, int i)
+{
+    if (k == 2) return Tab<2>::t.gll[i];
+    if (k == 3) return Tab<3>::t.gll[i];
+    return Tab<4>::t.gll[i];
+}
+
+// Lagrange polynomial a of the GLL points of degree k at x (product formula).
+static double gll_lagrange(int k, int a, double x)
+{
+    double v = 1.0;
+    for (int b = 0; b <= k; ++b)
+        if (b != a) v *= (x - gll_point(k, b)) / (gll_point(k, a) - gll_point(k, b));
+    return v;
+}
+
+static void amr_free(vpp_amr a)
+{
+    if (!a) return;
+    dev_free(a->d_cells); dev_free(a->d_fkind); dev_free(a->d_cptr); dev_free(a->d_ccol); dev_free(a->d_cw);
+    dev_free(a->d_ident); dev_free(a->phi); dev_free(a->diag); dev_free(a->inv64); dev_free(a->inv32);
+    free_reinit(a->w);
+    if (a->stream) (void)hipStreamDestroy(a->stream);
+    delete a;
+}
+
+template <typename T>
+static vpp_status upload(T** dst, const std::vector<T>& src, const char* what)
+{
+    vpp_status s = dev_alloc(dst, src.size(), what);
+    if (s) return s;
+    if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(VPP_ERR_HIP, std::string("upload of ") + what + " failed");
+    return VPP_OK;
+}
+
+extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, vpp_amr* out)
+{
+    if (!d || !refined || !out) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    vpp_status vs = validate_desc(d);
+    if (vs) return vs;
+    const int k = d->degree;
+    const int nc[3] = {d->ncells[0], d->ncells[1], d->ncells[2]};
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    if (ncell > (int64_t(1) << 27)) return fail(VPP_ERR_INVALID_ARG, "mesh too large for the refined lattice");
+    int64_t cn[3], fn[3];
+    for (int i = 0; i < 3; ++i) {
+        cn[i] = (int64_t)k * nc[i] + 1;
+        fn[i] = 2 * (int64_t)k * nc[i] + 1;
+    }
+    const int64_t Nc = cn[0] * cn[1] * cn[2], Nf = fn[0] * fn[1] * fn[2];
+    if (Nc + Nf > (int64_t)INT32_MAX) return fail(VPP_ERR_INVALID_ARG, "mesh too large (at most 2^31-1 entries)");
+    auto ref = [&](int64_t cx, int64_t cy, int64_t cz) { return refined[cx + nc[0] * (cy + (int64_t)nc[1] * cz)] != 0; };
+    // nodes of unrefined coarse cells; fine nodes of refined ones
+    std::vector<uint8_t> cact(Nc, 0), fin(Nf, 0);
+    std::vector<int> cells;
+    for (int cz = 0; cz < nc[2]; ++cz)
+        for (int cy = 0; cy < nc[1]; ++cy)
+            for (int cx = 0; cx < nc[0]; ++cx) {
+                if (ref(cx, cy, cz)) continue;
+                cells.push_back(cx + nc[0] * (cy + nc[1] * cz));
+                for (int a2 = 0; a2 <= k; ++a2)
+                    for (int a1 = 0; a1 <= k; ++a1)
+                        for (int a0 = 0; a0 <= k; ++a0)
+                            cact[(k * cx + a0) + cn[0] * ((k * cy + a1) + cn[1] * (k * cz + a2))] = 1;
+            }
+    for (int fz = 0; fz < 2 * nc[2]; ++fz)
+        for (int fy = 0; fy < 2 * nc[1]; ++fy)
+            for (int fx = 0; fx < 2 * nc[0]; ++fx) {
+                if (!ref(fx / 2, fy / 2, fz / 2)) continue;
+                cells.push_back(-(1 + (fx + 2 * nc[0] * (fy + 2 * nc[1] * fz))));
+                for (int a2 = 0; a2 <= k; ++a2)
+                    for (int a1 = 0; a1 <= k; ++a1)
+                        for (int a0 = 0; a0 <= k; ++a0)
+                            fin[(k * fx + a0) + fn[0] * ((k * fy + a1) + fn[1] * (k * fz + a2))] = 1;
+            }
+    // a fine node on the closure of an unrefined coarse cell takes that cell's
+    // Q_k interpolant (the first such cell in z, y, x order): its constraint list
+    std::vector<int> fkind(Nf, -2), cptr(1, 0), ccol;
+    std::vector<double> cwv;
+    const int twok = 2 * k;
+    for (int64_t gf = 0; gf < Nf; ++gf) {
+        if (!fin[gf]) continue;
+        const int64_t v[3] = {gf % fn[0], (gf / fn[0]) % fn[1], gf / (fn[0] * fn[1])};
+        int lo[3], hi[3];
+        for (int i = 0; i < 3; ++i) {
+            const int c = (int)(v[i] / twok);
+            lo[i] = (v[i] % twok == 0) ? c - 1 : c;
+            hi[i] = c;
+            lo[i] = std::max(lo[i], 0);
+            hi[i] = std::min(hi[i], nc[i] - 1);
+        }
+        int own[3] = {-1, -1, -1};
+        for (int cz = lo[2]; cz <= hi[2] && own[0] < 0; ++cz)
+            for (int cy = lo[1]; cy <= hi[1] && own[0] < 0; ++cy)
+                for (int cx = lo[0]; cx <= hi[0] && own[0] < 0; ++cx)
+                    if (!ref(cx, cy, cz)) {
+                        own[0] = cx; own[1] = cy; own[2] = cz;
+                    }
+        if (own[0] < 0) {
+            fkind[gf] = -1;
+            continue;
+        }
+        double xi[3];
+        for (int i = 0; i < 3; ++i)
+            xi[i] = ((double)(v[i] / k) + gll_point(k, (int)(v[i] % k))) * 0.5 - own[i];
+        fkind[gf] = (int)cptr.size() - 1;
+        for (int a2 = 0; a2 <= k; ++a2)
+            for (int a1 = 0; a1 <= k; ++a1)
+                for (int a0 = 0; a0 <= k; ++a0) {
+                    const double w = gll_lagrange(k, a0, xi[0]) * gll_lagrange(k, a1, xi[1]) * gll_lagrange(k, a2, xi[2]);
+                    if (w == 0.0) continue;
+                    ccol.push_back((int)((k * own[0] + a0) + cn[0] * ((k * own[1] + a1) + cn[1] * (k * own[2] + a2))));
+                    cwv.push_back(w);
+                }
+        cptr.push_back((int)ccol.size());
+    }
+    // identity rows: entries that are not free unknowns, and Dirichlet ones
+    auto on_dirichlet = [&](const int64_t (&nn)[3], int64_t g) {
+        const int64_t i = g % nn[0], j = (g / nn[0]) % nn[1], l = g / (nn[0] * nn[1]);
+        const int64_t idx[3] = {i, j, l};
+        for (int dd = 0; dd < 3; ++dd) {
+            if (d->bc[2 * dd] == VPP_BC_DIRICHLET && idx[dd] == 0) return true;
+            if (d->bc[2 * dd + 1] == VPP_BC_DIRICHLET && idx[dd] == nn[dd] - 1) return true;
+        }
+        return false;
+    };
+    std::vector<unsigned char> ident(Nc + Nf, 1);
+    int64_t nfree = 0;
+    for (int64_t g = 0; g < Nc; ++g)
+        if (cact[g] && !on_dirichlet(cn, g)) {
+            ident[g] = 0;
+            ++nfree;
+        }
+    for (int64_t gf = 0; gf < Nf; ++gf)
+        if (fkind[gf] == -1 && !on_dirichlet(fn, gf)) {
+            ident[Nc + gf] = 0;
+            ++nfree;
+        }
+    DeviceGuard dg(d->device);
+    vpp_amr a = new vpp_amr_s();
+    a->desc = *d;
+    a->k = k;
+    a->nc = Nc;
+    a->nf = Nf;
+    a->n = Nc + Nf;
+    a->nfree = nfree;
+    vpp_status st;
+    if ((st = upload(&a->d_cells, cells, "amr cells")) || (st = upload(&a->d_fkind, fkind, "amr node kinds")) ||
+        (st = upload(&a->d_cptr, cptr, "amr constraint lists")) || (st = upload(&a->d_ccol, ccol, "amr constraints")) ||
+        (st = upload(&a->d_cw, cwv, "amr weights")) || (st = upload(&a->d_ident, ident, "amr identity rows")) ||
+        (st = dev_alloc(&a->phi, a->n, "amr phi")) || (st = dev_alloc(&a->diag, a->n, "amr diag")) ||
+        (st = dev_alloc(&a->inv64, a->n, "amr inverse diag")) || (st = dev_alloc(&a->inv32, a->n, "amr inverse diag"))) {
+        amr_free(a);
+        return st;
+    }
+    if (hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking) != hipSuccess) {
+        amr_free(a);
+        return fail(VPP_ERR_HIP, "hipStreamCreate failed");
+    }
+    AmrArgs& g = a->args;
+    g.mc = make_mesh_args(*d);
+    vpp_desc fd = *d;
+    for (int i = 0; i < 3; ++i) fd.ncells[i] = 2 * d->ncells[i];
+    g.mf = make_mesh_args(fd);
+    for (int i = 0; i < 3; ++i) g.mc.ntile[i] = g.mf.ntile[i] = 1;
+    g.nc = Nc;
+    g.n = a->n;
+    g.cells = a->d_cells;
+    g.ncells = (int)cells.size();
+    g.fkind = a->d_fkind;
+    g.cptr = a->d_cptr;
+    g.ccol = a->d_ccol;
+    g.cw = a->d_cw;
+    g.ident = a->d_ident;
+    *out = a;
+    return VPP_OK;
+}
+
+extern "C" vpp_status vpp_amr_destroy(vpp_amr a)
+{
+    if (!a) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    DeviceGuard dg(a->desc.device);
+    (void)hipDeviceSynchronize();
+    amr_free(a);
+    return VPP_OK;
+}
+
+extern "C" int64_t vpp_amr_num_dofs(vpp_amr a) { return a ? a->n : -1; }
+extern "C" int64_t vpp_amr_num_free(vpp_amr a) { return a ? a->nfree : -1; }
+
+extern "C" vpp_status vpp_amr_set_phi(vpp_amr a, const double* phi, void* stream)
+{
+    if (!a || !phi) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, phi);
+    DeviceGuard dg(a->desc.device);
+    hipStream_t s = (hipStream_t)stream;
+    VPP_HIP(hipMemcpyAsync(a->phi, phi, a->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    VPP_HIP(launch_amr_diag(a->k, a->args, a->phi, a->diag, a->inv64, a->inv32, s));
+    a->phi_set = true;
+    return VPP_OK;
+}
+
+extern "C" vpp_status vpp_amr_apply(vpp_amr a, const double* x, double* y, void* stream)
+{
+    if (!a || !x || !y) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, x, y);
+    if ((const void*)x == y) return fail(VPP_ERR_INVALID_ARG, "x and y must not alias");
+    if (!a->phi_set) return fail(VPP_ERR_STATE, "vpp_amr_set_phi has not been called");
+    DeviceGuard dg(a->desc.device);
+    VPP_HIP(launch_amr_apply(a->k, a->args, a->phi, x, y, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+extern "C" vpp_status vpp_amr_diagonal(vpp_amr a, double* diag, void* stream)
+{
+    if (!a || !diag) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, diag);
+    if (!a->phi_set) return fail(VPP_ERR_STATE, "vpp_amr_set_phi has not been called");
+    DeviceGuard dg(a->desc.device);
+    VPP_HIP(hipMemcpyAsync(diag, a->diag, a->n * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return VPP_OK;
+}
+
+extern "C" vpp_status vpp_amr_cg_solve(vpp_amr a, const double* b, double* x, const vpp_cg_opts* o,
+                                       vpp_cg_info* info, void* stream)
+{
+    if (!a || !b || !x || !o) return fail(VPP_ERR_INVALID_ARG, "null argument");
+    VPP_ALIGNED(8, b, x);
+    if (!(o->rtol >= 0.0) || !(o->atol >= 0.0) || o->max_iter < 0)
+        return fail(VPP_ERR_INVALID_ARG, "CG options out of range");
+    if (o->precision != VPP_FP64) return fail(VPP_ERR_UNSUPPORTED, "the refined-mesh solver runs in FP64");
+    if (!a->phi_set) return fail(VPP_ERR_STATE, "vpp_amr_set_phi has not been called");
+    DeviceGuard dg(a->desc.device);
+    if (!a->w) {
+        ReinitWork* w = new ReinitWork();
+        const size_t n = (size_t)a->n;
+        vpp_status st;
+        if ((st = dev_alloc(&w->b, n, "amr cg b")) || (st = dev_alloc(&w->r, n, "amr cg r")) ||
+            (st = dev_alloc(&w->p, n, "amr cg p")) || (st = dev_alloc(&w->q, n, "amr cg q")) ||
+            (st = dev_alloc(&w->red, kRedDoubles, "amr cg partials")) ||
+            (st = dev_alloc(&w->dot, kMaxRedBlocks, "amr cg dot partials")) || (st = dev_alloc(&w->rr, 1, "norm")) ||
+            (st = dev_alloc(&w->st, 1, "amr cg state"))) {
+            free_reinit(w);
+            return st;
+        }
+        if (hipHostMalloc((void**)&w->hst, sizeof(CgState), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&w->hrr, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            free_reinit(w);
+            return fail(VPP_ERR_OUT_OF_MEMORY, "amr cg host mirrors");
+        }
+        a->w = w;
+    }
+    VPP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    hipStream_t s = a->stream;
+    ReinitWork& w = *a->w;
+    const int64_t n = a->n;
+    const int one[3] = {1, 1, 1};
+    const SharedEnum none = shared_enum(a->args.mc, a->k, one);   // no shared nodes: q is used as it is
+    const int gdot = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxRedBlocks, (n + 1023) / 1024));
+    VPP_HIP(launch_amr_apply(a->k, a->args, a->phi, x, w.q, s));
+    CgState* hs = w.hst;
+    std::memset(hs, 0, sizeof(CgState));
+    VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
+    VPP_HIP(launch_cg_init<double>(w.st, w.red, b, w.q, w.r, w.p, a->inv64, n, s));
+    VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    vpp_cg_info inf{};
+    const double r0 = std::sqrt(hs->rr_last), rz0 = hs->rz[0];
+    const double thr = std::max(o->rtol * r0, o->atol);
+    inf.rel_residual = r0 > 0 ? 1.0 : 0.0;
+    bool iterate = true;
+    if (!std::isfinite(r0) || !std::isfinite(rz0)) {
+        inf.status = VPP_ERR_BREAKDOWN;
+        iterate = false;
+    } else if (r0 == 0.0 || r0 < o->atol) {
+        inf.status = VPP_OK;
+        iterate = false;
+    } else if (o->max_iter == 0) {
+        inf.status = VPP_ERR_NOT_CONVERGED;
+        iterate = false;
+    }
+    if (iterate) {
+        CgState init{};
+        init.rz[0] = rz0;
+        init.tol2 = thr * thr;
+        init.max_iter = o->max_iter;
+        *hs = init;
+        VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
+        const int chunk = o->check_every > 0 ? o->check_every : 32;
+        for (int done = 0; done < o->max_iter + chunk;) {
+            for (int it = 0; it < chunk; ++it, ++done) {
+                const int par = done & 1;
+                VPP_HIP(launch_amr_apply(a->k, a->args, a->phi, w.p, w.q, s));
+                VPP_HIP(launch_dot_partials(w.p, w.q, n, w.dot, gdot, s));
+                VPP_HIP(launch_cg_assemble_update<double>(w.st, par, w.red, w.dot, gdot, a->args.mc, none, nullptr, 0,
+                                                          w.r, w.q, a->inv64, n, s));
+                VPP_HIP(launch_cg_pupdate<double>(w.st, par, w.red, x, w.r, w.p, a->inv64, n, s));
+            }
+            VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            VPP_HIP(hipStreamSynchronize(s));
+            if (hs->halt[0] || hs->halt[1]) break;
+        }
+        inf.iterations = hs->iters;
+        inf.rel_residual = std::sqrt(hs->rr_last) / r0;
+        if (hs->breakdown) inf.status = VPP_ERR_BREAKDOWN;
+        else if (hs->rr_last < init.tol2) inf.status = VPP_OK;
+        else inf.status = VPP_ERR_NOT_CONVERGED;
+    }
+    VPP_HIP(launch_amr_apply(a->k, a->args, a->phi, x, w.q, s));
+    VPP_HIP(launch_residual(b, w.q, nullptr, n, w.red, w.rr, s));
+    VPP_HIP(hipMemcpyAsync(w.hrr, w.rr, sizeof(double), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    inf.true_rel_residual = r0 > 0 ? std::sqrt(*w.hrr) / r0 : 0.0;
+    if (info) *info = inf;
+    if (inf.status == VPP_ERR_NOT_CONVERGED) return fail(VPP_ERR_NOT_CONVERGED, "CG did not converge");
+    if (inf.status == VPP_ERR_BREAKDOWN) return fail(VPP_ERR_BREAKDOWN, "CG breakdown (p.Ap <= 0 or non-finite)");
+    return VPP_OK;
+}
+
+extern "C" {
 
 static void put_config(vpp_problem p, int prec, const LaunchCfg& c)
 {

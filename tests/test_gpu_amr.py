@@ -1,0 +1,123 @@
+"""GPU operator on once-refined meshes with hanging nodes (vpp_amr_*) against
+the oracle (oracle/amr.py: A = C^T A_cells C by full quadrature with an
+explicit constraint matrix): apply within 1e-12 relative (2-norm and
+max-norm) over every entry of the two-lattice vector, diagonal within 1e-13,
+and Jacobi PCG within 1e-8 of the oracle's solution with its true residual
+recomputed by the oracle's matrix; small meshes for k = 2, 3, 4 with masks
+that meet along faces, edges only, or in an L, and a 32^3 Q2 mesh refined
+within three cells of a droplet's interface."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from gpu_util import dev, host, rel, rel_max, say
+from oracle import amr
+
+pytestmark = pytest.mark.gpu
+
+vpp = pytest.importorskip("paper_2401_07805_amd")
+
+
+def _mask(nc, cells):
+    r = np.zeros(nc[::-1], dtype=bool)
+    for (cx, cy, cz) in cells:
+        r[cz, cy, cx] = True
+    return r.ravel()
+
+
+MASKS = {
+    "box": lambda nc: _mask(nc, [(x, y, z) for x in (1, 2) for y in (1, 2) for z in (1,)]),
+    "L": lambda nc: _mask(nc, [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]),
+    "edge": lambda nc: _mask(nc, [(0, 0, 0), (1, 1, 0), (2, 2, 1)]),
+}
+
+
+def _phi2(m, centre=(0.45, 0.52, 0.5), r=0.3):
+    x, y, z = amr.node_coords(m)
+    d = r - np.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)
+    return np.tanh(d / (2 * m.eps))
+
+
+def _gpu(m, mask):
+    return vpp.AmrProblem(m.ncells, m.degree, mask, m.origin, m.extent, m.bc, m.rho_l, m.rho_g, m.heaviside)
+
+
+SINE = lambda x, y, z: 3 * np.pi ** 2 * np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("shape", ["box", "L", "edge"])
+@pytest.mark.parametrize("hv", [W.H_LINEAR, W.H_PAPER])
+def test_amr_apply_and_diagonal(k, shape, hv):
+    nc = (4, 3, 3)
+    m = W.Mesh(ncells=nc, degree=k, bc=(0, 1, 1, 0, 0, 1), rho_l=1000.0, rho_g=1.0, heaviside=hv)
+    m.eps = 0.1
+    mask = MASKS[shape](nc)
+    phi = _phi2(m)
+    A, cls = amr.operator(m, mask, phi)
+    p = _gpu(m, mask)
+    assert p.n == A.shape[0] and p.nfree == int((cls["free"] & ~cls["dirichlet"]).sum())
+    p.set_phi(dev(phi))
+    say("amr apply", k, shape, hv)
+    for seed in (3, 4):
+        x = np.random.default_rng(seed).uniform(-1, 1, p.n)
+        y = host(p.apply(dev(x)))
+        yr = A @ x
+        assert rel(y, yr) < 1e-12 and rel_max(y, yr) < 1e-12, (rel(y, yr), rel_max(y, yr))
+    d = host(p.diagonal())
+    assert rel_max(d, A.diagonal()) < 1e-13
+
+
+@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("shape", ["L", "edge"])
+def test_amr_solve(k, shape):
+    nc = (4, 3, 3)
+    m = W.Mesh(ncells=nc, degree=k, rho_l=1000.0, rho_g=1.0)
+    m.eps = 0.1
+    mask = MASKS[shape](nc)
+    phi = _phi2(m)
+    A, _ = amr.operator(m, mask, phi)
+    b = amr.load(m, mask, SINE)
+    ref = spla.spsolve(A.tocsc(), b)
+    p = _gpu(m, mask)
+    p.set_phi(dev(phi))
+    say("amr solve", k, shape)
+    x, info = p.cg_solve(dev(b), rtol=1e-12)
+    x = host(x)
+    res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert info["status"] == 0 and rel(x, ref) < 1e-8 and res < 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_amr_band_32cube():
+    """32^3 coarse Q2 cells, droplet r 0.25 (eps = h/2 of the fine cells), the
+    coarse cells within 3 cells of the interface refined: every entry of the
+    apply, the diagonal, and PCG to rtol 1e-8 (true residual by the oracle's
+    matrix) and 1e-12 (within 1e-8 of the oracle's PCG solution)."""
+    n = 32
+    m = W.unit_cube(n, 2, 1000.0, 1.0)
+    m.eps = 1.0 / n
+    mask = amr.band_mask(m, (0.5, 0.5, 0.5), 0.25, 3.0)
+    x, y, z = amr.node_coords(m)
+    phi = np.tanh((0.25 - np.sqrt((x - .5) ** 2 + (y - .5) ** 2 + (z - .5) ** 2)) / (2 * m.eps))
+    say("amr 32^3 oracle")
+    A, cls = amr.operator(m, mask, phi)
+    b = amr.load(m, mask, SINE)
+    say("amr 32^3 oracle pcg")
+    ref, it = amr.pcg(A, b, rtol=1e-13)
+    p = _gpu(m, mask)
+    p.set_phi(dev(phi))
+    say("amr 32^3 gpu", p.n, p.nfree)
+    xv = np.random.default_rng(9).uniform(-1, 1, p.n)
+    yv = host(p.apply(dev(xv)))
+    assert rel(yv, A @ xv) < 1e-12 and rel_max(yv, A @ xv) < 1e-12
+    assert rel_max(host(p.diagonal()), A.diagonal()) < 1e-13
+    s8, i8 = p.cg_solve(dev(b), rtol=1e-8)
+    res = np.linalg.norm(b - A @ host(s8)) / np.linalg.norm(b)
+    s12, i12 = p.cg_solve(dev(b), rtol=1e-12)
+    err = rel(host(s12), ref)
+    print(f"amr 32^3: free {p.nfree}; rtol 1e-8 it {i8['iterations']} true res {res:.2e}; "
+          f"rtol 1e-12 it {i12['iterations']} err vs oracle {err:.2e} (oracle it {it})")
+    assert i8["status"] == 0 and res < 1.01e-8
+    assert i12["status"] == 0 and err < 1e-8
