@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--extras", action="store_true", help="also time FP32, Q3/Q4, hot-cache applies, bubble solves")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--sweep", type=int, default=0, metavar="K",
+                    help="instead of the bench line: time every apply configuration of degree K on the droplet "
+                         "(cold, 100 applies) and print one JSON line per configuration")
+    ap.add_argument("--variants", default="", help="with --sweep: comma-separated kernel variants to time")
     return ap.parse_args()
 
 
@@ -325,7 +329,57 @@ def secondary(torch, vpp, W, dev, cache, xs, ys, probs_q2):
                      "roofline_frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
     del gphi
     out["adjoint_q2"] = res
+    out["amr_q2"] = amr_figures(torch, vpp, W, dev)
     return out
+
+
+def amr_figures(torch, vpp, W, dev):
+    """Once-refined mesh with hanging nodes: 32^3 coarse Q2 cells, the cells
+    within three cells of the droplet's interface (r 0.25) refined once, phi
+    with eps = half the fine cell size on both lattices, ratio 1000.  Hot apply
+    (HIP events, 20 applies) per free unknown, against 24 B per entry of the
+    two-lattice vector (x, phi read, y written), and PCG from 0 to rtol 1e-8
+    for the nodal values of sin(pi x) sin(pi y) sin(pi z) as a synthetic
+    right-hand side."""
+    n = 32
+    m = W.unit_cube(n, 2, 1000.0, 1.0)
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    mask = (np.abs(np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2) - 0.25) < 3.0 * h).ravel()
+    p = vpp.AmrProblem(m.ncells, 2, mask, m.origin, m.extent, m.bc, m.rho_l, m.rho_g, m.heaviside)
+    # node coordinates of both lattices (Q2: equidistant support points)
+    xs = []
+    for nn in (2 * n + 1, 4 * n + 1):
+        ax = np.linspace(0.0, 1.0, nn)
+        Zz, Yy, Xx = np.meshgrid(ax, ax, ax, indexing="ij")
+        xs.append((Xx.ravel(), Yy.ravel(), Zz.ravel()))
+    x, y, z = (np.concatenate([xs[0][d], xs[1][d]]) for d in range(3))
+    eps = 0.5 * h / 2.0
+    phi = np.tanh((0.25 - np.sqrt((x - .5) ** 2 + (y - .5) ** 2 + (z - .5) ** 2)) / (2 * eps))
+    p.set_phi(torch.from_numpy(phi).to(dev))
+    xv = torch.from_numpy(W.uniform_vectors(1, 1, p.n)[0]).to(dev)
+    yv = torch.empty_like(xv)
+    p.apply(xv, out=yv)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        p.apply(xv, out=yv)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / 20
+    b = torch.from_numpy(np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)).to(dev)
+    p.cg_solve(b, rtol=1e-8)
+    t0 = time.perf_counter()
+    _, info = p.cg_solve(b, rtol=1e-8)
+    t_cg = time.perf_counter() - t0
+    nbytes = 24.0 * p.n
+    return {"coarse_cells": n ** 3, "refined_cells": int(mask.sum()), "entries": p.n, "free": p.nfree,
+            "apply_us": us, "mdofs_free": p.nfree / us, "bytes_per_apply_24_per_entry": nbytes,
+            "roofline_frac_24_per_entry": nbytes / us / 1e3 / HBM_PEAK_GBS,
+            "cg_s": t_cg, "cg_iters": info["iterations"], "cg_true_rel_res": info["true_rel_residual"]}
 
 
 def extras(torch, vpp, W, dev, cache):
@@ -624,6 +678,53 @@ def batch_cg_figures(torch, bt, probs, bs):
             "batch_cg_sequential_iters_sum": sum(i["iterations"] for i in seq)}
 
 
+def config_sweep(torch, vpp, W, k, variants):
+    """Cold FP64 / FP32 apply time of every tuner candidate of degree k on the
+    droplet at its full size (64^3 Q2, 43^3 Q3, 32^3 Q4), each configuration's
+    FP64 output compared with the first one's.  FP32 is timed only for
+    configurations that have an FP32 kernel."""
+    dev = torch.device("cuda", 0)
+    wl = W.droplet_at_scale(k=k, nvec=0)
+    m = wl.mesh
+    N = m.ndofs
+    napp = 100
+    npool = max(1, min(napp, math.ceil(600e6 / (BYTES_PER_DOF_F64 * N))))
+    phi_t = torch.from_numpy(wl.phi).to(dev)
+    probs = []
+    for _ in range(npool):
+        p = vpp.Problem.from_mesh(m)
+        p.set_phi(phi_t)
+        probs.append(p)
+    xs = torch.from_numpy(W.uniform_vectors(1, napp, N)).to(dev)
+    ys = torch.empty_like(xs)
+    x32 = xs.float()
+    y32 = torch.empty_like(x32)
+    log(f"sweep k={k} N={N} pool={npool}")
+    ref = None
+    for cfg in vpp.config_candidates(k):
+        if variants and int(cfg["variant"]) not in variants:
+            continue
+        for p in probs:
+            p.set_config(cfg["variant"], cfg["tile"], "fp64")
+        t64 = cold_rate(torch, probs, xs, ys, napp)
+        line = {"k": k, "ndofs": N, "variant": int(cfg["variant"]), "tile": list(cfg["tile"]),
+                "fp64_us": t64 * 1e6, "fp64_frac": BYTES_PER_DOF_F64 * N / t64 / 1e9 / HBM_PEAK_GBS}
+        try:
+            for p in probs:
+                p.set_config(cfg["variant"], cfg["tile"], "fp32")
+        except vpp.VppError:
+            pass                      # an FP64-only configuration
+        else:
+            t32 = cold_rate(torch, probs, x32, y32, napp)
+            line["fp32_us"] = t32 * 1e6
+            line["fp32_frac"] = BYTES_PER_DOF_F32 * N / t32 / 1e9 / HBM_PEAK_GBS
+        y0 = ys[0].clone()
+        if ref is None:
+            ref = y0
+        line["rel_diff_vs_first"] = float(torch.linalg.norm(y0 - ref) / torch.linalg.norm(ref))
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -631,6 +732,12 @@ def main():
               "note); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.sweep:
+        import workloads as W
+        import paper_2401_07805_amd as vpp
+        variants = {int(v) for v in args.variants.split(",") if v}
+        config_sweep(torch, vpp, W, args.sweep, variants)
+        return
     import workloads as W
     import paper_2401_07805_amd as vpp
 
