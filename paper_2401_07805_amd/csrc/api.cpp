@@ -297,27 +297,16 @@ static bool arith_law(const vpp_desc& d) { return d.heaviside >= VPP_H_LINEAR_AR
 // Configurations a problem may run: those instantiated with the arithmetic
 // density mean or with the mass shift when it has one, else every
 // configuration of its degree.
-static bool config_ok(vpp_problem p, const LaunchCfg& c, int prec)
+static bool config_ok(vpp_problem p, const LaunchCfg& c)
 {
-    if (prec == VPP_FP32 && !config_has_fp32(c)) return false;
     if (arith_law(p->desc)) return arith_config_supported(c, p->k);
     return p->m.mass != 0.0 ? mass_config_supported(c, p->k) : apply_config_supported(c, p->k);
 }
 
-// Candidates of one precision (the FP64-only configurations left out for FP32).
-static int config_list(vpp_problem p, LaunchCfg* out, int cap, int prec)
+static int config_list(vpp_problem p, LaunchCfg* out, int cap)
 {
-    LaunchCfg all[64];
-    int n;
-    if (arith_law(p->desc)) n = list_arith_configs(p->k, all, 64);
-    else n = p->m.mass != 0.0 ? list_mass_configs(p->k, all, 64) : list_apply_configs(p->k, all, 64);
-    int m = 0;
-    for (int i = 0; i < std::min(n, 64); ++i)
-        if (prec != VPP_FP32 || config_has_fp32(all[i])) {
-            if (m < cap && out) out[m] = all[i];
-            ++m;
-        }
-    return m;
+    if (arith_law(p->desc)) return list_arith_configs(p->k, out, cap);
+    return p->m.mass != 0.0 ? list_mass_configs(p->k, out, cap) : list_apply_configs(p->k, out, cap);
 }
 
 static vpp_status do_apply64(vpp_problem p, const double* x, double* y, double* dot, const int* done, hipStream_t s)
@@ -1645,7 +1634,7 @@ vpp_status vpp_set_config_for(vpp_problem p, int32_t precision, const vpp_kernel
     if (precision != VPP_FP64 && precision != VPP_FP32)
         return fail(VPP_ERR_INVALID_ARG, "precision must be VPP_FP64 or VPP_FP32");
     LaunchCfg c{cfg->variant, {cfg->tile[0], cfg->tile[1], cfg->tile[2]}};
-    if (!config_ok(p, c, precision))
+    if (!config_ok(p, c))
         return fail(VPP_ERR_UNSUPPORTED, p->m.mass != 0.0 ? "kernel configuration not available with the mass shift"
                                                           : "kernel configuration not available");
     DeviceGuard dg(p->desc.device);
@@ -1660,8 +1649,6 @@ vpp_status vpp_set_config(vpp_problem p, const vpp_kernel_config* cfg)
 {
     vpp_status s = vpp_set_config_for(p, VPP_FP64, cfg);
     if (s) return s;
-    // an FP64-only configuration leaves the FP32 choice as it is
-    if (!config_has_fp32(LaunchCfg{cfg->variant, {cfg->tile[0], cfg->tile[1], cfg->tile[2]}})) return VPP_OK;
     return vpp_set_config_for(p, VPP_FP32, cfg);
 }
 
@@ -1688,7 +1675,7 @@ static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path
                                                              : (mass ? "applym/hbm" : "apply/hbm"),
                                             p->k, p->N);
     LaunchCfg c;
-    if (cache_lookup(cache_path, key, &c) && config_ok(p, c, prec)) {
+    if (cache_lookup(cache_path, key, &c) && config_ok(p, c)) {
         put_config(p, prec, c);
         return ensure_apply_scratch(p);
     }
@@ -1699,7 +1686,7 @@ static vpp_status tune_precision(vpp_problem p, int prec, const char* cache_path
     if (prec == VPP_FP32) VPP_HIP(launch_fill<float>(w.p32, p->N, 1.0f, s));
     else VPP_HIP(launch_fill<double>(w.x, p->N, 1.0, s));
     LaunchCfg cands[64];
-    const int n = std::min(config_list(p, cands, 64, prec), 64);
+    const int n = std::min(config_list(p, cands, 64), 64);
     constexpr int reps = 6;
     hipEvent_t ev[2 * reps] = {};
     for (int r = 0; r < 2 * reps && !st; ++r)

@@ -1,9 +1,6 @@
 // Instantiated apply configurations and the generic launcher.
 #pragma once
-#include <type_traits>
-
 #include "apply_impl.h"
-#include "apply_mfma.h"
 
 namespace vpp {
 
@@ -18,8 +15,6 @@ namespace vpp {
     X(2, 0, 16, 4, 4)         \
     X(2, 0, 8, 4, 4)          \
     X(2, 1, 8, 4, 2)          \
-    X(3, 6, 8, 4, 4)          \
-    X(3, 6, 4, 4, 4)          \
     X(3, 2, 8, 8, 4)          \
     X(3, 2, 8, 4, 4)          \
     X(3, 2, 4, 4, 4)          \
@@ -59,25 +54,20 @@ inline auto kernel_ptr()
     if constexpr (V == 0) return &apply_cell_kernel<K, T, TX, TY, TZ, HV, DOT>;
     else if constexpr (V == 1) return &apply_plane_kernel<K, T, TX, TY, TZ, HV, DOT, MASS>;
     else if constexpr (V == 2) return &apply_half_kernel<K, T, TX, TY, TZ, HV, DOT>;
-    else if constexpr (V == 6) return &apply_mfma_kernel<T, TX, TY, TZ, HV, DOT>;
     else return &apply_slot_kernel<K, T, TX, TY, TZ, HV, DOT, MASS>;
 }
 
 template <int K, typename T, int V, int TX, int TY, int TZ, int HV, bool DOT, bool MASS>
 inline hipError_t launch_hv(const ApplyArgs<T>& a, hipStream_t s)
 {
-    if constexpr (V == 6 && (K != 3 || !std::is_same<T, double>::value || MASS)) {
-        return hipErrorInvalidValue;   // the matrix-core variant: k = 3, FP64, no mass shift
-    } else {
     const int nblocks = a.m.ntile[0] * a.m.ntile[1] * a.m.ntile[2];
-    constexpr int threads = V == 6 ? 64 * (TX * TY * TZ / 16) : (V == 1 ? (K + 1) * TX * TY * TZ : (V == 2 ? 2 : 1) * TX * TY * TZ);
+    constexpr int threads = V == 1 ? (K + 1) * TX * TY * TZ : (V == 2 ? 2 : 1) * TX * TY * TZ;
     hipLaunchKernelGGL((kernel_ptr<K, T, V, TX, TY, TZ, HV, DOT, MASS>()), dim3(nblocks), dim3(threads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.tiles_only) return e;
     const int tile[3] = {TX, TY, TZ};
     AssembleArgs<T> b{a.m, shared_enum(a.m, K, tile), a.part, a.nshared, a.y, a.dot_part, nblocks, a.dot, a.done};
     return launch_assemble<T>(b, s);
-    }
 }
 
 template <int K, typename T, int V, int TX, int TY, int TZ, bool MASS = false>

@@ -27,12 +27,9 @@ struct ApplyArgs {
 // Per-problem launch configuration.
 struct LaunchCfg {
     int variant;        // 0 cell per thread (LDS atomics), 1 plane per thread, 2 half cell per thread (k = 3),
-                        // 4 cell per thread (LDS slots), 6 cell per wavefront on the matrix cores (k = 3, FP64)
+                        // 4 cell per thread (LDS slots)
     int tile[3];
 };
-
-// Whether a configuration also runs in FP32 (variant 6 runs the matrix cores in FP64 only).
-inline bool config_has_fp32(const LaunchCfg& c) { return c.variant != 6; }
 
 inline int block_nodes(const LaunchCfg& c, int k)
 {
