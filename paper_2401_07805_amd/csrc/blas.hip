@@ -241,6 +241,14 @@ __global__ void __launch_bounds__(BT) cg_assemble_update_kernel(CgState* st, int
     assemble_update_body<T>(blockIdx.x, gridDim.x, st, par, red, sp, r, q, invd, n);
 }
 
+// Packets a thread handles per batch in the search-direction update.  A
+// thread takes packets c, c + S, c + 2S, ... (S = threads of the system's
+// grid) in that order, as a plain grid-stride loop would, but loads a whole
+// batch before it uses any of it, and the first batch before the reduction
+// that gives beta: each batch then costs one memory latency instead of one
+// per packet.
+constexpr int kBatch = 4;
+
 // Body of the search-direction update for workgroup bid of nblk (one system;
 // ng partials of the update to sum).
 template <typename T>
@@ -252,6 +260,25 @@ __device__ __forceinline__ void pupdate_body(int bid, int nblk, CgState* st, int
         if (bid == 0 && threadIdx.x == 0) st->halt[1 - par] = 1;
         return;
     }
+    using P = Pack<T>;
+    constexpr int W = P::W, U = kBatch;
+    const int64_t np = n / W;
+    const int64_t S = (int64_t)nblk * BT;
+    const int64_t c0 = (int64_t)bid * BT + threadIdx.x;
+    P rv[U], dv[U], pv[U], xv[U];
+    auto load = [&](int64_t cb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t c = cb + u * S;
+            if (c < np) {
+                rv[u] = reinterpret_cast<const P*>(r)[c];
+                dv[u] = reinterpret_cast<const P*>(invd)[c];
+                pv[u] = reinterpret_cast<const P*>(p)[c];
+                xv[u] = reinterpret_cast<const P*>(x)[c];
+            }
+        }
+    };
+    load(c0);
     double rr, rzn;
     sum_partials(red, ng, rr, rzn);
     const double beta_d = rzn / st->rz[par];
@@ -272,23 +299,23 @@ __device__ __forceinline__ void pupdate_body(int bid, int nblk, CgState* st, int
     // the same alpha as the update's (same operands, same rounding)
     const T alpha = T(st->rz[par] / st->pAp);
     const T beta = T(beta_d);
-    using P = Pack<T>;
-    const int64_t np = n / P::W;
-    for (int64_t c = (int64_t)bid * BT + threadIdx.x; c < np; c += (int64_t)nblk * BT) {
-        const P rv = reinterpret_cast<const P*>(r)[c];
-        const P dv = reinterpret_cast<const P*>(invd)[c];
-        P pv = reinterpret_cast<const P*>(p)[c];
-        P xv = reinterpret_cast<const P*>(x)[c];
+    for (int64_t cb = c0; cb < np; cb += U * S) {
+        if (cb != c0) load(cb);
 #pragma unroll
-        for (int j = 0; j < P::W; ++j) {
-            xv.v[j] = fma(alpha, pv.v[j], xv.v[j]);
-            pv.v[j] = fma(beta, pv.v[j], rv.v[j] * dv.v[j]);
+        for (int u = 0; u < U; ++u) {
+            const int64_t c = cb + u * S;
+            if (c >= np) break;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                xv[u].v[j] = fma(alpha, pv[u].v[j], xv[u].v[j]);
+                pv[u].v[j] = fma(beta, pv[u].v[j], rv[u].v[j] * dv[u].v[j]);
+            }
+            reinterpret_cast<P*>(x)[c] = xv[u];
+            reinterpret_cast<P*>(p)[c] = pv[u];
         }
-        reinterpret_cast<P*>(x)[c] = xv;
-        reinterpret_cast<P*>(p)[c] = pv;
     }
     if (bid == 0)
-        for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) {
+        for (int64_t i = np * W + threadIdx.x; i < n; i += BT) {
             x[i] = fma(alpha, p[i], x[i]);
             p[i] = fma(beta, p[i], r[i] * invd[i]);
         }

@@ -17,3 +17,22 @@ def test_shared_node_enumeration(tmp_path):
     print(out.stdout)
     assert out.returncode == 0, out.stdout
     assert " 0 failures" in out.stdout
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    """The C oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc, CPU only) and driven through every entry point on small meshes of
+    degree 1-4, several boundary patterns, both Heaviside laws and the mass
+    shift; an invalid access, leak or undefined operation aborts the run."""
+    exe = str(tmp_path / "oracle_sanitize")
+    root = os.path.dirname(HERE)
+    subprocess.check_call(["gcc", "-std=c11", "-O1", "-g", "-fopenmp", "-D_GNU_SOURCE",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", os.path.join(root, "oracle", "oracle.c"),
+                           os.path.join(HERE, "host", "oracle_sanitize.c"), "-o", exe, "-lm"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", OMP_NUM_THREADS="2")
+    out = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    print(out.stdout[-2000:], out.stderr[-4000:])
+    assert out.returncode == 0, out.stderr[-4000:]
+    assert "0 failures" in out.stdout
+    assert "ERROR: AddressSanitizer" not in out.stderr and "runtime error" not in out.stderr
