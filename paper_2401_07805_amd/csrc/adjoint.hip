@@ -81,14 +81,13 @@ __global__ void __launch_bounds__(64) grad_coef_kernel(MeshArgs m, const double*
 
 template <int K>
 __global__ void __launch_bounds__(64) grad_phi_kernel(MeshArgs m, const double* __restrict__ phi,
-                                                      const double* __restrict__ g, double* __restrict__ out)
+                                                      const double* __restrict__ g, double* __restrict__ out,
+                                                      CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    if (cell >= ncell) return;
-    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
-              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    int cx, cy, cz;
+    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
+    const int64_t cell = cx + (int64_t)m.nc[0] * (cy + (int64_t)m.nc[1] * cz);
     double s[N3];
     load_cell<K>(m, phi, cx, cy, cz, false, s);
     sweep3<K, MS, false, 0>(s);
@@ -111,7 +110,7 @@ __global__ void __launch_bounds__(64) grad_phi_kernel(MeshArgs m, const double* 
         for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
             for (int a0 = 0; a0 < N; ++a0)
-                atomicAdd(&out[base + a0 + nx * a1 + nxy * a2], s[a0 + N * (a1 + N * a2)]);
+                out[base + a0 + nx * a1 + nxy * a2] += s[a0 + N * (a1 + N * a2)];
 }
 
 hipError_t launch_grad_coef(int k, const MeshArgs& m, const double* p, const double* lam, double* g, hipStream_t s)
@@ -129,15 +128,22 @@ hipError_t launch_grad_coef(int k, const MeshArgs& m, const double* p, const dou
 
 hipError_t launch_grad_phi(int k, const MeshArgs& m, const double* phi, const double* g, double* out, hipStream_t s)
 {
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    const int blocks = (int)((ncell + 63) / 64);
+    // one launch per cell colour: the scatter into the nodes needs no atomics
     switch (k) {
-    case 2: hipLaunchKernelGGL(grad_phi_kernel<2>, dim3(blocks), dim3(64), 0, s, m, phi, g, out); break;
-    case 3: hipLaunchKernelGGL(grad_phi_kernel<3>, dim3(blocks), dim3(64), 0, s, m, phi, g, out); break;
-    case 4: hipLaunchKernelGGL(grad_phi_kernel<4>, dim3(blocks), dim3(64), 0, s, m, phi, g, out); break;
+    case 2:
+        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {
+            hipLaunchKernelGGL(grad_phi_kernel<2>, dim3(blocks), dim3(64), 0, s, m, phi, g, out, cc);
+        });
+    case 3:
+        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {
+            hipLaunchKernelGGL(grad_phi_kernel<3>, dim3(blocks), dim3(64), 0, s, m, phi, g, out, cc);
+        });
+    case 4:
+        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {
+            hipLaunchKernelGGL(grad_phi_kernel<4>, dim3(blocks), dim3(64), 0, s, m, phi, g, out, cc);
+        });
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace vpp

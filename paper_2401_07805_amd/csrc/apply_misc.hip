@@ -7,18 +7,16 @@ namespace vpp {
 // ---------------------------------------------------------------------------
 // Diagonal: diag_a = sum_q cw_q sum_d rd[d] (dN_a/dxi_d (x_q))^2 (+ the mass
 // shift's mu hx hy hz sum_q wref_q N_a(x_q)^2), from squared 1D tables (each
-// term is a product of three 1D factors).  Runs once per phi.
+// term is a product of three 1D factors).  Runs once per phi, one launch per
+// cell colour (cell_color), adding into the zeroed diagonal without atomics.
 
 template <int K, int HV>
 __global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __restrict__ phi,
-                                                   double* __restrict__ diag)
+                                                   double* __restrict__ diag, CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    if (cell >= ncell) return;
-    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
-              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    int cx, cy, cz;
+    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double A[N3], Z[N3], Y[N3], out[N3];
     cell_coefficient<K, HV>(m, phi, cx, cy, cz, A);
 #pragma unroll
@@ -59,7 +57,7 @@ __global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __re
         for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
             for (int a0 = 0; a0 < N; ++a0)
-                atomicAdd(&diag[base + a0 + nx * a1 + nxy * a2], out[a0 + N * (a1 + N * a2)]);
+                diag[base + a0 + nx * a1 + nxy * a2] += out[a0 + N * (a1 + N * a2)];
 }
 
 __global__ void fix_diagonal_kernel(MeshArgs m, double* __restrict__ diag, double* __restrict__ inv64,
@@ -104,21 +102,23 @@ template hipError_t launch_fill<int>(int*, int64_t, int, hipStream_t);
 
 hipError_t launch_diag(int k, const MeshArgs& m, const double* phi, double* diag, hipStream_t s)
 {
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    const int blocks = (int)((ncell + 63) / 64);
-#define VPP_DIAG(K)                                                                                  \
-    if (m.heaviside == 0) hipLaunchKernelGGL((diag_kernel<K, 0>), dim3(blocks), dim3(64), 0, s, m, phi, diag);      \
-    else if (m.heaviside == 1) hipLaunchKernelGGL((diag_kernel<K, 1>), dim3(blocks), dim3(64), 0, s, m, phi, diag); \
-    else if (m.heaviside == 2) hipLaunchKernelGGL((diag_kernel<K, 2>), dim3(blocks), dim3(64), 0, s, m, phi, diag); \
-    else hipLaunchKernelGGL((diag_kernel<K, 3>), dim3(blocks), dim3(64), 0, s, m, phi, diag);
+    // one launch per cell colour: the scatter into the nodes needs no atomics
+#define VPP_DIAG(K)                                                                                              \
+    return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {                                         \
+        if (m.heaviside == 0) hipLaunchKernelGGL((diag_kernel<K, 0>), dim3(blocks), dim3(64), 0, s, m, phi, diag, cc); \
+        else if (m.heaviside == 1)                                                                               \
+            hipLaunchKernelGGL((diag_kernel<K, 1>), dim3(blocks), dim3(64), 0, s, m, phi, diag, cc);            \
+        else if (m.heaviside == 2)                                                                               \
+            hipLaunchKernelGGL((diag_kernel<K, 2>), dim3(blocks), dim3(64), 0, s, m, phi, diag, cc);            \
+        else hipLaunchKernelGGL((diag_kernel<K, 3>), dim3(blocks), dim3(64), 0, s, m, phi, diag, cc);           \
+    });
     switch (k) {
-    case 2: VPP_DIAG(2) break;
-    case 3: VPP_DIAG(3) break;
-    case 4: VPP_DIAG(4) break;
+    case 2: VPP_DIAG(2)
+    case 3: VPP_DIAG(3)
+    case 4: VPP_DIAG(4)
     default: return hipErrorInvalidValue;
     }
 #undef VPP_DIAG
-    return hipGetLastError();
 }
 
 hipError_t launch_fix_diagonal(const MeshArgs& m, double* diag, double* inv64, float* inv32, hipStream_t s)

@@ -52,6 +52,62 @@ __host__ __device__ inline bool is_dirichlet(const MeshArgs& m, int i, int j, in
            ((m.bcmask & 16) && l == 0) || ((m.bcmask & 32) && l == m.nn[2] - 1);
 }
 
+// Parity colouring of the cells for node scatter-adds without atomics: colour
+// c holds the cells whose indices have the parities (c & 1, (c >> 1) & 1,
+// (c >> 2) & 1).  Two cells of one colour are two or more cells apart along
+// some direction, so they share no node and their threads may add into the
+// nodes with plain loads and stores; the colours run one launch after another
+// in a fixed order, so every node sum is formed in the same order on every
+// run.
+struct CellColor {
+    int c[3];     // parity per direction
+    int n[3];     // cells of the colour per direction
+};
+
+__host__ __device__ inline CellColor cell_color(const MeshArgs& m, int color)
+{
+    CellColor cc;
+    for (int d = 0; d < 3; ++d) {
+        cc.c[d] = (color >> d) & 1;
+        cc.n[d] = m.nc[d] > cc.c[d] ? (m.nc[d] - cc.c[d] + 1) / 2 : 0;
+    }
+    return cc;
+}
+
+__host__ __device__ inline int64_t color_count(const CellColor& cc)
+{
+    return (int64_t)cc.n[0] * cc.n[1] * cc.n[2];
+}
+
+// Cell of position i in colour cc; false past the colour's last cell.
+__host__ __device__ inline bool color_cell(const CellColor& cc, int64_t i, int& cx, int& cy, int& cz)
+{
+    if (i >= color_count(cc)) return false;
+    const int a = (int)(i % cc.n[0]);
+    const int64_t r = i / cc.n[0];
+    const int b = (int)(r % cc.n[1]), e = (int)(r / cc.n[1]);
+    cx = 2 * a + cc.c[0];
+    cy = 2 * b + cc.c[1];
+    cz = 2 * e + cc.c[2];
+    return true;
+}
+
+// Launches launch(colour, blocks) for the eight colours in order, with
+// enough blocks of bt threads for one thread per cell of the colour.
+template <typename F>
+inline hipError_t for_each_color(const MeshArgs& m, int bt, F&& launch)
+{
+    for (int c = 0; c < 8; ++c) {
+        const CellColor cc = cell_color(m, c);
+        const int64_t n = color_count(cc);
+        if (n == 0) continue;
+        launch(cc, (int)((n + bt - 1) / bt));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Sine-ramp Heaviside of Eq. heaviside written in phi through Eq. distance:
 // with a = artanh(phi) = d/(2 eps), H = 1/2 + a/3 + sin(2 pi a/3)/(2 pi) for
 // |a| < 3/2, and 0 / 1 beyond.  eps cancels.

@@ -8,8 +8,9 @@
 //              n_h the (filtered) nodal normal components.
 // One cell per thread: values at the Gauss points by the interpolation
 // sweeps, derivatives by the collocation derivative along each direction,
-// the weights W_q, the transposed interpolation sweeps, and an atomic
-// scatter-add into the nodes (all rows assembled, no constraint applied).
+// the weights W_q, the transposed interpolation sweeps, and a scatter-add into
+// the nodes (all rows assembled, no constraint applied) without atomics: one
+// launch per cell colour (cell_color), so every node sum has a fixed order.
 #include "kernels.h"
 
 namespace vpp {
@@ -43,7 +44,7 @@ __device__ __forceinline__ void scatter_add(const MeshArgs& m, int cx, int cy, i
 #pragma unroll
         for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
-            for (int a0 = 0; a0 < N; ++a0) atomicAdd(&b[base + a0 + nx * a1 + nxy * a2], s[a0 + N * (a1 + N * a2)]);
+            for (int a0 = 0; a0 < N; ++a0) b[base + a0 + nx * a1 + nxy * a2] += s[a0 + N * (a1 + N * a2)];
 }
 
 template <int K>
@@ -57,15 +58,12 @@ __device__ __forceinline__ void transpose_interp(double (&s)[(K + 1) * (K + 1) *
 template <int K>
 __global__ void __launch_bounds__(64) normal_rhs_kernel(RhsGeo g, const double* __restrict__ phi,
                                                         double* __restrict__ b0, double* __restrict__ b1,
-                                                        double* __restrict__ b2)
+                                                        double* __restrict__ b2, CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = g.m;
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    if (cell >= ncell) return;
-    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
-              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    int cx, cy, cz;
+    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double gx[N3], gy[N3], gz[N3];
     load_nodes<K>(m, phi, cx, cy, cz, gx);
     sweep3<K, MS, false, 0>(gx);
@@ -111,15 +109,13 @@ __device__ __forceinline__ void add_derivative(const MeshArgs& m, const double* 
 template <int K>
 __global__ void __launch_bounds__(64) curvature_rhs_kernel(RhsGeo g, const double* __restrict__ n0,
                                                            const double* __restrict__ n1,
-                                                           const double* __restrict__ n2, double* __restrict__ b)
+                                                           const double* __restrict__ n2, double* __restrict__ b,
+                                                           CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = g.m;
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    if (cell >= ncell) return;
-    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
-              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    int cx, cy, cz;
+    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double div[N3];
 #pragma unroll
     for (int q = 0; q < N3; ++q) div[q] = 0.0;
@@ -137,8 +133,8 @@ __global__ void __launch_bounds__(64) curvature_rhs_kernel(RhsGeo g, const doubl
 // time with the compressive flux explicit):
 //   (psi', v)/dtau + eps ((grad psi' . n)(grad v . n)) = (psi, v)/dtau + ((1 - psi^2)/2 n, grad v),
 // boundary terms of the integrations by parts dropped, n the nodal normal
-// interpolated at the Gauss points as it is.  One cell per thread, atomic
-// scatter-add (the output is zeroed first).
+// interpolated at the Gauss points as it is.  One cell per thread, one launch
+// per cell colour, scatter-add without atomics (the output is zeroed first).
 
 // The nodal normal components at the Gauss points of a cell.
 template <int K>
@@ -197,15 +193,12 @@ __device__ __forceinline__ void add_flux(const double (&w)[(K + 1) * (K + 1) * (
 
 template <int K>
 __global__ void __launch_bounds__(64) reinit_apply_kernel(ReinitArgs r, const double* __restrict__ x,
-                                                          double* __restrict__ y)
+                                                          double* __restrict__ y, CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = r.g.m;
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    if (cell >= ncell) return;
-    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
-              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    int cx, cy, cz;
+    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     // One normal component is live at a time (interpolated again for the
     // flux pass): holding all three at the Gauss points left one wave per SIMD.
     double u[N3], s[N3], out[N3], nd[N3];
@@ -303,15 +296,12 @@ __device__ __forceinline__ void diag_pair(const ReinitArgs& r, const double (&nq
 }
 
 template <int K>
-__global__ void __launch_bounds__(64) reinit_diag_kernel(ReinitArgs r, double* __restrict__ diag)
+__global__ void __launch_bounds__(64) reinit_diag_kernel(ReinitArgs r, double* __restrict__ diag, CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = r.g.m;
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    if (cell >= ncell) return;
-    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
-              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    int cx, cy, cz;
+    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double nq[3][N3], out[N3], c[N3];
     normal_at_gauss<K>(r, cx, cy, cz, nq);
 #pragma unroll
@@ -331,15 +321,12 @@ __global__ void __launch_bounds__(64) reinit_diag_kernel(ReinitArgs r, double* _
 
 template <int K>
 __global__ void __launch_bounds__(64) reinit_rhs_kernel(ReinitArgs r, const double* __restrict__ psi,
-                                                        double* __restrict__ b)
+                                                        double* __restrict__ b, CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = r.g.m;
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
-    if (cell >= ncell) return;
-    const int cx = (int)(cell % m.nc[0]), cy = (int)((cell / m.nc[0]) % m.nc[1]),
-              cz = (int)(cell / ((int64_t)m.nc[0] * m.nc[1]));
+    int cx, cy, cz;
+    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double nq[3][N3], u[N3], w[N3], out[N3];
     normal_at_gauss<K>(r, cx, cy, cz, nq);
     load_nodes<K>(m, psi, cx, cy, cz, u);
@@ -378,86 +365,73 @@ __global__ void __launch_bounds__(256) dot_partials_kernel(const double* __restr
 
 }  // namespace
 
+// One launch of KERNEL<k> per cell colour (the scatter-adds need no atomics).
+#define VPP_COLORED(KERNEL, ...)                                                                               \
+    switch (k) {                                                                                                \
+    case 2:                                                                                                     \
+        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {                                    \
+            hipLaunchKernelGGL(KERNEL<2>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__, cc);                     \
+        });                                                                                                     \
+    case 3:                                                                                                     \
+        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {                                    \
+            hipLaunchKernelGGL(KERNEL<3>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__, cc);                     \
+        });                                                                                                     \
+    case 4:                                                                                                     \
+        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {                                    \
+            hipLaunchKernelGGL(KERNEL<4>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__, cc);                     \
+        });                                                                                                     \
+    default: return hipErrorInvalidValue;                                                                       \
+    }
+
 hipError_t launch_normal_rhs(int k, const RhsGeo& g, const double* phi, double* b0, double* b1, double* b2,
                              hipStream_t s)
 {
-    const int64_t n = (int64_t)g.m.nn[0] * g.m.nn[1] * g.m.nn[2];
+    const MeshArgs& m = g.m;
+    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
     hipError_t e;
     if ((e = launch_fill<double>(b0, n, 0.0, s)) != hipSuccess || (e = launch_fill<double>(b1, n, 0.0, s)) != hipSuccess ||
         (e = launch_fill<double>(b2, n, 0.0, s)) != hipSuccess)
         return e;
-    const int64_t ncell = (int64_t)g.m.nc[0] * g.m.nc[1] * g.m.nc[2];
-    const int blocks = (int)((ncell + 63) / 64);
-    switch (k) {
-    case 2: hipLaunchKernelGGL(normal_rhs_kernel<2>, dim3(blocks), dim3(64), 0, s, g, phi, b0, b1, b2); break;
-    case 3: hipLaunchKernelGGL(normal_rhs_kernel<3>, dim3(blocks), dim3(64), 0, s, g, phi, b0, b1, b2); break;
-    case 4: hipLaunchKernelGGL(normal_rhs_kernel<4>, dim3(blocks), dim3(64), 0, s, g, phi, b0, b1, b2); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    VPP_COLORED(normal_rhs_kernel, g, phi, b0, b1, b2)
 }
 
 hipError_t launch_curvature_rhs(int k, const RhsGeo& g, const double* n0, const double* n1, const double* n2,
                                 double* b, hipStream_t s)
 {
-    const int64_t n = (int64_t)g.m.nn[0] * g.m.nn[1] * g.m.nn[2];
+    const MeshArgs& m = g.m;
+    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
     hipError_t e = launch_fill<double>(b, n, 0.0, s);
     if (e != hipSuccess) return e;
-    const int64_t ncell = (int64_t)g.m.nc[0] * g.m.nc[1] * g.m.nc[2];
-    const int blocks = (int)((ncell + 63) / 64);
-    switch (k) {
-    case 2: hipLaunchKernelGGL(curvature_rhs_kernel<2>, dim3(blocks), dim3(64), 0, s, g, n0, n1, n2, b); break;
-    case 3: hipLaunchKernelGGL(curvature_rhs_kernel<3>, dim3(blocks), dim3(64), 0, s, g, n0, n1, n2, b); break;
-    case 4: hipLaunchKernelGGL(curvature_rhs_kernel<4>, dim3(blocks), dim3(64), 0, s, g, n0, n1, n2, b); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-#define VPP_REINIT_SWITCH(KERNEL, ...)                                                                         \
-    switch (k) {                                                                                                \
-    case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__); break;                   \
-    case 3: hipLaunchKernelGGL(KERNEL<3>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__); break;                   \
-    case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__); break;                   \
-    default: return hipErrorInvalidValue;                                                                       \
-    }
-
-static int reinit_blocks(const ReinitArgs& r)
-{
-    const int64_t ncell = (int64_t)r.g.m.nc[0] * r.g.m.nc[1] * r.g.m.nc[2];
-    return (int)((ncell + 63) / 64);
+    VPP_COLORED(curvature_rhs_kernel, g, n0, n1, n2, b)
 }
 
 hipError_t launch_reinit_apply(int k, const ReinitArgs& r, const double* x, double* y, hipStream_t s)
 {
-    const int64_t n = (int64_t)r.g.m.nn[0] * r.g.m.nn[1] * r.g.m.nn[2];
+    const MeshArgs& m = r.g.m;
+    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
     hipError_t e = launch_fill<double>(y, n, 0.0, s);
     if (e != hipSuccess) return e;
-    const int blocks = reinit_blocks(r);
-    VPP_REINIT_SWITCH(reinit_apply_kernel, r, x, y)
-    return hipGetLastError();
+    VPP_COLORED(reinit_apply_kernel, r, x, y)
 }
 
 hipError_t launch_reinit_diag(int k, const ReinitArgs& r, double* diag, hipStream_t s)
 {
-    const int64_t n = (int64_t)r.g.m.nn[0] * r.g.m.nn[1] * r.g.m.nn[2];
+    const MeshArgs& m = r.g.m;
+    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
     hipError_t e = launch_fill<double>(diag, n, 0.0, s);
     if (e != hipSuccess) return e;
-    const int blocks = reinit_blocks(r);
-    VPP_REINIT_SWITCH(reinit_diag_kernel, r, diag)
-    return hipGetLastError();
+    VPP_COLORED(reinit_diag_kernel, r, diag)
 }
 
 hipError_t launch_reinit_rhs(int k, const ReinitArgs& r, const double* psi, double* b, hipStream_t s)
 {
-    const int64_t n = (int64_t)r.g.m.nn[0] * r.g.m.nn[1] * r.g.m.nn[2];
+    const MeshArgs& m = r.g.m;
+    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
     hipError_t e = launch_fill<double>(b, n, 0.0, s);
     if (e != hipSuccess) return e;
-    const int blocks = reinit_blocks(r);
-    VPP_REINIT_SWITCH(reinit_rhs_kernel, r, psi, b)
-    return hipGetLastError();
+    VPP_COLORED(reinit_rhs_kernel, r, psi, b)
 }
-#undef VPP_REINIT_SWITCH
+#undef VPP_COLORED
 
 hipError_t launch_dot_partials(const double* x, const double* y, int64_t n, double* part, int nblocks, hipStream_t s)
 {

@@ -1,5 +1,6 @@
 // Host-side check of the shared-node enumeration and partial-slot arithmetic
 // used by the assembly kernels (compiled with hipcc, runs on the CPU only).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <set>
@@ -131,6 +132,46 @@ static void check(int k, const int (&nc)[3], const int (&tile)[3], int bcmask)
             }
 }
 
+// The parity colouring of the cells (cell_color / color_cell): every cell in
+// exactly one colour, and no node shared by two cells of one colour.
+static void check_colors(int k, const int (&nc)[3])
+{
+    MeshArgs m{};
+    for (int d = 0; d < 3; ++d) {
+        m.nc[d] = nc[d];
+        m.nn[d] = k * nc[d] + 1;
+    }
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    std::vector<int> seen(ncell, 0);
+    std::vector<int> owner((size_t)m.nn[0] * m.nn[1] * m.nn[2]);
+    for (int c = 0; c < 8; ++c) {
+        const CellColor cc = cell_color(m, c);
+        std::fill(owner.begin(), owner.end(), -1);
+        int cx, cy, cz;
+        CHECK(!color_cell(cc, color_count(cc), cx, cy, cz), "colour %d: position past the end accepted\n", c);
+        for (int64_t i = 0; i < color_count(cc); ++i) {
+            if (!color_cell(cc, i, cx, cy, cz)) {
+                CHECK(false, "colour %d: position %lld rejected\n", c, (long long)i);
+                continue;
+            }
+            const bool in = cx >= 0 && cx < nc[0] && cy >= 0 && cy < nc[1] && cz >= 0 && cz < nc[2];
+            CHECK(in, "colour %d: cell (%d %d %d) outside the mesh\n", c, cx, cy, cz);
+            if (!in) continue;
+            CHECK(((cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2)) == c, "cell (%d %d %d) in colour %d\n", cx, cy, cz, c);
+            ++seen[cx + (int64_t)nc[0] * (cy + (int64_t)nc[1] * cz)];
+            const int id = (int)(cx + nc[0] * (cy + nc[1] * cz));
+            for (int a2 = 0; a2 <= k; ++a2)
+                for (int a1 = 0; a1 <= k; ++a1)
+                    for (int a0 = 0; a0 <= k; ++a0) {
+                        const int64_t g = node_index(m, k * cx + a0, k * cy + a1, k * cz + a2);
+                        CHECK(owner[g] < 0, "colour %d: node %lld in cells %d and %d\n", c, (long long)g, owner[g], id);
+                        owner[g] = id;
+                    }
+        }
+    }
+    for (int64_t i = 0; i < ncell; ++i) CHECK(seen[i] == 1, "cell %lld in %d colours\n", (long long)i, seen[i]);
+}
+
 int main()
 {
     const int tiles[][3] = {{8, 8, 4}, {16, 4, 4}, {8, 4, 4}, {32, 2, 2}, {4, 4, 2}, {4, 2, 2}, {8, 2, 2},
@@ -144,6 +185,11 @@ int main()
                 check(k, s, t, (ncase % 3 == 0) ? 63 : (ncase % 3 == 1 ? 0 : 21));
                 ++ncase;
             }
+    for (int k = 1; k <= 4; ++k)
+        for (const auto& sz : sizes) {
+            check_colors(k, sz);
+            ++ncase;
+        }
     std::printf("%d cases, %d failures\n", ncase, fails);
     return fails ? 1 : 0;
 }
