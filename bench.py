@@ -55,7 +55,7 @@ CG_BYTES_PER_DOF_ITER_F64 = 104.0
 FLOPS_PER_CELL_Q2 = 1758.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_q2_64cube_traffic.md")
 KERNEL_SOURCES = ["apply_impl.h", "apply_configs.h", "apply_misc.hip", "apply_f64.hip", "common.h", "tables.h",
-                  "shared_nodes.h", "kernels.h"]
+                  "shared_nodes.h", "kernels.h", "bounds.h"]
 
 
 def parse():

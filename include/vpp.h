@@ -383,6 +383,17 @@ vpp_status vpp_batch_destroy(vpp_batch b);
 const char* vpp_last_error(void);            /* thread-local message, never NULL */
 int32_t vpp_abi_version(void);
 
+/* Bounds checks (no passage of the paper: a debugging aid for the index
+ * arithmetic of the tile kernels).  The same sources also build
+ * libvpp_debug.so with every global and LDS access of the apply tile kernels
+ * (all variants, single and batched) and of the shared-node assembly checked
+ * against the extent of the buffer it belongs to; an access outside is
+ * counted and dropped (a load yields zero), so kernels still complete.
+ * Returns the count since the previous call and resets it (synchronizes the
+ * current device first); -1 in the release library (no checks compiled in),
+ * -2 if the counters could not be read. */
+int64_t vpp_debug_bounds_violations(void);
+
 #ifdef __cplusplus
 }
 #endif

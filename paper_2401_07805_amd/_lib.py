@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvpp.so")
+# VPP_DEBUG_BOUNDS=1 in the environment selects the bounds-checked build of
+# the same sources (libvpp_debug.so; see vpp_debug_bounds_violations).
+LIB_PATH = os.path.join(HERE, "libvpp_debug.so" if os.environ.get("VPP_DEBUG_BOUNDS") == "1" else "libvpp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vpp.h")
 
 VPP_OK = 0
@@ -101,6 +103,7 @@ def load() -> C.CDLL:
         "vpp_amr_cg_solve": (C.c_int, [vp, vp, vp, C.POINTER(CgOpts), C.POINTER(CgInfo), vp]),
         "vpp_last_error": (C.c_char_p, []),
         "vpp_abi_version": (C.c_int32, []),
+        "vpp_debug_bounds_violations": (C.c_int64, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

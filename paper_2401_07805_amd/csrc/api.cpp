@@ -747,6 +747,25 @@ extern "C" {
 const char* vpp_last_error(void) { return g_err.c_str(); }
 int32_t vpp_abi_version(void) { return VPP_ABI_VERSION; }
 
+int64_t vpp_debug_bounds_violations(void)
+{
+#ifdef VPP_BOUNDS_CHECK
+    if (hipDeviceSynchronize() != hipSuccess) return -2;
+    const unsigned long long c[7] = {bounds_count_apply_f64_k2(), bounds_count_apply_f64_k3(),
+                                     bounds_count_apply_f64_k4(), bounds_count_apply_f32_k2(),
+                                     bounds_count_apply_f32_k3(), bounds_count_apply_f32_k4(),
+                                     bounds_count_misc()};
+    int64_t n = 0;
+    for (unsigned long long v : c) {
+        if (v == ~0ull) return -2;
+        n += (int64_t)v;
+    }
+    return n;
+#else
+    return -1;
+#endif
+}
+
 vpp_status vpp_create(const vpp_desc* d, vpp_problem* out)
 {
     if (!d || !out) return fail(VPP_ERR_INVALID_ARG, "null argument");

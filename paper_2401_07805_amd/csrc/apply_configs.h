@@ -93,29 +93,35 @@ inline hipError_t launch_one_arith(const ApplyArgs<T>& a, hipStream_t s)
     return launch_hv<K, T, V, TX, TY, TZ, 3, false, false>(a, s);
 }
 
-template <typename T>
-inline hipError_t launch_apply_t(const LaunchCfg& c, int k, const ApplyArgs<T>& a, hipStream_t s)
+// Launch of configuration c for the degree KS of the calling translation unit:
+// only that degree's configurations are instantiated there, so the units of
+// the three degrees compile in parallel.
+template <typename T, int KS>
+inline hipError_t launch_apply_t(const LaunchCfg& c, const ApplyArgs<T>& a, hipStream_t s)
 {
     if (a.m.heaviside >= 2) {
         if (a.m.mass != 0.0) return hipErrorInvalidValue;
-#define VPP_LAUNCH_ARITH(K, V, TX, TY, TZ)                                                   \
-    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) \
-        return launch_one_arith<K, T, V, TX, TY, TZ>(a, s);
+#define VPP_LAUNCH_ARITH(K, V, TX, TY, TZ)                                              \
+    if constexpr (K == KS)                                                              \
+        if (c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ)    \
+            return launch_one_arith<K, T, V, TX, TY, TZ>(a, s);
         VPP_ARITH_CONFIGS(VPP_LAUNCH_ARITH)
 #undef VPP_LAUNCH_ARITH
         return hipErrorInvalidValue;
     }
     if (a.m.mass != 0.0) {
-#define VPP_LAUNCH_MASS(K, V, TX, TY, TZ)                                                    \
-    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) \
-        return launch_one<K, T, V, TX, TY, TZ, true>(a, s);
+#define VPP_LAUNCH_MASS(K, V, TX, TY, TZ)                                               \
+    if constexpr (K == KS)                                                              \
+        if (c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ)    \
+            return launch_one<K, T, V, TX, TY, TZ, true>(a, s);
         VPP_MASS_CONFIGS(VPP_LAUNCH_MASS)
 #undef VPP_LAUNCH_MASS
         return hipErrorInvalidValue;
     }
-#define VPP_LAUNCH(K, V, TX, TY, TZ)                                                         \
-    if (k == K && c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) \
-        return launch_one<K, T, V, TX, TY, TZ>(a, s);
+#define VPP_LAUNCH(K, V, TX, TY, TZ)                                                    \
+    if constexpr (K == KS)                                                              \
+        if (c.variant == V && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ)    \
+            return launch_one<K, T, V, TX, TY, TZ>(a, s);
     VPP_APPLY_CONFIGS(VPP_LAUNCH)
 #undef VPP_LAUNCH
     return hipErrorInvalidValue;

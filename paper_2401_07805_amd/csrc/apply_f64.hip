@@ -1,11 +1,17 @@
-// FP64 apply kernels (all instantiated configurations).
+// FP64 apply: dispatch by degree to the per-degree units (apply_f64_k*.hip), and
+// the configuration lists.
 #include "apply_configs.h"
 
 namespace vpp {
 
 hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& a, hipStream_t s)
 {
-    return launch_apply_t<double>(c, k, a, s);
+    switch (k) {
+    case 2: return launch_apply_f64_k2(c, a, s);
+    case 3: return launch_apply_f64_k3(c, a, s);
+    case 4: return launch_apply_f64_k4(c, a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 bool apply_config_supported(const LaunchCfg& c, int k)
@@ -73,5 +79,6 @@ int list_mass_configs(int k, LaunchCfg* out, int cap)
 #undef VPP_MLIST
     return n;
 }
+
 
 }  // namespace vpp

@@ -26,6 +26,7 @@
 #pragma once
 #include "kernels.h"
 #include "shared_nodes.h"
+#include "bounds.h"
 
 namespace vpp {
 
@@ -62,7 +63,7 @@ __device__ __forceinline__ void gather_cell(const MeshArgs& m, const S* __restri
         for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
             for (int a0 = 0; a0 < N; ++a0)
-                u[a0 + N * (a1 + N * a2)] = T(x[base + a0 + nx * a1 + nxy * a2]);
+                u[a0 + N * (a1 + N * a2)] = T(VPP_LD(&x[base + a0 + nx * a1 + nxy * a2], BC_IN));
     if (faces) {
 #pragma unroll
         for (int a2 = 0; a2 < N; ++a2)
@@ -109,7 +110,7 @@ __device__ __forceinline__ void gather_cell_t(const S* __restrict__ tb, unsigned
         for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
             for (int a0 = 0; a0 < N; ++a0)
-                u[a0 + N * (a1 + N * a2)] = T(*at_byte(tb + (a0 + nx * a1 + nxy * a2), lane_b));
+                u[a0 + N * (a1 + N * a2)] = T(VPP_LD(at_byte(tb + (a0 + nx * a1 + nxy * a2), lane_b), BC_IN));
     if (faces) {
 #pragma unroll
         for (int a2 = 0; a2 < N; ++a2)
@@ -316,8 +317,8 @@ __device__ __forceinline__ double flush_owned_get(const MeshArgs& m, const TileC
                 const bool hi0 = a0 == K && has_hi[0], hi1 = a1 == K && has_hi[1], hi2 = a2 == K && has_hi[2];
                 if (faces && local_dirichlet<K>(faces, a0, a1, a2)) {
                     // identity row: every tile holding the node writes the same x
-                    const T xv = *at_byte(xt + row, lane_b);
-                    *at_byte(yt + row, lane_b) = xv;
+                    const T xv = VPP_LD(at_byte(xt + row, lane_b), BC_X);
+                    VPP_ST(at_byte(yt + row, lane_b), BC_Y, xv);
                     if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                     continue;
                 }
@@ -329,11 +330,11 @@ __device__ __forceinline__ double flush_owned_get(const MeshArgs& m, const TileC
                     else if (s1) f = fy + (hi1 ? nx : 0) + a0 + nx * nby * a2;
                     else f = fx + (hi0 ? 1 : 0) + nbx * (a1 + ny_free * a2);
                     const int rank = (lo0 ? 1 : 0) + (s0 ? 2 : 1) * ((lo1 ? 1 : 0) + (s1 ? 2 : 1) * (lo2 ? 1 : 0));
-                    part[(unsigned)rank * nsh + (unsigned)f] = v;
+                    VPP_ST(&part[(unsigned)rank * nsh + (unsigned)f], BC_PART, v);
                 } else {
-                    *at_byte(yt + row, lane_b) = v;
+                    VPP_ST(at_byte(yt + row, lane_b), BC_Y, v);
                 }
-                if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)v;
+                if (dot) dsum += (double)VPP_LD(at_byte(xt + row, lane_b), BC_X) * (double)v;
             }
         }
     }
@@ -349,7 +350,7 @@ __device__ __forceinline__ double flush_owned(const MeshArgs& m, const TileCoord
 {
     constexpr int BX = K * TX + 1, BY = K * TY + 1;
     const int lbase = K * lx + BX * (K * ly + BY * K * lz);
-    auto get = [&](int a0, int a1, int a2, const bool*) { return yb[lbase + a0 + BX * (a1 + BY * a2)]; };
+    auto get = [&](int a0, int a1, int a2, const bool*) { return VPP_LD(&yb[lbase + a0 + BX * (a1 + BY * a2)], BC_SLOT); };
     return flush_owned_get<K, T, TX, TY, TZ>(m, tc, get, lx, ly, lz, cx, cy, cz, a0_only, x, y, part, nshared, dot);
 }
 
@@ -364,7 +365,10 @@ __device__ __forceinline__ void scatter_cell_lds(T* yb, int BX, int BY, int lx, 
         for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
             for (int a0 = 0; a0 < N; ++a0)
-                atomicAdd(&yb[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))], u[a0 + N * (a1 + N * a2)]);
+            {
+                T* const cell_node = &yb[(K * lx + a0) + BX * ((K * ly + a1) + BY * (K * lz + a2))];
+                if (VPP_OK(cell_node, BC_SLOT)) atomicAdd(cell_node, u[a0 + N * (a1 + N * a2)]);
+            }
 }
 
 // ---------------------------------------------------------------------------
@@ -377,6 +381,8 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ;
     constexpr int BX = K * TX + 1, BY = K * TY + 1, BZ = K * TZ + 1;
     __shared__ T yb[BX * BY * BZ];
+    VPP_BC_BEGIN(a.x, a.y, a.phi, a.part, a.dot_part, yb, (int64_t)a.m.nn[0] * a.m.nn[1] * a.m.nn[2],
+                 8 * a.nshared, (int64_t)gridDim.x, BX * BY * BZ);
     if (a.done && *a.done) return;
     const MeshArgs& m = a.m;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -399,7 +405,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_cell_kernel(ApplyArgs<T> a
                                           DOT);
     if constexpr (DOT) {
         const double s = block_sum<NT>(d);
-        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+        if (threadIdx.x == 0) VPP_ST(&a.dot_part[blockIdx.x], BC_DOT, s);
     }
 }
 
@@ -491,7 +497,7 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
         const int zero = NT;
         auto rd = [&](int cx_, int qx, int cy_, int qy, int cz_, int qz) -> T {
             const bool ok = cx_ >= 0 && cy_ >= 0 && cz_ >= 0;
-            return f.slot[(qx + N * (qy + N * qz)) * f.cs + (ok ? cx_ + cy_ + cz_ : zero)];
+            return VPP_LD(&f.slot[(qx + N * (qy + N * qz)) * f.cs + (ok ? cx_ + cy_ + cz_ : zero)], BC_SLOT);
         };
         T v = rd(x0, p0, y0, r0, z0, s0);
         v += rd(x1, p1, y0, r0, z0, s0);
@@ -506,8 +512,8 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
         const bool lo0 = c0 == 0 && t0 > 0, lo1 = c1 == 0 && t1 > 0, lo2 = c2 == 0 && t2 > 0;
         const bool hi0 = c0 == E0 && t0 < f.nbx, hi1 = c1 == E1 && t1 < f.nby, hi2 = c2 == E2 && t2 < f.nbz;
         if (is_dirichlet(f.m, gi, gj, gl)) {
-            const T xv = f.xt[off];
-            f.yt[off] = xv;
+            const T xv = VPP_LD(&f.xt[off], BC_X);
+            VPP_ST(&f.yt[off], BC_Y, xv);
             if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
             continue;
         }
@@ -515,11 +521,11 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
             int64_t fi;
             int rank;
             shared_from_tile(f.m, f.tc.t, lo0, lo1, lo2, hi0, hi1, hi2, gi, gj, gl, fi, rank);
-            f.part[(unsigned)rank * f.nsh + (unsigned)fi] = v;
+            VPP_ST(&f.part[(unsigned)rank * f.nsh + (unsigned)fi], BC_PART, v);
         } else {
-            f.yt[off] = v;
+            VPP_ST(&f.yt[off], BC_Y, v);
         }
-        if (dot) dsum += (double)f.xt[off] * (double)v;
+        if (dot) dsum += (double)VPP_LD(&f.xt[off], BC_X) * (double)v;
     }
     return dsum;
 }
@@ -570,7 +576,7 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
             const int x0 = b0 ? cb[0] : ca[0], x1 = b1 ? cb[1] : ca[1], x2 = b2 ? cb[2] : ca[2];
             const int p = (b0 ? K : qa[0]) + N * ((b1 ? K : qa[1]) + N * (b2 ? K : qa[2]));
             const bool ok = x0 >= 0 && x1 >= 0 && x2 >= 0;
-            v += f.slot[p * f.cs + (ok ? x0 * CST[0] + x1 * CST[1] + x2 * CST[2] : NT)];
+            v += VPP_LD(&f.slot[p * f.cs + (ok ? x0 * CST[0] + x1 * CST[1] + x2 * CST[2] : NT)], BC_SLOT);
         }
         const unsigned off = (unsigned)(c[0] + f.nx * c[1] + f.nxy * c[2]);
         const bool lo0 = FACE != 0 && c[0] == 0 && t0 > 0;
@@ -579,8 +585,8 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
         const bool hi0 = c[0] == E0 && hn[0], hi1 = c[1] == E1 && hn[1], hi2 = c[2] == E2 && hn[2];
         if (anyd && ((dlo[0] && c[0] == 0) || (dhi[0] && c[0] == E0) || (dlo[1] && c[1] == 0) ||
                      (dhi[1] && c[1] == E1) || (dlo[2] && c[2] == 0) || (dhi[2] && c[2] == E2))) {
-            const T xv = f.xt[off];
-            f.yt[off] = xv;
+            const T xv = VPP_LD(&f.xt[off], BC_X);
+            VPP_ST(&f.yt[off], BC_Y, xv);
             if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
             continue;
         }
@@ -591,11 +597,11 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
             else if (s1) fi = fb[1] + c[0] + f.nx * ((hi1 ? 1 : 0) + f.nby * c[2]);
             else fi = fb[0] + (hi0 ? 1 : 0) + f.nbx * (c[1] + f.nyf * c[2]);
             const int rank = (lo0 ? 1 : 0) + (s0 ? 2 : 1) * ((lo1 ? 1 : 0) + (s1 ? 2 : 1) * (lo2 ? 1 : 0));
-            f.part[(unsigned)rank * f.nsh + (unsigned)fi] = v;
+            VPP_ST(&f.part[(unsigned)rank * f.nsh + (unsigned)fi], BC_PART, v);
         } else {
-            f.yt[off] = v;
+            VPP_ST(&f.yt[off], BC_Y, v);
         }
-        if (dot) dsum += (double)f.xt[off] * (double)v;
+        if (dot) dsum += (double)VPP_LD(&f.xt[off], BC_X) * (double)v;
     }
     return dsum;
 }
@@ -680,19 +686,19 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
                 for (int a0 = 0; a0 < K; ++a0) {
                     const bool z0 = a0 == 0, z1 = a1 == 0, z2 = a2 == 0;
                     T v = u[a0 + N * (a1 + N * a2)];
-                    if (z0) v += slot[(K + N * (a1 + N * a2)) * cs + nb0];
-                    if (z1) v += slot[(a0 + N * (K + N * a2)) * cs + nb1];
-                    if (z2) v += slot[(a0 + N * (a1 + N * K)) * cs + nb2];
-                    if (z0 && z1) v += slot[(K + N * (K + N * a2)) * cs + nb01];
-                    if (z0 && z2) v += slot[(K + N * (a1 + N * K)) * cs + nb02];
-                    if (z1 && z2) v += slot[(a0 + N * (K + N * K)) * cs + nb12];
-                    if (z0 && z1 && z2) v += slot[(K + N * (K + N * K)) * cs + nb012];
+                    if (z0) v += VPP_LD(&slot[(K + N * (a1 + N * a2)) * cs + nb0], BC_SLOT);
+                    if (z1) v += VPP_LD(&slot[(a0 + N * (K + N * a2)) * cs + nb1], BC_SLOT);
+                    if (z2) v += VPP_LD(&slot[(a0 + N * (a1 + N * K)) * cs + nb2], BC_SLOT);
+                    if (z0 && z1) v += VPP_LD(&slot[(K + N * (K + N * a2)) * cs + nb01], BC_SLOT);
+                    if (z0 && z2) v += VPP_LD(&slot[(K + N * (a1 + N * K)) * cs + nb02], BC_SLOT);
+                    if (z1 && z2) v += VPP_LD(&slot[(a0 + N * (K + N * K)) * cs + nb12], BC_SLOT);
+                    if (z0 && z1 && z2) v += VPP_LD(&slot[(K + N * (K + N * K)) * cs + nb012], BC_SLOT);
                     const int row = a0 + nx * a1 + nxy * a2;   // uniform
                     const bool lo0 = z0 && hl0, lo1 = z1 && hl1, lo2 = z2 && hl2;
                     const bool dir = (z0 && dl0) || (z1 && dl1) || (z2 && dl2);
                     if (dir) {
-                        const T xv = *at_byte(xt + row, lane_b);
-                        *at_byte(yt + row, lane_b) = xv;
+                        const T xv = VPP_LD(at_byte(xt + row, lane_b), BC_X);
+                        VPP_ST(at_byte(yt + row, lane_b), BC_Y, xv);
                         if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                         continue;
                     }
@@ -702,8 +708,8 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
                         const int rank = (lo0 ? 1 : 0) + (lo0 ? 2 : 1) * ((lo1 ? 1 : 0) + (lo1 ? 2 : 1) * (lo2 ? 1 : 0));
                         dst = part + ((unsigned)rank * nsh + (unsigned)f);
                     }
-                    *dst = v;
-                    if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)v;
+                    VPP_ST(dst, BC_OUT, v);
+                    if (dot) dsum += (double)VPP_LD(at_byte(xt + row, lane_b), BC_X) * (double)v;
                 }
     }
 
@@ -725,6 +731,8 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ, CS = NT + 1;
     __shared__ T slot[N3 * CS];
+    VPP_BC_BEGIN(a.x, a.y, a.phi, a.part, a.dot_part, slot, (int64_t)a.m.nn[0] * a.m.nn[1] * a.m.nn[2],
+                 8 * a.nshared, (int64_t)gridDim.x, N3 * CS);
     if (a.done && *a.done) return;
     const MeshArgs& m = a.m;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -733,7 +741,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
     const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
-    for (int q = tid; q < N3; q += NT) slot[q * CS + NT] = T(0);
+    for (int q = tid; q < N3; q += NT) VPP_ST(&slot[q * CS + NT], BC_SLOT, T(0));
     T u[N3];
     if (active) {
         const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
@@ -749,14 +757,14 @@ __global__ void __launch_bounds__(TX * TY * TZ) apply_slot_kernel(ApplyArgs<T> a
         cell_operator<K, T, MASS>(m, cw, u);
 #pragma unroll
         for (int q = 0; q < N3; ++q)
-            if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) slot[q * CS + tid] = u[q];
+            if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) VPP_ST(&slot[q * CS + tid], BC_SLOT, u[q]);
     }
     __syncthreads();
     const double d = flush_two_pass<K, T, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy, cz, a.x, a.y,
                                                       a.part, a.nshared, DOT);
     if constexpr (DOT) {
         const double s = block_sum<NT>(d);
-        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+        if (threadIdx.x == 0) VPP_ST(&a.dot_part[blockIdx.x], BC_DOT, s);
     }
 }
 
@@ -809,18 +817,18 @@ __device__ __forceinline__ double flush_plane_owned(const MeshArgs& m, const Til
         for (int a1 = 0; a1 < K; ++a1) {
             const bool z1 = a1 == 0, z2 = a2 == 0;
             T val = o[a1 + N * a2];
-            if (z0) val += slot[pos(K, a1, a2) * cs + nb0];
-            if (z1) val += slot[pos(ip, K, a2) * cs + nb1];
-            if (z2) val += slot[pos(ip, a1, K) * cs + nb2];
-            if (z0 && z1) val += slot[pos(K, K, a2) * cs + nb01];
-            if (z0 && z2) val += slot[pos(K, a1, K) * cs + nb02];
-            if (z1 && z2) val += slot[pos(ip, K, K) * cs + nb12];
-            if (z0 && z1 && z2) val += slot[pos(K, K, K) * cs + nb012];
+            if (z0) val += VPP_LD(&slot[pos(K, a1, a2) * cs + nb0], BC_SLOT);
+            if (z1) val += VPP_LD(&slot[pos(ip, K, a2) * cs + nb1], BC_SLOT);
+            if (z2) val += VPP_LD(&slot[pos(ip, a1, K) * cs + nb2], BC_SLOT);
+            if (z0 && z1) val += VPP_LD(&slot[pos(K, K, a2) * cs + nb01], BC_SLOT);
+            if (z0 && z2) val += VPP_LD(&slot[pos(K, a1, K) * cs + nb02], BC_SLOT);
+            if (z1 && z2) val += VPP_LD(&slot[pos(ip, K, K) * cs + nb12], BC_SLOT);
+            if (z0 && z1 && z2) val += VPP_LD(&slot[pos(K, K, K) * cs + nb012], BC_SLOT);
             const int row = nx * a1 + nxy * a2;   // uniform
             const bool lo1 = z1 && hl1, lo2 = z2 && hl2;
             if (dir0 || (z1 && dl1) || (z2 && dl2)) {
-                const T xv = *at_byte(xt + row, lane_b);
-                *at_byte(yt + row, lane_b) = xv;
+                const T xv = VPP_LD(at_byte(xt + row, lane_b), BC_X);
+                VPP_ST(at_byte(yt + row, lane_b), BC_Y, xv);
                 if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                 continue;
             }
@@ -830,8 +838,8 @@ __device__ __forceinline__ double flush_plane_owned(const MeshArgs& m, const Til
                 const int rank = (lo0 ? 1 : 0) + (lo0 ? 2 : 1) * ((lo1 ? 1 : 0) + (lo1 ? 2 : 1) * (lo2 ? 1 : 0));
                 dst = part + ((unsigned)rank * nsh + (unsigned)f);
             }
-            *dst = val;
-            if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)val;
+            VPP_ST(dst, BC_OUT, val);
+            if (dot) dsum += (double)VPP_LD(at_byte(xt + row, lane_b), BC_X) * (double)val;
         }
     return dsum;
 }
@@ -888,6 +896,8 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     constexpr bool QUAD = N == 4;
     static_assert(N * N2 * SS <= 2 * NC * CS, "slots must fit in the exchange buffers");
     __shared__ T xb[2 * NC * CS];
+    VPP_BC_BEGIN(a.x, a.y, a.phi, a.part, a.dot_part, xb, (int64_t)a.m.nn[0] * a.m.nn[1] * a.m.nn[2],
+                 8 * a.nshared, (int64_t)gridDim.x, 2 * NC * CS);
     if (a.done && *a.done) return;
     const MeshArgs& m = a.m;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -919,7 +929,7 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
 #pragma unroll
         for (int l = 0; l < N; ++l)
 #pragma unroll
-            for (int j = 0; j < N; ++j) cw[j + N * l] = T(a.phi[base + nx * j + nxy * l]);
+            for (int j = 0; j < N; ++j) cw[j + N * l] = T(VPP_LD(&a.phi[base + nx * j + nxy * l], BC_PHI));
         sweep2<K, MS, false, 0>(cw);
         sweep2<K, MS, false, 1>(cw);
         if constexpr (QUAD) {
@@ -962,7 +972,7 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
         for (int l = 0; l < N; ++l)
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                T v = T(a.x[base + nx * j + nxy * l]);
+                T v = T(VPP_LD(&a.x[base + nx * j + nxy * l], BC_X));
                 if (faces && local_dirichlet<K>(faces, ip, j, l)) v = T(0);
                 uq[j + N * l] = v;
             }
@@ -1073,12 +1083,12 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     // exchange of the cell results through slots (no atomics), on the x buffers
     __syncthreads();
     T* slot = xb;
-    for (int q = threadIdx.x; q < N * N2; q += NT) slot[q * SS + NC] = T(0);
+    for (int q = threadIdx.x; q < N * N2; q += NT) VPP_ST(&slot[q * SS + NC], BC_SLOT, T(0));
     if (active) {
 #pragma unroll
         for (int l = 0; l < N; ++l)
 #pragma unroll
-            for (int j = 0; j < N; ++j) slot[(ip + N * (j + N * l)) * SS + cell] = o[j + N * l];
+            for (int j = 0; j < N; ++j) VPP_ST(&slot[(ip + N * (j + N * l)) * SS + cell], BC_SLOT, o[j + N * l]);
     }
     __syncthreads();
     double d = 0.0;
@@ -1088,7 +1098,7 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
     d += upper_faces<K, T, TX, TY, TZ, NT>(m, tc, slot, SS, a.x, a.y, a.part, a.nshared, DOT);
     if constexpr (DOT) {
         const double s = block_sum<NT>(d);
-        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = s;
+        if (threadIdx.x == 0) VPP_ST(&a.dot_part[blockIdx.x], BC_DOT, s);
     }
 }
 
@@ -1204,18 +1214,18 @@ __device__ __forceinline__ double flush_half_owned(const MeshArgs& m, const Tile
             for (int a0 = 0; a0 < K; ++a0) {
                 const bool z0 = a0 == 0, z1 = a1 == 0;
                 T val = v[j][a0 + N * a1];
-                if (z0) val += slot[pos(K, a1, a2) * cs + nb0];
-                if (z1) val += slot[pos(a0, K, a2) * cs + nb1];
-                if (z2) val += slot[pos(a0, a1, K) * cs + nb2];
-                if (z0 && z1) val += slot[pos(K, K, a2) * cs + nb01];
-                if (z0 && z2) val += slot[pos(K, a1, K) * cs + nb02];
-                if (z1 && z2) val += slot[pos(a0, K, K) * cs + nb12];
-                if (z0 && z1 && z2) val += slot[pos(K, K, K) * cs + nb012];
+                if (z0) val += VPP_LD(&slot[pos(K, a1, a2) * cs + nb0], BC_SLOT);
+                if (z1) val += VPP_LD(&slot[pos(a0, K, a2) * cs + nb1], BC_SLOT);
+                if (z2) val += VPP_LD(&slot[pos(a0, a1, K) * cs + nb2], BC_SLOT);
+                if (z0 && z1) val += VPP_LD(&slot[pos(K, K, a2) * cs + nb01], BC_SLOT);
+                if (z0 && z2) val += VPP_LD(&slot[pos(K, a1, K) * cs + nb02], BC_SLOT);
+                if (z1 && z2) val += VPP_LD(&slot[pos(a0, K, K) * cs + nb12], BC_SLOT);
+                if (z0 && z1 && z2) val += VPP_LD(&slot[pos(K, K, K) * cs + nb012], BC_SLOT);
                 const int row = a0 + nx * a1 + nxy * a2;
                 const bool lo0 = z0 && hl0, lo1 = z1 && hl1, lo2 = z2 && hl2;
                 if ((z0 && dl0) || (z1 && dl1) || (z2 && dl2)) {
-                    const T xv = *at_byte(xt + row, lane_b);
-                    *at_byte(yt + row, lane_b) = xv;
+                    const T xv = VPP_LD(at_byte(xt + row, lane_b), BC_X);
+                    VPP_ST(at_byte(yt + row, lane_b), BC_Y, xv);
                     if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                     continue;
                 }
@@ -1226,8 +1236,8 @@ __device__ __forceinline__ double flush_half_owned(const MeshArgs& m, const Tile
                     const int rank = (lo0 ? 1 : 0) + (lo0 ? 2 : 1) * ((lo1 ? 1 : 0) + (lo1 ? 2 : 1) * (lo2 ? 1 : 0));
                     dst = part + ((unsigned)rank * nsh + (unsigned)f);
                 }
-                *dst = val;
-                if (dot) dsum += (double)*at_byte(xt + row, lane_b) * (double)val;
+                VPP_ST(dst, BC_OUT, val);
+                if (dot) dsum += (double)VPP_LD(at_byte(xt + row, lane_b), BC_X) * (double)val;
             }
     }
     return dsum;
@@ -1239,6 +1249,8 @@ __global__ void __launch_bounds__(2 * TX * TY * TZ) apply_half_kernel(ApplyArgs<
     static_assert(K == 3, "two z-planes per thread");
     constexpr int N = K + 1, N2 = N * N, N3 = N2 * N, NC = TX * TY * TZ, NTH = 2 * NC, CS = NC + 1;
     __shared__ T slot[N3 * CS];
+    VPP_BC_BEGIN(a.x, a.y, a.phi, a.part, a.dot_part, slot, (int64_t)a.m.nn[0] * a.m.nn[1] * a.m.nn[2],
+                 8 * a.nshared, (int64_t)gridDim.x, N3 * CS);
     if (a.done && *a.done) return;
     const MeshArgs& m = a.m;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -1247,7 +1259,7 @@ __global__ void __launch_bounds__(2 * TX * TY * TZ) apply_half_kernel(ApplyArgs<
     const int lx = c % TX, ly = (c / TX) % TY, lz = c / (TX * TY);
     const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
     const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
-    for (int q = tid; q < N3; q += NTH) slot[q * CS + NC] = T(0);
+    for (int q = tid; q < N3; q += NTH) VPP_ST(&slot[q * CS + NC], BC_SLOT, T(0));
     // cell plane of local plane j
     const int pl[2] = {hz ? K : 0, hz ? K - 1 : 1};
     T v[2][N2];
@@ -1264,8 +1276,8 @@ __global__ void __launch_bounds__(2 * TX * TY * TZ) apply_half_kernel(ApplyArgs<
             for (int a1 = 0; a1 < N; ++a1)
 #pragma unroll
                 for (int a0 = 0; a0 < N; ++a0) {
-                    cw[j][a0 + N * a1] = *at_byte(a.phi + tile0 + (a0 + nx * a1), lane_b);
-                    T xv = *at_byte(a.x + tile0 + (a0 + nx * a1), lane_b);
+                    cw[j][a0 + N * a1] = VPP_LD(at_byte(a.phi + tile0 + (a0 + nx * a1), lane_b), BC_PHI);
+                    T xv = VPP_LD(at_byte(a.x + tile0 + (a0 + nx * a1), lane_b), BC_X);
                     if (faces && local_dirichlet<K>(faces, a0, a1, pl[j])) xv = T(0);
                     u[j][a0 + N * a1] = xv;
                 }
@@ -1360,7 +1372,7 @@ __global__ void __launch_bounds__(2 * TX * TY * TZ) apply_half_kernel(ApplyArgs<
 #pragma unroll
             for (int q = 0; q < N2; ++q) {
                 const int a0 = q % N, a1 = q / N;
-                if (a0 == K || a1 == K || pl[j] == K) slot[(a0 + N * (a1 + N * pl[j])) * CS + c] = v[j][q];
+                if (a0 == K || a1 == K || pl[j] == K) VPP_ST(&slot[(a0 + N * (a1 + N * pl[j])) * CS + c], BC_SLOT, v[j][q]);
             }
     }
     __syncthreads();
@@ -1371,7 +1383,7 @@ __global__ void __launch_bounds__(2 * TX * TY * TZ) apply_half_kernel(ApplyArgs<
     dsum += upper_faces<K, T, TX, TY, TZ, NTH>(m, tc, slot, CS, a.x, a.y, a.part, a.nshared, DOT);
     if constexpr (DOT) {
         const double sum = block_sum<NTH>(dsum);
-        if (threadIdx.x == 0) a.dot_part[blockIdx.x] = sum;
+        if (threadIdx.x == 0) VPP_ST(&a.dot_part[blockIdx.x], BC_DOT, sum);
     }
 }
 

@@ -15,6 +15,9 @@ __global__ void __launch_bounds__(64) diag_kernel(MeshArgs m, const double* __re
                                                    double* __restrict__ diag, CellColor cc)
 {
     constexpr int N = K + 1, N3 = N * N * N;
+    // phi is gathered by the (instrumented) coefficient helper
+    VPP_BC_BEGIN((const double*)nullptr, (const double*)nullptr, phi, (const double*)nullptr,
+                 (const double*)nullptr, (const double*)nullptr, (int64_t)m.nn[0] * m.nn[1] * m.nn[2], 0, 0, 0);
     int cx, cy, cz;
     if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double A[N3], Z[N3], Y[N3], out[N3];
@@ -160,19 +163,21 @@ __device__ __forceinline__ void assemble_one(const SharedEnum& e, const MeshArgs
     shared_node(e, f, i, j, l);
     if (is_dirichlet(m, i, j, l)) return;
     const int n = sharer_count(e, i, j, l);
-    for (int c = 2; c < n; ++c) v += part[c * stride + f];
-    y[i + (int64_t)m.nn[0] * (j + (int64_t)m.nn[1] * l)] = v;
+    for (int c = 2; c < n; ++c) v += VPP_LD(&part[c * stride + f], BC_PART);
+    VPP_ST(&y[i + (int64_t)m.nn[0] * (j + (int64_t)m.nn[1] * l)], BC_Y, v);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) assemble_kernel(AssembleArgs<T> a)
 {
+    VPP_BC_BEGIN((const T*)nullptr, a.y, (const T*)nullptr, a.part, a.dot_part, (const T*)nullptr,
+                 (int64_t)a.m.nn[0] * a.m.nn[1] * a.m.nn[2], 8 * a.nshared, (int64_t)a.ndot, 0);
     if (a.done && *a.done) return;
     if (a.dot && blockIdx.x == 0) {
         // x . y from the per-workgroup partials, summed in a fixed order
         __shared__ double red[256];
         double s = 0.0;
-        for (int i = threadIdx.x; i < a.ndot; i += 256) s += a.dot_part[i];
+        for (int i = threadIdx.x; i < a.ndot; i += 256) s += VPP_LD(&a.dot_part[i], BC_DOT);
         red[threadIdx.x] = s;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
@@ -185,8 +190,8 @@ __global__ void __launch_bounds__(256) assemble_kernel(AssembleArgs<T> a)
     const int64_t count = e.cz + e.cy + e.cx;
     using P = typename Pair<T>::type;
     for (int64_t f = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); f < count; f += 2 * (int64_t)gridDim.x * 256) {
-        const P r0 = *reinterpret_cast<const P*>(a.part + f);
-        const P r1 = *reinterpret_cast<const P*>(a.part + a.nshared + f);
+        const P r0 = VPP_LD(reinterpret_cast<const P*>(a.part + f), BC_PART);
+        const P r1 = VPP_LD(reinterpret_cast<const P*>(a.part + a.nshared + f), BC_PART);
         assemble_one(e, a.m, a.part, a.nshared, f, r0.x + r1.x, a.y);
         if (f + 1 < count) assemble_one(e, a.m, a.part, a.nshared, f + 1, r0.y + r1.y, a.y);
     }
@@ -259,6 +264,11 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             any = false;
             for (int r = 0; r < nrhs; ++r) any = any || !a.st[rhs0 + r].halt[a.par];
         }
+        // the bounds table of the debug build: this problem's phi (the
+        // barrier first: the previous item's write-out may still read it)
+        VPP_BC_SYNC();
+        VPP_BC_BEGIN((const double*)nullptr, (const double*)nullptr, phi, (const double*)nullptr,
+                     (const double*)nullptr, slot, (int64_t)m.nn[0] * m.nn[1] * m.nn[2], 0, 0, N3 * CS);
         // the coefficient of the tile is computed once for all right-hand sides
         double cw[N3];
         if (active && any) {
@@ -274,6 +284,10 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             const double* x = a.x[rhs0 + r];
             double* y = a.y[rhs0 + r];
             double* part = a.part + a.probs[pi].part_begin + (int64_t)r * 8 * a.probs[pi].nshared;
+            VPP_BC_SYNC();
+            VPP_BC_BEGIN(x, y, phi, part, a.dot_part ? a.dot_part + a.probs[pi].dot_begin : nullptr, slot,
+                         (int64_t)m.nn[0] * m.nn[1] * m.nn[2], 8 * a.probs[pi].nshared,
+                         (int64_t)nrhs * a.probs[pi].ntiles, N3 * CS);
             double u[N3];
             if (active) {
                 gather_cell_t<K>(x + tile0, lane_b, nx, nxy, faces, u);
@@ -284,14 +298,14 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             if (active) {
 #pragma unroll
                 for (int q = 0; q < N3; ++q)
-                    if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) slot[q * CS + tid] = u[q];
+                    if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) VPP_ST(&slot[q * CS + tid], BC_SLOT, u[q]);
             }
             __syncthreads();
             const double d = flush_two_pass<K, double, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy,
                                                                    cz, x, y, part, a.probs[pi].nshared, a.st != nullptr);
             if (a.st) {
                 const double sum = block_sum<NT>(d);
-                if (tid == 0) a.dot_part[a.probs[pi].dot_begin + r * a.probs[pi].ntiles + tile] = sum;
+                if (tid == 0) VPP_ST(&a.dot_part[a.probs[pi].dot_begin + r * a.probs[pi].ntiles + tile], BC_DOT, sum);
             }
         }
     }
@@ -319,11 +333,13 @@ __global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a
     const int64_t ns = P.nshared;
     const double* part = a.part + P.part_begin + (int64_t)pr * 8 * ns;
     double* y = a.y[P.rhs_begin + pr];
+    VPP_BC_BEGIN((const double*)nullptr, y, (const double*)nullptr, part, (const double*)nullptr,
+                 (const double*)nullptr, (int64_t)P.m.nn[0] * P.m.nn[1] * P.m.nn[2], 8 * ns, 0, 0);
     const SharedEnum& e = P.se;
     const int64_t count = e.cz + e.cy + e.cx;
     for (int64_t f = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); f < count; f += 2 * (int64_t)gridDim.x * 256) {
-        const double2 r0 = *reinterpret_cast<const double2*>(part + f);
-        const double2 r1 = *reinterpret_cast<const double2*>(part + ns + f);
+        const double2 r0 = VPP_LD(reinterpret_cast<const double2*>(part + f), BC_PART);
+        const double2 r1 = VPP_LD(reinterpret_cast<const double2*>(part + ns + f), BC_PART);
         assemble_one(e, P.m, part, ns, f, r0.x + r1.x, y);
         if (f + 1 < count) assemble_one(e, P.m, part, ns, f + 1, r0.y + r1.y, y);
     }
@@ -385,5 +401,7 @@ int batch_blocks_per_cu(const LaunchCfg& c, int k)
 #undef VPP_BO
     return 0;
 }
+
+unsigned long long bounds_count_misc() { return bc_count_here(); }
 
 }  // namespace vpp

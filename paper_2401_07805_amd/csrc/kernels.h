@@ -53,7 +53,24 @@ inline int64_t shared_stride(const MeshArgs& m) { return (shared_node_count(m) +
 // instantiated.
 hipError_t launch_apply_f64(const LaunchCfg& c, int k, const ApplyArgs<double>& a, hipStream_t s);
 hipError_t launch_apply_f32(const LaunchCfg& c, int k, const ApplyArgs<float>& a, hipStream_t s);
+// The per-degree units behind launch_apply_f64 / launch_apply_f32.
+hipError_t launch_apply_f64_k2(const LaunchCfg& c, const ApplyArgs<double>& a, hipStream_t s);
+hipError_t launch_apply_f64_k3(const LaunchCfg& c, const ApplyArgs<double>& a, hipStream_t s);
+hipError_t launch_apply_f64_k4(const LaunchCfg& c, const ApplyArgs<double>& a, hipStream_t s);
+hipError_t launch_apply_f32_k2(const LaunchCfg& c, const ApplyArgs<float>& a, hipStream_t s);
+hipError_t launch_apply_f32_k3(const LaunchCfg& c, const ApplyArgs<float>& a, hipStream_t s);
+hipError_t launch_apply_f32_k4(const LaunchCfg& c, const ApplyArgs<float>& a, hipStream_t s);
 bool apply_config_supported(const LaunchCfg& c, int k);
+// Out-of-bounds accesses the instrumented kernels of one source file dropped
+// since the last call (the count is reset); the debug library only (0 in the
+// release library, ~0 if the counter could not be read).
+unsigned long long bounds_count_apply_f64_k2();
+unsigned long long bounds_count_apply_f64_k3();
+unsigned long long bounds_count_apply_f64_k4();
+unsigned long long bounds_count_apply_f32_k2();
+unsigned long long bounds_count_apply_f32_k3();
+unsigned long long bounds_count_apply_f32_k4();
+unsigned long long bounds_count_misc();
 int list_apply_configs(int k, LaunchCfg* out, int cap);
 // Configurations instantiated with the mass shift (a problem with mu != 0 runs these only).
 bool mass_config_supported(const LaunchCfg& c, int k);
