@@ -234,7 +234,15 @@ vpp_status vpp_closest_points_normal(vpp_problem p, const double* pts, int64_t n
                                      const double* n1, const double* n2, const vpp_cp_opts* opts,
                                      double* y, int32_t* info, void* stream);
 
-/* Right-hand sides of the level-set filter systems (vpp_set_mass), assembled
+/* vpp_grad_phi, the filter right-hand sides below and the reinitialization
+ * calls form every cell's contributions first and then sum them into the
+ * nodes, each node over its cells in a fixed order (no atomics: repeated calls
+ * give identical bits).  The contributions go to a scratch buffer of the
+ * problem, (k+1)^3 doubles per cell (three times that for vpp_normal_rhs),
+ * allocated at the first call that needs it (VPP_ERR_OUT_OF_MEMORY if it
+ * cannot be); calls on different streams that use it are ordered by an event.
+ *
+ * Right-hand sides of the level-set filter systems (vpp_set_mass), assembled
  * on every row of the problem's mesh with its (k+1)^3 Gauss rule, no
  * constraint applied:
  *   vpp_normal_rhs:    b_d = (n_bar_d, v), n_bar = grad phi_h / |grad phi_h|

@@ -81,13 +81,12 @@ __global__ void __launch_bounds__(64) grad_coef_kernel(MeshArgs m, const double*
 
 template <int K>
 __global__ void __launch_bounds__(64) grad_phi_kernel(MeshArgs m, const double* __restrict__ phi,
-                                                      const double* __restrict__ g, double* __restrict__ out,
-                                                      CellColor cc)
+                                                      const double* __restrict__ g, double* __restrict__ cv)
 {
     constexpr int N = K + 1, N3 = N * N * N;
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int cx, cy, cz;
-    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
-    const int64_t cell = cx + (int64_t)m.nc[0] * (cy + (int64_t)m.nc[1] * cz);
+    if (!cell_of(m, cell, cx, cy, cz)) return;
     double s[N3];
     load_cell<K>(m, phi, cx, cy, cz, false, s);
     sweep3<K, MS, false, 0>(s);
@@ -102,15 +101,10 @@ __global__ void __launch_bounds__(64) grad_phi_kernel(MeshArgs m, const double* 
     sweep3<K, MS, true, 2>(s);
     sweep3<K, MS, true, 1>(s);
     sweep3<K, MS, true, 0>(s);
-    const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
-    const int64_t base = node_index(m, (int64_t)K * cx, (int64_t)K * cy, (int64_t)K * cz);
+    // the cell's values, cell-major (the node sum adds them into the nodes)
+    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
 #pragma unroll
-    for (int a2 = 0; a2 < N; ++a2)
-#pragma unroll
-        for (int a1 = 0; a1 < N; ++a1)
-#pragma unroll
-            for (int a0 = 0; a0 < N; ++a0)
-                out[base + a0 + nx * a1 + nxy * a2] += s[a0 + N * (a1 + N * a2)];
+    for (int q = 0; q < N3; ++q) cv[q * ncell + cell] = s[q];
 }
 
 hipError_t launch_grad_coef(int k, const MeshArgs& m, const double* p, const double* lam, double* g, hipStream_t s)
@@ -126,24 +120,22 @@ hipError_t launch_grad_coef(int k, const MeshArgs& m, const double* p, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_grad_phi(int k, const MeshArgs& m, const double* phi, const double* g, double* out, hipStream_t s)
+hipError_t launch_grad_phi(int k, const MeshArgs& m, const double* phi, const double* g, double* out, double* cv,
+                           hipStream_t s)
 {
-    // one launch per cell colour: the scatter into the nodes needs no atomics
+    // the cells' contributions into a cell-major buffer, then the node sum
+    // (fixed order per node, no atomics)
+    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
+    const int blocks = (int)((ncell + 63) / 64);
     switch (k) {
-    case 2:
-        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {
-            hipLaunchKernelGGL(grad_phi_kernel<2>, dim3(blocks), dim3(64), 0, s, m, phi, g, out, cc);
-        });
-    case 3:
-        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {
-            hipLaunchKernelGGL(grad_phi_kernel<3>, dim3(blocks), dim3(64), 0, s, m, phi, g, out, cc);
-        });
-    case 4:
-        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {
-            hipLaunchKernelGGL(grad_phi_kernel<4>, dim3(blocks), dim3(64), 0, s, m, phi, g, out, cc);
-        });
+    case 2: hipLaunchKernelGGL(grad_phi_kernel<2>, dim3(blocks), dim3(64), 0, s, m, phi, g, cv); break;
+    case 3: hipLaunchKernelGGL(grad_phi_kernel<3>, dim3(blocks), dim3(64), 0, s, m, phi, g, cv); break;
+    case 4: hipLaunchKernelGGL(grad_phi_kernel<4>, dim3(blocks), dim3(64), 0, s, m, phi, g, cv); break;
     default: return hipErrorInvalidValue;
     }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_node_sum(k, m, cv, out, s);
 }
 
 }  // namespace vpp

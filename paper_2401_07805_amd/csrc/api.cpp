@@ -144,6 +144,9 @@ struct vpp_problem_s {
     size_t part_bytes = 0;
     double* dot_part = nullptr;     // per-workgroup partial dot products
     size_t dot_part_n = 0;
+    double* cellbuf = nullptr;      // cell-major scratch of the node-sum kernels
+    size_t cellbuf_n = 0;
+    hipEvent_t cell_evt = nullptr;  // last use of cellbuf (orders users on different streams)
     bool phi_set = false;
     hipStream_t stream = nullptr;   // library stream for solves and graph capture
     CgWork w;
@@ -254,6 +257,36 @@ static MeshArgs make_mesh_args(const vpp_desc& d)
 // Scratch of the apply for the current configurations of both precisions: the
 // partials of shared-face nodes (8 ranks x shared nodes, FP64-sized) and one
 // partial dot product per tile.
+// Cell-major scratch of the kernels that sum per-cell contributions into the
+// nodes (dJ/dphi, the filter right-hand sides, the reinitialization pieces):
+// nvec arrays of cell_values entries.  The calls using it are ordered by an
+// event, also when they run on different streams.
+static vpp_status cell_scratch_begin(vpp_problem p, int nvec, hipStream_t s, double** out)
+{
+    const size_t need = (size_t)nvec * (size_t)cell_values(p->k, p->m);
+    if (need > p->cellbuf_n) {
+        if (p->cellbuf) {
+            VPP_HIP(hipDeviceSynchronize());   // a previous call may still read it
+            dev_free(p->cellbuf);
+        }
+        p->cellbuf = nullptr;
+        p->cellbuf_n = 0;
+        vpp_status st = dev_alloc(&p->cellbuf, need, "cell scratch");
+        if (st) return st;
+        p->cellbuf_n = need;
+    }
+    if (!p->cell_evt) VPP_HIP(hipEventCreateWithFlags(&p->cell_evt, hipEventDisableTiming));
+    else VPP_HIP(hipStreamWaitEvent(s, p->cell_evt, 0));
+    *out = p->cellbuf;
+    return VPP_OK;
+}
+
+static vpp_status cell_scratch_end(vpp_problem p, hipStream_t s)
+{
+    VPP_HIP(hipEventRecord(p->cell_evt, s));
+    return VPP_OK;
+}
+
 static vpp_status ensure_apply_scratch(vpp_problem p)
 {
     const int64_t ns = std::max(shared_stride(p->m), shared_stride(p->m32));
@@ -821,7 +854,8 @@ vpp_status vpp_destroy(vpp_problem p)
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     free_work(p->w);
     dev_free(p->phi64); dev_free(p->phi32); dev_free(p->diag); dev_free(p->inv64); dev_free(p->inv32);
-    dev_free(p->part); dev_free(p->dot_part);
+    dev_free(p->part); dev_free(p->dot_part); dev_free(p->cellbuf);
+    if (p->cell_evt) (void)hipEventDestroy(p->cell_evt);
     dev_free(p->cp_list); dev_free(p->cp_ctr);
     free_reinit(p->rw);
     if (p->stream) (void)hipStreamDestroy(p->stream);
@@ -989,9 +1023,11 @@ vpp_status vpp_grad_phi(vpp_problem p, const double* g_q, double* g_phi, void* s
         return fail(VPP_ERR_UNSUPPORTED, "dJ/dphi is available for the reciprocal density mean (Eq. rhoEff) only");
     DeviceGuard dg(p->desc.device);
     hipStream_t s = (hipStream_t)stream;
-    VPP_HIP(launch_fill<double>(g_phi, p->N, 0.0, s));
-    VPP_HIP(launch_grad_phi(p->k, p->m, p->phi64, g_q, g_phi, s));
-    return VPP_OK;
+    double* cv;
+    vpp_status st;
+    if ((st = cell_scratch_begin(p, 1, s, &cv))) return st;
+    VPP_HIP(launch_grad_phi(p->k, p->m, p->phi64, g_q, g_phi, cv, s));
+    return cell_scratch_end(p, s);
 }
 
 static vpp_status closest_points(vpp_problem p, const double* pts, int64_t n, const double* const nrm[3],
@@ -1093,8 +1129,12 @@ vpp_status vpp_normal_rhs(vpp_problem p, const double* phi, double* b0, double* 
         (const void*)phi == b2)
         return fail(VPP_ERR_INVALID_ARG, "phi and the outputs must not alias");
     DeviceGuard dg(p->desc.device);
-    VPP_HIP(launch_normal_rhs(p->k, rhs_geometry(p), phi, b0, b1, b2, (hipStream_t)stream));
-    return VPP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* cv;
+    vpp_status st;
+    if ((st = cell_scratch_begin(p, 3, s, &cv))) return st;
+    VPP_HIP(launch_normal_rhs(p->k, rhs_geometry(p), phi, b0, b1, b2, cv, s));
+    return cell_scratch_end(p, s);
 }
 
 vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, const double* n2, double* b,
@@ -1105,8 +1145,12 @@ vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, 
     if ((const void*)b == n0 || (const void*)b == n1 || (const void*)b == n2)
         return fail(VPP_ERR_INVALID_ARG, "the output must not alias an input");
     DeviceGuard dg(p->desc.device);
-    VPP_HIP(launch_curvature_rhs(p->k, rhs_geometry(p), n0, n1, n2, b, (hipStream_t)stream));
-    return VPP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* cv;
+    vpp_status st;
+    if ((st = cell_scratch_begin(p, 1, s, &cv))) return st;
+    VPP_HIP(launch_curvature_rhs(p->k, rhs_geometry(p), n0, n1, n2, b, cv, s));
+    return cell_scratch_end(p, s);
 }
 
 static vpp_status ensure_reinit_work(vpp_problem p)
@@ -1157,11 +1201,13 @@ vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, c
     const int one[3] = {1, 1, 1};
     const SharedEnum none = shared_enum(m1, p->k, one);   // no shared nodes: q is used as it is
     const int gdot = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxRedBlocks, (n + 1023) / 1024));
-    VPP_HIP(launch_reinit_rhs(p->k, ra, psi, w.b, s));
-    VPP_HIP(launch_reinit_diag(p->k, ra, w.diag, s));
+    double* cv;
+    if ((st = cell_scratch_begin(p, 1, s, &cv))) return st;
+    VPP_HIP(launch_reinit_rhs(p->k, ra, psi, w.b, cv, s));
+    VPP_HIP(launch_reinit_diag(p->k, ra, w.diag, cv, s));
     VPP_HIP(launch_fix_diagonal(ra.g.m, w.diag, w.invd, w.inv32, s));
     VPP_HIP(hipMemcpyAsync(w.x, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    VPP_HIP(launch_reinit_apply(p->k, ra, w.x, w.q, s));
+    VPP_HIP(launch_reinit_apply(p->k, ra, w.x, w.q, cv, s));
     CgState* hs = w.hst;
     std::memset(hs, 0, sizeof(CgState));
     VPP_HIP(hipMemcpyAsync(w.st, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
@@ -1194,7 +1240,7 @@ vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, c
         for (int done = 0; done < o->max_iter + chunk;) {
             for (int it = 0; it < chunk; ++it, ++done) {
                 const int par = done & 1;
-                VPP_HIP(launch_reinit_apply(p->k, ra, w.p, w.q, s));
+                VPP_HIP(launch_reinit_apply(p->k, ra, w.p, w.q, cv, s));
                 VPP_HIP(launch_dot_partials(w.p, w.q, n, w.dot, gdot, s));
                 VPP_HIP(launch_cg_assemble_update<double>(w.st, par, w.red, w.dot, gdot, ra.g.m, none, nullptr, 0,
                                                           w.r, w.q, w.invd, n, s));
@@ -1211,8 +1257,9 @@ vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, c
         else inf.status = VPP_ERR_NOT_CONVERGED;
     }
     // true residual, then the new level set
-    VPP_HIP(launch_reinit_apply(p->k, ra, w.x, w.q, s));
+    VPP_HIP(launch_reinit_apply(p->k, ra, w.x, w.q, cv, s));
     VPP_HIP(launch_residual(w.b, w.q, nullptr, n, w.red, w.rr, s));
+    if ((st = cell_scratch_end(p, s))) return st;
     VPP_HIP(hipMemcpyAsync(w.hrr, w.rr, sizeof(double), hipMemcpyDeviceToHost, s));
     VPP_HIP(hipMemcpyAsync(psi_out, w.x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     VPP_HIP(hipStreamSynchronize(s));
@@ -1248,8 +1295,11 @@ vpp_status vpp_reinit_apply(vpp_problem p, const double* n0, const double* n1, c
     vpp_status st;
     if ((st = reinit_args(p, n0, n1, n2, o, &ra))) return st;
     DeviceGuard dg(p->desc.device);
-    VPP_HIP(launch_reinit_apply(p->k, ra, x, y, (hipStream_t)stream));
-    return VPP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* cv;
+    if ((st = cell_scratch_begin(p, 1, s, &cv))) return st;
+    VPP_HIP(launch_reinit_apply(p->k, ra, x, y, cv, s));
+    return cell_scratch_end(p, s);
 }
 
 vpp_status vpp_reinit_diagonal(vpp_problem p, const double* n0, const double* n1, const double* n2,
@@ -1263,8 +1313,11 @@ vpp_status vpp_reinit_diagonal(vpp_problem p, const double* n0, const double* n1
     vpp_status st;
     if ((st = reinit_args(p, n0, n1, n2, o, &ra))) return st;
     DeviceGuard dg(p->desc.device);
-    VPP_HIP(launch_reinit_diag(p->k, ra, diag, (hipStream_t)stream));
-    return VPP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* cv;
+    if ((st = cell_scratch_begin(p, 1, s, &cv))) return st;
+    VPP_HIP(launch_reinit_diag(p->k, ra, diag, cv, s));
+    return cell_scratch_end(p, s);
 }
 
 vpp_status vpp_reinit_rhs(vpp_problem p, const double* psi, const double* n0, const double* n1, const double* n2,
@@ -1278,8 +1331,11 @@ vpp_status vpp_reinit_rhs(vpp_problem p, const double* psi, const double* n0, co
     vpp_status st;
     if ((st = reinit_args(p, n0, n1, n2, o, &ra))) return st;
     DeviceGuard dg(p->desc.device);
-    VPP_HIP(launch_reinit_rhs(p->k, ra, psi, b, (hipStream_t)stream));
-    return VPP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* cv;
+    if ((st = cell_scratch_begin(p, 1, s, &cv))) return st;
+    VPP_HIP(launch_reinit_rhs(p->k, ra, psi, b, cv, s));
+    return cell_scratch_end(p, s);
 }
 
 }  // extern "C"

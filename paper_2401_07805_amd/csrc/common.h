@@ -52,6 +52,17 @@ __host__ __device__ inline bool is_dirichlet(const MeshArgs& m, int i, int j, in
            ((m.bcmask & 16) && l == 0) || ((m.bcmask & 32) && l == m.nn[2] - 1);
 }
 
+// Cell (cx, cy, cz) of linear index i (x fastest); false past the last cell.
+__host__ __device__ inline bool cell_of(const MeshArgs& m, int64_t i, int& cx, int& cy, int& cz)
+{
+    if (i >= (int64_t)m.nc[0] * m.nc[1] * m.nc[2]) return false;
+    cx = (int)(i % m.nc[0]);
+    const int64_t r = i / m.nc[0];
+    cy = (int)(r % m.nc[1]);
+    cz = (int)(r / m.nc[1]);
+    return true;
+}
+
 // Parity colouring of the cells for node scatter-adds without atomics: colour
 // c holds the cells whose indices have the parities (c & 1, (c >> 1) & 1,
 // (c >> 2) & 1).  Two cells of one colour are two or more cells apart along

@@ -109,8 +109,16 @@ hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
 // Adjoint kernels.
 hipError_t launch_grad_coef(int k, const MeshArgs& m, const double* p, const double* lam, double* g,
                             hipStream_t s);
-hipError_t launch_grad_phi(int k, const MeshArgs& m, const double* phi, const double* g, double* out,
+// cv: cell scratch of cell_values(k, m) doubles (the cells' contributions,
+// summed into out by launch_node_sum in a fixed order).
+hipError_t launch_grad_phi(int k, const MeshArgs& m, const double* phi, const double* g, double* out, double* cv,
                            hipStream_t s);
+
+// Values per cell-major scratch array of a mesh: (k+1)^3 per cell.
+int64_t cell_values(int k, const MeshArgs& m);
+// out[g] = the sum over the cells holding node g, in increasing cell index, of
+// cv[q * ncell + c] (q: the node's position in cell c); every node written.
+hipError_t launch_node_sum(int k, const MeshArgs& m, const double* cv, double* out, hipStream_t s);
 
 // Closest-point projection onto {phi_h = 0} (one thread per point).
 struct CpArgs {
@@ -139,12 +147,12 @@ struct RhsGeo {
     double ih[3];   // 1 / h_d
     double vol;     // hx hy hz
 };
-// b_d = (grad phi_h / |grad phi_h|, v)_d for d = 0, 1, 2.
+// b_d = (grad phi_h / |grad phi_h|, v)_d for d = 0, 1, 2; cv: 3 cell_values(k, m) doubles.
 hipError_t launch_normal_rhs(int k, const RhsGeo& g, const double* phi, double* b0, double* b1, double* b2,
-                             hipStream_t s);
-// b = (-div n_h, v) for the nodal components n0, n1, n2.
+                             double* cv, hipStream_t s);
+// b = (-div n_h, v) for the nodal components n0, n1, n2; cv: cell_values(k, m) doubles.
 hipError_t launch_curvature_rhs(int k, const RhsGeo& g, const double* n0, const double* n1, const double* n2,
-                                double* b, hipStream_t s);
+                                double* b, double* cv, hipStream_t s);
 
 // One semi-implicit step of the level-set reinitialization:
 //   A psi' = b,  A = M/dtau + eps K_n,  K_n = ((grad u . n)(grad v . n)),
@@ -156,9 +164,10 @@ struct ReinitArgs {
     const double* n1;
     const double* n2;
 };
-hipError_t launch_reinit_apply(int k, const ReinitArgs& r, const double* x, double* y, hipStream_t s);
-hipError_t launch_reinit_diag(int k, const ReinitArgs& r, double* diag, hipStream_t s);
-hipError_t launch_reinit_rhs(int k, const ReinitArgs& r, const double* psi, double* b, hipStream_t s);
+// cv: cell_values(k, m) doubles of scratch each.
+hipError_t launch_reinit_apply(int k, const ReinitArgs& r, const double* x, double* y, double* cv, hipStream_t s);
+hipError_t launch_reinit_diag(int k, const ReinitArgs& r, double* diag, double* cv, hipStream_t s);
+hipError_t launch_reinit_rhs(int k, const ReinitArgs& r, const double* psi, double* b, double* cv, hipStream_t s);
 // part[b] = partial of x . y over the elements workgroup b visits (nblocks <= 1024).
 hipError_t launch_dot_partials(const double* x, const double* y, int64_t n, double* part, int nblocks,
                                hipStream_t s);

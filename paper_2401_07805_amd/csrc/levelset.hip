@@ -8,9 +8,10 @@
 //              n_h the (filtered) nodal normal components.
 // One cell per thread: values at the Gauss points by the interpolation
 // sweeps, derivatives by the collocation derivative along each direction,
-// the weights W_q, the transposed interpolation sweeps, and a scatter-add into
-// the nodes (all rows assembled, no constraint applied) without atomics: one
-// launch per cell colour (cell_color), so every node sum has a fixed order.
+// the weights W_q and the transposed interpolation sweeps, stored per cell in
+// a cell-major buffer; a second launch adds them into the nodes (all rows
+// assembled, no constraint applied), each node summing its cells in a fixed
+// order, so no atomics are needed and every run gives the same bits.
 #include "kernels.h"
 
 namespace vpp {
@@ -32,19 +33,18 @@ __device__ __forceinline__ void load_nodes(const MeshArgs& m, const double* __re
             for (int a0 = 0; a0 < N; ++a0) u[a0 + N * (a1 + N * a2)] = v[base + a0 + nx * a1 + nxy * a2];
 }
 
+// The (k+1)^3 local results of cell (cx, cy, cz) into the cell-major buffer
+// cv (position q of cell c at cv[q * ncell + c]: a wave's stores are
+// consecutive); launch_node_sum then adds them into the nodes.
 template <int K>
-__device__ __forceinline__ void scatter_add(const MeshArgs& m, int cx, int cy, int cz,
-                                            const double (&s)[(K + 1) * (K + 1) * (K + 1)], double* __restrict__ b)
+__device__ __forceinline__ void store_cell(const MeshArgs& m, int cx, int cy, int cz,
+                                           const double (&s)[(K + 1) * (K + 1) * (K + 1)], double* __restrict__ cv)
 {
-    constexpr int N = K + 1;
-    const int64_t nx = m.nn[0], nxy = (int64_t)m.nn[0] * m.nn[1];
-    const int64_t base = node_index(m, (int64_t)K * cx, (int64_t)K * cy, (int64_t)K * cz);
+    constexpr int N3 = (K + 1) * (K + 1) * (K + 1);
+    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
+    const int64_t c = cx + (int64_t)m.nc[0] * (cy + (int64_t)m.nc[1] * cz);
 #pragma unroll
-    for (int a2 = 0; a2 < N; ++a2)
-#pragma unroll
-        for (int a1 = 0; a1 < N; ++a1)
-#pragma unroll
-            for (int a0 = 0; a0 < N; ++a0) b[base + a0 + nx * a1 + nxy * a2] += s[a0 + N * (a1 + N * a2)];
+    for (int q = 0; q < N3; ++q) cv[q * ncell + c] = s[q];
 }
 
 template <int K>
@@ -55,15 +55,62 @@ __device__ __forceinline__ void transpose_interp(double (&s)[(K + 1) * (K + 1) *
     sweep3<K, MS, true, 0>(s);
 }
 
+// out[g] = sum of the cell-major values cv[q * ncell + c] of the cells c holding
+// node g (q: the node's position in c), cells taken in increasing index.
+template <int K>
+__global__ void __launch_bounds__(256) node_sum_kernel(MeshArgs m, const double* __restrict__ cv,
+                                                       double* __restrict__ out)
+{
+    constexpr int N = K + 1;
+    const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];
+    const int64_t nn = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < nn; g += (int64_t)gridDim.x * 256) {
+        const int64_t r = g / m.nn[0];
+        const int idx[3] = {(int)(g - r * m.nn[0]), (int)(r % m.nn[1]), (int)(r / m.nn[1])};
+        int cell[3][2], loc[3][2], cnt[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int q = idx[d] / K, rem = idx[d] - q * K;
+            if (rem != 0) {
+                cell[d][0] = q;
+                loc[d][0] = rem;
+                cnt[d] = 1;
+            } else {
+                int c = 0;
+                if (q > 0) {
+                    cell[d][c] = q - 1;
+                    loc[d][c] = K;
+                    ++c;
+                }
+                if (q < m.nc[d]) {
+                    cell[d][c] = q;
+                    loc[d][c] = 0;
+                    ++c;
+                }
+                cnt[d] = c;
+            }
+        }
+        double v = 0.0;
+        for (int b2 = 0; b2 < cnt[2]; ++b2)
+            for (int b1 = 0; b1 < cnt[1]; ++b1)
+                for (int b0 = 0; b0 < cnt[0]; ++b0) {
+                    const int64_t c = cell[0][b0] + (int64_t)m.nc[0] * (cell[1][b1] + (int64_t)m.nc[1] * cell[2][b2]);
+                    const int q = loc[0][b0] + N * (loc[1][b1] + N * loc[2][b2]);
+                    v += cv[q * ncell + c];
+                }
+        out[g] = v;
+    }
+}
+
 template <int K>
 __global__ void __launch_bounds__(64) normal_rhs_kernel(RhsGeo g, const double* __restrict__ phi,
-                                                        double* __restrict__ b0, double* __restrict__ b1,
-                                                        double* __restrict__ b2, CellColor cc)
+                                                        double* __restrict__ cv0, double* __restrict__ cv1,
+                                                        double* __restrict__ cv2)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = g.m;
     int cx, cy, cz;
-    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
+    if (!cell_of(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double gx[N3], gy[N3], gz[N3];
     load_nodes<K>(m, phi, cx, cy, cz, gx);
     sweep3<K, MS, false, 0>(gx);
@@ -84,11 +131,11 @@ __global__ void __launch_bounds__(64) normal_rhs_kernel(RhsGeo g, const double* 
         gz[q] = w * c;
     }
     transpose_interp<K>(gx);
-    scatter_add<K>(m, cx, cy, cz, gx, b0);
+    store_cell<K>(m, cx, cy, cz, gx, cv0);
     transpose_interp<K>(gy);
-    scatter_add<K>(m, cx, cy, cz, gy, b1);
+    store_cell<K>(m, cx, cy, cz, gy, cv1);
     transpose_interp<K>(gz);
-    scatter_add<K>(m, cx, cy, cz, gz, b2);
+    store_cell<K>(m, cx, cy, cz, gz, cv2);
 }
 
 template <int K, int D>
@@ -109,13 +156,12 @@ __device__ __forceinline__ void add_derivative(const MeshArgs& m, const double* 
 template <int K>
 __global__ void __launch_bounds__(64) curvature_rhs_kernel(RhsGeo g, const double* __restrict__ n0,
                                                            const double* __restrict__ n1,
-                                                           const double* __restrict__ n2, double* __restrict__ b,
-                                                           CellColor cc)
+                                                           const double* __restrict__ n2, double* __restrict__ cv)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = g.m;
     int cx, cy, cz;
-    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
+    if (!cell_of(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double div[N3];
 #pragma unroll
     for (int q = 0; q < N3; ++q) div[q] = 0.0;
@@ -125,7 +171,7 @@ __global__ void __launch_bounds__(64) curvature_rhs_kernel(RhsGeo g, const doubl
 #pragma unroll
     for (int q = 0; q < N3; ++q) div[q] *= -g.vol * wref<K>(q % N, (q / N) % N, q / (N * N));
     transpose_interp<K>(div);
-    scatter_add<K>(m, cx, cy, cz, div, b);
+    store_cell<K>(m, cx, cy, cz, div, cv);
 }
 
 // ---------------------------------------------------------------------------
@@ -133,8 +179,8 @@ __global__ void __launch_bounds__(64) curvature_rhs_kernel(RhsGeo g, const doubl
 // time with the compressive flux explicit):
 //   (psi', v)/dtau + eps ((grad psi' . n)(grad v . n)) = (psi, v)/dtau + ((1 - psi^2)/2 n, grad v),
 // boundary terms of the integrations by parts dropped, n the nodal normal
-// interpolated at the Gauss points as it is.  One cell per thread, one launch
-// per cell colour, scatter-add without atomics (the output is zeroed first).
+// interpolated at the Gauss points as it is.  One cell per thread into the
+// cell-major buffer, then the node sum (launch_node_sum).
 
 // The nodal normal components at the Gauss points of a cell.
 template <int K>
@@ -193,12 +239,12 @@ __device__ __forceinline__ void add_flux(const double (&w)[(K + 1) * (K + 1) * (
 
 template <int K>
 __global__ void __launch_bounds__(64) reinit_apply_kernel(ReinitArgs r, const double* __restrict__ x,
-                                                          double* __restrict__ y, CellColor cc)
+                                                          double* __restrict__ cv)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = r.g.m;
     int cx, cy, cz;
-    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
+    if (!cell_of(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     // One normal component is live at a time (interpolated again for the
     // flux pass): holding all three at the Gauss points left one wave per SIMD.
     double u[N3], s[N3], out[N3], nd[N3];
@@ -227,7 +273,7 @@ __global__ void __launch_bounds__(64) reinit_apply_kernel(ReinitArgs r, const do
     normal_comp_at_gauss<K, 2>(r, cx, cy, cz, nd);
     add_flux<K, 2>(s, nd, r.g.ih[2], out);
     transpose_interp<K>(out);
-    scatter_add<K>(m, cx, cy, cz, out, y);
+    store_cell<K>(m, cx, cy, cz, out, cv);
 }
 
 // Transposed sweep along DIR with the product table T0(q,a) T1(q,a) of the
@@ -296,12 +342,12 @@ __device__ __forceinline__ void diag_pair(const ReinitArgs& r, const double (&nq
 }
 
 template <int K>
-__global__ void __launch_bounds__(64) reinit_diag_kernel(ReinitArgs r, double* __restrict__ diag, CellColor cc)
+__global__ void __launch_bounds__(64) reinit_diag_kernel(ReinitArgs r, double* __restrict__ cv)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = r.g.m;
     int cx, cy, cz;
-    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
+    if (!cell_of(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double nq[3][N3], out[N3], c[N3];
     normal_at_gauss<K>(r, cx, cy, cz, nq);
 #pragma unroll
@@ -316,17 +362,17 @@ __global__ void __launch_bounds__(64) reinit_diag_kernel(ReinitArgs r, double* _
     diag_pair<K, 0, 1>(r, nq, out);
     diag_pair<K, 0, 2>(r, nq, out);
     diag_pair<K, 1, 2>(r, nq, out);
-    scatter_add<K>(m, cx, cy, cz, out, diag);
+    store_cell<K>(m, cx, cy, cz, out, cv);
 }
 
 template <int K>
 __global__ void __launch_bounds__(64) reinit_rhs_kernel(ReinitArgs r, const double* __restrict__ psi,
-                                                        double* __restrict__ b, CellColor cc)
+                                                        double* __restrict__ cv)
 {
     constexpr int N = K + 1, N3 = N * N * N;
     const MeshArgs& m = r.g.m;
     int cx, cy, cz;
-    if (!color_cell(cc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
+    if (!cell_of(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cx, cy, cz)) return;
     double nq[3][N3], u[N3], w[N3], out[N3];
     normal_at_gauss<K>(r, cx, cy, cz, nq);
     load_nodes<K>(m, psi, cx, cy, cz, u);
@@ -343,7 +389,7 @@ __global__ void __launch_bounds__(64) reinit_rhs_kernel(ReinitArgs r, const doub
     add_flux<K, 1>(w, nq[1], r.g.ih[1], out);
     add_flux<K, 2>(w, nq[2], r.g.ih[2], out);
     transpose_interp<K>(out);
-    scatter_add<K>(m, cx, cy, cz, out, b);
+    store_cell<K>(m, cx, cy, cz, out, cv);
 }
 
 // Per-workgroup partials of x . y (fixed order inside the workgroup).
@@ -365,73 +411,82 @@ __global__ void __launch_bounds__(256) dot_partials_kernel(const double* __restr
 
 }  // namespace
 
-// One launch of KERNEL<k> per cell colour (the scatter-adds need no atomics).
-#define VPP_COLORED(KERNEL, ...)                                                                               \
-    switch (k) {                                                                                                \
-    case 2:                                                                                                     \
-        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {                                    \
-            hipLaunchKernelGGL(KERNEL<2>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__, cc);                     \
-        });                                                                                                     \
-    case 3:                                                                                                     \
-        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {                                    \
-            hipLaunchKernelGGL(KERNEL<3>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__, cc);                     \
-        });                                                                                                     \
-    case 4:                                                                                                     \
-        return for_each_color(m, 64, [&](const CellColor& cc, int blocks) {                                    \
-            hipLaunchKernelGGL(KERNEL<4>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__, cc);                     \
-        });                                                                                                     \
-    default: return hipErrorInvalidValue;                                                                       \
+// The cell kernel KERNEL<k> over all cells (64-thread workgroups), writing the
+// cell-major buffer(s) that the node sums then read.
+#define VPP_CELLS(KERNEL, ...)                                                                                  \
+    {                                                                                                           \
+        const int64_t ncell = (int64_t)m.nc[0] * m.nc[1] * m.nc[2];                                             \
+        const int blocks = (int)((ncell + 63) / 64);                                                            \
+        switch (k) {                                                                                            \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__); break;              \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__); break;              \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(blocks), dim3(64), 0, s, __VA_ARGS__); break;              \
+        default: return hipErrorInvalidValue;                                                                   \
+        }                                                                                                       \
+        const hipError_t e = hipGetLastError();                                                                 \
+        if (e != hipSuccess) return e;                                                                          \
     }
 
+hipError_t launch_node_sum(int k, const MeshArgs& m, const double* cv, double* out, hipStream_t s)
+{
+    const int64_t nn = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
+    const int64_t want = (nn + 255) / 256;
+    const int blocks = (int)(want < 16384 ? want : 16384);
+    switch (k) {
+    case 2: hipLaunchKernelGGL(node_sum_kernel<2>, dim3(blocks), dim3(256), 0, s, m, cv, out); break;
+    case 3: hipLaunchKernelGGL(node_sum_kernel<3>, dim3(blocks), dim3(256), 0, s, m, cv, out); break;
+    case 4: hipLaunchKernelGGL(node_sum_kernel<4>, dim3(blocks), dim3(256), 0, s, m, cv, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int64_t cell_values(int k, const MeshArgs& m)
+{
+    return (int64_t)(k + 1) * (k + 1) * (k + 1) * m.nc[0] * m.nc[1] * m.nc[2];
+}
+
 hipError_t launch_normal_rhs(int k, const RhsGeo& g, const double* phi, double* b0, double* b1, double* b2,
-                             hipStream_t s)
+                             double* cv, hipStream_t s)
 {
     const MeshArgs& m = g.m;
-    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
+    const int64_t nv = cell_values(k, m);
+    VPP_CELLS(normal_rhs_kernel, g, phi, cv, cv + nv, cv + 2 * nv)
     hipError_t e;
-    if ((e = launch_fill<double>(b0, n, 0.0, s)) != hipSuccess || (e = launch_fill<double>(b1, n, 0.0, s)) != hipSuccess ||
-        (e = launch_fill<double>(b2, n, 0.0, s)) != hipSuccess)
+    if ((e = launch_node_sum(k, m, cv, b0, s)) != hipSuccess || (e = launch_node_sum(k, m, cv + nv, b1, s)) != hipSuccess)
         return e;
-    VPP_COLORED(normal_rhs_kernel, g, phi, b0, b1, b2)
+    return launch_node_sum(k, m, cv + 2 * nv, b2, s);
 }
 
 hipError_t launch_curvature_rhs(int k, const RhsGeo& g, const double* n0, const double* n1, const double* n2,
-                                double* b, hipStream_t s)
+                                double* b, double* cv, hipStream_t s)
 {
     const MeshArgs& m = g.m;
-    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
-    hipError_t e = launch_fill<double>(b, n, 0.0, s);
-    if (e != hipSuccess) return e;
-    VPP_COLORED(curvature_rhs_kernel, g, n0, n1, n2, b)
+    VPP_CELLS(curvature_rhs_kernel, g, n0, n1, n2, cv)
+    return launch_node_sum(k, m, cv, b, s);
 }
 
-hipError_t launch_reinit_apply(int k, const ReinitArgs& r, const double* x, double* y, hipStream_t s)
+hipError_t launch_reinit_apply(int k, const ReinitArgs& r, const double* x, double* y, double* cv, hipStream_t s)
 {
     const MeshArgs& m = r.g.m;
-    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
-    hipError_t e = launch_fill<double>(y, n, 0.0, s);
-    if (e != hipSuccess) return e;
-    VPP_COLORED(reinit_apply_kernel, r, x, y)
+    VPP_CELLS(reinit_apply_kernel, r, x, cv)
+    return launch_node_sum(k, m, cv, y, s);
 }
 
-hipError_t launch_reinit_diag(int k, const ReinitArgs& r, double* diag, hipStream_t s)
+hipError_t launch_reinit_diag(int k, const ReinitArgs& r, double* diag, double* cv, hipStream_t s)
 {
     const MeshArgs& m = r.g.m;
-    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
-    hipError_t e = launch_fill<double>(diag, n, 0.0, s);
-    if (e != hipSuccess) return e;
-    VPP_COLORED(reinit_diag_kernel, r, diag)
+    VPP_CELLS(reinit_diag_kernel, r, cv)
+    return launch_node_sum(k, m, cv, diag, s);
 }
 
-hipError_t launch_reinit_rhs(int k, const ReinitArgs& r, const double* psi, double* b, hipStream_t s)
+hipError_t launch_reinit_rhs(int k, const ReinitArgs& r, const double* psi, double* b, double* cv, hipStream_t s)
 {
     const MeshArgs& m = r.g.m;
-    const int64_t n = (int64_t)m.nn[0] * m.nn[1] * m.nn[2];
-    hipError_t e = launch_fill<double>(b, n, 0.0, s);
-    if (e != hipSuccess) return e;
-    VPP_COLORED(reinit_rhs_kernel, r, psi, b)
+    VPP_CELLS(reinit_rhs_kernel, r, psi, cv)
+    return launch_node_sum(k, m, cv, b, s);
 }
-#undef VPP_COLORED
+#undef VPP_CELLS
 
 hipError_t launch_dot_partials(const double* x, const double* y, int64_t n, double* part, int nblocks, hipStream_t s)
 {
