@@ -1,7 +1,8 @@
-"""The node scatter-add kernels run without atomics, one launch per parity
-colour of the cells, so repeated calls give the same bits: the Jacobi
-diagonal, dJ/dphi, the level-set right-hand sides, and the reinitialization
-operator, diagonal and right-hand side.  Values are compared with the oracle
+"""The kernels that add per-cell contributions into the nodes run without
+atomics (the Jacobi diagonal one launch per parity colour of the cells; dJ/dphi,
+the level-set right-hand sides and the reinitialization operator, diagonal and
+right-hand side through a cell-major scratch and a node sum in a fixed cell
+order), so repeated calls give the same bits.  Values are compared with the oracle
 by the parity tests of each piece; this file checks bitwise repeatability on
 meshes large enough that many workgroups write every node's neighbours, and
 the diagonal against the oracle on an odd-sized mesh (ragged colours)."""
