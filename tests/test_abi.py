@@ -101,6 +101,7 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     # the largest meshes: node indices are 32-bit (4 * 400 + 1 = 1601 nodes per
     # side is 4.1e9 nodes), refused on the host
     d.degree = 4
+    d.bc[2] = 0
     d.ncells[:] = [400, 400, 400]
     assert lib.vpp_create(ctypes.byref(d), ctypes.byref(h)) == 1
     assert b"too large" in lib.vpp_last_error()
