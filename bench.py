@@ -14,8 +14,11 @@ value = operator MDoF/s of the applies (N * applies / apply time), timed with
 HIP events on the stream the kernels run on.  After the timed steps the line
 also carries the rest of the metric: the cold FP32 Q2 apply, the Q3 (43^3)
 FP64 and FP32 applies under the same protocol and its FP64-vs-mixed PCG to
-rtol 1e-8, the same solves on the 64^3 Q2 bubble, and the adjoint kernels
-against their algorithmic bytes.  After the timed steps the same
+rtol 1e-8, the same solves on the 64^3 Q2 bubble, the adjoint kernels
+against their algorithmic bytes, the once-refined mesh, the batched workload
+(8 meshes of 16^3..64^3 Q2 with 4 right-hand sides each: one persistent graph
+launch, and the batched FP64 PCG of its 32 systems) and FP64 vs mixed PCG on
+96^3 Q3 (24.1M DoFs, 20 spheres, ratio 1e4).  After the timed steps the same
 applies are also captured in one HIP graph and replayed (`apply_us_graph`,
 each replay checked against the eager outputs); `value` stays the eager rate.  One apply is two launches: the
 tile kernel and the shared-node assembly; `roofline` prices the pair against
@@ -253,7 +256,8 @@ def secondary(torch, vpp, W, dev, cache, xs, ys, probs_q2):
     the cold FP32 Q2 apply; the Q3 43^3 FP64 and FP32 applies (cold, same
     protocol) and its FP64-vs-mixed PCG to rtol 1e-8; the same solves on the 64^3
     Q2 bubble; dJ/dc (grad_coef) and dJ/dphi (grad_phi) at 64^3 Q2 against
-    their algorithmic bytes."""
+    their algorithmic bytes; the once-refined mesh; the batched workload's
+    aggregate apply rate and batched PCG; FP64 vs mixed PCG at 96^3 Q3."""
     out = {}
     napp = xs.shape[0]
     N2 = probs_q2[0].n
@@ -330,6 +334,10 @@ def secondary(torch, vpp, W, dev, cache, xs, ys, probs_q2):
     del gphi
     out["adjoint_q2"] = res
     out["amr_q2"] = amr_figures(torch, vpp, W, dev)
+    # the batched workload (aggregate rate and batched PCG) and mixed precision
+    # at scale (96^3 Q3, 24.1M DoFs)
+    out["c3_batch"] = batch_figures(torch, vpp, W, dev, cache, per_mesh=False)
+    out["c2_q3_96"] = c2_figures(torch, vpp, W, dev, cache)
     return out
 
 
@@ -612,10 +620,11 @@ def c2_figures(torch, vpp, W, dev, cache):
     return out
 
 
-def batch_figures(torch, vpp, W, dev, cache):
+def batch_figures(torch, vpp, W, dev, cache, per_mesh=True):
     """The batched workload: 8 independent single-sphere meshes of 16..64 cells per
     side (Q2, 7.6M DoFs) with 4 right-hand sides each, applied by one persistent
-    graph launch; aggregate and per-mesh DoF-rhs rates."""
+    graph launch; aggregate (and with per_mesh, per-mesh) DoF-rhs rates, and the
+    batched FP64 PCG of its 32 systems."""
     wls = W.batch_meshes()
     probs, xs = [], []
     for wl in wls:
@@ -645,7 +654,7 @@ def batch_figures(torch, vpp, W, dev, cache):
     out = {"batch_config": bt.config, "batch_dof_rhs": total, "batch_apply_us": t * 1e6,
            "batch_aggregate_mdofs": r, "batch_per_mesh_mdofs": []}
     i = 0
-    for p, wl, nr in zip(probs, wls, nrhs):
+    for p, wl, nr in zip(probs, wls, nrhs) if per_mesh else ():
         b1 = vpp.Batch([p], [nr], tune_cache=cache)
         _, r1 = rate(b1, xs[i:i + nr], ys[i:i + nr], wl.mesh.ndofs * nr)
         out["batch_per_mesh_mdofs"].append({"n": wl.mesh.ncells[0], "ratio": wl.extra["ratio"], "mdofs": r1})
