@@ -75,6 +75,8 @@ def parse():
                     help="instead of the bench line: time every apply configuration of degree K on the droplet "
                          "(cold, 100 applies) and print one JSON line per configuration")
     ap.add_argument("--variants", default="", help="with --sweep: comma-separated kernel variants to time")
+    ap.add_argument("--figure", default="", choices=["", "closest_points", "filter", "adjoint", "amr", "c2", "batch"],
+                    help="instead of the bench line: only this secondary figure, as one JSON line")
     return ap.parse_args()
 
 
@@ -746,6 +748,19 @@ def main():
         import paper_2401_07805_amd as vpp
         variants = {int(v) for v in args.variants.split(",") if v}
         config_sweep(torch, vpp, W, args.sweep, variants)
+        return
+    if args.figure:
+        import workloads as W
+        import paper_2401_07805_amd as vpp
+        dev = torch.device("cuda", 0)
+        cache = os.path.join(ROOT, "paper_2401_07805_amd", "tune_cache.json")
+        fig = {"closest_points": lambda: closest_point_figures(torch, vpp, W, dev),
+               "filter": lambda: filter_figures(torch, vpp, W, dev, cache),
+               "adjoint": lambda: adjoint_figures(torch, vpp, W, dev, cache),
+               "amr": lambda: amr_figures(torch, vpp, W, dev),
+               "c2": lambda: c2_figures(torch, vpp, W, dev, cache),
+               "batch": lambda: batch_figures(torch, vpp, W, dev, cache)}[args.figure]()
+        print(json.dumps({"figure": args.figure, **fig}), flush=True)
         return
     import workloads as W
     import paper_2401_07805_amd as vpp
