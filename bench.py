@@ -57,8 +57,8 @@ CG_BYTES_PER_DOF_ITER_F64 = 104.0
 # not counted.
 FLOPS_PER_CELL_Q2 = 1758.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_q2_64cube_traffic.md")
-KERNEL_SOURCES = ["apply_impl.h", "apply_configs.h", "apply_misc.hip", "apply_f64.hip", "common.h", "tables.h",
-                  "shared_nodes.h", "kernels.h", "bounds.h"]
+KERNEL_SOURCES = ["apply_impl.h", "apply_configs.h", "apply_misc.hip", "apply_f64.hip", "apply_f64_k2.hip", "common.h",
+                  "tables.h", "shared_nodes.h", "kernels.h", "bounds.h"]
 
 
 def parse():
@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--applies", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="leave out the secondary figures (Q3, FP32, batch, solvers of the other rows)")
     ap.add_argument("--extras", action="store_true", help="also time FP32, Q3/Q4, hot-cache applies, bubble solves")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run a plain 512 MiB device copy (counter calibration)")
@@ -823,8 +825,10 @@ def main():
     errmx = float(torch.linalg.norm(last[6] - pstar) / torch.linalg.norm(pstar))
     t_graph, graph_diff = graph_applies(torch, probs, xs, ys, napp, dev)
     traffic = measured_traffic(cfg)
-    log("secondary figures")
-    sec = secondary(torch, vpp, W, dev, cache, xs, ys, probs)
+    sec = {}
+    if not args.no_secondary:
+        log("secondary figures")
+        sec = secondary(torch, vpp, W, dev, cache, xs, ys, probs)
     out = {
         "metric": "operator MDoF/s + CG time to rtol 1e-8, FP64 vs FP32-mixed, Q2/Q3 hex",
         "value": value,
