@@ -91,12 +91,27 @@ typedef struct {
  * restarts it from the FP64 residual; a second one without progress hands the
  * rest of the solve to FP64 PCG.  inner_max_iter (0 = none) caps the FP32
  * iterations between two replacements.  check_every = iterations between host-side checks of the
- * device stop flag (0 = 32).  Scalars of every CG are FP64. */
+ * device stop flag (0 = 32).  Scalars of every CG are FP64.
+ *
+ * deflate (VPP_MIXED only; 0 = off, at most 8): the first FP32 phase is
+ * recorded (its FP32 residuals, at most deflate_history of them, 0 = 512, and
+ * never more than a quarter of the free device memory, allocated on first use
+ * and kept with the problem) and its CG coefficients give the Lanczos matrix
+ * of the Jacobi-scaled operator.  Of its `deflate` smallest Ritz values those
+ * followed by a gap (the next one at least 10 times larger: isolated near-null
+ * modes such as the nearly constant pressure inside a gas bubble) give Ritz
+ * vectors W, and every replacement also adds the Galerkin correction
+ * x += W (W^T A W)^-1 W^T r.  This keeps the smallest eigenvalues that FP64
+ * PCG would have resolved from returning at every replacement; without such a
+ * gap nothing is deflated.  A correction that would move the residual by more than a
+ * tenth of its norm is skipped (it would no longer fit the kept search
+ * direction); if the first one is, the solve continues without deflation. */
 typedef struct {
     double rtol, atol;
     int32_t max_iter, precision;
     double inner_rtol;
     int32_t inner_max_iter, check_every;
+    int32_t deflate, deflate_history;
 } vpp_cg_opts;
 
 typedef struct {
@@ -105,6 +120,8 @@ typedef struct {
     int32_t status;            /* vpp_status of the solve */
     double rel_residual;       /* ||r|| / ||r0|| as tracked by the (outer) iteration */
     double true_rel_residual;  /* ||b - A x|| / ||b - A x0|| recomputed in FP64 at the end */
+    int32_t deflation_corrections;   /* Galerkin corrections applied (VPP_MIXED with deflate > 0) */
+    double deflation_first_change;   /* ||A W c|| / ||r|| of the first correction considered (-1: none) */
 } vpp_cg_info;
 
 /* Options of the closest-point projection (vpp_closest_points). */

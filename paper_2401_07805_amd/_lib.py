@@ -25,12 +25,13 @@ class Desc(C.Structure):
 class CgOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("inner_rtol", C.c_double), ("inner_max_iter", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("deflate", C.c_int32), ("deflate_history", C.c_int32)]
 
 
 class CgInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer_iterations", C.c_int32), ("status", C.c_int32),
-                ("rel_residual", C.c_double), ("true_rel_residual", C.c_double)]
+                ("rel_residual", C.c_double), ("true_rel_residual", C.c_double),
+                ("deflation_corrections", C.c_int32), ("deflation_first_change", C.c_double)]
 
 
 class KernelConfig(C.Structure):

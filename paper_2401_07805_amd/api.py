@@ -20,6 +20,9 @@ class VppError(RuntimeError):
 
 
 _PREC = {"fp64": L.VPP_FP64, "fp32": L.VPP_FP32}
+# Largest number of Ritz vectors of the first FP32 phase that mixed-precision
+# solves deflate (0: none; only isolated small Ritz values are used)
+DEFLATE = 4
 
 
 def _check(status: int):
@@ -46,7 +49,8 @@ def _vec(t: torch.Tensor, n: int, dtype: torch.dtype, device: torch.device, name
 def _info(ci: L.CgInfo) -> dict:
     return {"iterations": ci.iterations, "outer_iterations": ci.outer_iterations, "status": ci.status,
             "status_name": L.STATUS_NAMES.get(ci.status, str(ci.status)),
-            "rel_residual": ci.rel_residual, "true_rel_residual": ci.true_rel_residual}
+            "rel_residual": ci.rel_residual, "true_rel_residual": ci.true_rel_residual,
+            "deflation_corrections": ci.deflation_corrections, "deflation_first_change": ci.deflation_first_change}
 
 
 class Problem:
@@ -235,10 +239,14 @@ class Problem:
     def cg_solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, rtol: float = 1e-8,
                  atol: float = 0.0, max_iter: int = 100000, precision: str = "fp64",
                  inner_rtol: float = 1e-2, inner_max_iter: int = 0, check_every: int = 0,
-                 raise_on_failure: bool = True):
+                 raise_on_failure: bool = True, deflate: int = DEFLATE, deflate_history: int = 0):
+        """Jacobi PCG; precision "mixed" runs FP32 recurrences with FP64
+        residual replacements, and with deflate > 0 a Galerkin correction in the
+        span of that many Ritz vectors of the first FP32 phase at every
+        replacement (vpp_cg_opts)."""
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         o = L.CgOpts(rtol, atol, int(max_iter), L.VPP_MIXED if precision == "mixed" else L.VPP_FP64,
-                     inner_rtol, int(inner_max_iter), int(check_every))
+                     inner_rtol, int(inner_max_iter), int(check_every), int(deflate), int(deflate_history))
         ci = L.CgInfo()
         st = L.load().vpp_cg_solve(self._h, _vec(b, self.n, torch.float64, self.device, "b"),
                                    _vec(x, self.n, torch.float64, self.device, "x"), C.byref(o),
@@ -341,13 +349,13 @@ class Batch:
         _check(L.load().vpp_batch_apply(self._h, tx, ty, _stream(self.device)))
 
     def cg_solve(self, bs, xs, rtol=1e-8, atol=0.0, max_iter=100000, precision="fp64", inner_rtol=1e-2,
-                 check_every=0, raise_on_failure=True):
+                 check_every=0, raise_on_failure=True, deflate=DEFLATE):
         """Solve A_i x = b for every (problem, rhs) pair; xs hold the initial
         guesses and receive the solutions.  Returns one info dict per pair."""
         tb, tx = self._tables(bs, xs)
         n = len(bs)
         o = L.CgOpts(rtol, atol, int(max_iter), L.VPP_MIXED if precision == "mixed" else L.VPP_FP64,
-                     inner_rtol, 0, int(check_every))
+                     inner_rtol, 0, int(check_every), int(deflate), 0)
         infos = (L.CgInfo * n)()
         st = L.load().vpp_batch_cg_solve(self._h, tb, tx, C.byref(o), infos, _stream(self.device))
         if st != L.VPP_OK and (raise_on_failure or st not in (5, 6)):

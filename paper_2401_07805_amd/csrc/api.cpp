@@ -17,6 +17,7 @@
 
 #include "../../include/vpp.h"
 #include "blas.h"
+#include "tridiag.h"
 #include "amr.h"
 #include "kernels.h"
 #include "noalloc.h"
@@ -116,6 +117,17 @@ struct CgWork {
     int graph_iters = 0;
     LaunchCfg graph_cfg{-1, {0, 0, 0}};
     LaunchCfg graph_cfg32{-1, {0, 0, 0}};
+    // deflation of the mixed-precision solver (allocated on first use)
+    float* hist = nullptr;        // FP32 residuals of the first phase: hist_cap rows of hist_stride
+    int hist_cap = 0;
+    int64_t hist_stride = 0;
+    double* coef = nullptr;       // alpha, beta, r.z of every recorded iteration
+    double* dW = nullptr;         // Ritz vectors, kMaxDefl x N
+    double* dAW = nullptr;        // the operator applied to them
+    double* dC = nullptr;         // their coefficients on the recorded residuals
+    double* dred = nullptr;       // kMaxDefl x kMaxRedBlocks partial sums
+    double* dout = nullptr;       // kMaxDefl dot products
+    double* hout = nullptr;       // pinned host mirror of dout
 };
 
 // Workspace of the reinitialization step (allocated on first use).
@@ -371,10 +383,15 @@ static void free_work(CgWork& w)
     dev_free(w.x); dev_free(w.b); dev_free(w.r); dev_free(w.p); dev_free(w.q);
     dev_free(w.x32); dev_free(w.r32); dev_free(w.p32); dev_free(w.q32); dev_free(w.xb);
     dev_free(w.st); dev_free(w.st32); dev_free(w.rr); dev_free(w.red);
+    dev_free(w.hist); dev_free(w.coef); dev_free(w.dW); dev_free(w.dAW); dev_free(w.dC); dev_free(w.dred);
+    dev_free(w.dout);
+    w.hist_cap = 0;
     if (w.hst) (void)hipHostFree(w.hst);
     if (w.hrr) (void)hipHostFree(w.hrr);
+    if (w.hout) (void)hipHostFree(w.hout);
     w.hst = nullptr;
     w.hrr = nullptr;
+    w.hout = nullptr;
 }
 
 static vpp_status ensure_work(vpp_problem p, bool mixed)
@@ -544,6 +561,206 @@ static vpp_status residual64(vpp_problem p, double* rr)
     return VPP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Deflation of the mixed-precision solver.  FP32 PCG follows FP64 PCG
+// iteration for iteration until its true residual stalls (near 1e-3 of the
+// scaled residual at 64^3 and density ratio 1000), but every replacement of
+// the residual puts FP32-sized perturbations back into the eigenvectors of the
+// smallest eigenvalues, which the FP64 recurrence would have left resolved:
+// the later phases then converge at the unaccelerated rate.  The first FP32
+// phase is a Lanczos process: its CG coefficients define the tridiagonal
+// matrix T of D^-1/2 A D^-1/2 on the basis v_j = D^-1/2 r_j / sqrt(r_j.z_j),
+// whose smallest eigenpairs (theta, s) give Ritz vectors w = D^-1 sum_j s_j
+// r_j / sqrt(r_j.z_j) in the original variables.  Only Ritz values followed by
+// a gap (the next one at least 10 times larger) are used: an isolated
+// near-null mode is resolved accurately by the FP32 Lanczos process, a cluster
+// is not, and deflating part of one slows the later phases down.  At every
+// replacement the FP64 iterate gets the Galerkin correction in span(W): x += W G^-1 W^T r,
+// r -= A W G^-1 W^T r with G = W^T A W (a pivoted Cholesky factor that drops
+// dependent columns).  A correction that would move r by more than a tenth of
+// ||r|| (||A W c||, from the Gram matrix of A W) is not applied: the kept
+// search direction would no longer fit the residual.  Converged Ritz vectors
+// of the smallest eigenvalues move r very little (their eigenvalues are
+// small); if the first correction is refused, the solve continues without
+// deflation.
+
+struct Defl {
+    int k = 0;                     // Ritz vectors in W (0: off)
+    int nk = 0;                    // columns kept by the pivoted factorization
+    int perm[kMaxDefl] = {};
+    double L[kMaxDefl][kMaxDefl] = {};
+    double H[kMaxDefl][kMaxDefl] = {};   // (A W)^T (A W): ||A W c|| without a pass over the vectors
+    bool accepted = false;
+};
+
+static vpp_status ensure_defl(vpp_problem p, int cap, int* got)
+{
+    CgWork& w = p->w;
+    const int64_t stride = ((p->N + 63) / 64) * 64;
+    if (w.hist && w.hist_stride == stride && w.hist_cap >= cap) {
+        *got = cap;
+        return VPP_OK;
+    }
+    dev_free(w.hist);
+    dev_free(w.coef);
+    w.hist_cap = 0;
+    size_t fr = 0, tot = 0;
+    VPP_HIP(hipMemGetInfo(&fr, &tot));
+    // at most a quarter of the free device memory for the record
+    const int64_t fit = (int64_t)(fr / 4 / ((size_t)stride * sizeof(float)));
+    cap = (int)std::min<int64_t>(cap, fit);
+    *got = 0;
+    if (cap < 16) return VPP_OK;
+    vpp_status st;
+    const size_t n = (size_t)p->N;
+    if ((st = dev_alloc(&w.hist, (size_t)cap * (size_t)stride, "deflation record")) ||
+        (st = dev_alloc(&w.coef, 3 * (size_t)cap + 3, "deflation coefficients")))
+        return st;
+    if (!w.dW && ((st = dev_alloc(&w.dW, kMaxDefl * n, "Ritz vectors")) ||
+                  (st = dev_alloc(&w.dAW, kMaxDefl * n, "Ritz images")) ||
+                  (st = dev_alloc(&w.dred, (size_t)kMaxDefl * kMaxRedBlocks, "deflation partials")) ||
+                  (st = dev_alloc(&w.dout, kMaxDefl, "deflation dots"))))
+        return st;
+    if (!w.hout) VPP_HIP(hipHostMalloc((void**)&w.hout, kMaxDefl * sizeof(double), hipHostMallocDefault));
+    dev_free(w.dC);
+    if ((st = dev_alloc(&w.dC, (size_t)cap * kMaxDefl, "Ritz coefficients"))) return st;
+    w.hist_cap = cap;
+    w.hist_stride = stride;
+    *got = cap;
+    return VPP_OK;
+}
+
+// out[t] = V[t] . y for t < k, on the host.
+static vpp_status multi_dot_host(vpp_problem p, const double* V, int k, const double* y, double* out)
+{
+    CgWork& w = p->w;
+    hipStream_t s = p->stream;
+    VPP_HIP(launch_multi_dot(V, k, y, p->N, w.dred, w.dout, s));
+    VPP_HIP(hipMemcpyAsync(w.hout, w.dout, k * sizeof(double), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    for (int t = 0; t < k; ++t) out[t] = w.hout[t];
+    return VPP_OK;
+}
+
+// Ritz vectors of the first FP32 phase (m recorded iterations, m below the
+// record's length) and the factor of G.
+static vpp_status build_defl(vpp_problem p, int kreq, int m, Defl& df)
+{
+    CgWork& w = p->w;
+    hipStream_t s = p->stream;
+    df = Defl{};
+    if (m < 2 || kreq < 1) return VPP_OK;
+    std::vector<double> cf(3 * (size_t)(m + 1));
+    VPP_HIP(hipMemcpyAsync(cf.data(), w.coef, cf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    std::vector<double> d(m), e(m), rz(m);
+    for (int j = 0; j < m; ++j) {
+        const double al = cf[3 * (j + 1)], be = cf[3 * (j + 1) + 1];
+        rz[j] = cf[3 * j + 2];
+        if (!(al > 0.0) || !(be >= 0.0) || !(rz[j] > 0.0) || !std::isfinite(al) || !std::isfinite(be) ||
+            !std::isfinite(rz[j]))
+            return VPP_OK;
+        d[j] = 1.0 / al + (j > 0 ? cf[3 * j + 1] / cf[3 * j] : 0.0);
+        e[j] = -std::sqrt(be) / al;
+    }
+    // Ritz values of the first phase: deflate the smallest ones only where a gap
+    // of 10 follows them (isolated near-null modes, such as the nearly constant
+    // pressure of a gas bubble); a cluster without a gap is left alone
+    const int kmax = std::min(std::min(kreq, (int)kMaxDefl), m - 1);
+    if (kmax < 1) return VPP_OK;
+    std::vector<double> vals(kmax + 1);
+    if (tridiag_smallest_values(m, d.data(), e.data(), kmax + 1, vals.data()) != kmax + 1) return VPP_OK;
+    int k = 0;
+    for (int i = 1; i <= kmax; ++i)
+        if (vals[i - 1] > 0.0 && vals[i] >= 10.0 * vals[i - 1]) k = i;
+    if (k == 0) return VPP_OK;
+    std::vector<double> vecs((size_t)k * m), C((size_t)m * k);
+    tridiag_vectors(m, d.data(), e.data(), k, vals.data(), vecs.data());
+    for (int j = 0; j < m; ++j)
+        for (int t = 0; t < k; ++t) C[(size_t)j * k + t] = vecs[(size_t)t * m + j] / std::sqrt(rz[j]);
+    VPP_HIP(hipMemcpyAsync(w.dC, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    VPP_HIP(launch_ritz(w.hist, w.hist_stride, m, w.dC, k, p->inv64, w.dW, p->N, s));
+    vpp_status st;
+    for (int t = 0; t < k; ++t)
+        if ((st = do_apply64(p, w.dW + (size_t)t * p->N, w.dAW + (size_t)t * p->N, nullptr, nullptr, s))) return st;
+    double G[kMaxDefl][kMaxDefl];
+    for (int t = 0; t < k; ++t) {
+        double col[kMaxDefl];
+        if ((st = multi_dot_host(p, w.dW, k, w.dAW + (size_t)t * p->N, col))) return st;
+        for (int u = 0; u < k; ++u) G[u][t] = col[u];
+    }
+    for (int u = 0; u < k; ++u)
+        for (int t = u + 1; t < k; ++t) G[u][t] = G[t][u] = 0.5 * (G[u][t] + G[t][u]);
+    // pivoted Cholesky G(perm, perm) = L L^T, stopping at pivots below 1e-12 of the largest diagonal
+    double gmax = 0.0;
+    for (int t = 0; t < k; ++t) gmax = std::max(gmax, G[t][t]);
+    if (!(gmax > 0.0) || !std::isfinite(gmax)) return VPP_OK;
+    int idx[kMaxDefl];
+    for (int t = 0; t < k; ++t) idx[t] = t;
+    double S[kMaxDefl][kMaxDefl];
+    for (int u = 0; u < k; ++u)
+        for (int t = 0; t < k; ++t) S[u][t] = G[u][t];
+    int nk = 0;
+    for (; nk < k; ++nk) {
+        int best = nk;
+        for (int t = nk + 1; t < k; ++t)
+            if (S[idx[t]][idx[t]] > S[idx[best]][idx[best]]) best = t;
+        std::swap(idx[nk], idx[best]);
+        const double piv = S[idx[nk]][idx[nk]];
+        if (!(piv > 1e-12 * gmax) || !std::isfinite(piv)) break;
+        const double lkk = std::sqrt(piv);
+        df.L[nk][nk] = lkk;
+        for (int t = nk + 1; t < k; ++t) df.L[t][nk] = S[idx[t]][idx[nk]] / lkk;
+        for (int t = nk + 1; t < k; ++t)
+            for (int u = nk + 1; u < k; ++u) S[idx[t]][idx[u]] -= df.L[t][nk] * df.L[u][nk];
+    }
+    if (nk == 0) return VPP_OK;
+    for (int t = 0; t < k; ++t) {
+        double col[kMaxDefl];
+        if ((st = multi_dot_host(p, w.dAW, k, w.dAW + (size_t)t * p->N, col))) return st;
+        for (int u = 0; u < k; ++u) df.H[u][t] = col[u];
+    }
+    df.k = k;
+    df.nk = nk;
+    for (int t = 0; t < k; ++t) df.perm[t] = idx[t];
+    return VPP_OK;
+}
+
+// Coefficients of the Galerkin correction of the residual w.r in span(W).
+static vpp_status defl_coef(vpp_problem p, const Defl& df, DeflCoef* c)
+{
+    vpp_status st;
+    double dots[kMaxDefl];
+    if ((st = multi_dot_host(p, p->w.dW, df.k, p->w.r, dots))) return st;
+    double y[kMaxDefl];
+    for (int i = 0; i < df.nk; ++i) {
+        double v = dots[df.perm[i]];
+        for (int j = 0; j < i; ++j) v -= df.L[i][j] * y[j];
+        y[i] = v / df.L[i][i];
+    }
+    for (int i = df.nk - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int j = i + 1; j < df.nk; ++j) v -= df.L[j][i] * y[j];
+        y[i] = v / df.L[i][i];
+    }
+    *c = DeflCoef{};
+    for (int i = 0; i < df.nk; ++i) c->c[df.perm[i]] = y[i];
+    return VPP_OK;
+}
+
+// w.x += W c, w.r -= A W c; *rn = ||w.r|| afterwards.
+static vpp_status defl_update(vpp_problem p, const Defl& df, const DeflCoef& c, double* rn)
+{
+    CgWork& w = p->w;
+    hipStream_t s = p->stream;
+    VPP_HIP(launch_defl_update(w.x, w.r, w.dW, w.dAW, c, df.k, p->N, w.red, w.rr, s));
+    VPP_HIP(hipMemcpyAsync(w.hrr, w.rr, sizeof(double), hipMemcpyDeviceToHost, s));
+    VPP_HIP(hipStreamSynchronize(s));
+    *rn = std::sqrt(*w.hrr);
+    return VPP_OK;
+}
+
 // Mixed precision PCG with reliable updates.  The Jacobi-PCG recurrences run
 // in FP32 (operator, vectors) with FP64 scalars on a residual scaled to unit
 // norm; whenever the scaled FP32 residual has dropped by inner_rtol since the
@@ -565,6 +782,8 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
     info.outer_iterations = 0;
     info.rel_residual = r0 > 0 ? 1.0 : 0.0;
     info.status = VPP_OK;
+    info.deflation_corrections = 0;
+    info.deflation_first_change = -1.0;
     if (!std::isfinite(rr)) {
         info.status = VPP_ERR_BREAKDOWN;
         return VPP_OK;
@@ -573,12 +792,29 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
     if (!(r0 >= thr) || r0 == 0.0) return VPP_OK;
     const double delta = o.inner_rtol > 0 ? o.inner_rtol : 1e-2;
     CgState* hs = w.hst;
+    // deflation: record the first FP32 phase (its residuals and CG coefficients)
+    const int kdef = std::min(std::max(o.deflate, 0), (int)kMaxDefl);
+    int rec_cap = 0;
+    if (kdef > 0 && (st = ensure_defl(p, o.deflate_history > 0 ? std::min(o.deflate_history, 4096) : 512, &rec_cap)))
+        return st;
     std::memset(hs, 0, sizeof(CgState));
     hs->tol2 = delta * delta;   // the replaced residual has unit norm
     hs->max_iter = o.max_iter;
+    if (rec_cap > 0) {
+        hs->hist = w.hist;
+        hs->coef = w.coef;
+        hs->hist_stride = w.hist_stride;
+        hs->hist_cap = rec_cap;
+    }
     VPP_HIP(hipMemcpyAsync(w.st32, hs, sizeof(CgState), hipMemcpyHostToDevice, s));
     double rn = r0;
     VPP_HIP(launch_cg_replace32(w.st32, w.red, w.r, 1.0 / rn, 0.0, w.r32, w.p32, w.x32, p->inv32, p->N, s));
+    if (rec_cap > 0) {
+        // r_0 and r_0.z_0 of the record (the later ones come from the CG kernels)
+        VPP_HIP(hipMemcpyAsync(w.hist, w.r32, p->N * sizeof(float), hipMemcpyDeviceToDevice, s));
+        VPP_HIP(hipMemcpyAsync(w.coef + 2, &w.st32->rz[0], sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    Defl df;
     const int max_phases = 10000;
     int last_iters = 0, bad_phases = 0;
     while (true) {
@@ -588,13 +824,39 @@ static vpp_status pcg_mixed(vpp_problem p, const vpp_cg_opts& o, vpp_cg_info& in
         hs->max_iter = cap;
         VPP_HIP(hipMemcpyAsync(&w.st32->max_iter, &hs->max_iter, sizeof(int), hipMemcpyHostToDevice, s));
         if ((st = run_until_done(p, w.g32, w.st32, hs, o.max_iter))) return st;
+        const bool first_phase = info.outer_iterations == 0;
+        if (first_phase && rec_cap > 0) {
+            // the record covers the first phase only
+            hs->hist_cap = 0;
+            VPP_HIP(hipMemcpyAsync(&w.st32->hist_cap, &hs->hist_cap, sizeof(int), hipMemcpyHostToDevice, s));
+        }
         last_iters = hs->iters;
         const bool broke = hs->breakdown != 0;
         // apply the phase's correction, keeping the previous iterate
         VPP_HIP(hipMemcpyAsync(w.xb, w.x, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
         VPP_HIP(launch_promote_add(w.x, w.x32, rn, p->N, s));
         if ((st = residual64(p, &rr))) return st;
-        const double rn_new = std::sqrt(rr);
+        double rn_new = std::sqrt(rr);
+        if (first_phase && rec_cap > 0 && !broke && rn_new < rn && rn_new >= thr && std::isfinite(rn_new))
+            if ((st = build_defl(p, kdef, std::min(hs->iters, rec_cap - 1), df))) return st;
+        if (df.k > 0 && rn_new >= thr) {
+            DeflCoef c;
+            if ((st = defl_coef(p, df, &c))) return st;
+            double dr2 = 0.0;
+            for (int u = 0; u < df.k; ++u)
+                for (int t = 0; t < df.k; ++t) dr2 += c.c[u] * df.H[u][t] * c.c[t];
+            const double change = std::sqrt(std::max(dr2, 0.0)) / rn_new;
+            if (info.deflation_first_change < 0.0) info.deflation_first_change = change;
+            if (std::isfinite(dr2) && change <= 0.1) {
+                double rn_d = 0.0;
+                if ((st = defl_update(p, df, c, &rn_d))) return st;
+                rn_new = rn_d;
+                df.accepted = true;
+                info.deflation_corrections += 1;
+            } else if (!df.accepted) {
+                df.k = 0;   // Ritz vectors that do not describe the small eigenvalues
+            }
+        }
         info.outer_iterations += 1;
         if (rn_new < thr) {
             rn = rn_new;
@@ -991,6 +1253,7 @@ vpp_status vpp_cg_solve(vpp_problem p, const double* b, double* x, const vpp_cg_
     VPP_HIP(hipMemcpyAsync(w.b, b, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
     VPP_HIP(hipMemcpyAsync(w.x, x, p->N * sizeof(double), hipMemcpyDeviceToDevice, s));
     vpp_cg_info inf{};
+    inf.deflation_first_change = -1.0;
     double r0 = 0.0;
     if (mixed) st = pcg_mixed(p, *opts, inf, &r0);
     else st = pcg64(p, *opts, inf, &r0);
@@ -1215,6 +1478,7 @@ vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, c
     VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     VPP_HIP(hipStreamSynchronize(s));
     vpp_cg_info inf{};
+    inf.deflation_first_change = -1.0;
     const double r0 = std::sqrt(hs->rr_last), rz0 = hs->rz[0];
     const double thr = std::max(o->rtol * r0, o->atol);
     inf.rel_residual = r0 > 0 ? 1.0 : 0.0;
@@ -1627,6 +1891,7 @@ extern "C" vpp_status vpp_amr_cg_solve(vpp_amr a, const double* b, double* x, co
     VPP_HIP(hipMemcpyAsync(hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     VPP_HIP(hipStreamSynchronize(s));
     vpp_cg_info inf{};
+    inf.deflation_first_change = -1.0;
     const double r0 = std::sqrt(hs->rr_last), rz0 = hs->rz[0];
     const double thr = std::max(o->rtol * r0, o->atol);
     inf.rel_residual = r0 > 0 ? 1.0 : 0.0;
@@ -2176,6 +2441,7 @@ static vpp_status batch_pcg64_lockstep(vpp_batch b, const double* const* rhs, do
         const double thr = std::max(o.rtol * r0[l], o.atol);
         tol2[l] = thr * thr;
         inf = vpp_cg_info{};
+        inf.deflation_first_change = -1.0;
         inf.rel_residual = r0[l] > 0 ? 1.0 : 0.0;
         CgState init{};
         init.rz[0] = rz0;

@@ -19,6 +19,14 @@ struct CgState {
     int breakdown;    // p.Ap <= 0 or a non-finite scalar
     int iters;
     int max_iter;
+    // Record of an FP32 phase (mixed-precision deflation; all zero = off): the
+    // update of iteration it stores its residual r_it at hist + it * hist_stride
+    // and the direction update stores alpha_{it-1}, beta_{it-1}, r_it.z_it at
+    // coef[3 it .. 3 it + 2], for every it < hist_cap.
+    float* hist;
+    double* coef;
+    int64_t hist_stride;
+    int hist_cap;
 };
 
 // Reduction workspace: per-workgroup partial sums of two quantities, summed in
@@ -72,6 +80,21 @@ hipError_t launch_cg_batch_step(const CgSystem<double>* sys, int nsys, int total
                                 hipStream_t s);
 
 // r = b - q in FP64 (r may be null) and *rr = r.r.
+// Deflation space of the mixed-precision solver: W[t] = D^-1 sum_j C[j k + t]
+// hist[j] for t < k (k <= kMaxDefl), FP64 vectors of length n, W[t] at W + t n.
+constexpr int kMaxDefl = 8;
+hipError_t launch_ritz(const float* hist, int64_t stride, int m, const double* C, int k, const double* invd,
+                       double* W, int64_t n, hipStream_t s);
+// out[t] = V[t] . y for t < k (V[t] at V + t n), summed in a fixed order; red
+// holds k * kMaxRedBlocks partials.
+hipError_t launch_multi_dot(const double* V, int k, const double* y, int64_t n, double* red, double* out,
+                            hipStream_t s);
+struct DeflCoef {
+    double c[kMaxDefl];
+};
+// x += sum_t c[t] W[t], r -= sum_t c[t] AW[t]; *rr = r.r afterwards.
+hipError_t launch_defl_update(double* x, double* r, const double* W, const double* AW, DeflCoef c, int k, int64_t n,
+                              double* red, double* rr, hipStream_t s);
 hipError_t launch_residual(const double* b, const double* q, double* r, int64_t n, double* red, double* rr,
                            hipStream_t s);
 // Residual replacement of the FP32 inner PCG: r32 = (float)(scale r64),

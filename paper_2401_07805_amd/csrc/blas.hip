@@ -185,6 +185,13 @@ __device__ __forceinline__ void assemble_update_body(int bid, int nblk, CgState*
     double rr = 0.0, rz = 0.0;
     using P = Pack<T>;
     const int64_t np = n / P::W;
+    // residual record of an FP32 phase (iterations counted by the previous
+    // direction update, which has completed)
+    T* hrec = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        const int hit = st->iters + 1;
+        if (st->hist && hit < st->hist_cap) hrec = st->hist + (size_t)hit * (size_t)st->hist_stride;
+    }
     for (int64_t c = (int64_t)bid * BT + threadIdx.x; c < np; c += (int64_t)nblk * BT) {
         P rv = reinterpret_cast<const P*>(r)[c];
         const P dv = reinterpret_cast<const P*>(invd)[c];
@@ -221,11 +228,13 @@ __device__ __forceinline__ void assemble_update_body(int bid, int nblk, CgState*
             rz += (double)ri * (double)(ri * dv.v[j]);
         }
         reinterpret_cast<P*>(r)[c] = rv;
+        if (hrec) reinterpret_cast<P*>(hrec)[c] = rv;
     }
     if (bid == 0)
         for (int64_t i = np * P::W + threadIdx.x; i < n; i += BT) {
             const T ri = fma(-alpha, node_value(sp, q, i), r[i]);
             r[i] = ri;
+            if (hrec) hrec[i] = ri;
             rr += (double)ri * (double)ri;
             rz += (double)ri * (double)(ri * invd[i]);
         }
@@ -294,6 +303,11 @@ __device__ __forceinline__ void pupdate_body(int bid, int nblk, CgState* st, int
             st->halt[1 - par] = 1;
         } else if (rr < st->tol2 || it >= st->max_iter) {
             st->halt[1 - par] = 1;
+        }
+        if (st->coef && it < st->hist_cap) {
+            st->coef[3 * it] = st->rz[par] / st->pAp;
+            st->coef[3 * it + 1] = beta_d;
+            st->coef[3 * it + 2] = rzn;
         }
     }
     // the same alpha as the update's (same operands, same rounding)
@@ -483,6 +497,120 @@ hipError_t launch_cg_batch_step(const CgSystem<double>* sys, int nsys, int total
 VPP_INST(double)
 VPP_INST(float)
 #undef VPP_INST
+
+// ---------------------------------------------------------------------------
+// Deflation space of the mixed-precision solver (Ritz vectors of the first
+// FP32 phase and the Galerkin correction in their span).
+
+__global__ void __launch_bounds__(BT) ritz_kernel(const float* __restrict__ hist, int64_t stride, int m,
+                                                  const double* __restrict__ C, int k,
+                                                  const double* __restrict__ invd, double* __restrict__ W, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+        double acc[kMaxDefl];
+#pragma unroll
+        for (int t = 0; t < kMaxDefl; ++t) acc[t] = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double h = (double)hist[(size_t)j * (size_t)stride + (size_t)i];
+#pragma unroll
+            for (int t = 0; t < kMaxDefl; ++t)
+                if (t < k) acc[t] = fma(C[j * k + t], h, acc[t]);
+        }
+        const double di = invd[i];
+#pragma unroll
+        for (int t = 0; t < kMaxDefl; ++t)
+            if (t < k) W[(size_t)t * (size_t)n + (size_t)i] = acc[t] * di;
+    }
+}
+
+__global__ void __launch_bounds__(BT) multi_dot_kernel(const double* __restrict__ V, int k,
+                                                       const double* __restrict__ y, int64_t n, double* red)
+{
+    double acc[kMaxDefl];
+#pragma unroll
+    for (int t = 0; t < kMaxDefl; ++t) acc[t] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+        const double yi = y[i];
+#pragma unroll
+        for (int t = 0; t < kMaxDefl; ++t)
+            if (t < k) acc[t] = fma(V[(size_t)t * (size_t)n + (size_t)i], yi, acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxDefl; t += 2) {
+        double a = acc[t], b = acc[t + 1];
+        block_sum2<BT>(a, b);
+        if (threadIdx.x == 0) {
+            if (t < k) red[(size_t)t * kMaxRedBlocks + blockIdx.x] = a;
+            if (t + 1 < k) red[(size_t)(t + 1) * kMaxRedBlocks + blockIdx.x] = b;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(BT) multi_dot_finish_kernel(const double* red, int k, int ng, double* out)
+{
+    for (int t = 0; t < k; t += 2) {
+        double a = 0.0, b = 0.0;
+        for (int i = threadIdx.x; i < ng; i += BT) {
+            a += red[(size_t)t * kMaxRedBlocks + i];
+            if (t + 1 < k) b += red[(size_t)(t + 1) * kMaxRedBlocks + i];
+        }
+        block_sum2<BT>(a, b);
+        if (threadIdx.x == 0) {
+            out[t] = a;
+            if (t + 1 < k) out[t + 1] = b;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(BT) defl_update_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                         const double* __restrict__ W,
+                                                         const double* __restrict__ AW, DeflCoef c, int k,
+                                                         int64_t n, double* red)
+{
+    double s2 = 0.0, unused = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+        double xi = x[i], ri = r[i];
+#pragma unroll
+        for (int t = 0; t < kMaxDefl; ++t)
+            if (t < k) {
+                xi = fma(c.c[t], W[(size_t)t * (size_t)n + (size_t)i], xi);
+                ri = fma(-c.c[t], AW[(size_t)t * (size_t)n + (size_t)i], ri);
+            }
+        x[i] = xi;
+        r[i] = ri;
+        s2 += ri * ri;
+    }
+    block_sum2<BT>(s2, unused);
+    write_partials(red, s2, 0.0);
+}
+
+hipError_t launch_ritz(const float* hist, int64_t stride, int m, const double* C, int k, const double* invd,
+                       double* W, int64_t n, hipStream_t s)
+{
+    if (k < 1 || k > kMaxDefl) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(ritz_kernel, dim3(grid_for<double>(n)), dim3(BT), 0, s, hist, stride, m, C, k, invd, W, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_dot(const double* V, int k, const double* y, int64_t n, double* red, double* out,
+                            hipStream_t s)
+{
+    if (k < 1 || k > kMaxDefl) return hipErrorInvalidValue;
+    const int g = grid_for<double>(n);
+    hipLaunchKernelGGL(multi_dot_kernel, dim3(g), dim3(BT), 0, s, V, k, y, n, red);
+    hipLaunchKernelGGL(multi_dot_finish_kernel, dim3(1), dim3(BT), 0, s, red, k, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_defl_update(double* x, double* r, const double* W, const double* AW, DeflCoef c, int k, int64_t n,
+                              double* red, double* rr, hipStream_t s)
+{
+    if (k < 1 || k > kMaxDefl) return hipErrorInvalidValue;
+    const int g = grid_for<double>(n);
+    hipLaunchKernelGGL(defl_update_kernel, dim3(g), dim3(BT), 0, s, x, r, W, AW, c, k, n, red);
+    hipLaunchKernelGGL(sum_finish_kernel, dim3(1), dim3(BT), 0, s, red, g, rr);
+    return hipGetLastError();
+}
 
 hipError_t launch_residual(const double* b, const double* q, double* r, int64_t n, double* red, double* rr,
                            hipStream_t s)

@@ -115,9 +115,12 @@ def test_c2_levels_against_oracle(n):
 @pytest.mark.parametrize("bubble", [False, True])
 def test_c1_solve_oracle_rhs_and_residual(bubble):
     """64^3 Q2 (2.15M DoFs), droplet or bubble r 0.25, eps = 2h, ratio 1000: b is
-    the oracle's load of the analytic f (R7).  FP64 and mixed PCG to rtol 1e-8
-    reach a true residual <= 1e-8 ||b|| recomputed with the oracle's CSR, and
-    at rtol 1e-12 lie within 1e-8 of the oracle's PCG solution (rtol 1e-13)."""
+    the oracle's load of the analytic f (R7).  FP64 PCG and mixed PCG, with and
+    without the Ritz-vector deflation, to rtol 1e-8 reach a true residual
+    <= 1e-8 ||b|| recomputed with the oracle's CSR, and at rtol 1e-12 lie within
+    1e-8 of the oracle's PCG solution (rtol 1e-13).  On the bubble the isolated
+    smallest Ritz value is deflated and the mixed solve needs fewer FP32
+    iterations than without."""
     wl = W.droplet_at_scale(k=2, nvec=0, bubble=bubble)
     m = wl.mesh
     say("c1 oracle assembly", wl.name)
@@ -128,18 +131,52 @@ def test_c1_solve_oracle_rhs_and_residual(bubble):
     prob = _setup(m, wl.phi)
     bd = dev(b)
     nb = np.linalg.norm(b)
-    for prec in ("fp64", "mixed"):
-        say("c1 solve", wl.name, prec)
-        p, info = prob.cg_solve(bd, rtol=1e-8, precision=prec)
+    iters = {}
+    for prec, defl in (("fp64", 0), ("mixed", 0), ("mixed", 4)):
+        say("c1 solve", wl.name, prec, "deflate", defl)
+        p, info = prob.cg_solve(bd, rtol=1e-8, precision=prec, deflate=defl)
         p = host(p)
         res = np.linalg.norm(b - op.matvec(p)) / nb
-        pt, tinfo = prob.cg_solve(bd, rtol=1e-12, precision=prec)
+        pt, tinfo = prob.cg_solve(bd, rtol=1e-12, precision=prec, deflate=defl)
         e12 = rel(host(pt), pref)
-        print(f"{wl.name} {prec}: rtol 1e-8 it {info['iterations']} true res {res:.3e}; "
+        iters[(prec, defl)] = info["iterations"]
+        print(f"{wl.name} {prec} deflate {defl}: rtol 1e-8 it {info['iterations']} true res {res:.3e}; "
               f"rtol 1e-12 it {tinfo['iterations']} err vs oracle {e12:.3e}")
         assert info["status"] == 0 and res < 1e-8 * 1.01
         assert abs(info["true_rel_residual"] - res) < 1e-3 * res
         assert tinfo["status"] == 0 and e12 < 1e-8
+        if bubble and defl:
+            # the gas bubble's nearly constant pressure mode is an isolated Ritz value
+            assert info["deflation_corrections"] > 0
+    if bubble:
+        assert iters[("mixed", 4)] < iters[("mixed", 0)]
+
+
+@pytest.mark.parametrize("k,n,defl,hist", [(2, 24, 8, 16), (3, 12, 2, 0), (2, 24, 1, 0)])
+def test_deflated_mixed_against_oracle(k, n, defl, hist):
+    """Mixed PCG with deflation on a bubble (ratio 1000): a full record, and a
+    record cut at 16 residuals (Ritz vectors of a truncated Lanczos process,
+    whose corrections the residual-change check may refuse): the solution at rtol 1e-12
+    lies within 1e-8 of the oracle's, and the true residual at rtol 1e-8 is
+    below 1e-8 ||b|| with the oracle's CSR."""
+    m = W.unit_cube(n, k, 1000.0, 1.0)
+    m.eps = 2.0 / n
+    phi = W.bubble_phi(m, 0.25, m.eps)
+    op = oracle.Operator(m, phi=phi)
+    b = oracle.manufactured_sine_rhs(m, 0.25, m.eps, sign=-1.0)
+    pref, oinfo = op.pcg(b, rtol=1e-13)
+    assert oinfo["status"] == 0
+    prob = _setup(m, phi)
+    bd = dev(b)
+    say("deflated mixed", k, n, defl, hist)
+    p, info = prob.cg_solve(bd, rtol=1e-8, precision="mixed", deflate=defl, deflate_history=hist)
+    res = np.linalg.norm(b - op.matvec(host(p))) / np.linalg.norm(b)
+    pt, tinfo = prob.cg_solve(bd, rtol=1e-12, precision="mixed", deflate=defl, deflate_history=hist)
+    e12 = rel(host(pt), pref)
+    print(f"bubble {n}^3 Q{k} deflate {defl} record {hist}: it {info['iterations']} res {res:.3e} "
+          f"err {e12:.3e}")
+    assert info["status"] == 0 and res < 1e-8 * 1.01
+    assert tinfo["status"] == 0 and e12 < 1e-8
 
 
 def test_warm_start_and_failures():

@@ -36,3 +36,76 @@ def test_oracle_under_sanitizers(tmp_path):
     assert out.returncode == 0, out.stderr[-4000:]
     assert "0 failures" in out.stdout
     assert "ERROR: AddressSanitizer" not in out.stderr and "runtime error" not in out.stderr
+
+
+def _tridiag_run(exe, d, e, k):
+    import numpy as np
+    text = f"{len(d)} {k}\n" + " ".join(repr(float(v)) for v in d) + "\n" + " ".join(repr(float(v)) for v in e) + "\n"
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    lines = out.stdout.split("\n")
+    got = int(lines[0])
+    vals = np.array([float(v) for v in lines[1:1 + got]])
+    vecs = np.array([[float(v) for v in lines[1 + got + t].split()] for t in range(got)])
+    return vals, vecs
+
+
+def test_tridiagonal_smallest_eigenpairs(tmp_path):
+    """The host eigensolver of the mixed-precision solver's deflation (bisection
+    on Sturm counts, inverse iteration) against numpy's dense eigh: random
+    matrices, the 1D Laplacian (closed-form spectrum 2 - 2 cos(j pi / (m+1))),
+    a matrix with tiny and clustered eigenvalues like the Lanczos matrices of a
+    high-contrast Poisson solve, and two decoupled identical blocks (every
+    eigenvalue doubled: residual and orthogonality checked instead of the vectors)."""
+    import numpy as np
+    exe = str(tmp_path / "tridiag_check")
+    root = os.path.dirname(HERE)
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(root, "paper_2401_07805_amd", "csrc"),
+                           os.path.join(HERE, "host", "tridiag_check.cpp"), "-o", exe])
+    rng = np.random.default_rng(5)
+    cases = []
+    for m in (1, 2, 7, 60, 300):
+        cases.append((rng.uniform(-1, 3, m), rng.uniform(-1, 1, max(m - 1, 0))))
+    m = 200
+    cases.append((np.full(m, 2.0), np.full(m - 1, -1.0)))
+    # a symmetric positive matrix with one isolated tiny eigenvalue and a cluster above it
+    Q, _ = np.linalg.qr(rng.standard_normal((120, 120)))
+    lam = np.concatenate([[5e-6], 2.3e-3 + 1e-5 * np.arange(6), rng.uniform(0.01, 2.0, 113)])
+    A = (Q * lam) @ Q.T
+    # Householder-free tridiagonalisation: Lanczos on A with full reorthogonalisation
+    V = np.zeros((120, 120)); a = np.zeros(120); b = np.zeros(119)
+    v = rng.standard_normal(120); V[:, 0] = v / np.linalg.norm(v)
+    for j in range(120):
+        w = A @ V[:, j]
+        a[j] = V[:, j] @ w
+        w -= V[:, :j + 1] @ (V[:, :j + 1].T @ w)
+        w -= V[:, :j + 1] @ (V[:, :j + 1].T @ w)
+        if j + 1 < 120:
+            b[j] = np.linalg.norm(w); V[:, j + 1] = w / b[j]
+    cases.append((a, b))
+    for d, e in cases:
+        m = len(d)
+        T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+        ref_vals, ref_vecs = np.linalg.eigh(T)
+        k = min(8, m)
+        vals, vecs = _tridiag_run(exe, d, e, k)
+        scale = np.abs(T).sum(axis=1).max()
+        assert np.allclose(vals, ref_vals[:k], rtol=0, atol=1e-12 * scale), (m, vals, ref_vals[:k])
+        for t in range(k):
+            gap = min([abs(ref_vals[t] - ref_vals[s]) for s in range(m) if s != t] or [scale])
+            r = np.linalg.norm(T @ vecs[t] - vals[t] * vecs[t])
+            assert abs(np.linalg.norm(vecs[t]) - 1) < 1e-12
+            assert r < 1e-10 * scale, (m, t, r)
+            if gap > 1e-6 * scale:
+                assert abs(vecs[t] @ ref_vecs[:, t]) > 1 - 1e-8, (m, t)
+    # two identical decoupled blocks: each eigenvalue twice
+    d0, e0 = rng.uniform(1, 3, 20), rng.uniform(-0.5, 0.5, 19)
+    d = np.concatenate([d0, d0]); e = np.concatenate([e0, [0.0], e0])
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    vals, vecs = _tridiag_run(exe, d, e, 6)
+    ref = np.linalg.eigvalsh(T)[:6]
+    assert np.allclose(vals, ref, atol=1e-12 * np.abs(T).sum(axis=1).max())
+    for t in range(6):
+        assert np.linalg.norm(T @ vecs[t] - vals[t] * vecs[t]) < 1e-10
+    G = vecs @ vecs.T
+    assert np.abs(G - np.eye(6)).max() < 1e-8
