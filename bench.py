@@ -252,6 +252,8 @@ def solve_pair(p, b, rtol=1e-8):
         out[f"cg_{prec}_s"] = time.perf_counter() - t0
         out[f"cg_{prec}_iters"] = info["iterations"]
         out[f"cg_{prec}_true_rel_res"] = info["true_rel_residual"]
+        if prec == "mixed":
+            out["cg_mixed_deflation_corrections"] = info["deflation_corrections"]
     return out
 
 
