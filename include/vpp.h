@@ -283,7 +283,9 @@ vpp_status vpp_curvature_rhs(vpp_problem p, const double* n0, const double* n1, 
  * the Gauss points as they are; the boundary terms of both integrations by
  * parts are dropped (natural conditions on every face, whatever the problem's
  * faces).  The operator, its diagonal and the right-hand side are evaluated
- * per cell (sum factorization, atomic scatter).  psi, n0..n2, psi_out: N
+ * per cell by sum factorization into the problem's cell scratch, then summed
+ * into the nodes over their cells in a fixed order (no atomics: repeated calls
+ * give the same bits).  psi, n0..n2, psi_out: N
  * entries, FP64 device pointers; psi_out may alias psi.  The problem's phi and
  * mass shift are not used.  Synchronizes; info as for vpp_cg_solve. */
 vpp_status vpp_reinit_step(vpp_problem p, const double* psi, const double* n0, const double* n1,
@@ -332,10 +334,16 @@ vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const
  * matrices of the active cells with the coefficient of Eq. rhoEff from the
  * nodal phi of the cell's own lattice), with identity rows and columns on
  * every entry that is not a free unknown and on free unknowns of Dirichlet
- * faces (as A_D).  One cell per thread with atomic scatter (summation order
- * not fixed: results vary at the rounding level); FP64 only.
+ * faces (as A_D).  The apply runs one cell per thread into a cell-major
+ * scratch, then sums every entry over the cell results reaching it (lists
+ * built on the host, constraint weights included) in a fixed order; the
+ * diagonal runs the cells one colour per launch (the cells of a colour write
+ * disjoint entries, also through constraint lists) with plain read-modify-write
+ * adds.  No atomics: repeated calls give the same bits; FP64 only.
  *   vpp_amr_create:   host call; VPP_ERR_INVALID_ARG as vpp_create, or for a
- *                     NULL mask, more than 2^27 coarse cells or 2^31 entries.
+ *                     NULL mask, more than 2^27 coarse cells or 2^31 entries;
+ *                     VPP_ERR_UNSUPPORTED if the colouring needs more than 64
+ *                     colours.
  *   vpp_amr_set_phi:  nodal phi on both lattices (vpp_amr_num_dofs entries);
  *                     builds the Jacobi diagonal.
  *   vpp_amr_apply:    y = A x (all entries written); x, y not aliased.

@@ -6,8 +6,12 @@
 // Each active cell (an unrefined coarse cell, or one of the eight fine cells of
 // a refined one) is one thread: it gathers its (k+1)^3 values, applies the
 // cell operator by sum factorisation (the same building blocks as the uniform
-// apply, with the cell size of its lattice) and scatters the result with
-// atomic adds.  A fine node on the boundary of an unrefined coarse cell is
+// apply, with the cell size of its lattice) and stores its results in a
+// cell-major scratch; a second launch sums every entry of y over the cell
+// results that reach it, through a list built on the host, in a fixed order.
+// The diagonal (once per phi) adds into its entries with plain loads and
+// stores instead, the cells launched one colour at a time (the cells of a
+// colour write disjoint entries).  A fine node on the boundary of an unrefined coarse cell is
 // constrained: its value is sum_p w_p x[src_p] over the coarse cell's nodes
 // (the Q_k interpolant there), and its result goes back to those nodes with
 // the same weights (C^T).  Entries that are not free unknowns (unused nodes of
@@ -66,9 +70,8 @@ __device__ __forceinline__ void amr_coefficient(const MeshArgs& m, int64_t base,
 // One active cell of lattice m (FINE: the fine lattice, whose nodes may be
 // constrained).
 template <int K, int HV, bool FINE>
-__device__ __forceinline__ void amr_apply_cell(const AmrArgs& a, const MeshArgs& m, int idx,
-                                               const double* __restrict__ phi, const double* __restrict__ x,
-                                               double* __restrict__ y)
+__device__ __forceinline__ void amr_apply_cell(const AmrArgs& a, const MeshArgs& m, int idx, int e,
+                                               const double* __restrict__ phi, const double* __restrict__ x)
 {
     constexpr int N3 = (K + 1) * (K + 1) * (K + 1);
     const int64_t base = amr_base<K>(m, idx), off = FINE ? a.nc : 0;
@@ -88,33 +91,32 @@ __device__ __forceinline__ void amr_apply_cell(const AmrArgs& a, const MeshArgs&
     }
     cell_operator<K, double>(m, cw, u);
 #pragma unroll
-    for (int q = 0; q < N3; ++q) {
-        const int64_t gl = amr_local<K>(m, base, q);
-        const int kind = amr_kind<FINE>(a, gl);
-        if (kind < 0) {
-            atomicAdd(&y[off + gl], u[q]);
-        } else {
-            for (int p = a.cptr[kind]; p < a.cptr[kind + 1]; ++p) atomicAdd(&y[a.ccol[p]], a.cw[p] * u[q]);
-        }
-    }
+    for (int q = 0; q < N3; ++q) a.scratch[(size_t)q * (size_t)a.ncells + (size_t)e] = u[q];
 }
 
 template <int K, int HV>
 __global__ void __launch_bounds__(64) amr_apply_kernel(AmrArgs a, const double* __restrict__ phi,
-                                                       const double* __restrict__ x, double* __restrict__ y)
+                                                       const double* __restrict__ x)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.ncells) return;
     const int code = a.cells[e];
-    if (code >= 0) amr_apply_cell<K, HV, false>(a, a.mc, code, phi, x, y);
-    else amr_apply_cell<K, HV, true>(a, a.mf, -(code + 1), phi, x, y);
+    if (code >= 0) amr_apply_cell<K, HV, false>(a, a.mc, code, e, phi, x);
+    else amr_apply_cell<K, HV, true>(a, a.mf, -(code + 1), e, phi, x);
 }
 
-// y = x on identity rows (after the cells have scattered).
-__global__ void amr_identity_kernel(AmrArgs a, const double* __restrict__ x, double* __restrict__ y)
+// y[g] = x[g] on identity rows, else the sum of the cell results reaching g.
+__global__ void amr_node_sum_kernel(AmrArgs a, const double* __restrict__ x, double* __restrict__ y)
 {
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x)
-        if (a.ident[g]) y[g] = x[g];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+        if (a.ident[g]) {
+            y[g] = x[g];
+            continue;
+        }
+        double v = 0.0;
+        for (int j = a.nptr[g]; j < a.nptr[g + 1]; ++j) v = fma(a.nw[j], a.scratch[a.nidx[j]], v);
+        y[g] = v;
+    }
 }
 
 // Diagonal of C^T K_e C for one cell: K_aa from the squared 1D tables for the
@@ -156,7 +158,7 @@ __device__ __forceinline__ void amr_diag_cell(const AmrArgs& a, const MeshArgs& 
 #pragma unroll
         for (int q = 0; q < N3; ++q) {
             const int64_t gl = amr_local<K>(m, base, q);
-            if (amr_kind<FINE>(a, gl) < 0) atomicAdd(&diag[off + gl], out[q]);
+            if (amr_kind<FINE>(a, gl) < 0) diag[off + gl] += out[q];
         }
     }
     if constexpr (FINE) {
@@ -189,7 +191,7 @@ __device__ __forceinline__ void amr_diag_cell(const AmrArgs& a, const MeshArgs& 
                 cell_operator<K, double>(m, cw, kv);
                 double d = 0.0;
                 for (int r = 0; r < N3; ++r) d = fma(ev[r], kv[r], d);
-                atomicAdd(&diag[src], d);
+                diag[src] += d;
             }
         }
     }
@@ -197,11 +199,11 @@ __device__ __forceinline__ void amr_diag_cell(const AmrArgs& a, const MeshArgs& 
 
 template <int K, int HV>
 __global__ void __launch_bounds__(64) amr_diag_kernel(AmrArgs a, const double* __restrict__ phi,
-                                                      double* __restrict__ diag)
+                                                      double* __restrict__ diag, int first, int count)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.ncells) return;
-    const int code = a.cells[e];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int code = a.cells[first + t];
     if (code >= 0) amr_diag_cell<K, HV, false>(a, a.mc, code, phi, diag);
     else amr_diag_cell<K, HV, true>(a, a.mf, -(code + 1), phi, diag);
 }
@@ -243,14 +245,13 @@ static int stream_blocks(int64_t n)
 
 hipError_t launch_amr_apply(int k, const AmrArgs& a, const double* phi, const double* x, double* y, hipStream_t s)
 {
-    hipError_t e = launch_fill<double>(y, a.n, 0.0, s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     if (a.ncells > 0) {
         const int blocks = (a.ncells + 63) / 64;
-        VPP_AMR_SWITCH(amr_apply_kernel, phi, x, y)
+        VPP_AMR_SWITCH(amr_apply_kernel, phi, x)
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(amr_identity_kernel, dim3(stream_blocks(a.n)), dim3(256), 0, s, a, x, y);
+    hipLaunchKernelGGL(amr_node_sum_kernel, dim3(stream_blocks(a.n)), dim3(256), 0, s, a, x, y);
     return hipGetLastError();
 }
 
@@ -259,9 +260,11 @@ hipError_t launch_amr_diag(int k, const AmrArgs& a, const double* phi, double* d
 {
     hipError_t e = launch_fill<double>(diag, a.n, 0.0, s);
     if (e != hipSuccess) return e;
-    if (a.ncells > 0) {
-        const int blocks = (a.ncells + 63) / 64;
-        VPP_AMR_SWITCH(amr_diag_kernel, phi, diag)
+    for (int c = 0; c < a.ncolors; ++c) {
+        const int first = a.colptr[c], count = a.colptr[c + 1] - first;
+        if (count <= 0) continue;
+        const int blocks = (count + 63) / 64;
+        VPP_AMR_SWITCH(amr_diag_kernel, phi, diag, first, count)
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(amr_fix_diag_kernel, dim3(stream_blocks(a.n)), dim3(256), 0, s, a, diag, inv64, inv32);

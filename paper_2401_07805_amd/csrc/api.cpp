@@ -1614,12 +1614,15 @@ struct vpp_amr_s {
     AmrArgs args{};
     int *d_cells = nullptr, *d_fkind = nullptr, *d_cptr = nullptr, *d_ccol = nullptr;
     double* d_cw = nullptr;
+    int *d_nptr = nullptr, *d_nidx = nullptr;   // per entry: the cell results that reach it
+    double *d_nw = nullptr, *d_scratch = nullptr;
     unsigned char* d_ident = nullptr;
     double *phi = nullptr, *diag = nullptr, *inv64 = nullptr;
     float* inv32 = nullptr;
     bool phi_set = false;
     hipStream_t stream = nullptr;
     ReinitWork* w = nullptr;   // CG vectors (allocated by the first solve)
+    std::vector<int> colptr;   // cell colours (host; ranges of the colour-ordered cell list)
 };
 
 static double gll_point(int k, int i)
@@ -1643,6 +1646,7 @@ static void amr_free(vpp_amr a)
     if (!a) return;
     dev_free(a->d_cells); dev_free(a->d_fkind); dev_free(a->d_cptr); dev_free(a->d_ccol); dev_free(a->d_cw);
     dev_free(a->d_ident); dev_free(a->phi); dev_free(a->diag); dev_free(a->inv64); dev_free(a->inv32);
+    dev_free(a->d_nptr); dev_free(a->d_nidx); dev_free(a->d_nw); dev_free(a->d_scratch);
     free_reinit(a->w);
     if (a->stream) (void)hipStreamDestroy(a->stream);
     delete a;
@@ -1762,10 +1766,103 @@ extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, 
             ident[Nc + gf] = 0;
             ++nfree;
         }
+    // colour the cells: no two cells of a colour write the same vector entry,
+    // directly (a free node) or through a constraint list (the coarse sources
+    // of a constrained fine node); greedy, lowest free colour, cells in order
+    std::vector<uint64_t> used((size_t)(Nc + Nf), 0);
+    std::vector<int> color(cells.size());
+    std::vector<int64_t> wset;
+    int ncol = 0;
+    for (size_t e = 0; e < cells.size(); ++e) {
+        wset.clear();
+        const int code = cells[e];
+        const bool fine = code < 0;
+        const int idx = fine ? -(code + 1) : code;
+        const int64_t* nn = fine ? fn : cn;
+        const int ncx = fine ? 2 * nc[0] : nc[0], ncy = fine ? 2 * nc[1] : nc[1];
+        const int64_t cx = idx % ncx, cy = (idx / ncx) % ncy, cz = idx / ((int64_t)ncx * ncy);
+        for (int a2 = 0; a2 <= k; ++a2)
+            for (int a1 = 0; a1 <= k; ++a1)
+                for (int a0 = 0; a0 <= k; ++a0) {
+                    const int64_t gl = (k * cx + a0) + nn[0] * ((k * cy + a1) + nn[1] * (k * cz + a2));
+                    if (!fine) {
+                        wset.push_back(gl);
+                    } else if (fkind[gl] < 0) {
+                        wset.push_back(Nc + gl);
+                    } else {
+                        for (int p = cptr[fkind[gl]]; p < cptr[fkind[gl] + 1]; ++p) wset.push_back(ccol[p]);
+                    }
+                }
+        uint64_t forb = 0;
+        for (int64_t g : wset) forb |= used[g];
+        if (forb == ~0ull) return fail(VPP_ERR_UNSUPPORTED, "refinement pattern needs more than 64 cell colours");
+        int c = 0;
+        while (forb & (1ull << c)) ++c;
+        color[e] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int64_t g : wset) used[g] |= 1ull << c;
+    }
+    std::vector<int> colptr(ncol + 1, 0), sorted(cells.size());
+    for (int c : color) ++colptr[c + 1];
+    for (int c = 0; c < ncol; ++c) colptr[c + 1] += colptr[c];
+    {
+        std::vector<int> pos(colptr.begin(), colptr.end() - 1);
+        for (size_t e = 0; e < cells.size(); ++e) sorted[pos[color[e]]++] = cells[e];
+    }
+    cells.swap(sorted);
+    // the cell results reaching each entry (apply's second launch): cell e's
+    // local node q is scratch slot q * ncells + e; a free node takes it with
+    // weight 1, a constrained one passes it to its sources with their weights.
+    // Slots are visited in increasing order, so each entry's list is sorted.
+    const int64_t ncell_act = (int64_t)cells.size();
+    const int n3 = (k + 1) * (k + 1) * (k + 1);
+    if (ncell_act * n3 > (int64_t)INT32_MAX) return fail(VPP_ERR_INVALID_ARG, "too many active cells");
+    std::vector<int> nptr((size_t)(Nc + Nf) + 1, 0), nidx;
+    std::vector<double> nwv;
+    {
+        // local node q of every cell, as (target entry, weight) terms
+        std::vector<int64_t> tgt;
+        std::vector<double> tw;
+        std::vector<int> tslot;
+        for (int q = 0; q < n3; ++q) {
+            const int a0 = q % (k + 1), a1 = (q / (k + 1)) % (k + 1), a2 = q / ((k + 1) * (k + 1));
+            for (int64_t e = 0; e < ncell_act; ++e) {
+                const int code = cells[e];
+                const bool fine = code < 0;
+                const int idx = fine ? -(code + 1) : code;
+                const int64_t* nn = fine ? fn : cn;
+                const int ncx = fine ? 2 * nc[0] : nc[0], ncy = fine ? 2 * nc[1] : nc[1];
+                const int64_t cx = idx % ncx, cy = (idx / ncx) % ncy, cz = idx / ((int64_t)ncx * ncy);
+                const int64_t gl = (k * cx + a0) + nn[0] * ((k * cy + a1) + nn[1] * (k * cz + a2));
+                const int slot = (int)(q * ncell_act + e);
+                if (!fine) {
+                    tgt.push_back(gl); tw.push_back(1.0); tslot.push_back(slot);
+                } else if (fkind[gl] < 0) {
+                    tgt.push_back(Nc + gl); tw.push_back(1.0); tslot.push_back(slot);
+                } else {
+                    for (int p = cptr[fkind[gl]]; p < cptr[fkind[gl] + 1]; ++p) {
+                        tgt.push_back(ccol[p]); tw.push_back(cwv[p]); tslot.push_back(slot);
+                    }
+                }
+            }
+        }
+        if ((int64_t)tgt.size() > (int64_t)INT32_MAX) return fail(VPP_ERR_INVALID_ARG, "too many cell results");
+        for (int64_t g : tgt) ++nptr[g + 1];
+        for (size_t g = 0; g + 1 < nptr.size(); ++g) nptr[g + 1] += nptr[g];
+        nidx.resize(tgt.size());
+        nwv.resize(tgt.size());
+        std::vector<int> pos(nptr.begin(), nptr.end() - 1);
+        for (size_t t = 0; t < tgt.size(); ++t) {
+            const int j = pos[tgt[t]]++;
+            nidx[j] = tslot[t];
+            nwv[j] = tw[t];
+        }
+    }
     DeviceGuard dg(d->device);
     vpp_amr a = new vpp_amr_s();
     a->desc = *d;
     a->k = k;
+    a->colptr = colptr;
     a->nc = Nc;
     a->nf = Nf;
     a->n = Nc + Nf;
@@ -1775,7 +1872,10 @@ extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, 
         (st = upload(&a->d_cptr, cptr, "amr constraint lists")) || (st = upload(&a->d_ccol, ccol, "amr constraints")) ||
         (st = upload(&a->d_cw, cwv, "amr weights")) || (st = upload(&a->d_ident, ident, "amr identity rows")) ||
         (st = dev_alloc(&a->phi, a->n, "amr phi")) || (st = dev_alloc(&a->diag, a->n, "amr diag")) ||
-        (st = dev_alloc(&a->inv64, a->n, "amr inverse diag")) || (st = dev_alloc(&a->inv32, a->n, "amr inverse diag"))) {
+        (st = dev_alloc(&a->inv64, a->n, "amr inverse diag")) || (st = dev_alloc(&a->inv32, a->n, "amr inverse diag")) ||
+        (st = upload(&a->d_nptr, nptr, "amr entry lists")) || (st = upload(&a->d_nidx, nidx, "amr entry slots")) ||
+        (st = upload(&a->d_nw, nwv, "amr entry weights")) ||
+        (st = dev_alloc(&a->d_scratch, (size_t)std::max<int64_t>(ncell_act * n3, 1), "amr cell results"))) {
         amr_free(a);
         return st;
     }
@@ -1798,6 +1898,12 @@ extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, 
     g.ccol = a->d_ccol;
     g.cw = a->d_cw;
     g.ident = a->d_ident;
+    g.colptr = a->colptr.data();
+    g.ncolors = (int)a->colptr.size() - 1;
+    g.scratch = a->d_scratch;
+    g.nptr = a->d_nptr;
+    g.nidx = a->d_nidx;
+    g.nw = a->d_nw;
     *out = a;
     return VPP_OK;
 }
