@@ -334,16 +334,13 @@ vpp_status vpp_extend(vpp_problem p, const double* y, const int32_t* info, const
  * matrices of the active cells with the coefficient of Eq. rhoEff from the
  * nodal phi of the cell's own lattice), with identity rows and columns on
  * every entry that is not a free unknown and on free unknowns of Dirichlet
- * faces (as A_D).  The apply runs one cell per thread into a cell-major
- * scratch, then sums every entry over the cell results reaching it (lists
- * built on the host, constraint weights included) in a fixed order; the
- * diagonal runs the cells one colour per launch (the cells of a colour write
- * disjoint entries, also through constraint lists) with plain read-modify-write
- * adds.  No atomics: repeated calls give the same bits; FP64 only.
+ * faces (as A_D).  The apply and the diagonal run one cell per thread into a
+ * cell-major scratch, then sum every entry over the cell results reaching it
+ * (lists built on the host, constraint weights included) in a fixed order: no
+ * atomics, repeated calls give the same bits; FP64 only.  Calls on one mesh
+ * share that scratch and must not overlap.
  *   vpp_amr_create:   host call; VPP_ERR_INVALID_ARG as vpp_create, or for a
- *                     NULL mask, more than 2^27 coarse cells or 2^31 entries;
- *                     VPP_ERR_UNSUPPORTED if the colouring needs more than 64
- *                     colours.
+ *                     NULL mask, more than 2^27 coarse cells or 2^31 entries.
  *   vpp_amr_set_phi:  nodal phi on both lattices (vpp_amr_num_dofs entries);
  *                     builds the Jacobi diagonal.
  *   vpp_amr_apply:    y = A x (all entries written); x, y not aliased.

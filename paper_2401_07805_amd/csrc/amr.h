@@ -20,21 +20,22 @@ struct AmrArgs {
     const int* ccol;              // coarse vector entry of each term
     const double* cw;             // its weight
     const unsigned char* ident;   // per entry: 1 = identity row (not a free unknown, or Dirichlet)
-    // Colours of the cells (host array, read by the launchers only): cells
-    // [colptr[c], colptr[c+1]) of `cells` write disjoint vector entries, also
-    // through constraint lists, so one launch per colour in increasing order
-    // adds into y with plain loads and stores in a fixed order.
-    const int* colptr;
-    int ncolors;
-    // Apply in two launches: every active cell e stores its (k+1)^3 results
-    // at scratch[q * ncells + e]; then entry g of y sums scratch[nidx[j]]
-    // * nw[j] for j in [nptr[g], nptr[g+1]) (free nodes with weight 1,
-    // constrained nodes through their constraint weights), in increasing
-    // scratch index.
+    // Apply and diagonal in two launches each, no atomics.  Every active cell
+    // e stores its (k+1)^3 results at scratch[q * ncells + e]; then entry g of
+    // y sums scratch[nidx[j]] * nw[j] for j in [nptr[g], nptr[g+1]) (free
+    // nodes with weight 1, constrained nodes through their constraint
+    // weights), in increasing scratch index.  The diagonal also stores, for
+    // every coarse node a fine cell reaches through constraints (in the order
+    // the cell meets them), e^T K_e e at scratch[nfree_slots + soff[e] + i];
+    // entry g of diag sums scratch[didx[j]] for j in [dptr[g], dptr[g+1]).
     double* scratch;
     const int* nptr;
     const int* nidx;
     const double* nw;
+    const int* soff;
+    const int* dptr;
+    const int* didx;
+    int64_t nfree_slots;
 };
 
 // y = A x (zeroes y first); every entry of y is written.

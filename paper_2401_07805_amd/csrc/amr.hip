@@ -8,10 +8,8 @@
 // cell operator by sum factorisation (the same building blocks as the uniform
 // apply, with the cell size of its lattice) and stores its results in a
 // cell-major scratch; a second launch sums every entry of y over the cell
-// results that reach it, through a list built on the host, in a fixed order.
-// The diagonal (once per phi) adds into its entries with plain loads and
-// stores instead, the cells launched one colour at a time (the cells of a
-// colour write disjoint entries).  A fine node on the boundary of an unrefined coarse cell is
+// results that reach it, through a list built on the host, in a fixed order
+// (the diagonal likewise).  A fine node on the boundary of an unrefined coarse cell is
 // constrained: its value is sum_p w_p x[src_p] over the coarse cell's nodes
 // (the Q_k interpolant there), and its result goes back to those nodes with
 // the same weights (C^T).  Entries that are not free unknowns (unused nodes of
@@ -124,8 +122,8 @@ __global__ void amr_node_sum_kernel(AmrArgs a, const double* __restrict__ x, dou
 // e_i^T K_e e_i with e_i the cell vector of node i's weights, K_e applied by
 // the cell operator (each such coarse node once per cell).
 template <int K, int HV, bool FINE>
-__device__ __forceinline__ void amr_diag_cell(const AmrArgs& a, const MeshArgs& m, int idx,
-                                              const double* __restrict__ phi, double* __restrict__ diag)
+__device__ __forceinline__ void amr_diag_cell(const AmrArgs& a, const MeshArgs& m, int idx, int e,
+                                              const double* __restrict__ phi)
 {
     constexpr int N3 = (K + 1) * (K + 1) * (K + 1);
     const int64_t base = amr_base<K>(m, idx), off = FINE ? a.nc : 0;
@@ -158,12 +156,14 @@ __device__ __forceinline__ void amr_diag_cell(const AmrArgs& a, const MeshArgs& 
 #pragma unroll
         for (int q = 0; q < N3; ++q) {
             const int64_t gl = amr_local<K>(m, base, q);
-            if (amr_kind<FINE>(a, gl) < 0) diag[off + gl] += out[q];
+            if (amr_kind<FINE>(a, gl) < 0) a.scratch[(size_t)q * (size_t)a.ncells + (size_t)e] = out[q];
         }
     }
     if constexpr (FINE) {
         // coarse nodes reached through constraints: visit each (node q, term p)
         // pair and handle its coarse node at its first occurrence in that order
+        // (the host numbers the slots in the same order)
+        int64_t slot = a.nfree_slots + a.soff[e];
         for (int q = 0; q < N3; ++q) {
             const int kq = a.fkind[amr_local<K>(m, base, q)];
             if (kq < 0) continue;
@@ -191,29 +191,31 @@ __device__ __forceinline__ void amr_diag_cell(const AmrArgs& a, const MeshArgs& 
                 cell_operator<K, double>(m, cw, kv);
                 double d = 0.0;
                 for (int r = 0; r < N3; ++r) d = fma(ev[r], kv[r], d);
-                diag[src] += d;
+                a.scratch[slot++] = d;
             }
         }
     }
 }
 
 template <int K, int HV>
-__global__ void __launch_bounds__(64) amr_diag_kernel(AmrArgs a, const double* __restrict__ phi,
-                                                      double* __restrict__ diag, int first, int count)
+__global__ void __launch_bounds__(64) amr_diag_kernel(AmrArgs a, const double* __restrict__ phi)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    const int code = a.cells[first + t];
-    if (code >= 0) amr_diag_cell<K, HV, false>(a, a.mc, code, phi, diag);
-    else amr_diag_cell<K, HV, true>(a, a.mf, -(code + 1), phi, diag);
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.ncells) return;
+    const int code = a.cells[e];
+    if (code >= 0) amr_diag_cell<K, HV, false>(a, a.mc, code, e, phi);
+    else amr_diag_cell<K, HV, true>(a, a.mf, -(code + 1), e, phi);
 }
 
-// diag = 1 on identity rows, then the FP64 and FP32 inverses.
+// diag = 1 on identity rows, else the sum of its cell slots; then the FP64
+// and FP32 inverses.
 __global__ void amr_fix_diag_kernel(AmrArgs a, double* __restrict__ diag, double* __restrict__ inv64,
                                     float* __restrict__ inv32)
 {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
-        const double d = a.ident[g] ? 1.0 : diag[g];
+        double s = 0.0;
+        for (int j = a.dptr[g]; j < a.dptr[g + 1]; ++j) s += a.scratch[a.didx[j]];
+        const double d = a.ident[g] ? 1.0 : s;
         diag[g] = d;
         inv64[g] = 1.0 / d;
         inv32[g] = (float)(1.0 / d);
@@ -258,13 +260,10 @@ hipError_t launch_amr_apply(int k, const AmrArgs& a, const double* phi, const do
 hipError_t launch_amr_diag(int k, const AmrArgs& a, const double* phi, double* diag, double* inv64, float* inv32,
                            hipStream_t s)
 {
-    hipError_t e = launch_fill<double>(diag, a.n, 0.0, s);
-    if (e != hipSuccess) return e;
-    for (int c = 0; c < a.ncolors; ++c) {
-        const int first = a.colptr[c], count = a.colptr[c + 1] - first;
-        if (count <= 0) continue;
-        const int blocks = (count + 63) / 64;
-        VPP_AMR_SWITCH(amr_diag_kernel, phi, diag, first, count)
+    hipError_t e;
+    if (a.ncells > 0) {
+        const int blocks = (a.ncells + 63) / 64;
+        VPP_AMR_SWITCH(amr_diag_kernel, phi)
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(amr_fix_diag_kernel, dim3(stream_blocks(a.n)), dim3(256), 0, s, a, diag, inv64, inv32);

@@ -1616,13 +1616,13 @@ struct vpp_amr_s {
     double* d_cw = nullptr;
     int *d_nptr = nullptr, *d_nidx = nullptr;   // per entry: the cell results that reach it
     double *d_nw = nullptr, *d_scratch = nullptr;
+    int *d_soff = nullptr, *d_dptr = nullptr, *d_didx = nullptr;   // the same for the diagonal
     unsigned char* d_ident = nullptr;
     double *phi = nullptr, *diag = nullptr, *inv64 = nullptr;
     float* inv32 = nullptr;
     bool phi_set = false;
     hipStream_t stream = nullptr;
     ReinitWork* w = nullptr;   // CG vectors (allocated by the first solve)
-    std::vector<int> colptr;   // cell colours (host; ranges of the colour-ordered cell list)
 };
 
 static double gll_point(int k, int i)
@@ -1647,6 +1647,7 @@ static void amr_free(vpp_amr a)
     dev_free(a->d_cells); dev_free(a->d_fkind); dev_free(a->d_cptr); dev_free(a->d_ccol); dev_free(a->d_cw);
     dev_free(a->d_ident); dev_free(a->phi); dev_free(a->diag); dev_free(a->inv64); dev_free(a->inv32);
     dev_free(a->d_nptr); dev_free(a->d_nidx); dev_free(a->d_nw); dev_free(a->d_scratch);
+    dev_free(a->d_soff); dev_free(a->d_dptr); dev_free(a->d_didx);
     free_reinit(a->w);
     if (a->stream) (void)hipStreamDestroy(a->stream);
     delete a;
@@ -1766,50 +1767,6 @@ extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, 
             ident[Nc + gf] = 0;
             ++nfree;
         }
-    // colour the cells: no two cells of a colour write the same vector entry,
-    // directly (a free node) or through a constraint list (the coarse sources
-    // of a constrained fine node); greedy, lowest free colour, cells in order
-    std::vector<uint64_t> used((size_t)(Nc + Nf), 0);
-    std::vector<int> color(cells.size());
-    std::vector<int64_t> wset;
-    int ncol = 0;
-    for (size_t e = 0; e < cells.size(); ++e) {
-        wset.clear();
-        const int code = cells[e];
-        const bool fine = code < 0;
-        const int idx = fine ? -(code + 1) : code;
-        const int64_t* nn = fine ? fn : cn;
-        const int ncx = fine ? 2 * nc[0] : nc[0], ncy = fine ? 2 * nc[1] : nc[1];
-        const int64_t cx = idx % ncx, cy = (idx / ncx) % ncy, cz = idx / ((int64_t)ncx * ncy);
-        for (int a2 = 0; a2 <= k; ++a2)
-            for (int a1 = 0; a1 <= k; ++a1)
-                for (int a0 = 0; a0 <= k; ++a0) {
-                    const int64_t gl = (k * cx + a0) + nn[0] * ((k * cy + a1) + nn[1] * (k * cz + a2));
-                    if (!fine) {
-                        wset.push_back(gl);
-                    } else if (fkind[gl] < 0) {
-                        wset.push_back(Nc + gl);
-                    } else {
-                        for (int p = cptr[fkind[gl]]; p < cptr[fkind[gl] + 1]; ++p) wset.push_back(ccol[p]);
-                    }
-                }
-        uint64_t forb = 0;
-        for (int64_t g : wset) forb |= used[g];
-        if (forb == ~0ull) return fail(VPP_ERR_UNSUPPORTED, "refinement pattern needs more than 64 cell colours");
-        int c = 0;
-        while (forb & (1ull << c)) ++c;
-        color[e] = c;
-        ncol = std::max(ncol, c + 1);
-        for (int64_t g : wset) used[g] |= 1ull << c;
-    }
-    std::vector<int> colptr(ncol + 1, 0), sorted(cells.size());
-    for (int c : color) ++colptr[c + 1];
-    for (int c = 0; c < ncol; ++c) colptr[c + 1] += colptr[c];
-    {
-        std::vector<int> pos(colptr.begin(), colptr.end() - 1);
-        for (size_t e = 0; e < cells.size(); ++e) sorted[pos[color[e]]++] = cells[e];
-    }
-    cells.swap(sorted);
     // the cell results reaching each entry (apply's second launch): cell e's
     // local node q is scratch slot q * ncells + e; a free node takes it with
     // weight 1, a constrained one passes it to its sources with their weights.
@@ -1858,11 +1815,68 @@ extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, 
             nwv[j] = tw[t];
         }
     }
+    // the diagonal's cell slots: free nodes as above (constrained ones have
+    // none), then for every fine cell the coarse nodes its constrained nodes
+    // reach, numbered in the order the diagonal kernel meets them (node q,
+    // then term p; a coarse node at its first occurrence)
+    std::vector<int> soff(ncell_act + 1, 0), dptr((size_t)(Nc + Nf) + 1, 0), didx;
+    {
+        std::vector<int64_t> tgt;
+        std::vector<int64_t> tslot;
+        for (int q = 0; q < n3; ++q) {
+            const int a0 = q % (k + 1), a1 = (q / (k + 1)) % (k + 1), a2 = q / ((k + 1) * (k + 1));
+            for (int64_t e = 0; e < ncell_act; ++e) {
+                const int code = cells[e];
+                const bool fine = code < 0;
+                const int idx = fine ? -(code + 1) : code;
+                const int64_t* nn = fine ? fn : cn;
+                const int ncx = fine ? 2 * nc[0] : nc[0], ncy = fine ? 2 * nc[1] : nc[1];
+                const int64_t cx = idx % ncx, cy = (idx / ncx) % ncy, cz = idx / ((int64_t)ncx * ncy);
+                const int64_t gl = (k * cx + a0) + nn[0] * ((k * cy + a1) + nn[1] * (k * cz + a2));
+                if (!fine) {
+                    tgt.push_back(gl);
+                    tslot.push_back(q * ncell_act + e);
+                } else if (fkind[gl] < 0) {
+                    tgt.push_back(Nc + gl);
+                    tslot.push_back(q * ncell_act + e);
+                }
+            }
+        }
+        const int64_t nfree_slots = ncell_act * n3;
+        std::vector<int> srcs;
+        for (int64_t e = 0; e < ncell_act; ++e) {
+            soff[e + 1] = soff[e];
+            const int code = cells[e];
+            if (code >= 0) continue;
+            const int idx = -(code + 1);
+            const int ncx = 2 * nc[0], ncy = 2 * nc[1];
+            const int64_t cx = idx % ncx, cy = (idx / ncx) % ncy, cz = idx / ((int64_t)ncx * ncy);
+            srcs.clear();
+            for (int q = 0; q < n3; ++q) {
+                const int a0 = q % (k + 1), a1 = (q / (k + 1)) % (k + 1), a2 = q / ((k + 1) * (k + 1));
+                const int64_t gl = (k * cx + a0) + fn[0] * ((k * cy + a1) + fn[1] * (k * cz + a2));
+                if (fkind[gl] < 0) continue;
+                for (int p = cptr[fkind[gl]]; p < cptr[fkind[gl] + 1]; ++p)
+                    if (std::find(srcs.begin(), srcs.end(), ccol[p]) == srcs.end()) srcs.push_back(ccol[p]);
+            }
+            if ((int64_t)soff[e] + (int64_t)srcs.size() + nfree_slots > (int64_t)INT32_MAX)
+                return fail(VPP_ERR_INVALID_ARG, "too many cell results");
+            for (size_t i = 0; i < srcs.size(); ++i) {
+                tgt.push_back(srcs[i]);
+                tslot.push_back(nfree_slots + soff[e] + (int64_t)i);
+            }
+            soff[e + 1] = soff[e] + (int)srcs.size();
+        }
+        for (int64_t g : tgt) ++dptr[g + 1];
+        for (size_t g = 0; g + 1 < dptr.size(); ++g) dptr[g + 1] += dptr[g];
+        didx.resize(tgt.size());
+        std::vector<int> pos(dptr.begin(), dptr.end() - 1);
+        for (size_t t = 0; t < tgt.size(); ++t) didx[pos[tgt[t]]++] = (int)tslot[t];
+    }
     DeviceGuard dg(d->device);
     vpp_amr a = new vpp_amr_s();
     a->desc = *d;
     a->k = k;
-    a->colptr = colptr;
     a->nc = Nc;
     a->nf = Nf;
     a->n = Nc + Nf;
@@ -1874,8 +1888,10 @@ extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, 
         (st = dev_alloc(&a->phi, a->n, "amr phi")) || (st = dev_alloc(&a->diag, a->n, "amr diag")) ||
         (st = dev_alloc(&a->inv64, a->n, "amr inverse diag")) || (st = dev_alloc(&a->inv32, a->n, "amr inverse diag")) ||
         (st = upload(&a->d_nptr, nptr, "amr entry lists")) || (st = upload(&a->d_nidx, nidx, "amr entry slots")) ||
-        (st = upload(&a->d_nw, nwv, "amr entry weights")) ||
-        (st = dev_alloc(&a->d_scratch, (size_t)std::max<int64_t>(ncell_act * n3, 1), "amr cell results"))) {
+        (st = upload(&a->d_nw, nwv, "amr entry weights")) || (st = upload(&a->d_soff, soff, "amr source slots")) ||
+        (st = upload(&a->d_dptr, dptr, "amr diagonal lists")) || (st = upload(&a->d_didx, didx, "amr diagonal slots")) ||
+        (st = dev_alloc(&a->d_scratch, (size_t)std::max<int64_t>(ncell_act * n3 + soff[ncell_act], 1),
+                        "amr cell results"))) {
         amr_free(a);
         return st;
     }
@@ -1898,12 +1914,14 @@ extern "C" vpp_status vpp_amr_create(const vpp_desc* d, const uint8_t* refined, 
     g.ccol = a->d_ccol;
     g.cw = a->d_cw;
     g.ident = a->d_ident;
-    g.colptr = a->colptr.data();
-    g.ncolors = (int)a->colptr.size() - 1;
     g.scratch = a->d_scratch;
     g.nptr = a->d_nptr;
     g.nidx = a->d_nidx;
     g.nw = a->d_nw;
+    g.soff = a->d_soff;
+    g.dptr = a->d_dptr;
+    g.didx = a->d_didx;
+    g.nfree_slots = ncell_act * n3;
     *out = a;
     return VPP_OK;
 }

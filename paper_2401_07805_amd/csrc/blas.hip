@@ -502,19 +502,29 @@ VPP_INST(float)
 // Deflation space of the mixed-precision solver (Ritz vectors of the first
 // FP32 phase and the Galerkin correction in their span).
 
+// One unknown per thread; the recorded residuals are read eight at a time
+// (all loads of a group issued before their use).
 __global__ void __launch_bounds__(BT) ritz_kernel(const float* __restrict__ hist, int64_t stride, int m,
                                                   const double* __restrict__ C, int k,
                                                   const double* __restrict__ invd, double* __restrict__ W, int64_t n)
 {
+    constexpr int G = 8;
     for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
         double acc[kMaxDefl];
 #pragma unroll
         for (int t = 0; t < kMaxDefl; ++t) acc[t] = 0.0;
-        for (int j = 0; j < m; ++j) {
-            const double h = (double)hist[(size_t)j * (size_t)stride + (size_t)i];
+        const float* col = hist + (size_t)i;
+        for (int j0 = 0; j0 < m; j0 += G) {
+            float h[G];
 #pragma unroll
-            for (int t = 0; t < kMaxDefl; ++t)
-                if (t < k) acc[t] = fma(C[j * k + t], h, acc[t]);
+            for (int u = 0; u < G; ++u) h[u] = (j0 + u < m) ? col[(size_t)(j0 + u) * (size_t)stride] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (j0 + u >= m) break;
+#pragma unroll
+                for (int t = 0; t < kMaxDefl; ++t)
+                    if (t < k) acc[t] = fma(C[(j0 + u) * k + t], (double)h[u], acc[t]);
+            }
         }
         const double di = invd[i];
 #pragma unroll
@@ -588,7 +598,9 @@ hipError_t launch_ritz(const float* hist, int64_t stride, int m, const double* C
                        double* W, int64_t n, hipStream_t s)
 {
     if (k < 1 || k > kMaxDefl) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ritz_kernel, dim3(grid_for<double>(n)), dim3(BT), 0, s, hist, stride, m, C, k, invd, W, n);
+    const int64_t want = (n + BT - 1) / BT;
+    const int g = (int)(want < 1 ? 1 : (want > 65536 ? 65536 : want));
+    hipLaunchKernelGGL(ritz_kernel, dim3(g), dim3(BT), 0, s, hist, stride, m, C, k, invd, W, n);
     return hipGetLastError();
 }
 

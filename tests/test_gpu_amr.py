@@ -114,8 +114,7 @@ def test_amr_band_32cube():
     yv = host(p.apply(dev(xv)))
     assert rel(yv, A @ xv) < 1e-12 and rel_max(yv, A @ xv) < 1e-12
     assert rel_max(host(p.diagonal()), A.diagonal()) < 1e-13
-    # no atomics (cell scratch + entry sum; colour launches for the diagonal):
-    # repeated calls give the same bits
+    # no atomics (cell scratch + entry sum): repeated calls give the same bits
     xd = dev(xv)
     y0 = p.apply(xd)
     d0 = p.diagonal()
