@@ -45,8 +45,10 @@ def test_struct_layouts_match_header(tmp_path):
 int main(void){
   printf("%zu %zu %zu %zu %zu\n", sizeof(vpp_desc), offsetof(vpp_desc, origin), offsetof(vpp_desc, degree),
          offsetof(vpp_desc, rho_l), offsetof(vpp_desc, device));
-  printf("%zu %zu %zu\n", sizeof(vpp_cg_opts), offsetof(vpp_cg_opts, inner_rtol), offsetof(vpp_cg_opts, check_every));
-  printf("%zu %zu\n", sizeof(vpp_cg_info), offsetof(vpp_cg_info, rel_residual));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(vpp_cg_opts), offsetof(vpp_cg_opts, inner_rtol), offsetof(vpp_cg_opts, check_every),
+         offsetof(vpp_cg_opts, deflate), offsetof(vpp_cg_opts, deflate_history));
+  printf("%zu %zu %zu %zu\n", sizeof(vpp_cg_info), offsetof(vpp_cg_info, rel_residual),
+         offsetof(vpp_cg_info, deflation_corrections), offsetof(vpp_cg_info, deflation_first_change));
   printf("%zu %zu\n", sizeof(vpp_kernel_config), offsetof(vpp_kernel_config, variant));
   printf("%zu %zu %zu\n", sizeof(vpp_cp_opts), offsetof(vpp_cp_opts, max_iter), offsetof(vpp_cp_opts, normal_steps));
   printf("%zu %zu\n", sizeof(vpp_reinit_opts), offsetof(vpp_reinit_opts, max_iter));
@@ -58,8 +60,10 @@ int main(void){
     D, O, I, K = _lib.Desc, _lib.CgOpts, _lib.CgInfo, _lib.KernelConfig
     assert out[0].split() == [str(v) for v in (ctypes.sizeof(D), D.origin.offset, D.degree.offset,
                                                 D.rho_l.offset, D.device.offset)]
-    assert out[1].split() == [str(v) for v in (ctypes.sizeof(O), O.inner_rtol.offset, O.check_every.offset)]
-    assert out[2].split() == [str(v) for v in (ctypes.sizeof(I), I.rel_residual.offset)]
+    assert out[1].split() == [str(v) for v in (ctypes.sizeof(O), O.inner_rtol.offset, O.check_every.offset,
+                                               O.deflate.offset, O.deflate_history.offset)]
+    assert out[2].split() == [str(v) for v in (ctypes.sizeof(I), I.rel_residual.offset,
+                                               I.deflation_corrections.offset, I.deflation_first_change.offset)]
     assert out[3].split() == [str(v) for v in (ctypes.sizeof(K), K.variant.offset)]
     P = _lib.CpOpts
     assert out[4].split() == [str(v) for v in (ctypes.sizeof(P), P.max_iter.offset, P.normal_steps.offset)]
