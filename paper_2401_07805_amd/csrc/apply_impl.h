@@ -568,6 +568,10 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
             qa[d] = r;
             cb[d] = (r == 0 && q > 0) ? q - 1 : -1;
         }
+        const unsigned off = (unsigned)(c[0] + f.nx * c[1] + f.nxy * c[2]);
+        // on a tile with a Dirichlet face the node's x is loaded before the slot
+        // reads (an identity row copies it), so its latency overlaps them
+        const T xe = anyd ? VPP_LD(&f.xt[off], BC_X) : T(0);
         T v = T(0);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -578,14 +582,13 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
             const bool ok = x0 >= 0 && x1 >= 0 && x2 >= 0;
             v += VPP_LD(&f.slot[p * f.cs + (ok ? x0 * CST[0] + x1 * CST[1] + x2 * CST[2] : NT)], BC_SLOT);
         }
-        const unsigned off = (unsigned)(c[0] + f.nx * c[1] + f.nxy * c[2]);
         const bool lo0 = FACE != 0 && c[0] == 0 && t0 > 0;
         const bool lo1 = FACE != 1 && c[1] == 0 && t1 > 0;
         const bool lo2 = FACE != 2 && c[2] == 0 && t2 > 0;
         const bool hi0 = c[0] == E0 && hn[0], hi1 = c[1] == E1 && hn[1], hi2 = c[2] == E2 && hn[2];
         if (anyd && ((dlo[0] && c[0] == 0) || (dhi[0] && c[0] == E0) || (dlo[1] && c[1] == 0) ||
                      (dhi[1] && c[1] == E1) || (dlo[2] && c[2] == 0) || (dhi[2] && c[2] == E2))) {
-            const T xv = VPP_LD(&f.xt[off], BC_X);
+            const T xv = xe;
             VPP_ST(&f.yt[off], BC_Y, xv);
             if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
             continue;
@@ -678,6 +681,18 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
         const int fz = i0 + nx * j0 + nxy * (t2 - 1);
         const int fy = cz_n + i0 + nx * ((t1 - 1) + nby * (l0 - t2));
         const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));
+        // x at the owned positions of a cell on a Dirichlet face (identity rows
+        // copy it), all loads issued together rather than one round trip per row
+        T xd[K * K * K];
+        if (dl0 || dl1 || dl2) {
+#pragma unroll
+            for (int a2 = 0; a2 < K; ++a2)
+#pragma unroll
+                for (int a1 = 0; a1 < K; ++a1)
+#pragma unroll
+                    for (int a0 = 0; a0 < K; ++a0)
+                        xd[a0 + K * (a1 + K * a2)] = VPP_LD(at_byte(xt + (a0 + nx * a1 + nxy * a2), lane_b), BC_X);
+        }
 #pragma unroll
         for (int a2 = 0; a2 < K; ++a2)
 #pragma unroll
@@ -697,7 +712,7 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
                     const bool lo0 = z0 && hl0, lo1 = z1 && hl1, lo2 = z2 && hl2;
                     const bool dir = (z0 && dl0) || (z1 && dl1) || (z2 && dl2);
                     if (dir) {
-                        const T xv = VPP_LD(at_byte(xt + row, lane_b), BC_X);
+                        const T xv = xd[a0 + K * (a1 + K * a2)];
                         VPP_ST(at_byte(yt + row, lane_b), BC_Y, xv);
                         if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                         continue;
