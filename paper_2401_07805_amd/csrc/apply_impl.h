@@ -569,9 +569,10 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
             cb[d] = (r == 0 && q > 0) ? q - 1 : -1;
         }
         const unsigned off = (unsigned)(c[0] + f.nx * c[1] + f.nxy * c[2]);
-        // on a tile with a Dirichlet face the node's x is loaded before the slot
-        // reads (an identity row copies it), so its latency overlaps them
-        const T xe = anyd ? VPP_LD(&f.xt[off], BC_X) : T(0);
+        // on a tile with a Dirichlet face (an identity row copies it) or for
+        // x . Ax the node's x is loaded before the slot reads, so its latency
+        // overlaps them
+        const T xe = (anyd || dot) ? VPP_LD(&f.xt[off], BC_X) : T(0);
         T v = T(0);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -604,7 +605,7 @@ __device__ __forceinline__ double upper_face_full(const FaceCtx<T>& f, const int
         } else {
             VPP_ST(&f.yt[off], BC_Y, v);
         }
-        if (dot) dsum += (double)VPP_LD(&f.xt[off], BC_X) * (double)v;
+        if (dot) dsum += (double)xe * (double)v;
     }
     return dsum;
 }
@@ -681,10 +682,11 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
         const int fz = i0 + nx * j0 + nxy * (t2 - 1);
         const int fy = cz_n + i0 + nx * ((t1 - 1) + nby * (l0 - t2));
         const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));
-        // x at the owned positions of a cell on a Dirichlet face (identity rows
-        // copy it), all loads issued together rather than one round trip per row
+        // x at the owned positions (identity rows on a Dirichlet face copy it,
+        // x . Ax needs it), all loads issued together rather than one round
+        // trip per row
         T xd[K * K * K];
-        if (dl0 || dl1 || dl2) {
+        if (dot || dl0 || dl1 || dl2) {
 #pragma unroll
             for (int a2 = 0; a2 < K; ++a2)
 #pragma unroll
@@ -724,7 +726,7 @@ __device__ __forceinline__ double flush_two_pass(const MeshArgs& m, const TileCo
                         dst = part + ((unsigned)rank * nsh + (unsigned)f);
                     }
                     VPP_ST(dst, BC_OUT, v);
-                    if (dot) dsum += (double)VPP_LD(at_byte(xt + row, lane_b), BC_X) * (double)v;
+                    if (dot) dsum += (double)xd[a0 + K * (a1 + K * a2)] * (double)v;
                 }
     }
 
