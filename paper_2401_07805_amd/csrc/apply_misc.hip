@@ -190,10 +190,30 @@ __global__ void __launch_bounds__(256) assemble_kernel(AssembleArgs<T> a)
     const int64_t count = e.cz + e.cy + e.cx;
     using P = typename Pair<T>::type;
     for (int64_t f = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); f < count; f += 2 * (int64_t)gridDim.x * 256) {
+        // positions and sharer counts of nodes f and f + 1 first (no memory),
+        // then every partial of both nodes loaded before any is used
+        int i0, j0, l0, i1 = 0, j1 = 0, l1 = 0;
+        shared_node(e, f, i0, j0, l0);
+        const bool has1 = f + 1 < count;
+        if (has1) shared_node(e, f + 1, i1, j1, l1);
+        const int n0 = is_dirichlet(a.m, i0, j0, l0) ? 0 : sharer_count(e, i0, j0, l0);
+        const int n1 = !has1 || is_dirichlet(a.m, i1, j1, l1) ? 0 : sharer_count(e, i1, j1, l1);
         const P r0 = VPP_LD(reinterpret_cast<const P*>(a.part + f), BC_PART);
         const P r1 = VPP_LD(reinterpret_cast<const P*>(a.part + a.nshared + f), BC_PART);
-        assemble_one(e, a.m, a.part, a.nshared, f, r0.x + r1.x, a.y);
-        if (f + 1 < count) assemble_one(e, a.m, a.part, a.nshared, f + 1, r0.y + r1.y, a.y);
+        T x0[6], x1[6];
+#pragma unroll
+        for (int c = 2; c < 8; ++c) {
+            x0[c - 2] = c < n0 ? VPP_LD(&a.part[c * a.nshared + f], BC_PART) : T(0);
+            x1[c - 2] = c < n1 ? VPP_LD(&a.part[c * a.nshared + f + 1], BC_PART) : T(0);
+        }
+        T v0 = r0.x + r1.x, v1 = r0.y + r1.y;
+#pragma unroll
+        for (int c = 2; c < 8; ++c) {
+            if (c < n0) v0 += x0[c - 2];
+            if (c < n1) v1 += x1[c - 2];
+        }
+        if (n0 > 0) VPP_ST(&a.y[i0 + (int64_t)a.m.nn[0] * (j0 + (int64_t)a.m.nn[1] * l0)], BC_Y, v0);
+        if (n1 > 0) VPP_ST(&a.y[i1 + (int64_t)a.m.nn[0] * (j1 + (int64_t)a.m.nn[1] * l1)], BC_Y, v1);
     }
 }
 
