@@ -213,11 +213,19 @@ __device__ __forceinline__ void assemble_update_body(int bid, int nblk, CgState*
             for (int j = 0; j < P::W; ++j)
                 if (!shared_lookup(sp.e, sp.bcmask, g0 + j, f[j], cnt[j])) cnt[j] = 0;
         }
+        // (loaded into pv first, then summed in rank order as a plain loop would)
+        T pv[P::W][8];
+#pragma unroll
+        for (int j = 0; j < P::W; ++j)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pv[j][k] = k < cnt[j] ? sp.part[k * sp.stride + f[j]] : T(0);
 #pragma unroll
         for (int j = 0; j < P::W; ++j)
             if (cnt[j]) {
-                T v = sp.part[f[j]] + sp.part[sp.stride + f[j]];
-                for (int k = 2; k < cnt[j]; ++k) v += sp.part[k * sp.stride + f[j]];
+                T v = pv[j][0] + pv[j][1];
+#pragma unroll
+                for (int k = 2; k < 8; ++k)
+                    if (k < cnt[j]) v += pv[j][k];
                 qv.v[j] = v;
             }
 #pragma unroll
