@@ -172,7 +172,22 @@ __device__ __forceinline__ void assemble_update_body(int bid, int nblk, CgState*
                                                      const SharedParts<T>& sp, T* __restrict__ r,
                                                      const T* __restrict__ q, const T* __restrict__ invd, int64_t n)
 {
-    if (st->halt[par]) return;
+    // every state field this kernel needs, read at once (before the barrier of
+    // the reduction, so the loads overlap it instead of following it)
+    const int halt = st->halt[par];
+    const double rz_par = st->rz[par];
+    float* hist = nullptr;
+    int hit = 0, hcap = 0;
+    int64_t hstride = 0;
+    if constexpr (sizeof(T) == 4) {
+        // residual record of an FP32 phase (iterations counted by the previous
+        // direction update, which has completed)
+        hist = st->hist;
+        hit = st->iters + 1;
+        hcap = st->hist_cap;
+        hstride = st->hist_stride;
+    }
+    if (halt) return;
     double pAp = 0.0, unused = 0.0;
     for (int i = threadIdx.x; i < sp.ndot; i += BT) pAp += sp.dot_part[i];
     block_sum2<BT>(pAp, unused);
@@ -181,17 +196,13 @@ __device__ __forceinline__ void assemble_update_body(int bid, int nblk, CgState*
         if (bid == 0 && threadIdx.x == 0) st->breakdown = 1;
         return;
     }
-    const T alpha = T(st->rz[par] / pAp);
+    const T alpha = T(rz_par / pAp);
     double rr = 0.0, rz = 0.0;
     using P = Pack<T>;
     const int64_t np = n / P::W;
-    // residual record of an FP32 phase (iterations counted by the previous
-    // direction update, which has completed)
     T* hrec = nullptr;
-    if constexpr (sizeof(T) == 4) {
-        const int hit = st->iters + 1;
-        if (st->hist && hit < st->hist_cap) hrec = st->hist + (size_t)hit * (size_t)st->hist_stride;
-    }
+    if constexpr (sizeof(T) == 4)
+        if (hist && hit < hcap) hrec = hist + (size_t)hit * (size_t)hstride;
     for (int64_t c = (int64_t)bid * BT + threadIdx.x; c < np; c += (int64_t)nblk * BT) {
         P rv = reinterpret_cast<const P*>(r)[c];
         const P dv = reinterpret_cast<const P*>(invd)[c];
@@ -273,7 +284,13 @@ __device__ __forceinline__ void pupdate_body(int bid, int nblk, CgState* st, int
                                              T* __restrict__ x, const T* __restrict__ r, T* __restrict__ p,
                                              const T* __restrict__ invd, int64_t n)
 {
-    if (st->halt[par] || st->breakdown) {
+    // every state field this kernel reads, at once (before the reduction's
+    // barrier); thread 0 of workgroup 0 is the only writer, of other fields
+    const int halt = st->halt[par], brk = st->breakdown;
+    const double rz_par = st->rz[par], pAp_par = st->pAp, tol2 = st->tol2;
+    const int iters0 = st->iters, max_iter = st->max_iter, hcap = st->hist_cap;
+    double* const coef = st->coef;
+    if (halt || brk) {
         if (bid == 0 && threadIdx.x == 0) st->halt[1 - par] = 1;
         return;
     }
@@ -298,9 +315,9 @@ __device__ __forceinline__ void pupdate_body(int bid, int nblk, CgState* st, int
     load(c0);
     double rr, rzn;
     sum_partials(red, ng, rr, rzn);
-    const double beta_d = rzn / st->rz[par];
+    const double beta_d = rzn / rz_par;
     if (bid == 0 && threadIdx.x == 0) {
-        const int it = st->iters + 1;
+        const int it = iters0 + 1;
         st->iters = it;
         st->rr_last = rr;
         st->rr[par] = rr;
@@ -309,17 +326,17 @@ __device__ __forceinline__ void pupdate_body(int bid, int nblk, CgState* st, int
         if (!isfinite(rr) || !isfinite(rzn)) {
             st->breakdown = 1;
             st->halt[1 - par] = 1;
-        } else if (rr < st->tol2 || it >= st->max_iter) {
+        } else if (rr < tol2 || it >= max_iter) {
             st->halt[1 - par] = 1;
         }
-        if (st->coef && it < st->hist_cap) {
-            st->coef[3 * it] = st->rz[par] / st->pAp;
-            st->coef[3 * it + 1] = beta_d;
-            st->coef[3 * it + 2] = rzn;
+        if (coef && it < hcap) {
+            coef[3 * it] = rz_par / pAp_par;
+            coef[3 * it + 1] = beta_d;
+            coef[3 * it + 2] = rzn;
         }
     }
     // the same alpha as the update's (same operands, same rounding)
-    const T alpha = T(st->rz[par] / st->pAp);
+    const T alpha = T(rz_par / pAp_par);
     const T beta = T(beta_d);
     for (int64_t cb = c0; cb < np; cb += U * S) {
         if (cb != c0) load(cb);
