@@ -485,7 +485,24 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
     const int nc0 = E0 / K, nc1 = E1 / K, nc2 = E2 / K;
     const int t0 = f.tc.t[0], t1 = f.tc.t[1], t2 = f.tc.t[2];
     double dsum = 0.0;
-    for (int n = threadIdx.x; n < count; n += NTH) {
+    // the node's x (identity rows copy it, x . Ax needs it) for every
+    // iteration of this thread, loaded before the first one; a ragged tile has
+    // at most the iterations of a complete one
+    constexpr int CMAX = (FACE == 0 ? K * TY + 1 : K * TX) * (FACE == 2 ? K * TY : K * TZ + 1);
+    constexpr int MAXIT = (CMAX + NTH - 1) / NTH;
+    T xe[MAXIT];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int n = threadIdx.x + it * NTH;
+        if (n >= count) break;
+        const int ib = n / na, ia = n - ib * na;
+        const int c0 = FACE == 0 ? E0 : ia, c1 = FACE == 0 ? ia : (FACE == 1 ? E1 : ib), c2 = FACE == 2 ? E2 : ib;
+        xe[it] = VPP_LD(&f.xt[(unsigned)(c0 + f.nx * c1 + f.nxy * c2)], BC_X);
+    }
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int n = threadIdx.x + it * NTH;
+        if (n >= count) break;
         const int ib = n / na, ia = n - ib * na;
         const int c0 = FACE == 0 ? E0 : ia;
         const int c1 = FACE == 0 ? ia : (FACE == 1 ? E1 : ib);
@@ -512,7 +529,7 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
         const bool lo0 = c0 == 0 && t0 > 0, lo1 = c1 == 0 && t1 > 0, lo2 = c2 == 0 && t2 > 0;
         const bool hi0 = c0 == E0 && t0 < f.nbx, hi1 = c1 == E1 && t1 < f.nby, hi2 = c2 == E2 && t2 < f.nbz;
         if (is_dirichlet(f.m, gi, gj, gl)) {
-            const T xv = VPP_LD(&f.xt[off], BC_X);
+            const T xv = xe[it];
             VPP_ST(&f.yt[off], BC_Y, xv);
             if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
             continue;
@@ -525,7 +542,7 @@ __device__ __forceinline__ double upper_face(const FaceCtx<T>& f, bool dot)
         } else {
             VPP_ST(&f.yt[off], BC_Y, v);
         }
-        if (dot) dsum += (double)VPP_LD(&f.xt[off], BC_X) * (double)v;
+        if (dot) dsum += (double)xe[it] * (double)v;
     }
     return dsum;
 }
@@ -1220,6 +1237,20 @@ __device__ __forceinline__ double flush_half_owned(const MeshArgs& m, const Tile
     const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));
     auto pos = [](int b0, int b1, int b2) { return b0 + N * (b1 + N * b2); };
     double dsum = 0.0;
+    // x at the owned positions (identity rows copy it, x . Ax needs it), all
+    // loads issued together rather than one round trip per row
+    T xd[2][K * K];
+    if (dot || dl0 || dl1 || dl2) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (pl[j] >= K) continue;
+#pragma unroll
+            for (int a1 = 0; a1 < K; ++a1)
+#pragma unroll
+                for (int a0 = 0; a0 < K; ++a0)
+                    xd[j][a0 + K * a1] = VPP_LD(at_byte(xt + (a0 + nx * a1 + nxy * pl[j]), lane_b), BC_X);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int a2 = pl[j];
@@ -1241,7 +1272,7 @@ __device__ __forceinline__ double flush_half_owned(const MeshArgs& m, const Tile
                 const int row = a0 + nx * a1 + nxy * a2;
                 const bool lo0 = z0 && hl0, lo1 = z1 && hl1, lo2 = z2 && hl2;
                 if ((z0 && dl0) || (z1 && dl1) || (z2 && dl2)) {
-                    const T xv = VPP_LD(at_byte(xt + row, lane_b), BC_X);
+                    const T xv = xd[j][a0 + K * a1];
                     VPP_ST(at_byte(yt + row, lane_b), BC_Y, xv);
                     if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                     continue;
@@ -1254,7 +1285,7 @@ __device__ __forceinline__ double flush_half_owned(const MeshArgs& m, const Tile
                     dst = part + ((unsigned)rank * nsh + (unsigned)f);
                 }
                 VPP_ST(dst, BC_OUT, val);
-                if (dot) dsum += (double)VPP_LD(at_byte(xt + row, lane_b), BC_X) * (double)val;
+                if (dot) dsum += (double)xd[j][a0 + K * a1] * (double)val;
             }
     }
     return dsum;
