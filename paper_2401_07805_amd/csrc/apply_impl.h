@@ -845,6 +845,15 @@ __device__ __forceinline__ double flush_plane_owned(const MeshArgs& m, const Til
     const int fx = cz_n + cy_n + (t0 - 1) + nbx * ((j0 - t1) + ny_free * (l0 - t2));
     auto pos = [](int b0, int b1, int b2) { return b0 + N * (b1 + N * b2); };
     double dsum = 0.0;
+    // x at the owned positions of this plane (identity rows copy it, x . Ax
+    // needs it), all loads issued together rather than one round trip per row
+    T xd[K * K];
+    if (dot || dir0 || dl1 || dl2) {
+#pragma unroll
+        for (int a2 = 0; a2 < K; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 < K; ++a1) xd[a1 + K * a2] = VPP_LD(at_byte(xt + (nx * a1 + nxy * a2), lane_b), BC_X);
+    }
 #pragma unroll
     for (int a2 = 0; a2 < K; ++a2)
 #pragma unroll
@@ -861,7 +870,7 @@ __device__ __forceinline__ double flush_plane_owned(const MeshArgs& m, const Til
             const int row = nx * a1 + nxy * a2;   // uniform
             const bool lo1 = z1 && hl1, lo2 = z2 && hl2;
             if (dir0 || (z1 && dl1) || (z2 && dl2)) {
-                const T xv = VPP_LD(at_byte(xt + row, lane_b), BC_X);
+                const T xv = xd[a1 + K * a2];
                 VPP_ST(at_byte(yt + row, lane_b), BC_Y, xv);
                 if (dot && !(lo0 || lo1 || lo2)) dsum += (double)xv * (double)xv;
                 continue;
@@ -873,7 +882,7 @@ __device__ __forceinline__ double flush_plane_owned(const MeshArgs& m, const Til
                 dst = part + ((unsigned)rank * nsh + (unsigned)f);
             }
             VPP_ST(dst, BC_OUT, val);
-            if (dot) dsum += (double)VPP_LD(at_byte(xt + row, lane_b), BC_X) * (double)val;
+            if (dot) dsum += (double)xd[a1 + K * a2] * (double)val;
         }
     return dsum;
 }
@@ -1005,11 +1014,15 @@ __global__ void __launch_bounds__((K + 1) * TX * TY * TZ) apply_plane_kernel(App
 #pragma unroll
         for (int l = 0; l < N; ++l)
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                T v = T(VPP_LD(&a.x[base + nx * j + nxy * l], BC_X));
-                if (faces && local_dirichlet<K>(faces, ip, j, l)) v = T(0);
-                uq[j + N * l] = v;
-            }
+            for (int j = 0; j < N; ++j) uq[j + N * l] = T(VPP_LD(&a.x[base + nx * j + nxy * l], BC_X));
+        // Dirichlet entries zeroed after every load has been issued
+        if (faces) {
+#pragma unroll
+            for (int l = 0; l < N; ++l)
+#pragma unroll
+                for (int j = 0; j < N; ++j)
+                    if (local_dirichlet<K>(faces, ip, j, l)) uq[j + N * l] = T(0);
+        }
         sweep2<K, MS, false, 0>(uq);
         sweep2<K, MS, false, 1>(uq);
         if constexpr (QUAD) {
@@ -1325,10 +1338,19 @@ __global__ void __launch_bounds__(2 * TX * TY * TZ) apply_half_kernel(ApplyArgs<
 #pragma unroll
                 for (int a0 = 0; a0 < N; ++a0) {
                     cw[j][a0 + N * a1] = VPP_LD(at_byte(a.phi + tile0 + (a0 + nx * a1), lane_b), BC_PHI);
-                    T xv = VPP_LD(at_byte(a.x + tile0 + (a0 + nx * a1), lane_b), BC_X);
-                    if (faces && local_dirichlet<K>(faces, a0, a1, pl[j])) xv = T(0);
-                    u[j][a0 + N * a1] = xv;
+                    u[j][a0 + N * a1] = VPP_LD(at_byte(a.x + tile0 + (a0 + nx * a1), lane_b), BC_X);
                 }
+        }
+        // Dirichlet entries zeroed after every load has been issued (zeroing
+        // inside the load loop made each group of loads wait for the last)
+        if (faces) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int a1 = 0; a1 < N; ++a1)
+#pragma unroll
+                    for (int a0 = 0; a0 < N; ++a0)
+                        if (local_dirichlet<K>(faces, a0, a1, pl[j])) u[j][a0 + N * a1] = T(0);
         }
         // coefficient at the Gauss points of the two planes (frame plane j is
         // Gauss plane j or k - j, with the same weight)
