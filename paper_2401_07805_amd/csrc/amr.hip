@@ -75,15 +75,28 @@ __device__ __forceinline__ void amr_apply_cell(const AmrArgs& a, const MeshArgs&
     const int64_t base = amr_base<K>(m, idx), off = FINE ? a.nc : 0;
     double cw[N3], u[N3];
     amr_coefficient<K, HV>(m, base, off, phi, cw);
+    // gather in stages, each stage's loads issued together: the constraint
+    // kinds of the cell's nodes, then x and the identity flag of every free
+    // node, then the constrained nodes' terms
+    int kind[N3];
+#pragma unroll
+    for (int q = 0; q < N3; ++q) kind[q] = amr_kind<FINE>(a, amr_local<K>(m, base, q));
+    unsigned char idb[N3];
+#pragma unroll
+    for (int q = 0; q < N3; ++q)
+        if (kind[q] < 0) {
+            const int64_t g = off + amr_local<K>(m, base, q);
+            u[q] = x[g];
+            idb[q] = a.ident[g];
+        }
 #pragma unroll
     for (int q = 0; q < N3; ++q) {
-        const int64_t gl = amr_local<K>(m, base, q);
-        const int kind = amr_kind<FINE>(a, gl);
-        if (kind < 0) {
-            u[q] = amr_read(a, x, off + gl);
+        if (kind[q] < 0) {
+            if (idb[q]) u[q] = 0.0;
         } else {
             double s = 0.0;
-            for (int p = a.cptr[kind]; p < a.cptr[kind + 1]; ++p) s = fma(a.cw[p], amr_read(a, x, a.ccol[p]), s);
+            for (int p = a.cptr[kind[q]]; p < a.cptr[kind[q] + 1]; ++p)
+                s = fma(a.cw[p], amr_read(a, x, a.ccol[p]), s);
             u[q] = s;
         }
     }
