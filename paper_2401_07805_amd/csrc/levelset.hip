@@ -90,14 +90,29 @@ __global__ void __launch_bounds__(256) node_sum_kernel(MeshArgs m, const double*
                 cnt[d] = c;
             }
         }
+        // every contribution loaded before any is added; added in increasing
+        // cell order (b2, b1, b0 nested) as before
+        double t[8];
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+            for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+                for (int b0 = 0; b0 < 2; ++b0)
+                    if (b0 < cnt[0] && b1 < cnt[1] && b2 < cnt[2]) {
+                        const int64_t c =
+                            cell[0][b0] + (int64_t)m.nc[0] * (cell[1][b1] + (int64_t)m.nc[1] * cell[2][b2]);
+                        const int q = loc[0][b0] + N * (loc[1][b1] + N * loc[2][b2]);
+                        t[b0 + 2 * (b1 + 2 * b2)] = cv[q * ncell + c];
+                    }
         double v = 0.0;
-        for (int b2 = 0; b2 < cnt[2]; ++b2)
-            for (int b1 = 0; b1 < cnt[1]; ++b1)
-                for (int b0 = 0; b0 < cnt[0]; ++b0) {
-                    const int64_t c = cell[0][b0] + (int64_t)m.nc[0] * (cell[1][b1] + (int64_t)m.nc[1] * cell[2][b2]);
-                    const int q = loc[0][b0] + N * (loc[1][b1] + N * loc[2][b2]);
-                    v += cv[q * ncell + c];
-                }
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+            for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+                for (int b0 = 0; b0 < 2; ++b0)
+                    if (b0 < cnt[0] && b1 < cnt[1] && b2 < cnt[2]) v += t[b0 + 2 * (b1 + 2 * b2)];
         out[g] = v;
     }
 }
