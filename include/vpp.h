@@ -377,7 +377,7 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream);
 /* Candidate list for a degree: writes up to `cap` configs, returns the count. */
 int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap);
 
-/* Batch of independent problems (same degree k = 2, FP64) with nrhs[i]
+/* Batch of independent problems (same degree, k = 2 or 3; FP64) with nrhs[i]
  * right-hand sides each, applied by ONE persistent kernel that pulls
  * (problem, tile) work items from a device queue (the coefficient of a tile is
  * computed once and reused for all right-hand sides of its problem), followed

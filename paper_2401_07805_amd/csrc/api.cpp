@@ -2240,7 +2240,7 @@ static vpp_status batch_build_table(vpp_batch b)
         tab[i].ntiles = tile_count(m);
         tab[i].dot_begin = dot;
         dot += tab[i].ntiles * b->nrhs[i];
-        item += tile_count(m);
+        item += batch_items(b->k, tab[i].ntiles, b->nrhs[i]);
         rhs += b->nrhs[i];
         part += 8 * std::max<int64_t>(1, tab[i].nshared) * b->nrhs[i];
     }
@@ -2408,7 +2408,7 @@ static vpp_status batch_cg_setup(vpp_batch b)
         P.rhs_begin = rhs;
         P.dot_begin = ndot;
         for (int j = 0; j < b->nrhs[i]; ++j) b->cg_index[k + j] = rhs + j;
-        item += P.ntiles;
+        item += batch_items(b->k, P.ntiles, P.nrhs);
         rhs += P.nrhs;
         ndot += P.ntiles * P.nrhs;
         tab.push_back(P);
@@ -2640,7 +2640,7 @@ vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32
         if (!probs[i]->phi_set) return fail(VPP_ERR_STATE, "vpp_set_phi has not been called for every problem");
         if (nrhs[i] < 1) return fail(VPP_ERR_INVALID_ARG, "nrhs must be >= 1");
     }
-    if (k != 2) return fail(VPP_ERR_UNSUPPORTED, "batched apply is available for degree 2");
+    if (k != 2 && k != 3) return fail(VPP_ERR_UNSUPPORTED, "batched apply is available for degrees 2 and 3");
     DeviceGuard dg(dev);
     vpp_batch b = new vpp_batch_s();
     b->device = dev;

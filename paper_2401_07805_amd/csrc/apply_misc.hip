@@ -253,6 +253,13 @@ template <int K, int TX, int TY, int TZ, int HV>
 __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ, CS = NT + 1;
+    // Q2: a work item is a (problem, tile) whose coefficient is computed once
+    // for all right-hand sides of the problem.  Q3: a work item is a (problem,
+    // tile, rhs), the items of one tile consecutive, and the coefficient is
+    // recomputed per item (its 64 values held across a loop over right-hand
+    // sides, beside the cell's 64, would not fit in the registers; the tile's
+    // phi is still in the caches for the next item).
+    constexpr bool per_tile = K == 2;
     __shared__ double slot[N3 * CS];
     __shared__ int item_s;
     const int tid = threadIdx.x;
@@ -270,7 +277,8 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
         const MeshArgs m = a.probs[pi].m;
         const double* phi = a.probs[pi].phi;
         const int nrhs = a.probs[pi].nrhs, rhs0 = a.probs[pi].rhs_begin;
-        const int tile = item - a.probs[pi].tile_begin;
+        const int local = item - a.probs[pi].tile_begin;
+        const int tile = per_tile ? local : local / nrhs;   // the inverse of batch_items
         const TileCoord tc = tile_coord<K, TX, TY, TZ>(m, tile);
         const int cx = tc.t[0] * TX + lx, cy = tc.t[1] * TY + ly, cz = tc.t[2] * TZ + lz;
         const bool active = cx < m.nc[0] && cy < m.nc[1] && cz < m.nc[2];
@@ -278,29 +286,16 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
         const int nx = m.nn[0], nxy = m.nn[0] * m.nn[1];
         const int64_t tile0 = uniform_i64(node_index(m, tc.n0[0], tc.n0[1], tc.n0[2]));
         const unsigned lane_b = (unsigned)(K * lx + nx * K * ly + nxy * K * lz) * (unsigned)sizeof(double);
-        // systems of a batched PCG that have stopped are skipped
-        bool any = true;
-        if (a.st) {
-            any = false;
-            for (int r = 0; r < nrhs; ++r) any = any || !a.st[rhs0 + r].halt[a.par];
-        }
-        // the bounds table of the debug build: this problem's phi (the
-        // barrier first: the previous item's write-out may still read it)
-        VPP_BC_SYNC();
-        VPP_BC_BEGIN((const double*)nullptr, (const double*)nullptr, phi, (const double*)nullptr,
-                     (const double*)nullptr, slot, (int64_t)m.nn[0] * m.nn[1] * m.nn[2], 0, 0, N3 * CS);
-        // the coefficient of the tile is computed once for all right-hand sides
-        double cw[N3];
-        if (active && any) {
-            gather_cell_t<K>(phi + tile0, lane_b, nx, nxy, 0, cw);
-            sweep3<K, MS, false, 0>(cw);
-            sweep3<K, MS, false, 1>(cw);
-            sweep3<K, MS, false, 2>(cw);
-            coef_weights3<K, HV>(m, cw);
-        }
         const int faces = active ? cell_dirichlet_faces(m, cx, cy, cz) : 0;
-        for (int r = 0; r < nrhs; ++r) {
-            if (a.st && a.st[rhs0 + r].halt[a.par]) continue;   // uniform over the workgroup
+        auto coefficient = [&](double (&w)[N3]) {
+            gather_cell_t<K>(phi + tile0, lane_b, nx, nxy, 0, w);
+            sweep3<K, MS, false, 0>(w);
+            sweep3<K, MS, false, 1>(w);
+            sweep3<K, MS, false, 2>(w);
+            coef_weights3<K, HV>(m, w);
+        };
+        // one right-hand side r of this tile with the coefficient cw
+        auto one_rhs = [&](int r, const double (&cw)[N3]) {
             const double* x = a.x[rhs0 + r];
             double* y = a.y[rhs0 + r];
             double* part = a.part + a.probs[pi].part_begin + (int64_t)r * 8 * a.probs[pi].nshared;
@@ -327,6 +322,34 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
                 const double sum = block_sum<NT>(d);
                 if (tid == 0) VPP_ST(&a.dot_part[a.probs[pi].dot_begin + r * a.probs[pi].ntiles + tile], BC_DOT, sum);
             }
+        };
+        if constexpr (per_tile) {
+            // systems of a batched PCG that have stopped are skipped
+            bool any = true;
+            if (a.st) {
+                any = false;
+                for (int r = 0; r < nrhs; ++r) any = any || !a.st[rhs0 + r].halt[a.par];
+            }
+            // the bounds table of the debug build: this problem's phi (the
+            // barrier first: the previous item's write-out may still read it)
+            VPP_BC_SYNC();
+            VPP_BC_BEGIN((const double*)nullptr, (const double*)nullptr, phi, (const double*)nullptr,
+                         (const double*)nullptr, slot, (int64_t)m.nn[0] * m.nn[1] * m.nn[2], 0, 0, N3 * CS);
+            double cw[N3];
+            if (active && any) coefficient(cw);
+            for (int r = 0; r < nrhs; ++r) {
+                if (a.st && a.st[rhs0 + r].halt[a.par]) continue;   // uniform over the workgroup
+                one_rhs(r, cw);
+            }
+        } else {
+            const int r = local - tile * nrhs;
+            if (a.st && a.st[rhs0 + r].halt[a.par]) continue;   // uniform over the workgroup
+            VPP_BC_SYNC();
+            VPP_BC_BEGIN((const double*)nullptr, (const double*)nullptr, phi, (const double*)nullptr,
+                         (const double*)nullptr, slot, (int64_t)m.nn[0] * m.nn[1] * m.nn[2], 0, 0, N3 * CS);
+            double cw[N3];
+            if (active) coefficient(cw);
+            one_rhs(r, cw);
         }
     }
 }
@@ -370,7 +393,9 @@ __global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a
     X(2, 32, 4, 4)           \
     X(2, 8, 8, 4)            \
     X(2, 16, 4, 4)           \
-    X(2, 8, 4, 4)
+    X(2, 8, 4, 4)            \
+    X(3, 8, 4, 4)            \
+    X(3, 4, 4, 4)
 
 hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
                               bool tiles_only, hipStream_t s)

@@ -173,6 +173,11 @@ hipError_t launch_dot_partials(const double* x, const double* y, int64_t n, doub
                                hipStream_t s);
 
 // Batched persistent apply (FP64).
+// Work items of one problem of a batch: a (tile) at degree 2, whose
+// coefficient serves all right-hand sides, a (tile, rhs) at degree 3, the
+// items of one tile consecutive (batch_apply_kernel).
+__host__ __device__ inline int batch_items(int k, int ntiles, int nrhs) { return k == 2 ? ntiles : ntiles * nrhs; }
+
 struct BatchProblem {
     MeshArgs m;
     const double* phi;

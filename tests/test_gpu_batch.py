@@ -230,3 +230,81 @@ def test_c3_batch_apply_against_oracle():
             say("c3 mesh", m.ncells[0], "ratio", wl.extra["ratio"], "rhs", r, f"err {err:.2e} max {errm:.2e}")
             assert err < 1e-12 and errm < 1e-12
             i += 1
+
+
+def test_batch_q3_apply_against_oracle():
+    """Q3 batches (a work item per (mesh, tile, rhs), the coefficient recomputed
+    per item): five meshes of 4..13 cells per side (ragged tiles in every
+    direction), density ratios from {1e2, 1e3, 1e4}, three right-hand sides
+    each; every output against the oracle's CSR product at 1e-12 and against
+    the single-problem apply, for every batch kernel configuration of degree 3,
+    and graph replays repeat the bits."""
+    wls = W.batch_meshes(sizes=(4, 6, 9, 5, 13), nrhs=3, k=3)
+    probs, ops = [], []
+    for wl in wls:
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(dev(wl.phi))
+        probs.append(p)
+        ops.append(oracle.Operator(wl.mesh, phi=wl.phi))
+    xs = [dev(wl.vectors[r]) for wl in wls for r in range(3)]
+    say("q3 batch create")
+    bt = vpp.Batch(probs, [3] * len(probs))
+    assert bt.config["variant"] == 4
+    ys = [torch.empty_like(x) for x in xs]
+    say("q3 batch apply", bt.config)
+    bt.apply(xs, ys)
+    i = 0
+    for p, wl, op in zip(probs, wls, ops):
+        for r in range(3):
+            y = host(ys[i])
+            yref = op.matvec(wl.vectors[r])
+            say("q3 mesh", wl.mesh.ncells[0], "rhs", r, f"err {rel(y, yref):.2e} max {rel_max(y, yref):.2e}")
+            assert rel(y, yref) < 1e-12 and rel_max(y, yref) < 1e-12
+            assert rel(y, host(p.apply(xs[i]))) < 1e-13
+            i += 1
+    first = [y.clone() for y in ys]
+    for _ in range(2):
+        bt.apply(xs, ys)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(first, ys))
+
+
+def test_batch_q3_cg_fp64_matches_oracle():
+    """Lockstep FP64 PCG of Q3 systems (three meshes, two right-hand sides
+    each: the manufactured sine load of the mesh's sphere and the phi-free sine
+    load): each reaches the oracle's direct solution with its true residual
+    (oracle CSR) below rtol, in the oracle PCG's iteration count +-2."""
+    wls = W.batch_meshes(sizes=(4, 6, 5), nrhs=2, k=3)
+    probs, systems = [], []
+    for wl in wls:
+        m = wl.mesh
+        p = vpp.Problem.from_mesh(m)
+        p.set_phi(dev(wl.phi))
+        probs.append(p)
+        op = oracle.Operator(m, phi=wl.phi)
+        for b in (oracle.manufactured_sine_rhs(m, wl.extra["radius"], m.eps), oracle.sine_load(m)):
+            systems.append((op, b))
+    bt = vpp.Batch(probs, [2] * len(probs))
+    bs = [dev(b) for _, b in systems]
+    xs = [torch.zeros_like(b) for b in bs]
+    say("q3 batch cg", bt.config)
+    infos = bt.cg_solve(bs, xs, rtol=1e-10, check_every=4)
+    for i, ((op, b), inf) in enumerate(zip(systems, infos)):
+        x = host(xs[i])
+        pref = spla.spsolve(op.to_scipy().tocsc(), b)
+        res = np.linalg.norm(b - op.matvec(x)) / np.linalg.norm(b)
+        _, oinf = op.pcg(b, rtol=1e-10)
+        say("q3 system", i, inf["iterations"], "oracle", oinf["iterations"], f"res {res:.2e}")
+        assert inf["status"] == 0
+        assert res < 1e-10 * 1.01
+        assert rel(x, pref) < 1e-8
+        assert abs(inf["iterations"] - oinf["iterations"]) <= 2
+
+
+def test_batch_rejects_degree_four():
+    wl = W.batch_meshes(sizes=(3,), nrhs=1, k=4)[0]
+    p = vpp.Problem.from_mesh(wl.mesh)
+    p.set_phi(dev(wl.phi))
+    with pytest.raises(vpp.VppError) as e:
+        vpp.Batch([p], [1])
+    assert "degrees 2 and 3" in str(e.value)

@@ -3,7 +3,7 @@ global and LDS access of the apply tile kernels and of the shared-node
 assembly checked against its buffer, see vpp_debug_bounds_violations) runs
 every instantiated configuration on ragged meshes, in FP64 and FP32, with
 and without the x . Ax partials (inside CG), with the mass shift, the
-arithmetic density mean, the batched apply and the allocation-free apply:
+arithmetic density mean, the batched apply (Q2 and Q3) and the allocation-free apply:
 no access falls outside its buffer, and every configuration gives the same
 result.  The release library reports -1 (no checks compiled in).
 
@@ -107,27 +107,28 @@ for k, shapes in MESHES.items():
         rz = rel(yz, pz.apply(xq))
         out["max_rel"] = max(out["max_rel"], rz)
         check(f"k={k} {shape} noalloc rel {rz:.1e}")
-# batched apply (k = 2) over two ragged meshes, two right-hand sides each
-probs, xs, ys = [], [], []
-for shape in ((13, 7, 5), (6, 9, 4)):
-    m = W.Mesh(ncells=shape, degree=2, bc=(0,) * 6, rho_l=1000.0, rho_g=1.0)
-    pr = vpp.Problem.from_mesh(m)
-    pr.set_phi(torch.from_numpy(W.droplet_phi(m, 0.3, 0.08)).to(dev))
-    probs.append(pr)
-    for r in range(2):
-        xs.append(torch.from_numpy(W.uniform_vectors(9 + r, 1, m.ndofs)[0]).to(dev))
-        ys.append(torch.empty_like(xs[-1]))
-bt = vpp.Batch(probs, [2, 2])
-bt.apply(xs, ys)
-torch.cuda.synchronize()
-check("batch")
-i = 0
-for pr in probs:
-    for r in range(2):
-        rb = rel(ys[i], pr.apply(xs[i]))
-        print("batch rhs", i, "rel", rb, flush=True)
-        out["max_rel"] = max(out["max_rel"], rb)
-        i += 1
+# batched apply (k = 2 and 3) over two ragged meshes, two right-hand sides each
+for k, shapes in ((2, ((13, 7, 5), (6, 9, 4))), (3, ((9, 5, 3), (4, 6, 5)))):
+    probs, xs, ys = [], [], []
+    for shape in shapes:
+        m = W.Mesh(ncells=shape, degree=k, bc=(0,) * 6, rho_l=1000.0, rho_g=1.0)
+        pr = vpp.Problem.from_mesh(m)
+        pr.set_phi(torch.from_numpy(W.droplet_phi(m, 0.3, 0.08)).to(dev))
+        probs.append(pr)
+        for r in range(2):
+            xs.append(torch.from_numpy(W.uniform_vectors(9 + r, 1, m.ndofs)[0]).to(dev))
+            ys.append(torch.empty_like(xs[-1]))
+    bt = vpp.Batch(probs, [2, 2])
+    bt.apply(xs, ys)
+    torch.cuda.synchronize()
+    check(f"batch k={k} {bt.config}")
+    i = 0
+    for pr in probs:
+        for r in range(2):
+            rb = rel(ys[i], pr.apply(xs[i]))
+            print("batch k", k, "rhs", i, "rel", rb, flush=True)
+            out["max_rel"] = max(out["max_rel"], rb)
+            i += 1
 print("RESULT", json.dumps(out), flush=True)
 """
 
