@@ -2262,6 +2262,13 @@ static vpp_status batch_build_table(vpp_batch b)
     return VPP_OK;
 }
 
+static int batch_any_mass(vpp_batch b)
+{
+    for (const auto& t : b->tab)
+        if (t.m.mass != 0.0) return 1;
+    return 0;
+}
+
 static vpp_status batch_build_graph(vpp_batch b)
 {
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
@@ -2270,6 +2277,7 @@ static vpp_status batch_build_graph(vpp_batch b)
     VPP_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     BatchArgs ba{b->d_probs, (int)b->probs.size(), b->nitems, b->d_x, b->d_y, b->d_part, b->d_queue,
                  b->probs[0]->desc.heaviside, nullptr, 0, nullptr};
+    ba.any_mass = batch_any_mass(b);
     hipError_t err = launch_batch_apply(b->cfg, b->k, ba, b->nblocks, b->total_rhs, false, b->stream);
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (err != hipSuccess) {
@@ -2497,6 +2505,7 @@ static vpp_status batch_cg_graph(vpp_batch b, int iters)
         const int par = it & 1;
         BatchArgs ba{b->cg_probs, (int)b->cg_prob.size(), b->cg_nitems, b->cg_tp, b->cg_tq, b->d_part, b->d_queue,
                      b->probs[0]->desc.heaviside, b->cg_st, par, b->cg_dot};
+        ba.any_mass = batch_any_mass(b);
         err = launch_batch_apply(b->cfg, b->k, ba, b->cg_nblocks, b->cg_nsys, true, b->stream);
         if (err == hipSuccess)
             err = launch_cg_batch_step(b->cg_sys, b->cg_nsys, b->cg_blocks, par, b->d_queue, b->stream);
@@ -2519,6 +2528,7 @@ static vpp_status batch_cg_apply_x(vpp_batch b)
 {
     BatchArgs ba{b->cg_probs, (int)b->cg_prob.size(), b->cg_nitems, b->cg_tx, b->cg_tq, b->d_part, b->d_queue,
                  b->probs[0]->desc.heaviside, nullptr, 0, nullptr};
+    ba.any_mass = batch_any_mass(b);
     VPP_HIP(launch_batch_apply(b->cfg, b->k, ba, b->cg_nblocks, b->cg_nsys, false, b->stream));
     return VPP_OK;
 }

@@ -249,7 +249,7 @@ int device_cu_count()
 // and reused for all right-hand sides of its problem.  A second launch
 // assembles the shared-face nodes of every (problem, rhs) and resets the counter.
 
-template <int K, int TX, int TY, int TZ, int HV>
+template <int K, int TX, int TY, int TZ, int HV, int DM>
 __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
 {
     constexpr int N = K + 1, N3 = N * N * N, NT = TX * TY * TZ, CS = NT + 1;
@@ -258,7 +258,10 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
     // tile, rhs), the items of one tile consecutive, and the coefficient is
     // recomputed per item (its 64 values held across a loop over right-hand
     // sides, beside the cell's 64, would not fit in the registers; the tile's
-    // phi is still in the caches for the next item).
+    // phi is still in the caches for the next item).  At degree 3 the x . Ax
+    // partials of the batched PCG (DM & 1) and the mass shift (DM & 2) are
+    // template choices, as in the single-problem kernel, which keeps the
+    // branches they would add out of the register allocation.
     constexpr bool per_tile = K == 2;
     __shared__ double slot[N3 * CS];
     __shared__ int item_s;
@@ -306,8 +309,12 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             double u[N3];
             if (active) {
                 gather_cell_t<K>(x + tile0, lane_b, nx, nxy, faces, u);
-                if (m.mass != 0.0) cell_operator<K, double, true>(m, cw, u);   // uniform per problem
-                else cell_operator<K>(m, cw, u);
+                if constexpr (per_tile) {
+                    if (m.mass != 0.0) cell_operator<K, double, true>(m, cw, u);   // uniform per problem
+                    else cell_operator<K>(m, cw, u);
+                } else {
+                    cell_operator<K, double, (DM & 2) != 0>(m, cw, u);   // a zero shift adds exact zeros
+                }
             }
             __syncthreads();   // the previous write-out has finished reading the slots
             if (active) {
@@ -316,9 +323,10 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
                     if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) VPP_ST(&slot[q * CS + tid], BC_SLOT, u[q]);
             }
             __syncthreads();
+            const bool dot = per_tile ? a.st != nullptr : (DM & 1) != 0;
             const double d = flush_two_pass<K, double, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy,
-                                                                   cz, x, y, part, a.probs[pi].nshared, a.st != nullptr);
-            if (a.st) {
+                                                                   cz, x, y, part, a.probs[pi].nshared, dot);
+            if (dot) {
                 const double sum = block_sum<NT>(d);
                 if (tid == 0) VPP_ST(&a.dot_part[a.probs[pi].dot_begin + r * a.probs[pi].ntiles + tile], BC_DOT, sum);
             }
@@ -397,17 +405,29 @@ __global__ void __launch_bounds__(256) batch_assemble_kernel(BatchAssembleArgs a
     X(3, 8, 4, 4)            \
     X(3, 4, 4, 4)
 
+template <int K, int TX, int TY, int TZ, int HV>
+static void launch_batch_tiles(const BatchArgs& a, int nblocks, hipStream_t s)
+{
+    const dim3 g(nblocks), blk(TX * TY * TZ);
+    if constexpr (K == 2) {
+        hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 0>), g, blk, 0, s, a);
+    } else {
+        switch ((a.st ? 1 : 0) | (a.any_mass ? 2 : 0)) {
+        case 0: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 0>), g, blk, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 1>), g, blk, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 2>), g, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 3>), g, blk, 0, s, a); break;
+        }
+    }
+}
+
 hipError_t launch_batch_apply(const LaunchCfg& c, int k, const BatchArgs& a, int nblocks, int total_rhs,
                               bool tiles_only, hipStream_t s)
 {
 #define VPP_BL(K, TX, TY, TZ)                                                                       \
     if (k == K && c.variant == 4 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {       \
-        if (a.heaviside == 0)                                                                       \
-            hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, 0>), dim3(nblocks),                \
-                               dim3(TX * TY * TZ), 0, s, a);                                        \
-        else                                                                                        \
-            hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, 1>), dim3(nblocks),                \
-                               dim3(TX * TY * TZ), 0, s, a);                                        \
+        if (a.heaviside == 0) launch_batch_tiles<K, TX, TY, TZ, 0>(a, nblocks, s);                  \
+        else launch_batch_tiles<K, TX, TY, TZ, 1>(a, nblocks, s);                                   \
         hipError_t e = hipGetLastError();                                                           \
         if (e != hipSuccess || tiles_only) return e;                                                \
         BatchAssembleArgs b{a.probs, a.nprob, a.y, a.part, a.queue};                                \
@@ -437,7 +457,7 @@ int batch_blocks_per_cu(const LaunchCfg& c, int k)
     int nb = 0;
 #define VPP_BO(K, TX, TY, TZ)                                                                      \
     if (k == K && c.variant == 4 && c.tile[0] == TX && c.tile[1] == TY && c.tile[2] == TZ) {      \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_apply_kernel<K, TX, TY, TZ, 0>,\
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_apply_kernel<K, TX, TY, TZ, 0, 0>,\
                                                          TX * TY * TZ, 0) != hipSuccess)          \
             return 0;                                                                              \
         return nb;                                                                                 \

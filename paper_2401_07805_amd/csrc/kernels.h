@@ -206,6 +206,7 @@ struct BatchArgs {
     const CgState* st;
     int par;
     double* dot_part;
+    int any_mass = 0;    // some problem has a mass shift (at degree 3 it selects the kernel instantiation)
 };
 
 // Persistent tile kernel over all work items, then (unless tiles_only) one

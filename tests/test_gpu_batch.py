@@ -308,3 +308,33 @@ def test_batch_rejects_degree_four():
     with pytest.raises(vpp.VppError) as e:
         vpp.Batch([p], [1])
     assert "degrees 2 and 3" in str(e.value)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_batch_with_mass_shift_equals_single(k):
+    """A batch of two meshes, one with the mass shift mu M (set before the batch
+    is created) and one without: every output equals the single-problem apply
+    of its problem (which the oracle pins with and without the shift), and the
+    lockstep PCG of the shifted systems reaches the single solve's iterate."""
+    wls = W.batch_meshes(sizes=(5, 7), nrhs=2, k=k)
+    probs = []
+    for i, wl in enumerate(wls):
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(dev(wl.phi))
+        if i == 0:
+            p.set_mass(0.75)
+        probs.append(p)
+    bt = vpp.Batch(probs, [2, 2])
+    xs = [dev(wl.vectors[r]) for wl in wls for r in range(2)]
+    ys = [torch.empty_like(x) for x in xs]
+    say("mass batch", k, bt.config)
+    bt.apply(xs, ys)
+    for i, p in enumerate(q for q in probs for _ in range(2)):
+        assert rel(host(ys[i]), host(p.apply(xs[i]))) < 1e-13
+    bs = [p.apply(x) for p, x in zip((q for q in probs for _ in range(2)), xs)]
+    sol = [torch.zeros_like(b) for b in bs]
+    infos = bt.cg_solve(bs, sol, rtol=1e-10)
+    for i, (p, inf) in enumerate(zip((q for q in probs for _ in range(2)), infos)):
+        x1, inf1 = p.cg_solve(bs[i], rtol=1e-10)
+        assert inf["status"] == 0 and abs(inf["iterations"] - inf1["iterations"]) <= 1
+        assert rel(host(sol[i]), host(x1)) < 1e-8
