@@ -629,8 +629,9 @@ def c2_figures(torch, vpp, W, dev, cache):
 def batch_figures(torch, vpp, W, dev, cache, per_mesh=True):
     """The batched workload: 8 independent single-sphere meshes of 16..64 cells per
     side (Q2, 7.6M DoFs) with 4 right-hand sides each, applied by one persistent
-    graph launch; aggregate (and with per_mesh, per-mesh) DoF-rhs rates, and the
-    batched FP64 PCG of its 32 systems."""
+    graph launch; aggregate (and with per_mesh, per-mesh) DoF-rhs rates, the
+    batched FP64 PCG of its 32 systems, and a Q3 batch (8 meshes of 8..32 cells
+    per side, 4 right-hand sides each) against its 32 single applies."""
     wls = W.batch_meshes()
     probs, xs = [], []
     for wl in wls:
@@ -666,6 +667,28 @@ def batch_figures(torch, vpp, W, dev, cache, per_mesh=True):
         out["batch_per_mesh_mdofs"].append({"n": wl.mesh.ncells[0], "ratio": wl.extra["ratio"], "mdofs": r1})
         i += nr
     out.update(batch_cg_figures(torch, bt, probs, xs))
+    # Q3 batches: eight meshes of 8..32 cells per side with four right-hand
+    # sides each, batched against the same 32 single-problem applies
+    q3 = W.batch_meshes(sizes=(8, 10, 12, 14, 16, 20, 24, 32), nrhs=4, k=3)
+    qp, qx = [], []
+    for wl in q3:
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(torch.from_numpy(wl.phi).to(dev))
+        qp.append(p)
+        qx += [torch.from_numpy(v).to(dev) for v in wl.vectors]
+    qy = [torch.empty_like(x) for x in qx]
+    qb = vpp.Batch(qp, [4] * len(qp), tune_cache=cache)
+    qtotal = sum(wl.mesh.ndofs * 4 for wl in q3)
+    tq, rq = rate(qb, qx, qy, qtotal)
+
+    class Singles:
+        def apply(self, xx, yy):
+            for j, (x, y) in enumerate(zip(xx, yy)):
+                qp[j // 4].apply(x, out=y)
+
+    ts, rs = rate(Singles(), qx, qy, qtotal)
+    out.update({"q3_batch_config": qb.config, "q3_batch_dof_rhs": qtotal, "q3_batch_apply_us": tq * 1e6,
+                "q3_batch_aggregate_mdofs": rq, "q3_single_applies_us": ts * 1e6, "q3_single_applies_mdofs": rs})
     return out
 
 
