@@ -338,3 +338,43 @@ def test_batch_with_mass_shift_equals_single(k):
         x1, inf1 = p.cg_solve(bs[i], rtol=1e-10)
         assert inf["status"] == 0 and abs(inf["iterations"] - inf1["iterations"]) <= 1
         assert rel(host(sol[i]), host(x1)) < 1e-8
+
+
+@pytest.mark.timeout(600)
+def test_q3_batch_bench_workload_against_oracle():
+    """The Q3 batch that bench.py times (8 meshes of 8..32 cells per side, 4
+    seeded right-hand sides each, one persistent batched apply in the tuned
+    configuration): every output against the oracle at 1e-12 relative - all
+    rows on the meshes up to 12^3 (CSR), 1500 seeded rows plus every 997th row
+    on the larger ones (row by row)."""
+    wls = W.batch_meshes(sizes=(8, 10, 12, 14, 16, 20, 24, 32), nrhs=4, k=3)
+    probs, xs = [], []
+    for wl in wls:
+        p = vpp.Problem.from_mesh(wl.mesh)
+        p.set_phi(dev(wl.phi))
+        probs.append(p)
+        xs += [dev(v) for v in wl.vectors]
+    ys = [torch.empty_like(x) for x in xs]
+    bt = vpp.Batch(probs, [4] * len(probs))
+    say("q3 bench batch apply", bt.config)
+    bt.apply(xs, ys)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(78)
+    i = 0
+    for wl in wls:
+        m = wl.mesh
+        full = m.ncells[0] <= 12
+        op = oracle.Operator(m, phi=wl.phi) if full else None
+        rows = None if full else np.unique(np.concatenate([rng.choice(m.ndofs, 1500, replace=False),
+                                                            np.arange(0, m.ndofs, 997)]))
+        for r in range(4):
+            y, x = host(ys[i]), wl.vectors[r]
+            if full:
+                yref = op.matvec(x)
+                err, errm = rel(y, yref), rel_max(y, yref)
+            else:
+                yr = oracle.apply_rows(m, wl.phi, x, rows)
+                err, errm = rel(y[rows], yr), rel_max(y[rows], yr)
+            say("q3 bench mesh", m.ncells[0], "rhs", r, f"err {err:.2e} max {errm:.2e}")
+            assert err < 1e-12 and errm < 1e-12
+            i += 1
