@@ -378,11 +378,13 @@ vpp_status vpp_tune(vpp_problem p, const char* cache_path, void* stream);
 int32_t vpp_config_candidates(int32_t degree, vpp_kernel_config* out, int32_t cap);
 
 /* Batch of independent problems (same degree, k = 2 or 3; FP64) with nrhs[i]
- * right-hand sides each, applied by ONE persistent kernel that pulls
- * (problem, tile) work items from a device queue (the coefficient of a tile is
- * computed once and reused for all right-hand sides of its problem), followed
- * by one assembly launch for the shared-face nodes of every (problem, rhs);
- * both launches are recorded in one hipGraph.
+ * right-hand sides each, applied by ONE persistent kernel that pulls work
+ * items from a device queue, followed by one assembly launch for the
+ * shared-face nodes of every (problem, rhs); both launches are recorded in one
+ * hipGraph.  k = 2: an item is a (problem, tile), the coefficient of the tile
+ * computed once for all right-hand sides of its problem; k = 3: an item is a
+ * (problem, tile, rhs), the items of one tile consecutive, the coefficient
+ * recomputed per item.  Degree 4 returns VPP_ERR_UNSUPPORTED.
  * tune_cache: JSON cache path for the autotuner, or NULL to tune without a cache.
  * The problems must have phi set and outlive the batch. */
 vpp_status vpp_batch_create(const vpp_problem* probs, const int32_t* nrhs, int32_t nprob,
