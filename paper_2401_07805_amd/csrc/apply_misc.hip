@@ -258,10 +258,10 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
     // tile, rhs), the items of one tile consecutive, and the coefficient is
     // recomputed per item (its 64 values held across a loop over right-hand
     // sides, beside the cell's 64, would not fit in the registers; the tile's
-    // phi is still in the caches for the next item).  At degree 3 the x . Ax
-    // partials of the batched PCG (DM & 1) and the mass shift (DM & 2) are
-    // template choices, as in the single-problem kernel, which keeps the
-    // branches they would add out of the register allocation.
+    // phi is still in the caches for the next item).  The x . Ax partials of
+    // the batched PCG (DM & 1) and the mass shift (DM & 2) are template
+    // choices, as in the single-problem kernel, which keeps the branches they
+    // would add out of the register allocation.
     constexpr bool per_tile = K == 2;
     __shared__ double slot[N3 * CS];
     __shared__ int item_s;
@@ -309,12 +309,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
             double u[N3];
             if (active) {
                 gather_cell_t<K>(x + tile0, lane_b, nx, nxy, faces, u);
-                if constexpr (per_tile) {
-                    if (m.mass != 0.0) cell_operator<K, double, true>(m, cw, u);   // uniform per problem
-                    else cell_operator<K>(m, cw, u);
-                } else {
-                    cell_operator<K, double, (DM & 2) != 0>(m, cw, u);   // a zero shift adds exact zeros
-                }
+                cell_operator<K, double, (DM & 2) != 0>(m, cw, u);   // a zero shift adds exact zeros
             }
             __syncthreads();   // the previous write-out has finished reading the slots
             if (active) {
@@ -323,7 +318,7 @@ __global__ void __launch_bounds__(TX * TY * TZ) batch_apply_kernel(BatchArgs a)
                     if (!owned_pos<K>(q % N, (q / N) % N, q / (N * N))) VPP_ST(&slot[q * CS + tid], BC_SLOT, u[q]);
             }
             __syncthreads();
-            const bool dot = per_tile ? a.st != nullptr : (DM & 1) != 0;
+            constexpr bool dot = (DM & 1) != 0;
             const double d = flush_two_pass<K, double, TX, TY, TZ>(m, tc, slot, CS, u, active, lx, ly, lz, cx, cy,
                                                                    cz, x, y, part, a.probs[pi].nshared, dot);
             if (dot) {
@@ -409,15 +404,11 @@ template <int K, int TX, int TY, int TZ, int HV>
 static void launch_batch_tiles(const BatchArgs& a, int nblocks, hipStream_t s)
 {
     const dim3 g(nblocks), blk(TX * TY * TZ);
-    if constexpr (K == 2) {
-        hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 0>), g, blk, 0, s, a);
-    } else {
-        switch ((a.st ? 1 : 0) | (a.any_mass ? 2 : 0)) {
-        case 0: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 0>), g, blk, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 1>), g, blk, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 2>), g, blk, 0, s, a); break;
-        default: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 3>), g, blk, 0, s, a); break;
-        }
+    switch ((a.st ? 1 : 0) | (a.any_mass ? 2 : 0)) {
+    case 0: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 0>), g, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 1>), g, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 2>), g, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((batch_apply_kernel<K, TX, TY, TZ, HV, 3>), g, blk, 0, s, a); break;
     }
 }
 
